@@ -1,0 +1,98 @@
+/*
+ * swccl_oracle.h -- the CPU oracle for the Swendsen-Wang sweep and for
+ * connected-component labeling on 2D square lattices.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, sequential, deliberately slow
+ * reference.  Only the test-suite, the smoke check and the CPU-baseline leg of
+ * the benchmark may call it; the product path never does.  It shares no code,
+ * header, table or helper with the GPU library.
+ *
+ * Conventions (shared *by definition*, not by code, with the GPU library):
+ *   - site index i = y*W + x, x fastest; N = W*H.
+ *   - site i owns two bonds: "right" to (x+1 mod W, y) and "down" to
+ *     (x, y+1 mod H).  Packed bond byte: bit0 = right, bit1 = down.
+ *   - Potts states are stored as 0..q-1 (the paper's 1..q shifted by one).
+ *   - Philox4x32-10: key = (lo32(seed), hi32(seed)), counter =
+ *     (index word, sweep t, tag, stream id), tags below.
+ *   - a bond between equal spins is active iff its 32-bit uniform r satisfies
+ *     r < T with T = floor(p * 2^32), p = 1 - exp(-K)  (Sec. II, Eq. fortuin3
+ *     and the bond-activation rule of Sec. II.A).
+ *   - the canonical label of a cluster is its minimum site index.
+ *
+ * Each function cites the passage of the paper it follows.
+ */
+#ifndef SWCCL_ORACLE_H
+#define SWCCL_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_TAG_INIT = 0, ORC_TAG_BOND = 1, ORC_TAG_FLIP = 2 };
+enum { ORC_PERIODIC = 0, ORC_OPEN = 1 };
+
+/* Per-sweep record written by orc_sw_run (one row of ORC_REC_LEN int64). */
+enum {
+    ORC_REC_ACTIVE = 0,   /* active bonds of the sweep's bond configuration */
+    ORC_REC_NCLUST = 1,   /* number of clusters (components)                 */
+    ORC_REC_MAXCL = 2,    /* largest cluster size                            */
+    ORC_REC_NSAT = 3,     /* satisfied bonds of the spins after the flip     */
+    ORC_REC_COUNTS = 4,   /* counts[0..7] of states after the flip           */
+    ORC_REC_LEN = 12
+};
+
+/* Philox4x32-10 block function (Salmon et al., SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* T = floor((1 - exp(-K)) * 2^32), clamped to [0, 2^32]. */
+uint64_t orc_threshold(double K);
+
+/* Random initial states 0..q-1 (tag INIT, sweep word 0). */
+void orc_init_states(int32_t W, int32_t H, int32_t q, uint64_t seed, uint32_t sid,
+                     uint8_t *state);
+
+/* Step 1 of the SW update: packed bond bytes for sweep t. */
+void orc_activate_bonds(int32_t W, int32_t H, const uint8_t *state, uint64_t T,
+                        uint64_t seed, uint32_t t, uint32_t sid, uint8_t *bonds);
+
+/* Step 2: canonical component labels of a bond configuration.  mode is
+ * ORC_PERIODIC or ORC_OPEN (wrap bonds ignored).  Returns the cluster count. */
+int64_t orc_label_bonds(int32_t W, int32_t H, const uint8_t *bonds, int32_t mode,
+                        int32_t *labels);
+
+/* Labeling of a binary image: 4-connected occupied pixels (occ != 0), open
+ * boundaries; background pixels get label -1.  Returns the cluster count. */
+int64_t orc_label_sites(int32_t W, int32_t H, const uint8_t *occ, int32_t *labels);
+
+/* Cluster sizes: roots in ascending order and their sizes; labels < 0 are
+ * skipped.  roots/sizes may be NULL.  Returns the cluster count and the largest
+ * size in *max_size (if not NULL). */
+int64_t orc_cluster_sizes(int64_t N, const int32_t *labels, int32_t *roots,
+                          int32_t *sizes, int64_t *max_size);
+
+/* Step 3: every cluster takes the state drawn at its canonical root. */
+void orc_flip(int32_t W, int32_t H, int32_t q, const int32_t *labels, uint64_t seed,
+              uint32_t t, uint32_t sid, uint8_t *state);
+
+/* Satisfied bonds (s_i == s_j over all 2N bonds) and, for k < min(q, 8),
+ * counts[k] = number of sites in state k. */
+int64_t orc_satisfied(int32_t W, int32_t H, int32_t q, const uint8_t *state,
+                      int64_t counts[8]);
+
+/* One SW sweep t in place.  bonds/labels (may be NULL) receive the sweep's
+ * bond configuration and canonical labels (both of the pre-flip spins).
+ * rec (may be NULL) receives one ORC_REC_LEN record. */
+void orc_sw_sweep(int32_t W, int32_t H, int32_t q, uint64_t T, uint64_t seed,
+                  uint32_t sid, uint32_t t, uint8_t *state, uint8_t *bonds,
+                  int32_t *labels, int64_t *rec);
+
+/* n sweeps t0..t0+n-1, one record per sweep into rec[n][ORC_REC_LEN]. */
+void orc_sw_run(int32_t W, int32_t H, int32_t q, uint64_t T, uint64_t seed,
+                uint32_t sid, uint32_t t0, int32_t n, uint8_t *state, int64_t *rec);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
