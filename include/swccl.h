@@ -1,0 +1,183 @@
+/*
+ * swccl.h -- C ABI of the MI355X (gfx950) Swendsen-Wang / connected-component
+ * labeling library (libswccl.so).
+ *
+ * The library runs one Swendsen-Wang (SW) sweep of a periodic 2D q-state Potts
+ * or Ising lattice as three device phases -- bond activation fused with tile
+ * labeling, cross-tile merging, and flatten + cluster flip -- and exposes the
+ * same labeling kernels as a standalone connected-component labeling call.
+ *
+ * Model and update (M. Weigel, "Connected component identification and
+ * cluster update on GPU", arXiv:1105.5804):
+ *   - Potts Hamiltonian, Sec. II, Eq. potts_hamiltonian; q = 2 is the Ising
+ *     model.
+ *   - Bond variables and p = 1 - exp(-K), Sec. II, Eqs. fortuin1-fortuin3
+ *     (K = beta*J in the Potts normalisation; for Ising spins s = +-1 with
+ *     H = -J sum s_i s_j pass K = 2*beta*J).
+ *   - SW steps 1-3 (activate bonds between equal spins with probability p,
+ *     identify connected components, draw one new state per component),
+ *     Sec. II enumerated steps; bond activation rule, Sec. II.A; cluster
+ *     flipping, Sec. II.D.
+ *   - Connected-component labeling as image segmentation / percolation,
+ *     Sec. I and Sec. II.
+ *
+ * Conventions (bit-exact contract; the CPU oracle implements the same
+ * definitions independently):
+ *   - site index i = y*W + x (x fastest), N = W*H, N < 2^31.
+ *   - site i owns the "right" bond to (x+1 mod W, y) and the "down" bond to
+ *     (x, y+1 mod H).  Packed bond byte: bit0 = right, bit1 = down.
+ *   - random numbers: Philox4x32-10 (Salmon et al., SC'11) with
+ *     key = (lo32(seed), hi32(seed)) and counter = (word, t, tag, stream_id).
+ *       init  (tag 0): state_i = (w * q) >> 32, w = block(i>>2, 0)[i&3]
+ *       bonds (tag 1): block(i>>1, t): right uses word 2(i&1), down 2(i&1)+1
+ *       flip  (tag 2): a cluster with canonical root r takes
+ *                      (block(r>>2, t)[r&3] * q) >> 32
+ *   - a bond between equal spins is active iff its word r < T, with
+ *     T = floor((1 - exp(-K)) * 2^32) computed on the host in double.
+ *   - the canonical label of a cluster is the minimum site index in it.
+ *   - states are stored 0..q-1 (SW_SPIN_POTTS_U8, the paper's 1..q minus one)
+ *     or as int8 -1/+1 (SW_SPIN_ISING_I8, q = 2, state 0 <-> -1).
+ *
+ * Memory and ownership: every device buffer is allocated and owned by the
+ * caller; the library allocates no device memory.  Scratch space is the caller's
+ * workspace of at least *_workspace_bytes() bytes.  A lattice handle is a small
+ * host object created by sw_init and freed by sw_destroy.
+ *
+ * Streams: every call enqueues on the given stream (a hipStream_t passed as
+ * void*; NULL is the null stream) and returns without waiting, except
+ * sw_observables, which waits for the stream.
+ *
+ * Errors: every entry point returns an sw_status; arguments are checked before
+ * anything is enqueued and nothing throws across the ABI.  SW_ERR_DEVICE means
+ * a HIP launch or copy failed; sw_last_error() returns its message.
+ */
+#ifndef SWCCL_H
+#define SWCCL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWCCL_ABI_VERSION 1
+
+typedef int32_t sw_status;
+enum {
+    SW_OK = 0,
+    SW_ERR_ARG = 1,         /* null pointer, bad enum, q out of range, n < 0 */
+    SW_ERR_SIZE = 2,        /* W or H < 1 (< 2 for SW), or W*H >= 2^31      */
+    SW_ERR_WORKSPACE = 3,   /* workspace missing or smaller than required   */
+    SW_ERR_DEVICE = 4,      /* a HIP call failed (see sw_last_error)         */
+    SW_ERR_STATE = 5,       /* sweep counter would overflow 32 bits          */
+    SW_ERR_UNSUPPORTED = 6  /* combination not supported by this build       */
+};
+
+/* Spin storage. */
+enum { SW_SPIN_ISING_I8 = 0, SW_SPIN_POTTS_U8 = 1 };
+
+/* sw_params.flags */
+enum { SW_F_KEEP_SPINS = 1u << 0 }; /* sw_init: do not draw initial spins; use the
+                                       caller's (restart from a saved state) */
+
+/* Input kinds of ccl_label. */
+enum {
+    CCL_BONDS_PERIODIC = 0, /* packed bond bytes, bonds wrap around both axes */
+    CCL_BONDS_OPEN = 1,     /* packed bond bytes, wrap bonds ignored          */
+    CCL_SITES_OPEN = 2      /* binary image (byte != 0 occupied), 4-connected,
+                               open boundary; background pixels get label -1 */
+};
+
+typedef struct sw_params {
+    int32_t W, H;       /* lattice extent, W, H >= 2, W*H < 2^31             */
+    int32_t q;          /* number of Potts states, 2..255 (2 for Ising)     */
+    int32_t spin_kind;  /* SW_SPIN_ISING_I8 (q must be 2) or SW_SPIN_POTTS_U8 */
+    double K;           /* FK coupling: p = 1 - exp(-K); K <= 0 gives p = 0,
+                           K = +inf gives p = 1                              */
+    uint64_t seed;      /* Philox key                                       */
+    uint32_t stream_id; /* fourth counter word: independent replicas        */
+    uint32_t flags;     /* SW_F_*                                           */
+} sw_params;
+
+/* Device buffers of one lattice.  All are row-major (i = y*W + x). */
+typedef struct sw_buffers {
+    void *spins;            /* N bytes (int8 or uint8), read and written     */
+    int32_t *labels;        /* N int32 or NULL: canonical labels of the last
+                               sweep's bond configuration                   */
+    uint8_t *bonds;         /* N bytes or NULL: packed bonds of the last sweep */
+    void *workspace;        /* sw_workspace_bytes() bytes, 256-byte aligned  */
+    size_t workspace_bytes;
+} sw_buffers;
+
+/* Observables; see sw_observables. */
+typedef struct sw_obs {
+    uint64_t t;              /* sweeps done so far                              */
+    uint64_t threshold;      /* T used for bond activation                      */
+    int64_t n_sat;           /* satisfied bonds of the current spins (-H/J)     */
+    int64_t magnet;          /* Ising: sum of spins; Potts: 0                   */
+    int64_t counts[8];       /* sites in state k, k < min(q, 8)                 */
+    int64_t n_active_bonds;  /* active bonds of the last sweep (-1: none yet)   */
+    int64_t n_clusters;      /* clusters of the last sweep (-1: none yet)       */
+} sw_obs;
+
+typedef struct sw_lattice sw_lattice;
+
+/* Library and build information. */
+int32_t swccl_abi_version(void);
+const char *sw_status_string(sw_status s);
+/* Message of the last SW_ERR_DEVICE on the calling thread ("" if none). */
+const char *sw_last_error(void);
+
+/* T = floor((1 - exp(-K)) * 2^32) clamped to [0, 2^32]: the integer threshold a
+ * bond's 32-bit uniform must stay below (Sec. II.A activation rule). */
+uint64_t sw_threshold(double K);
+
+/* Workspace bytes needed by a lattice with these parameters (0 if invalid). */
+size_t sw_workspace_bytes(const sw_params *p);
+
+/* Create a lattice handle over caller-owned buffers and, unless
+ * SW_F_KEEP_SPINS is set, draw the initial spins (t = 0, Philox tag 0).
+ * The handle keeps copies of p and b; the buffers must outlive it.
+ * Returns SW_ERR_ARG / SW_ERR_SIZE / SW_ERR_WORKSPACE before enqueuing
+ * anything. */
+sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, void *stream);
+
+/* Enqueue n_sweeps SW sweeps t, t+1, ... (Sec. II, steps 1-3).  After the call
+ * the spins hold the configuration after the last sweep; labels / bonds (if
+ * given) hold that sweep's canonical labels / bond bytes, taken before its
+ * flip.  n_sweeps = 0 is a no-op. */
+sw_status sw_sweep(sw_lattice *h, int32_t n_sweeps, void *stream);
+
+/* Measure the current spins and the last sweep's counters; waits for the
+ * stream. */
+sw_status sw_observables(sw_lattice *h, sw_obs *out, void *stream);
+
+/* Checkpointing: the full state of a lattice is (spins, t); a restart is
+ * sw_init with SW_F_KEEP_SPINS over the saved spins plus sw_set_t. */
+sw_status sw_get_t(const sw_lattice *h, uint64_t *t);
+sw_status sw_set_t(sw_lattice *h, uint64_t t);
+
+/* Free the host handle (device buffers stay with the caller). */
+sw_status sw_destroy(sw_lattice *h);
+
+/* Workspace bytes needed by ccl_label for this shape (0 if invalid). */
+size_t ccl_workspace_bytes(int32_t W, int32_t H, int32_t mode);
+
+/* Connected-component labeling of a bond or site input (steps 2 of the SW
+ * update on a given graph; Sec. II.B-II.C solve the same problem).
+ *   in          device, N bytes (packed bonds or image, see CCL_*)
+ *   labels      device, N int32: canonical labels (min index; -1 background).
+ *               Must not alias in.
+ *   roots,sizes device, N int32 each, or both NULL: roots in ascending order
+ *               and the size of each root's cluster, in the first n entries
+ *   n_clusters  device, 1 int32, or NULL: number of clusters n
+ * W, H >= 1, W*H < 2^31. */
+sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32_t *labels,
+                    int32_t *roots, int32_t *sizes, int32_t *n_clusters, void *workspace,
+                    size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

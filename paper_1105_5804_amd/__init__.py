@@ -1,0 +1,230 @@
+"""Swendsen-Wang cluster updates and connected-component labeling on MI355X.
+
+Thin Python layer over the C ABI of ``libswccl.so`` (``include/swccl.h``):
+torch provides device memory and the current HIP stream, every step of the
+computation runs in the library's gfx950 kernels.  There is no CPU fallback:
+without the built library or a GPU every compute call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+from . import _lib
+from ._lib import (  # noqa: F401
+    CCL_BONDS_OPEN,
+    CCL_BONDS_PERIODIC,
+    CCL_SITES_OPEN,
+    SW_SPIN_ISING_I8,
+    SW_SPIN_POTTS_U8,
+    SwccLError,
+)
+
+__all__ = [
+    "SWLattice",
+    "ccl_label",
+    "ccl_workspace_bytes",
+    "threshold",
+    "ising_K",
+    "potts_K",
+    "CCL_BONDS_PERIODIC",
+    "CCL_BONDS_OPEN",
+    "CCL_SITES_OPEN",
+]
+
+_MODES = {"bonds_periodic": CCL_BONDS_PERIODIC, "bonds_open": CCL_BONDS_OPEN, "sites_open": CCL_SITES_OPEN}
+
+
+def threshold(K: float) -> int:
+    """Integer bond threshold T = floor((1 - exp(-K)) 2^32) used by the library."""
+    return int(_lib.lib().sw_threshold(float(K)))
+
+
+def ising_K(beta: float, J: float = 1.0) -> float:
+    """FK coupling of the +-1 Ising model, H = -J sum s_i s_j: K = 2 beta J."""
+    return 2.0 * beta * J
+
+
+def potts_K(beta: float, J: float = 1.0) -> float:
+    """FK coupling of the Potts model, H = -J sum delta(s_i, s_j): K = beta J."""
+    return beta * J
+
+
+BETA_C_ISING = 0.5 * math.log1p(math.sqrt(2.0))
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("swccl needs a ROCm GPU: torch.cuda.is_available() is False")
+    return torch
+
+
+def _stream(torch, stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _workspace(torch, nbytes: int, device):
+    """A 256-byte aligned device byte range of at least nbytes (tensor, pointer)."""
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    p = buf.data_ptr()
+    return buf, p + ((-p) % 256)
+
+
+class SWLattice:
+    """One periodic W x H lattice advanced by Swendsen-Wang sweeps on the GPU.
+
+    ``spins`` is an (H, W) int8 (Ising, +-1) or uint8 (Potts, 0..q-1) tensor.
+    With ``keep_labels`` / ``keep_bonds`` the canonical labels / packed bonds of
+    the last sweep are kept in ``labels`` / ``bonds``.
+    """
+
+    def __init__(self, W: int, H: int, q: int = 2, K: float | None = None, seed: int = 0,
+                 stream_id: int = 0, ising: bool | None = None, keep_labels: bool = False,
+                 keep_bonds: bool = False, spins=None, t: int = 0, device: str = "cuda"):
+        torch = _torch()
+        L = _lib.lib()
+        if ising is None:
+            ising = q == 2
+        if K is None:
+            K = ising_K(BETA_C_ISING) if q == 2 else math.log1p(math.sqrt(q))
+        self.W, self.H, self.q, self.K = int(W), int(H), int(q), float(K)
+        self.seed, self.stream_id, self.ising = int(seed), int(stream_id), bool(ising)
+        self.device = torch.device(device)
+        p = _lib.SwParams(self.W, self.H, self.q, _lib.SW_SPIN_ISING_I8 if ising else _lib.SW_SPIN_POTTS_U8,
+                          self.K, self.seed & (2**64 - 1), self.stream_id, 0)
+        ws = L.sw_workspace_bytes(ctypes.byref(p))
+        if ws == 0:
+            _lib.check(_lib.SW_ERR_ARG if self.W >= 2 and self.H >= 2 else _lib.SW_ERR_SIZE, "sw_workspace_bytes")
+        dt = torch.int8 if ising else torch.uint8
+        if spins is not None:
+            if spins.shape != (self.H, self.W) or spins.dtype != dt or spins.device.type != "cuda":
+                raise ValueError(f"spins must be a ({self.H}, {self.W}) {dt} GPU tensor")
+            self.spins = spins.contiguous()
+            p.flags = _lib.SW_F_KEEP_SPINS
+        else:
+            self.spins = torch.empty((self.H, self.W), dtype=dt, device=self.device)
+        self.labels = torch.empty((self.H, self.W), dtype=torch.int32, device=self.device) if keep_labels else None
+        self.bonds = torch.empty((self.H, self.W), dtype=torch.uint8, device=self.device) if keep_bonds else None
+        self._ws_buf, ws_ptr = _workspace(torch, ws, self.device)
+        self._bufs = _lib.SwBuffers(
+            self.spins.data_ptr(),
+            self.labels.data_ptr() if self.labels is not None else None,
+            self.bonds.data_ptr() if self.bonds is not None else None,
+            ws_ptr,
+            ws,
+        )
+        self._params = p
+        self._h = ctypes.c_void_p()
+        _lib.check(L.sw_init(ctypes.byref(self._h), ctypes.byref(p), ctypes.byref(self._bufs),
+                             _stream(torch)), "sw_init")
+        if t:
+            _lib.check(L.sw_set_t(self._h, int(t)), "sw_set_t")
+
+    @property
+    def threshold(self) -> int:
+        return threshold(self.K)
+
+    @property
+    def t(self) -> int:
+        v = ctypes.c_uint64()
+        _lib.check(_lib.lib().sw_get_t(self._h, ctypes.byref(v)), "sw_get_t")
+        return int(v.value)
+
+    @t.setter
+    def t(self, value: int) -> None:
+        _lib.check(_lib.lib().sw_set_t(self._h, int(value)), "sw_set_t")
+
+    def sweep(self, n: int = 1, stream=None) -> None:
+        """Enqueue n sweeps on the current (or given) stream; does not wait."""
+        torch = _torch()
+        _lib.check(_lib.lib().sw_sweep(self._h, int(n), _stream(torch, stream)), "sw_sweep")
+
+    def observables(self, stream=None) -> dict:
+        """Counters of the current spins and of the last sweep (waits for the stream)."""
+        torch = _torch()
+        o = _lib.SwObs()
+        _lib.check(_lib.lib().sw_observables(self._h, ctypes.byref(o), _stream(torch, stream)), "sw_observables")
+        N = self.W * self.H
+        d = {
+            "t": int(o.t),
+            "threshold": int(o.threshold),
+            "n_sat": int(o.n_sat),
+            "magnet": int(o.magnet),
+            "counts": [int(c) for c in o.counts][: min(self.q, 8)],
+            "n_active_bonds": int(o.n_active_bonds),
+            "n_clusters": int(o.n_clusters),
+        }
+        if self.ising:
+            d["energy_per_site"] = -(2.0 * d["n_sat"] - 2.0 * N) / N
+            d["abs_m"] = abs(d["magnet"]) / N
+        else:
+            d["energy_per_site"] = -d["n_sat"] / N
+        return d
+
+    def state(self):
+        """(spins copy, t): everything needed to resume bit-exactly."""
+        return self.spins.clone(), self.t
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().sw_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ccl_workspace_bytes(W: int, H: int, mode: str | int = "bonds_periodic") -> int:
+    m = _MODES[mode] if isinstance(mode, str) else int(mode)
+    return int(_lib.lib().ccl_workspace_bytes(int(W), int(H), m))
+
+
+def ccl_label(inp, mode: str | int = "bonds_periodic", sizes: bool = False, workspace=None,
+              labels=None, stream=None):
+    """Connected-component labels of an (H, W) uint8 GPU tensor.
+
+    mode: "bonds_periodic" / "bonds_open" (packed bonds, bit0 right, bit1 down)
+    or "sites_open" (binary image, 4-connected, background label -1).
+    Returns labels, or (labels, roots, sizes, n_clusters) when sizes=True;
+    roots ascend and sizes[k] belongs to roots[k].
+    """
+    torch = _torch()
+    L = _lib.lib()
+    m = _MODES[mode] if isinstance(mode, str) else int(mode)
+    if inp.dim() != 2 or inp.dtype != torch.uint8 or inp.device.type != "cuda":
+        raise ValueError("input must be a 2D uint8 GPU tensor")
+    inp = inp.contiguous()
+    H, W = inp.shape
+    ws = L.ccl_workspace_bytes(W, H, m)
+    if ws == 0:
+        _lib.check(_lib.SW_ERR_SIZE, "ccl_workspace_bytes")
+    if workspace is None:
+        wbuf, wptr = _workspace(torch, ws, inp.device)
+    else:
+        wbuf = workspace
+        p = workspace.data_ptr()
+        wptr = p + ((-p) % 256)
+        if workspace.numel() * workspace.element_size() - (wptr - p) < ws:
+            raise ValueError("workspace too small")
+    if labels is None:
+        labels = torch.empty((H, W), dtype=torch.int32, device=inp.device)
+    ncl = torch.zeros(1, dtype=torch.int32, device=inp.device)
+    roots = szs = None
+    if sizes:
+        roots = torch.empty(H * W, dtype=torch.int32, device=inp.device)
+        szs = torch.empty(H * W, dtype=torch.int32, device=inp.device)
+    st = L.ccl_label(inp.data_ptr(), W, H, m, labels.data_ptr(),
+                     roots.data_ptr() if sizes else None, szs.data_ptr() if sizes else None,
+                     ncl.data_ptr(), wptr, ws, _stream(torch, stream))
+    _lib.check(st, "ccl_label")
+    del wbuf
+    if not sizes:
+        return labels
+    n = int(ncl.item())
+    return labels, roots[:n], szs[:n], n

@@ -1,0 +1,101 @@
+"""ctypes declarations of the C ABI in ``include/swccl.h`` (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswccl.so")
+
+# status codes
+SW_OK, SW_ERR_ARG, SW_ERR_SIZE, SW_ERR_WORKSPACE, SW_ERR_DEVICE, SW_ERR_STATE, SW_ERR_UNSUPPORTED = range(7)
+SW_SPIN_ISING_I8, SW_SPIN_POTTS_U8 = 0, 1
+SW_F_KEEP_SPINS = 1
+CCL_BONDS_PERIODIC, CCL_BONDS_OPEN, CCL_SITES_OPEN = 0, 1, 2
+
+
+class SwParams(ctypes.Structure):
+    _fields_ = [
+        ("W", ctypes.c_int32),
+        ("H", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("spin_kind", ctypes.c_int32),
+        ("K", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("stream_id", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class SwBuffers(ctypes.Structure):
+    _fields_ = [
+        ("spins", ctypes.c_void_p),
+        ("labels", ctypes.c_void_p),
+        ("bonds", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class SwObs(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_uint64),
+        ("threshold", ctypes.c_uint64),
+        ("n_sat", ctypes.c_int64),
+        ("magnet", ctypes.c_int64),
+        ("counts", ctypes.c_int64 * 8),
+        ("n_active_bonds", ctypes.c_int64),
+        ("n_clusters", ctypes.c_int64),
+    ]
+
+
+class SwccLError(RuntimeError):
+    """A non-zero sw_status from the library."""
+
+
+_lib = None
+
+# name -> (restype, argtypes); every function declared in include/swccl.h
+SIGNATURES = {
+    "swccl_abi_version": (ctypes.c_int32, []),
+    "sw_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "sw_last_error": (ctypes.c_char_p, []),
+    "sw_threshold": (ctypes.c_uint64, [ctypes.c_double]),
+    "sw_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SwParams)]),
+    "sw_init": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SwParams),
+                                 ctypes.POINTER(SwBuffers), ctypes.c_void_p]),
+    "sw_sweep": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "sw_observables": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(SwObs), ctypes.c_void_p]),
+    "sw_get_t": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "sw_set_t": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64]),
+    "sw_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "ccl_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "ccl_label": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
+            )
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str) -> None:
+    if status != SW_OK:
+        L = lib()
+        msg = L.sw_status_string(status).decode()
+        extra = L.sw_last_error().decode() if status == SW_ERR_DEVICE else ""
+        raise SwccLError(f"{what}: {msg} ({status}) {extra}".strip())

@@ -1,0 +1,49 @@
+// philox.hpp -- device Philox4x32-10 for gfx950.
+//
+// Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten rounds
+// of two 32x32->64-bit multiplies and xors, with the 64-bit key bumped by the
+// Weyl increments between rounds.  Written for the GPU library alone.  The key
+// and the t/tag/stream counter words are wave-uniform, so the compiler keeps
+// them, and the key schedule, in scalar registers; only the index word and the
+// products are per-lane.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swccl {
+
+struct U4 {
+    uint32_t v0, v1, v2, v3;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = static_cast<uint64_t>(0xD2511F53u) * c0;  // one v_mad_u64_u32
+        const uint64_t b = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t n0 = static_cast<uint32_t>(b >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = static_cast<uint32_t>(a >> 32) ^ c3 ^ k1;
+        c1 = static_cast<uint32_t>(b);
+        c3 = static_cast<uint32_t>(a);
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint32_t pick(const U4 &b, uint32_t j)
+{
+    return j == 0 ? b.v0 : j == 1 ? b.v1 : j == 2 ? b.v2 : b.v3;
+}
+
+// floor(w * q / 2^32): one uniform state in 0..q-1 from a 32-bit word.
+__device__ __forceinline__ uint32_t draw_state(uint32_t w, uint32_t q)
+{
+    return static_cast<uint32_t>((static_cast<uint64_t>(w) * q) >> 32);
+}
+
+}  // namespace swccl

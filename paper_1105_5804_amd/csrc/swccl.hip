@@ -1,0 +1,442 @@
+// swccl.hip -- host side of the C ABI declared in include/swccl.h.
+//
+// Validates arguments, carves the caller's workspace, and enqueues the kernels
+// of kernels.hpp on the caller's stream.  Allocates no device memory.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/swccl.h"
+#include "kernels.hpp"
+
+using namespace swccl;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct Layout {
+    Grid g;
+    bool sizes;
+    int64_t nrow;  // H * ntx: entries of the per-(row, tile column) root counts
+    size_t codes, gkey, gparent, gsize, edges, xbits, nb, stats;
+    size_t row_count, row_off, scan_tmp, rl_slot, rl_size;
+    size_t total;
+};
+
+// Scratch for the multi-level exclusive scan of n values: two arrays of block
+// totals per level.
+size_t scan_tmp_bytes(int64_t n)
+{
+    size_t b = 0;
+    while (true) {
+        const int64_t nb = cdiv(n, SCAN_ITEMS);
+        if (nb <= 1) break;
+        b += align_up(static_cast<size_t>(nb) * 4) * 2;
+        n = nb;
+    }
+    return b + ALIGN;
+}
+
+bool valid_shape(int32_t W, int32_t H, int32_t min_side)
+{
+    if (W < min_side || H < min_side) return false;
+    return static_cast<int64_t>(W) * H < (static_cast<int64_t>(1) << 31);
+}
+
+Layout make_layout(int32_t W, int32_t H, bool sizes)
+{
+    Layout L{};
+    L.g.W = W;
+    L.g.H = H;
+    L.g.ntx = static_cast<int>(cdiv(W, TW));
+    L.g.nty = static_cast<int>(cdiv(H, TH));
+    L.g.ntiles = L.g.ntx * L.g.nty;
+    L.sizes = sizes;
+    L.nrow = static_cast<int64_t>(H) * L.g.ntx;
+    const size_t nt = static_cast<size_t>(L.g.ntiles);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align_up(bytes);
+        return at;
+    };
+    L.codes = take(nt * TSITES * sizeof(uint16_t));
+    L.gkey = take(nt * CAP * sizeof(int32_t));
+    L.gparent = take(nt * CAP * sizeof(int32_t));
+    L.edges = take(nt * EDGE * sizeof(uint16_t));
+    L.xbits = take(nt * XW * sizeof(uint64_t));
+    L.nb = take(nt * sizeof(int32_t));
+    L.stats = take(3 * ST_LEN * sizeof(unsigned long long));
+    if (sizes) {
+        L.gsize = take(nt * CAP * sizeof(int32_t));
+        L.row_count = take(static_cast<size_t>(L.nrow + 1) * sizeof(int32_t));
+        L.row_off = take(static_cast<size_t>(L.nrow + 1) * sizeof(int32_t));
+        L.scan_tmp = take(scan_tmp_bytes(L.nrow + 1));
+        L.rl_slot = take(nt * TSITES * sizeof(int32_t));
+        L.rl_size = take(nt * TSITES * sizeof(int32_t));
+    }
+    L.total = off;
+    return L;
+}
+
+template <typename T>
+T *at(void *ws, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+sw_status device_status(hipError_t e, const char *where)
+{
+    if (e == hipSuccess) return SW_OK;
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return SW_ERR_DEVICE;
+}
+
+sw_status launch_status(const char *where) { return device_status(hipGetLastError(), where); }
+
+// Exclusive scan of n int32 values (in -> out) with block totals in tmp.
+void scan_i32(const int32_t *in, int32_t *out, int64_t n, char *tmp, hipStream_t s)
+{
+    const int64_t nb = cdiv(n, SCAN_ITEMS);
+    if (nb <= 1) {
+        hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(NT), 0, s, in, out, n, nullptr);
+        return;
+    }
+    int32_t *tot = reinterpret_cast<int32_t *>(tmp);
+    int32_t *tot_off = reinterpret_cast<int32_t *>(tmp + align_up(static_cast<size_t>(nb) * 4));
+    char *next = tmp + 2 * align_up(static_cast<size_t>(nb) * 4);
+    hipLaunchKernelGGL(k_scan_block, dim3(static_cast<unsigned>(nb)), dim3(NT), 0, s, in, out, n, tot);
+    scan_i32(tot, tot_off, nb, next, s);
+    hipLaunchKernelGGL(k_scan_add, dim3(static_cast<unsigned>(cdiv(n, NT))), dim3(NT), 0, s, out, n, tot_off);
+}
+
+TileArgs tile_args(const Layout &L, void *ws, const uint8_t *in)
+{
+    TileArgs a{};
+    a.g = L.g;
+    a.in = in;
+    a.codes = at<uint16_t>(ws, L.codes);
+    a.gkey = at<int32_t>(ws, L.gkey);
+    a.gparent = at<int32_t>(ws, L.gparent);
+    a.gsize = L.sizes ? at<int32_t>(ws, L.gsize) : nullptr;
+    a.edges = at<uint16_t>(ws, L.edges);
+    a.xbits = at<uint64_t>(ws, L.xbits);
+    a.nb = at<int32_t>(ws, L.nb);
+    return a;
+}
+
+MergeArgs merge_args(const Layout &L, void *ws)
+{
+    MergeArgs m{};
+    m.g = L.g;
+    m.edges = at<uint16_t>(ws, L.edges);
+    m.xbits = at<uint64_t>(ws, L.xbits);
+    m.gkey = at<int32_t>(ws, L.gkey);
+    m.gparent = at<int32_t>(ws, L.gparent);
+    return m;
+}
+
+FlatArgs flat_args(const Layout &L, void *ws)
+{
+    FlatArgs f{};
+    f.g = L.g;
+    f.codes = at<uint16_t>(ws, L.codes);
+    f.gkey = at<int32_t>(ws, L.gkey);
+    f.gparent = at<int32_t>(ws, L.gparent);
+    f.nb = at<int32_t>(ws, L.nb);
+    if (L.sizes) {
+        f.gsize = at<int32_t>(ws, L.gsize);
+        f.row_count = at<int32_t>(ws, L.row_count);
+        f.rl_slot = at<int32_t>(ws, L.rl_slot);
+        f.rl_size = at<int32_t>(ws, L.rl_size);
+    }
+    return f;
+}
+
+uint64_t threshold_of(double K)
+{
+    if (!(K > 0.0)) return 0;
+    const double p = -std::expm1(-K);
+    const double v = std::floor(std::ldexp(p, 32));
+    if (v >= 4294967296.0) return 4294967296ull;
+    if (v <= 0.0) return 0;
+    return static_cast<uint64_t>(v);
+}
+
+}  // namespace
+
+struct sw_lattice {
+    sw_params p;
+    sw_buffers b;
+    Layout L;
+    uint64_t T;
+    uint64_t t;
+    bool swept;       // at least one sweep since init / set_t
+    bool need_zero;   // per-sweep counters must be cleared before the next sweep
+};
+
+extern "C" {
+
+int32_t swccl_abi_version(void) { return SWCCL_ABI_VERSION; }
+
+const char *sw_status_string(sw_status s)
+{
+    switch (s) {
+    case SW_OK: return "ok";
+    case SW_ERR_ARG: return "invalid argument";
+    case SW_ERR_SIZE: return "invalid lattice size";
+    case SW_ERR_WORKSPACE: return "workspace missing or too small";
+    case SW_ERR_DEVICE: return "device error";
+    case SW_ERR_STATE: return "invalid state";
+    case SW_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char *sw_last_error(void) { return g_last_error.c_str(); }
+
+uint64_t sw_threshold(double K) { return threshold_of(K); }
+
+static sw_status check_params(const sw_params *p)
+{
+    if (!p) return SW_ERR_ARG;
+    if (!valid_shape(p->W, p->H, 2)) return SW_ERR_SIZE;
+    if (p->q < 2 || p->q > 255) return SW_ERR_ARG;
+    if (p->spin_kind != SW_SPIN_ISING_I8 && p->spin_kind != SW_SPIN_POTTS_U8) return SW_ERR_ARG;
+    if (p->spin_kind == SW_SPIN_ISING_I8 && p->q != 2) return SW_ERR_ARG;
+    if (std::isnan(p->K)) return SW_ERR_ARG;
+    if (p->flags & ~static_cast<uint32_t>(SW_F_KEEP_SPINS)) return SW_ERR_ARG;
+    return SW_OK;
+}
+
+size_t sw_workspace_bytes(const sw_params *p)
+{
+    if (check_params(p) != SW_OK) return 0;
+    return make_layout(p->W, p->H, false).total;
+}
+
+static sw_status zero_stats(sw_lattice *h, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s,
+                       at<unsigned long long>(h->b.workspace, h->L.stats), 3 * ST_LEN);
+    return launch_status("zero stats");
+}
+
+sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, void *stream)
+{
+    if (!out || !b) return SW_ERR_ARG;
+    const sw_status ps = check_params(p);
+    if (ps != SW_OK) return ps;
+    if (!b->spins) return SW_ERR_ARG;
+    const Layout L = make_layout(p->W, p->H, false);
+    if (!b->workspace || b->workspace_bytes < L.total) return SW_ERR_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(b->workspace) % ALIGN) return SW_ERR_WORKSPACE;
+    sw_lattice *h = new (std::nothrow) sw_lattice();
+    if (!h) return SW_ERR_ARG;
+    h->p = *p;
+    h->b = *b;
+    h->L = L;
+    h->T = threshold_of(p->K);
+    h->t = 0;
+    h->swept = false;
+    h->need_zero = false;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t N = static_cast<int64_t>(p->W) * p->H;
+    if (!(p->flags & SW_F_KEEP_SPINS)) {
+        const int64_t nthreads = cdiv(N, 4);
+        hipLaunchKernelGGL(k_init, dim3(static_cast<unsigned>(cdiv(nthreads, NT))), dim3(NT), 0, s,
+                           static_cast<uint8_t *>(b->spins), N, static_cast<uint32_t>(p->q),
+                           p->spin_kind == SW_SPIN_ISING_I8 ? 1 : 0, static_cast<uint32_t>(p->seed),
+                           static_cast<uint32_t>(p->seed >> 32), p->stream_id);
+        const sw_status st = launch_status("k_init");
+        if (st != SW_OK) {
+            delete h;
+            return st;
+        }
+    }
+    const sw_status st = zero_stats(h, s);
+    if (st != SW_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return SW_OK;
+}
+
+sw_status sw_sweep(sw_lattice *h, int32_t n_sweeps, void *stream)
+{
+    if (!h || n_sweeps < 0) return SW_ERR_ARG;
+    if (h->t + static_cast<uint64_t>(n_sweeps) > 0xFFFFFFFFull) return SW_ERR_STATE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout &L = h->L;
+    void *ws = h->b.workspace;
+    unsigned long long *stats = at<unsigned long long>(ws, L.stats);
+    const uint32_t k0 = static_cast<uint32_t>(h->p.seed), k1 = static_cast<uint32_t>(h->p.seed >> 32);
+    const dim3 grid(static_cast<unsigned>(L.g.ntiles)), block(NT);
+    if (n_sweeps > 0 && h->need_zero) {
+        const sw_status st = zero_stats(h, s);
+        if (st != SW_OK) return st;
+        h->need_zero = false;
+    }
+
+    TileArgs ta = tile_args(L, ws, static_cast<const uint8_t *>(h->b.spins));
+    ta.bonds_out = h->b.bonds;
+    ta.T = h->T;
+    ta.k0 = k0;
+    ta.k1 = k1;
+    ta.sid = h->p.stream_id;
+    const MergeArgs ma = merge_args(L, ws);
+    FlatArgs fa = flat_args(L, ws);
+    fa.spins = static_cast<uint8_t *>(h->b.spins);
+    fa.labels = h->b.labels;
+    fa.q = static_cast<uint32_t>(h->p.q);
+    fa.k0 = k0;
+    fa.k1 = k1;
+    fa.sid = h->p.stream_id;
+    fa.ising = h->p.spin_kind == SW_SPIN_ISING_I8 ? 1 : 0;
+
+    for (int32_t n = 0; n < n_sweeps; ++n) {
+        const uint32_t t = static_cast<uint32_t>(h->t);
+        ta.t = t;
+        ta.stats = stats + (t & 1u) * ST_LEN;
+        fa.t = t;
+        fa.stats = ta.stats;
+        fa.stats_next = stats + ((t + 1u) & 1u) * ST_LEN;
+        hipLaunchKernelGGL((k_tile<M_SW>), grid, block, 0, s, ta);
+        hipLaunchKernelGGL(k_merge, grid, block, 0, s, ma);
+        hipLaunchKernelGGL((k_flatten<M_SW, false>), grid, block, 0, s, fa);
+        const sw_status st = launch_status("sw_sweep");
+        if (st != SW_OK) return st;
+        h->t += 1;
+        h->swept = true;
+    }
+    return SW_OK;
+}
+
+sw_status sw_observables(sw_lattice *h, sw_obs *out, void *stream)
+{
+    if (!h || !out) return SW_ERR_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned long long *stats = at<unsigned long long>(h->b.workspace, h->L.stats);
+    unsigned long long *obs = stats + 2 * ST_LEN;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, obs, ST_LEN);
+    const int64_t N = static_cast<int64_t>(h->p.W) * h->p.H;
+    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(cdiv(N, NT), 4096));
+    hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(NT), 0, s, static_cast<const uint8_t *>(h->b.spins),
+                       h->p.W, h->p.H, static_cast<uint32_t>(h->p.q), h->p.spin_kind == SW_SPIN_ISING_I8 ? 1 : 0,
+                       obs);
+    sw_status st = launch_status("k_observe");
+    if (st != SW_OK) return st;
+    unsigned long long host[3 * ST_LEN];
+    st = device_status(hipMemcpyAsync(host, stats, sizeof(host), hipMemcpyDeviceToHost, s), "copy stats");
+    if (st != SW_OK) return st;
+    st = device_status(hipStreamSynchronize(s), "sync");
+    if (st != SW_OK) return st;
+    std::memset(out, 0, sizeof(*out));
+    out->t = h->t;
+    out->threshold = h->T;
+    const unsigned long long *o = host + 2 * ST_LEN;
+    out->n_sat = static_cast<int64_t>(o[ST_NSAT]);
+    out->magnet = h->p.spin_kind == SW_SPIN_ISING_I8 ? static_cast<int64_t>(o[ST_MAGNET]) : 0;
+    for (int k = 0; k < 8; ++k) out->counts[k] = k < h->p.q ? static_cast<int64_t>(o[ST_COUNTS + k]) : 0;
+    if (h->swept) {
+        const unsigned long long *l = host + ((h->t - 1) & 1u) * ST_LEN;
+        out->n_active_bonds = static_cast<int64_t>(l[ST_ACTIVE]);
+        out->n_clusters = static_cast<int64_t>(l[ST_NCLUST]);
+    } else {
+        out->n_active_bonds = -1;
+        out->n_clusters = -1;
+    }
+    return SW_OK;
+}
+
+sw_status sw_get_t(const sw_lattice *h, uint64_t *t)
+{
+    if (!h || !t) return SW_ERR_ARG;
+    *t = h->t;
+    return SW_OK;
+}
+
+sw_status sw_set_t(sw_lattice *h, uint64_t t)
+{
+    if (!h) return SW_ERR_ARG;
+    if (t > 0xFFFFFFFFull) return SW_ERR_STATE;
+    h->t = t;
+    h->swept = false;
+    h->need_zero = true;
+    return SW_OK;
+}
+
+sw_status sw_destroy(sw_lattice *h)
+{
+    if (!h) return SW_ERR_ARG;
+    delete h;
+    return SW_OK;
+}
+
+size_t ccl_workspace_bytes(int32_t W, int32_t H, int32_t mode)
+{
+    if (mode < CCL_BONDS_PERIODIC || mode > CCL_SITES_OPEN) return 0;
+    if (!valid_shape(W, H, 1)) return 0;
+    return make_layout(W, H, true).total;
+}
+
+sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32_t *labels, int32_t *roots,
+                    int32_t *sizes, int32_t *n_clusters, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!in || !labels) return SW_ERR_ARG;
+    if (mode < CCL_BONDS_PERIODIC || mode > CCL_SITES_OPEN) return SW_ERR_ARG;
+    if ((roots == nullptr) != (sizes == nullptr)) return SW_ERR_ARG;
+    if (!valid_shape(W, H, 1)) return SW_ERR_SIZE;
+    const int64_t N = static_cast<int64_t>(W) * H;
+    const uintptr_t ib = reinterpret_cast<uintptr_t>(in), lb = reinterpret_cast<uintptr_t>(labels);
+    if (ib < lb + static_cast<uintptr_t>(N) * 4 && lb < ib + static_cast<uintptr_t>(N)) return SW_ERR_ARG;
+    const bool want_sizes = roots != nullptr;
+    const Layout L = make_layout(W, H, want_sizes);
+    if (!workspace || workspace_bytes < L.total) return SW_ERR_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return SW_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const dim3 grid(static_cast<unsigned>(L.g.ntiles)), block(NT);
+
+    if (n_clusters) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, n_clusters, 1);
+    const TileArgs ta = tile_args(L, workspace, in);
+    switch (mode) {
+    case CCL_BONDS_PERIODIC: hipLaunchKernelGGL((k_tile<M_BONDS_PERIODIC>), grid, block, 0, s, ta); break;
+    case CCL_BONDS_OPEN: hipLaunchKernelGGL((k_tile<M_BONDS_OPEN>), grid, block, 0, s, ta); break;
+    default: hipLaunchKernelGGL((k_tile<M_SITES>), grid, block, 0, s, ta); break;
+    }
+    hipLaunchKernelGGL(k_merge, grid, block, 0, s, merge_args(L, workspace));
+    FlatArgs fa = flat_args(L, workspace);
+    fa.labels = labels;
+    fa.n_clusters = n_clusters;
+    if (want_sizes) {
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, fa.row_count + L.nrow, 1);
+        // the flatten mode only matters for M_SW; all labeling inputs share one path
+        hipLaunchKernelGGL((k_flatten<M_BONDS_PERIODIC, true>), grid, block, 0, s, fa);
+        int32_t *row_off = at<int32_t>(workspace, L.row_off);
+        scan_i32(fa.row_count, row_off, L.nrow + 1, at<char>(workspace, L.scan_tmp), s);
+        EmitArgs ea{};
+        ea.g = L.g;
+        ea.row_off = row_off;
+        ea.rl_slot = fa.rl_slot;
+        ea.rl_size = fa.rl_size;
+        ea.gsize = fa.gsize;
+        ea.roots = roots;
+        ea.sizes = sizes;
+        hipLaunchKernelGGL(k_emit, grid, block, 0, s, ea);
+    } else {
+        hipLaunchKernelGGL((k_flatten<M_BONDS_PERIODIC, false>), grid, block, 0, s, fa);
+    }
+    return launch_status("ccl_label");
+}
+
+}  // extern "C"

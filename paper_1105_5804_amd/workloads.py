@@ -1,0 +1,65 @@
+"""Seeded synthetic workloads shaped like the paper's benchmarks.
+
+This module only produces parameter sets and random inputs; it contains none of
+the method's arithmetic, and both the GPU path and the CPU oracle consume what
+it produces.  Random inputs come from numpy's PCG64.
+
+Workloads (Sec. II.E and Table tab:results study critical Potts models and
+percolation on periodic square lattices):
+  ising64      q=2 Ising, L=64, beta_c, 1000 sweeps, energy/|m| per sweep
+  ising4096    q=2 Ising, L=4096, beta_c, packed bonds kept, 200 + 1000 sweeps
+  potts16384   q=3 Potts, L=16384, beta_c = ln(1+sqrt3) (Potts normalisation),
+               100 sweeps; plus a labeling pass on bond percolation at p = 1/2
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+SEED_BASE = 0x1105580400000000
+
+K_ISING_C = math.log1p(math.sqrt(2.0))   # K = 2 beta_c J for +-1 spins
+K_POTTS3_C = math.log1p(math.sqrt(3.0))  # K = beta_c J for q = 3
+
+
+@dataclass(frozen=True)
+class SWConfig:
+    name: str
+    W: int
+    H: int
+    q: int
+    ising: bool
+    K: float
+    seed: int
+    sweeps: int
+    warmup: int = 0
+    keep_bonds: bool = False
+
+
+CONFIGS = {
+    "ising64": SWConfig("ising64", 64, 64, 2, True, K_ISING_C, SEED_BASE | 1, 1000),
+    "ising4096": SWConfig("ising4096", 4096, 4096, 2, True, K_ISING_C, SEED_BASE | 2, 1000, 200, True),
+    "potts16384": SWConfig("potts16384", 16384, 16384, 3, False, K_POTTS3_C, SEED_BASE | 3, 100),
+}
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def percolation_bonds(W: int, H: int, seed: int) -> np.ndarray:
+    """Packed bond bytes (bit0 right, bit1 down), every bond open with p = 1/2."""
+    return (rng(seed).integers(0, 256, size=(H, W), dtype=np.uint8) & 3).astype(np.uint8)
+
+
+def random_bonds(W: int, H: int, p: float, seed: int) -> np.ndarray:
+    """Packed bond bytes with every bond open independently with probability p."""
+    r = rng(seed).random((H, W, 2)) < p
+    return (r[..., 0].astype(np.uint8) | (r[..., 1].astype(np.uint8) << 1)).astype(np.uint8)
+
+
+def site_image(W: int, H: int, p: float, seed: int) -> np.ndarray:
+    """Binary image: each pixel occupied (1) with probability p."""
+    return (rng(seed).random((H, W)) < p).astype(np.uint8)

@@ -1,0 +1,124 @@
+"""Host-side tests of the C ABI: the library loads, exports every declared
+entry point, and rejects bad arguments before anything reaches a GPU.
+
+None of these calls enqueues device work (every case returns during argument
+checking), so they run without a GPU.
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1105_5804_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "swccl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set()
+    for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w]*\s*\**\s*([A-Za-z_]\w*)\s*\(", src, flags=re.M):
+        names.add(m.group(1))
+    return names
+
+
+def test_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = _declared_functions()
+    assert {"sw_init", "sw_sweep", "ccl_label", "sw_observables"} <= names
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in _lib.SIGNATURES, n
+    assert L.swccl_abi_version() == 1
+
+
+def test_status_strings():
+    L = _lib.lib()
+    for s in range(7):
+        assert L.sw_status_string(s)
+    assert L.sw_status_string(99) == b"unknown status"
+
+
+def test_threshold_matches_oracle():
+    L = _lib.lib()
+    Ks = [0.0, -3.0, float("inf"), 1e-12, math.log(2.0), math.log1p(math.sqrt(2.0)),
+          math.log1p(math.sqrt(3.0))] + list(np.linspace(1e-3, 40, 997))
+    for K in Ks:
+        assert L.sw_threshold(K) == oracle.threshold(K), K
+
+
+def _params(W=64, H=64, q=2, kind=0, K=0.88, flags=0):
+    return _lib.SwParams(W, H, q, kind, K, 1, 0, flags)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(W=1), dict(H=1), dict(W=0), dict(W=-5), dict(W=65536, H=32768),
+    dict(q=1), dict(q=256), dict(kind=0, q=3), dict(kind=7), dict(K=float("nan")), dict(flags=8),
+])
+def test_bad_params_rejected(kw):
+    L = _lib.lib()
+    p = _params(**kw)
+    assert L.sw_workspace_bytes(ctypes.byref(p)) == 0
+    h = ctypes.c_void_p()
+    buf = _lib.SwBuffers(0x1000, None, None, 0x100000, 1 << 30)
+    st = L.sw_init(ctypes.byref(h), ctypes.byref(p), ctypes.byref(buf), None)
+    assert st in (_lib.SW_ERR_ARG, _lib.SW_ERR_SIZE)
+
+
+def test_good_params_sized():
+    L = _lib.lib()
+    for W, H in [(2, 2), (64, 64), (4096, 4096), (16384, 16384), (3, 1000)]:
+        p = _params(W=W, H=H)
+        assert L.sw_workspace_bytes(ctypes.byref(p)) > 0
+    big = _params(W=16384, H=16384, q=3, kind=1)
+    # codes (2 B/site) dominate; the rest is O(N / tile)
+    assert L.sw_workspace_bytes(ctypes.byref(big)) < 16384 * 16384 * 3
+
+
+def test_init_argument_errors():
+    L = _lib.lib()
+    p = _params()
+    need = L.sw_workspace_bytes(ctypes.byref(p))
+    h = ctypes.c_void_p()
+    assert L.sw_init(None, ctypes.byref(p), None, None) == _lib.SW_ERR_ARG
+    buf = _lib.SwBuffers(None, None, None, 0x100000, need)
+    assert L.sw_init(ctypes.byref(h), ctypes.byref(p), ctypes.byref(buf), None) == _lib.SW_ERR_ARG
+    buf = _lib.SwBuffers(0x1000, None, None, 0x100000, need - 1)
+    assert L.sw_init(ctypes.byref(h), ctypes.byref(p), ctypes.byref(buf), None) == _lib.SW_ERR_WORKSPACE
+    buf = _lib.SwBuffers(0x1000, None, None, 0x100010, need)
+    assert L.sw_init(ctypes.byref(h), ctypes.byref(p), ctypes.byref(buf), None) == _lib.SW_ERR_WORKSPACE
+    buf = _lib.SwBuffers(0x1000, None, None, None, need)
+    assert L.sw_init(ctypes.byref(h), ctypes.byref(p), ctypes.byref(buf), None) == _lib.SW_ERR_WORKSPACE
+    assert L.sw_sweep(None, 1, None) == _lib.SW_ERR_ARG
+    assert L.sw_observables(None, None, None) == _lib.SW_ERR_ARG
+    assert L.sw_get_t(None, None) == _lib.SW_ERR_ARG
+    assert L.sw_set_t(None, 0) == _lib.SW_ERR_ARG
+    assert L.sw_destroy(None) == _lib.SW_ERR_ARG
+
+
+def test_ccl_argument_errors():
+    L = _lib.lib()
+    W = H = 100
+    need = L.ccl_workspace_bytes(W, H, 0)
+    assert need > 0
+    assert L.ccl_workspace_bytes(W, H, 3) == 0
+    assert L.ccl_workspace_bytes(0, H, 0) == 0
+    assert L.ccl_workspace_bytes(65536, 32768, 0) == 0
+    assert L.ccl_workspace_bytes(1, 1, 2) > 0
+    inp, lab, ws = 0x10000000, 0x20000000, 0x40000000
+    call = L.ccl_label
+    assert call(None, W, H, 0, lab, None, None, None, ws, need, None) == _lib.SW_ERR_ARG
+    assert call(inp, W, H, 0, None, None, None, None, ws, need, None) == _lib.SW_ERR_ARG
+    assert call(inp, W, H, 5, lab, None, None, None, ws, need, None) == _lib.SW_ERR_ARG
+    assert call(inp, W, H, 0, lab, 0x50000000, None, None, ws, need, None) == _lib.SW_ERR_ARG
+    assert call(inp, 0, H, 0, lab, None, None, None, ws, need, None) == _lib.SW_ERR_SIZE
+    assert call(inp, W, H, 0, inp + 8, None, None, None, ws, need, None) == _lib.SW_ERR_ARG  # aliasing
+    assert call(inp, W, H, 0, lab, None, None, None, ws, 1024, None) == _lib.SW_ERR_WORKSPACE
+    assert call(inp, W, H, 0, lab, 0x50000000, 0x60000000, None, ws, need - 1, None) == _lib.SW_ERR_WORKSPACE
+    assert call(inp, W, H, 0, lab, None, None, None, None, need, None) == _lib.SW_ERR_WORKSPACE
+    assert call(inp, W, H, 0, lab, None, None, None, ws + 4, need, None) == _lib.SW_ERR_WORKSPACE

@@ -1,0 +1,91 @@
+"""GPU parity of connected-component labeling against the CPU oracle.
+
+Labels, roots (ascending), sizes and the cluster count must match bit-exactly
+for periodic and open bond inputs and for binary images, on shapes that span
+many tiles with ragged tails, the degenerate shapes (1 x n, n x 1), empty and
+full inputs, and the full-size bond-percolation pass at L = 16384.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1105_5804_amd as sw
+from paper_1105_5804_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+MODES = {"bonds_periodic": oracle.PERIODIC, "bonds_open": oracle.OPEN}
+
+
+def _oracle(inp, mode):
+    H, W = inp.shape
+    if mode == "sites_open":
+        return oracle.label_sites(W, H, inp.reshape(-1))
+    return oracle.label_bonds(W, H, inp.reshape(-1), MODES[mode])
+
+
+def _check(inp, mode):
+    H, W = inp.shape
+    print(f"ccl W={W} H={H} mode={mode}", flush=True)
+    g = torch.from_numpy(inp).cuda()
+    lab, roots, sizes, n = sw.ccl_label(g, mode, sizes=True)
+    want, nref = _oracle(inp, mode)
+    got = lab.cpu().numpy().reshape(-1)
+    assert np.array_equal(got, want)
+    assert n == nref
+    r_ref, s_ref, _ = oracle.cluster_sizes(want)
+    assert np.array_equal(roots.cpu().numpy(), r_ref)
+    assert np.array_equal(sizes.cpu().numpy(), s_ref)
+    lab2 = sw.ccl_label(g, mode)
+    assert torch.equal(lab, lab2)
+
+
+SHAPES = [(1, 1), (1, 300), (300, 1), (2, 2), (127, 31), (128, 32), (129, 33), (256, 64),
+          (1000, 37), (37, 1000), (515, 260), (1024, 1024)]
+
+
+@pytest.mark.parametrize("mode", ["bonds_periodic", "bonds_open"])
+@pytest.mark.parametrize("W,H", SHAPES)
+def test_bonds(W, H, mode):
+    for k, p in enumerate((0.0, 0.35, 0.5, 0.65, 1.0)):
+        _check(wl.random_bonds(W, H, p, seed=1000 + 7 * W + H + k), mode)
+
+
+@pytest.mark.parametrize("W,H", SHAPES)
+def test_sites(W, H):
+    for k, p in enumerate((0.0, 0.4, 0.5927, 0.7, 1.0)):
+        _check(wl.site_image(W, H, p, seed=2000 + 7 * W + H + k), "sites_open")
+
+
+def test_structured_inputs():
+    W, H = 300, 200
+    cb = ((np.add.outer(np.arange(H), np.arange(W)) % 2) == 0).astype(np.uint8)
+    _check(cb, "sites_open")
+    stripes = np.zeros((H, W), np.uint8)
+    stripes[::3, :] = 1  # horizontal lines of right bonds, wrap included
+    _check(stripes, "bonds_periodic")
+    _check(stripes, "bonds_open")
+    spiral = np.zeros((H, W), np.uint8)
+    spiral[1:-1, 1] = 2
+    spiral[-2, 1:-2] = 1
+    spiral[2:-1, -3] = 2
+    _check(spiral, "bonds_open")
+
+
+def test_percolation_16384():
+    """Full-size labeling pass: bond percolation at p = 1/2, L = 16384."""
+    L = 16384
+    inp = wl.percolation_bonds(L, L, seed=wl.SEED_BASE | 3)
+    g = torch.from_numpy(inp).cuda()
+    lab, roots, sizes, n = sw.ccl_label(g, "bonds_periodic", sizes=True)
+    want, nref = oracle.label_bonds(L, L, inp.reshape(-1), oracle.PERIODIC)
+    assert n == nref
+    assert np.array_equal(lab.cpu().numpy().reshape(-1), want)
+    del lab
+    r_ref, s_ref, _ = oracle.cluster_sizes(want)
+    assert np.array_equal(roots.cpu().numpy(), r_ref)
+    assert np.array_equal(sizes.cpu().numpy(), s_ref)
+    # exact density of bond-percolation clusters at p = 1/2 is (3 sqrt3 - 5)/2
+    assert abs(n / L**2 - (3 * np.sqrt(3) - 5) / 2) < 1e-3
