@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark of the Swendsen-Wang sweep on one MI355X.
+
+A step is one full sweep (bond activation + tile labeling, cross-tile merge,
+flatten + flip) of the q=3 Potts lattice L=16384 at its critical coupling
+(``potts16384``), with inputs resident in HBM.  Prints one JSON line with:
+
+* value: ns per spin per sweep over the timed steps (lower is better);
+* phases: per-phase device time from HIP events on the launch stream;
+* roofline: the dominant kernel against the HBM and ALU ceilings;
+* ccl: the labeling-only pass on bond percolation at p = 1/2, same L
+  (labeled sites/s);
+* cpu_baseline: the CPU oracle on the machine's host, one sweep of the same lattice.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+CUS, CLOCK_GHZ, LANES_PER_CU_CLK = 256, 2.4, 64
+# Algorithmic bytes per site (a sweep needs the spin read and written once and
+# one int32 label per site written and read back across the tile/merge split).
+SWEEP_BYTES_PER_SITE = 10
+TILE_BYTES_PER_SITE = 5   # spin in (1) + label out (4)
+FLIP_BYTES_PER_SITE = 5   # label in (4) + spin out (1)
+CCL_BYTES_PER_SITE = 13   # input (1) + label write, read and canonical write (3 x 4)
+# Philox4x32-10 per site for the bonds: half a block = 10 32x32->64 multiplies.
+MULS_PER_SITE_TILE = 10
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="potts16384")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ccl", action="store_true")
+    return ap.parse_args()
+
+
+def _mul64_peak_tops(rate: float) -> float:
+    """Peak 32x32->64 multiplies per second if one issues every 1/rate lane-slots."""
+    return CUS * LANES_PER_CU_CLK * CLOCK_GHZ * 1e9 * rate / 1e12
+
+
+def main() -> int:
+    args = _args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(a lattice would shard by row strips; see the design notes)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1105_5804_amd as sw
+    from paper_1105_5804_amd import workloads as wl
+
+    cfg = wl.CONFIGS[args.workload]
+    N = cfg.W * cfg.H
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    lat = sw.SWLattice(cfg.W, cfg.H, q=cfg.q, K=cfg.K, seed=cfg.seed, ising=cfg.ising,
+                       keep_bonds=cfg.keep_bonds)
+    for _ in range(args.warmup):
+        lat.sweep(1)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K full sweeps ----
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall0 = time.perf_counter()
+    e0.record(stream)
+    lat.sweep(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall0
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    ns_spin = ms_step * 1e6 / N
+
+    # ---- per-phase breakdown (same kernels, events between launches) ----
+    nph = 3
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nph + 1)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        for ph in range(nph):
+            lat.sweep_phase(ph)
+            evs[k][ph + 1].record(stream)
+    torch.cuda.synchronize()
+    phase_ms = [float(np.mean([evs[k][ph].elapsed_time(evs[k][ph + 1]) for k in range(args.steps)]))
+                for ph in range(nph)]
+    names = ["tile", "merge", "flatten_flip"]
+    obs = lat.observables()
+
+    dom = int(np.argmax(phase_ms))
+    dom_ms = phase_ms[dom]
+    dom_bytes = [TILE_BYTES_PER_SITE, 0, FLIP_BYTES_PER_SITE][dom] * N
+    achieved_gbs = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_bytes else 0.0
+    roofline = {
+        "kernel": {0: "k_tile", 1: "k_merge", 2: "k_flatten"}[dom],
+        "bound": "hbm",
+        "achieved": round(achieved_gbs, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "bytes_per_site": [TILE_BYTES_PER_SITE, 0, FLIP_BYTES_PER_SITE][dom],
+        "sweep_frac_of_hbm_roofline": round(SWEEP_BYTES_PER_SITE * N / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    if dom == 0:
+        muls = MULS_PER_SITE_TILE * N / (dom_ms * 1e-3) / 1e12
+        roofline["alu_mul64_tops"] = round(muls, 3)
+        roofline["alu_mul64_peak_tops_quarter_rate"] = round(_mul64_peak_tops(0.25), 3)
+
+    out = {
+        "metric": "ns/spin per SW sweep at L=16384; labeled sites/s; batched/served vs plain",
+        "value": round(ns_spin, 6),
+        "unit": "ns/spin/sweep",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "W": cfg.W, "H": cfg.H, "q": cfg.q, "K": cfg.K,
+                   "spins": "int8" if cfg.ising else "uint8", "seed": hex(cfg.seed)},
+        "spins_per_s": round(N / (ms_step * 1e-3), 1),
+        "wall_s_timed": round(wall, 4),
+        "phases_ms": {n: round(v, 4) for n, v in zip(names, phase_ms)},
+        "roofline": roofline,
+        "final_obs": {"t": obs["t"], "energy_per_site": obs["energy_per_site"],
+                      "n_clusters": obs["n_clusters"], "n_active_bonds": obs["n_active_bonds"]},
+    }
+    del lat
+    torch.cuda.empty_cache()
+
+    # ---- labeling-only pass: bond percolation p = 1/2, same L ----
+    if not args.no_ccl:
+        inp = torch.from_numpy(wl.percolation_bonds(cfg.W, cfg.H, seed=wl.SEED_BASE | 3)).cuda()
+        ws = torch.empty(sw.ccl_workspace_bytes(cfg.W, cfg.H) + 256, dtype=torch.uint8, device="cuda")
+        labels = torch.empty((cfg.H, cfg.W), dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            sw.ccl_label(inp, "bonds_periodic", workspace=ws, labels=labels)
+        torch.cuda.synchronize()
+        reps = max(3, args.steps // 2)
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(reps):
+            sw.ccl_label(inp, "bonds_periodic", workspace=ws, labels=labels)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        ms = c0.elapsed_time(c1) / reps
+        gbs = CCL_BYTES_PER_SITE * N / (ms * 1e-3) / 1e9
+        out["ccl"] = {"workload": "bond percolation p=1/2, periodic", "ms": round(ms, 4),
+                      "labeled_sites_per_s": round(N / (ms * 1e-3), 1),
+                      "bytes_per_site": CCL_BYTES_PER_SITE, "achieved_gbs": round(gbs, 1),
+                      "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        del inp, ws, labels
+
+    # ---- CPU oracle on the host: one sweep of the same lattice ----
+    if not args.no_cpu_baseline:
+        import oracle
+
+        st = oracle.init_states(cfg.W, cfg.H, cfg.q, cfg.seed)
+        T = oracle.threshold(cfg.K)
+        c = time.perf_counter()
+        oracle.sw_sweep(cfg.W, cfg.H, cfg.q, T, cfg.seed, 0, 0, st)
+        dt = time.perf_counter() - c
+        out["cpu_baseline"] = {"value": round(dt * 1e9 / N, 3), "unit": "ns/spin/sweep", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"1 sweep of the same {cfg.W}x{cfg.H} q={cfg.q} lattice from its "
+                                         f"initial state, single thread"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -149,6 +149,15 @@ sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, voi
  * flip.  n_sweeps = 0 is a no-op. */
 sw_status sw_sweep(sw_lattice *h, int32_t n_sweeps, void *stream);
 
+/* One phase of a sweep, for per-phase timing (Sec. II.E decomposes T_SW into
+ * activation + local labeling, consolidation across tiles, and flipping):
+ * SW_PHASE_TILE, SW_PHASE_MERGE, SW_PHASE_FLIP in this order make one sweep,
+ * identical to sw_sweep(h, 1); t advances after SW_PHASE_FLIP.  A phase out of
+ * order returns SW_ERR_STATE; sw_sweep and sw_set_t need the next phase to be
+ * SW_PHASE_TILE. */
+enum { SW_PHASE_TILE = 0, SW_PHASE_MERGE = 1, SW_PHASE_FLIP = 2 };
+sw_status sw_sweep_phase(sw_lattice *h, int32_t phase, void *stream);
+
 /* Measure the current spins and the last sweep's counters; waits for the
  * stream. */
 sw_status sw_observables(sw_lattice *h, sw_obs *out, void *stream);

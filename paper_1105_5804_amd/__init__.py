@@ -142,6 +142,11 @@ class SWLattice:
         torch = _torch()
         _lib.check(_lib.lib().sw_sweep(self._h, int(n), _stream(torch, stream)), "sw_sweep")
 
+    def sweep_phase(self, phase: int, stream=None) -> None:
+        """Enqueue one phase (0 tile, 1 merge, 2 flip) of the next sweep."""
+        torch = _torch()
+        _lib.check(_lib.lib().sw_sweep_phase(self._h, int(phase), _stream(torch, stream)), "sw_sweep_phase")
+
     def observables(self, stream=None) -> dict:
         """Counters of the current spins and of the last sweep (waits for the stream)."""
         torch = _torch()

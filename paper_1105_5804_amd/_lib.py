@@ -12,6 +12,7 @@ SW_OK, SW_ERR_ARG, SW_ERR_SIZE, SW_ERR_WORKSPACE, SW_ERR_DEVICE, SW_ERR_STATE, S
 SW_SPIN_ISING_I8, SW_SPIN_POTTS_U8 = 0, 1
 SW_F_KEEP_SPINS = 1
 CCL_BONDS_PERIODIC, CCL_BONDS_OPEN, CCL_SITES_OPEN = 0, 1, 2
+SW_PHASE_TILE, SW_PHASE_MERGE, SW_PHASE_FLIP = 0, 1, 2
 
 
 class SwParams(ctypes.Structure):
@@ -65,6 +66,7 @@ SIGNATURES = {
     "sw_init": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SwParams),
                                  ctypes.POINTER(SwBuffers), ctypes.c_void_p]),
     "sw_sweep": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "sw_sweep_phase": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "sw_observables": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(SwObs), ctypes.c_void_p]),
     "sw_get_t": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "sw_set_t": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64]),

@@ -256,7 +256,7 @@ struct TileArgs {
     uint16_t *edges;          // [ntiles][EDGE]
     uint64_t *xbits;          // [ntiles][XW]
     int32_t *nb;              // [ntiles]
-    unsigned long long *stats;  // this sweep's counters (M_SW) or nullptr
+    int32_t *tile_act;        // [ntiles]: active bonds owned by the tile (M_SW)
     uint64_t T;
     uint32_t k0, k1, t, sid;
 };
@@ -264,14 +264,17 @@ struct TileArgs {
 template <int MODE>
 __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
 {
+    constexpr bool NEED_DOWN = MODE == M_SW || MODE == M_SITES;  // bonds from two rows
+    constexpr bool NEED_HALO = MODE == M_SW || MODE == M_SITES;  // column right of the tile
     __shared__ int P[TSITES];
     __shared__ uint16_t ID[TSITES];
     __shared__ M128 Rm[TH];  // in-tile right bonds per row
     __shared__ M128 Dm[TH];  // in-tile down bonds per row
     __shared__ M128 Om[TH];  // occupied sites per row (all valid sites unless M_SITES)
-    __shared__ unsigned long long xr_s;
+    __shared__ unsigned long long xr_w[NWAVE];  // right crossing bonds, per wave's rows
     __shared__ M128 xd_s;
     __shared__ int nb_s;
+    __shared__ int act_w[NWAVE];
 
     const int W = a.g.W, H = a.g.H;
     const int tile = xcd_remap(blockIdx.x, a.g.ntiles);
@@ -281,41 +284,57 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx0 = 2 * lane, lx1 = lx0 + 1;
     const bool v0 = lx0 < tw, v1 = lx1 < tw;
+    const bool last0 = lx0 == tw - 1, last1 = lx1 == tw - 1;
     const int hx = (gx0 + tw == W) ? 0 : gx0 + tw;  // column right of the tile
     const bool right_is_wrap = (gx0 + tw == W);
     const bool bottom_is_wrap = (gy0 + th == H);
+    const int ly0 = wave * RPW;
+    const int nr = max(0, min(RPW, th - ly0));  // tile rows owned by this wave
 
-    if (threadIdx.x == 0) {
-        xr_s = 0ull;
-        xd_s = M128{0ull, 0ull};
-        nb_s = 0;
+    if (threadIdx.x == 0) nb_s = 0;  // first used after the barrier closing phase A
+
+    // ---- A0: issue every load of the wave's rows (and the row below) up front.
+    // pr[r] holds the bytes of sites lx0 (bits 0-7) and lx1 (bits 8-15).
+    uint32_t pr[RPW + 1];
+    uint8_t hl[RPW];
+#pragma unroll
+    for (int r = 0; r <= RPW; ++r) {
+        pr[r] = 0;
+        if (r < RPW) hl[r] = 0;
+        const bool want = nr > 0 && (r < nr || (NEED_DOWN && r == nr));
+        if (want) {
+            int gy = gy0 + ly0 + r;
+            if (gy == H) gy = 0;  // ly0 + r <= th, so at most one wrap
+            const int64_t rowb = static_cast<int64_t>(gy) * W;
+            const int64_t i0 = rowb + gx0 + lx0;
+            if (v1 && !(i0 & 1)) {
+                pr[r] = *reinterpret_cast<const uint16_t *>(a.in + i0);
+            } else {
+                if (v0) pr[r] = a.in[i0];
+                if (v1) pr[r] |= static_cast<uint32_t>(a.in[i0 + 1]) << 8;
+            }
+            if (NEED_HALO && r < nr && (last0 || last1)) hl[r] = a.in[rowb + hx];
+        }
     }
-    __syncthreads();
 
-    unsigned long long nact = 0, xr_w = 0;
-
-    // ---- A: bonds of each row, row masks, row-run parents ----
+    // ---- A1: bonds of each row, row masks, row-run parents ----
+    unsigned long long nact = 0, xr = 0;
+#pragma unroll
     for (int r = 0; r < RPW; ++r) {
-        const int ly = wave * RPW + r;
-        if (ly >= th) break;
+        if (r >= nr) break;
+        const int ly = ly0 + r;
         const int gy = gy0 + ly;
         const int64_t rowb = static_cast<int64_t>(gy) * W;
-        const int gyd = (gy + 1 == H) ? 0 : gy + 1;
-        const int64_t rowd = static_cast<int64_t>(gyd) * W;
         const int64_t i0 = rowb + gx0 + lx0;
-        const bool last0 = lx0 == tw - 1, last1 = lx1 == tw - 1;
+        const uint32_t cur = pr[r], dn = pr[r + 1];
         bool bR0 = false, bR1 = false, bD0 = false, bD1 = false, o0 = v0, o1 = v1;
 
         if constexpr (MODE == M_SW) {
-            const uint8_t s0 = v0 ? a.in[i0] : 0;
-            const uint8_t s1 = v1 ? a.in[i0 + 1] : 0;
-            const uint8_t d0 = v0 ? a.in[rowd + gx0 + lx0] : 0;
-            const uint8_t d1 = v1 ? a.in[rowd + gx0 + lx1] : 0;
-            const uint8_t nxt = static_cast<uint8_t>(__shfl_down(static_cast<int>(s0), 1));
-            uint8_t halo = 0;
-            if (last0 || last1) halo = a.in[rowb + hx];
-            const uint8_t sr0 = last0 ? halo : s1;
-            const uint8_t sr1 = last1 ? halo : nxt;
+            const uint32_t s0 = cur & 0xFFu, s1 = (cur >> 8) & 0xFFu;
+            const uint32_t d0 = dn & 0xFFu, d1 = (dn >> 8) & 0xFFu;
+            const uint32_t nxt = static_cast<uint32_t>(__shfl_down(static_cast<int>(s0), 1));
+            const uint32_t sr0 = last0 ? hl[r] : s1;
+            const uint32_t sr1 = last1 ? hl[r] : nxt;
             uint32_t r0R, r0D, r1R, r1D;
             const U4 blk = philox4x32_10(static_cast<uint32_t>(i0 >> 1), a.t, TAG_BOND, a.sid, a.k0, a.k1);
             if ((rowb & 1) == 0) {  // the pair (i0, i0+1) shares one block
@@ -341,12 +360,10 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
             }
             nact += static_cast<unsigned>(bR0) + bD0 + bR1 + bD1;
         } else if constexpr (MODE == M_BONDS_PERIODIC || MODE == M_BONDS_OPEN) {
-            const uint8_t b0 = v0 ? a.in[i0] : 0;
-            const uint8_t b1 = v1 ? a.in[i0 + 1] : 0;
-            bR0 = b0 & 1;
-            bD0 = (b0 >> 1) & 1;
-            bR1 = b1 & 1;
-            bD1 = (b1 >> 1) & 1;
+            bR0 = cur & 1u;
+            bD0 = (cur >> 1) & 1u;
+            bR1 = (cur >> 8) & 1u;
+            bD1 = (cur >> 9) & 1u;
             if (MODE == M_BONDS_OPEN) {
                 if (right_is_wrap) {
                     bR0 = bR0 && !last0;
@@ -355,14 +372,13 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
                 if (bottom_is_wrap && ly == th - 1) bD0 = bD1 = false;
             }
         } else {  // M_SITES: 4-connected occupied pixels, open boundary
-            o0 = v0 && a.in[i0] != 0;
-            o1 = v1 && a.in[i0 + 1] != 0;
+            o0 = v0 && (cur & 0xFFu) != 0;
+            o1 = v1 && (cur & 0xFF00u) != 0;
             const bool has_down = gy + 1 < H;
-            const bool d0 = has_down && v0 && a.in[rowd + gx0 + lx0] != 0;
-            const bool d1 = has_down && v1 && a.in[rowd + gx0 + lx1] != 0;
+            const bool d0 = has_down && (dn & 0xFFu) != 0;
+            const bool d1 = has_down && (dn & 0xFF00u) != 0;
             const bool nxt = __shfl_down(static_cast<int>(o0), 1) != 0;
-            bool halo = false;
-            if ((last0 || last1) && !right_is_wrap) halo = a.in[rowb + hx] != 0;
+            const bool halo = !right_is_wrap && hl[r] != 0;
             bR0 = o0 && (last0 ? halo : o1);
             bR1 = o1 && (last1 ? halo : nxt);
             bD0 = o0 && d0;
@@ -372,7 +388,7 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         // Crossing bonds leave the tile: the last column's right bond and the
         // last row's down bonds.  They are merged by k_merge.
         const bool cross = (last0 && bR0) || (last1 && bR1);
-        if (__ballot(cross)) xr_w |= 1ull << ly;
+        if (__ballot(cross)) xr |= 1ull << ly;
         const M128 Rrow = interleave(__ballot(bR0 && !last0), __ballot(bR1 && !last1));
         M128 Drow = M128{0ull, 0ull};
         const M128 Dall = interleave(__ballot(bD0), __ballot(bD1));
@@ -393,12 +409,16 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         ID[base + lx0] = ID_NONE;
         ID[base + lx1] = ID_NONE;
     }
-    if (lane == 0 && xr_w) atomicOr(&xr_s, xr_w);
+    if (lane == 0) xr_w[wave] = xr;
+    if constexpr (MODE == M_SW) {
+        const unsigned long long s = wave_sum(nact);
+        if (lane == 0) act_w[wave] = static_cast<int>(s);
+    }
     __syncthreads();
 
     // ---- B: down bonds join row runs; one union per vertical contact ----
     for (int r = 0; r < RPW; ++r) {
-        const int ly = wave * RPW + r;
+        const int ly = ly0 + r;
         if (ly + 1 >= th) break;
         const M128 D = Dm[ly], Ra = Rm[ly], Rb = Rm[ly + 1];
         // Site s repeats the contact of s-1 when s-1 has a down bond and both
@@ -413,31 +433,27 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     __syncthreads();
 
     // ---- C: full path compression ----
-    for (int r = 0; r < RPW; ++r) {
-        const int ly = wave * RPW + r;
-        if (ly >= th) break;
-        const int base = ly * TW;
+    for (int r = 0; r < nr; ++r) {
+        const int base = (ly0 + r) * TW;
         if (v0) lds_st(&P[base + lx0], lfind(P, base + lx0));
         if (v1) lds_st(&P[base + lx1], lfind(P, base + lx1));
     }
     __syncthreads();
 
     // ---- D: mark roots of clusters that touch the tile border ----
-    for (int r = 0; r < RPW; ++r) {
-        const int ly = wave * RPW + r;
-        if (ly >= th) break;
+    for (int r = 0; r < nr; ++r) {
+        const int ly = ly0 + r;
         const M128 O = Om[ly];
         const int base = ly * TW;
         const bool edge_row = (ly == 0) || (ly == th - 1);
-        if (v0 && bit128(O, lx0) && (edge_row || lx0 == 0 || lx0 == tw - 1)) ID[P[base + lx0]] = ID_MARK;
-        if (v1 && bit128(O, lx1) && (edge_row || lx1 == tw - 1)) ID[P[base + lx1]] = ID_MARK;
+        if (v0 && bit128(O, lx0) && (edge_row || lx0 == 0 || last0)) ID[P[base + lx0]] = ID_MARK;
+        if (v1 && bit128(O, lx1) && (edge_row || last1)) ID[P[base + lx1]] = ID_MARK;
     }
     __syncthreads();
 
     // ---- E: compact boundary ids ----
-    for (int r = 0; r < RPW; ++r) {
-        const int ly = wave * RPW + r;
-        if (ly >= th) break;
+    for (int r = 0; r < nr; ++r) {
+        const int ly = ly0 + r;
         const int base = ly * TW;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -464,9 +480,8 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     // ---- F: codes, edge ids, crossing bits ----
     uint32_t *codes32 = reinterpret_cast<uint32_t *>(a.codes + static_cast<int64_t>(tile) * TSITES);
     uint16_t *edg = a.edges + static_cast<int64_t>(tile) * EDGE;
-    for (int r = 0; r < RPW; ++r) {
-        const int ly = wave * RPW + r;
-        if (ly >= th) break;
+    for (int r = 0; r < nr; ++r) {
+        const int ly = ly0 + r;
         const M128 O = Om[ly];
         const int base = ly * TW;
         uint16_t c[2];
@@ -492,14 +507,13 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     }
     if (threadIdx.x == 0) {
         uint64_t *xb = a.xbits + static_cast<int64_t>(tile) * XW;
-        xb[0] = xr_s;
-        xb[1] = xd_s.lo;
-        xb[2] = xd_s.hi;
+        unsigned long long xrt = 0;
+        for (int w = 0; w < NWAVE; ++w) xrt |= xr_w[w];
+        xb[0] = xrt;
+        xb[1] = th > 0 ? xd_s.lo : 0ull;
+        xb[2] = th > 0 ? xd_s.hi : 0ull;
         a.nb[tile] = nb_s;
-    }
-    if constexpr (MODE == M_SW) {
-        const unsigned long long s = wave_sum(nact);
-        if (lane == 0 && a.stats) add_stat(&a.stats[ST_ACTIVE], s);
+        if (MODE == M_SW && a.tile_act) a.tile_act[tile] = act_w[0] + act_w[1] + act_w[2] + act_w[3];
     }
 }
 
@@ -556,9 +570,7 @@ struct FlatArgs {
     const int32_t *nb;
     uint8_t *spins;           // M_SW: written
     int32_t *labels;          // canonical labels or nullptr
-    unsigned long long *stats;  // M_SW: this sweep's counters
-    unsigned long long *stats_next;  // M_SW: next sweep's counters, zeroed here
-    int32_t *n_clusters;      // labeling: device counter or nullptr
+    int32_t *tile_ncl;        // [ntiles]: clusters whose canonical root lies in the tile
     // cluster sizes (nullptr when not requested)
     int32_t *gsize;           // [ntiles][CAP]
     int32_t *row_count;       // [H][ntx]: roots per (row, tile column)
@@ -568,13 +580,24 @@ struct FlatArgs {
     int ising;
 };
 
+// New state of the cluster whose canonical root is R (Sec. II.D: one uniform
+// draw per cluster, here taken at the minimum site index).
+__device__ __forceinline__ uint8_t flip_state(uint32_t R, const FlatArgs &a)
+{
+    const U4 b = philox4x32_10(R >> 2, a.t, TAG_FLIP, a.sid, a.k0, a.k1);
+    return static_cast<uint8_t>(draw_state(pick(b, R & 3u), a.q));
+}
+
 template <int MODE, bool SIZES>
 __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
 {
-    __shared__ int32_t Rb[CAP];   // canonical root (site index) per boundary id
-    __shared__ int32_t Gid[CAP];  // root id per boundary id
-    __shared__ uint8_t Sb[CAP];   // new state per boundary id
+    __shared__ int32_t Rb[CAP];     // canonical root (site index) per boundary id
+    __shared__ int32_t Gid[CAP];    // root id per boundary id
+    __shared__ uint8_t Sb[CAP];     // new state per boundary id
     __shared__ uint8_t Si[TSITES];  // new state per interior root slot
+    __shared__ uint16_t rlist[TSITES];  // interior root slots
+    __shared__ int nroot_s;
+    __shared__ int ncl_w[NWAVE];
     __shared__ int32_t Ci[SIZES ? TSITES : 1];  // sizes of interior clusters
     __shared__ int32_t Cb[SIZES ? CAP : 1];     // per-tile part of boundary clusters
     __shared__ int32_t rowc[TH + 1];
@@ -586,88 +609,113 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
     const int tw = min(TW, W - gx0), th = min(TH, a.g.H - gy0);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx0 = 2 * lane;
+    const int ly0 = wave * RPW;
+    const int nr = max(0, min(RPW, th - ly0));
     const int nbt = a.nb[tile];
-    unsigned long long ncl = 0;
 
-    if (MODE == M_SW && blockIdx.x == 0 && threadIdx.x < ST_LEN && a.stats_next) a.stats_next[threadIdx.x] = 0ull;
-
+    if (threadIdx.x == 0) nroot_s = 0;
     if constexpr (SIZES) {
         for (int k = threadIdx.x; k < TSITES; k += NT) Ci[k] = 0;
         for (int k = threadIdx.x; k < CAP; k += NT) Cb[k] = 0;
     }
+    uint32_t cc[RPW];
+    const uint32_t *codes32 = reinterpret_cast<const uint32_t *>(a.codes + static_cast<int64_t>(tile) * TSITES);
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) cc[r] = r < nr ? codes32[((ly0 + r) * TW + lx0) >> 1] : 0xFFFFFFFFu;
+    __syncthreads();
+
+    // interior roots (code = CAP + own slot) into a compact list
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        if (r >= nr) break;
+        const int base = (ly0 + r) * TW;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int s = lx0 + j;
+            const uint32_t code = (cc[r] >> (16 * j)) & 0xFFFFu;
+            const bool isr = s < tw && code == static_cast<uint32_t>(CAP + base + s);
+            const uint64_t m = __ballot(isr);
+            if (m) {
+                int first = 0;
+                if (lane == 0) first = atomicAdd(&nroot_s, __popcll(m));
+                first = __shfl(first, 0);
+                if (isr) rlist[first + __popcll(m & ((1ull << lane) - 1ull))] = static_cast<uint16_t>(base + s);
+            }
+        }
+    }
+
+    // boundary ids: resolve to the global root; the root's key is the
+    // cluster's minimum site index
+    int nbr = 0;
     for (int k = threadIdx.x; k < nbt; k += NT) {
         const int id = tile * CAP + k;
         const int root = gfind(a.gparent, id);
         const int R = a.gkey[root];
         Rb[k] = R;
         Gid[k] = root;
-        if (root == id) ++ncl;
-        if constexpr (MODE == M_SW) {
-            const U4 b = philox4x32_10(static_cast<uint32_t>(R) >> 2, a.t, TAG_FLIP, a.sid, a.k0, a.k1);
-            Sb[k] = static_cast<uint8_t>(draw_state(pick(b, R & 3), a.q));
-        }
+        nbr += root == id;
+        if constexpr (MODE == M_SW) Sb[k] = flip_state(static_cast<uint32_t>(R), a);
     }
+    {
+        const unsigned long long s = wave_sum(static_cast<unsigned long long>(nbr));
+        if (lane == 0) ncl_w[wave] = static_cast<int>(s);
+    }
+    __syncthreads();
+    const int nroot = nroot_s;
+    if constexpr (MODE == M_SW) {
+        for (int j = threadIdx.x; j < nroot; j += NT) {
+            const int slot = rlist[j];
+            Si[slot] = flip_state(static_cast<uint32_t>((gy0 + (slot >> 7)) * W + gx0 + (slot & (TW - 1))), a);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && a.tile_ncl) a.tile_ncl[tile] = nroot + ncl_w[0] + ncl_w[1] + ncl_w[2] + ncl_w[3];
 
-    uint32_t cc[RPW];
+#pragma unroll
     for (int r = 0; r < RPW; ++r) {
-        const int ly = wave * RPW + r;
-        cc[r] = 0xFFFFFFFFu;
-        if (ly >= th) continue;
+        if (r >= nr) break;
+        const int ly = ly0 + r;
         const int base = ly * TW;
-        cc[r] = reinterpret_cast<const uint32_t *>(a.codes + static_cast<int64_t>(tile) * TSITES)[(base + lx0) >> 1];
+        const int64_t i0 = static_cast<int64_t>(gy0 + ly) * W + gx0 + lx0;
+        int32_t R[2];
+        uint32_t st[2] = {0u, 0u};
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const int s = lx0 + j;
             const uint32_t code = (cc[r] >> (16 * j)) & 0xFFFFu;
-            if (s < tw && code == static_cast<uint32_t>(CAP + base + s)) {
-                ++ncl;
-                if constexpr (MODE == M_SW) {
-                    const uint32_t R = static_cast<uint32_t>((gy0 + ly) * W + gx0 + s);
-                    const U4 b = philox4x32_10(R >> 2, a.t, TAG_FLIP, a.sid, a.k0, a.k1);
-                    Si[base + s] = static_cast<uint8_t>(draw_state(pick(b, R & 3), a.q));
+            if (code == CODE_BG) {
+                R[j] = -1;
+            } else if (code < static_cast<uint32_t>(CAP)) {
+                R[j] = Rb[code];
+                if constexpr (MODE == M_SW) st[j] = Sb[code];
+                if constexpr (SIZES) {
+                    if (lx0 + j < tw) atomicAdd(&Cb[code], 1);
+                }
+            } else {
+                const int slot = static_cast<int>(code) - CAP;
+                R[j] = (gy0 + (slot >> 7)) * W + gx0 + (slot & (TW - 1));
+                if constexpr (MODE == M_SW) st[j] = Si[slot];
+                if constexpr (SIZES) {
+                    if (lx0 + j < tw) atomicAdd(&Ci[slot], 1);
                 }
             }
         }
-    }
-    __syncthreads();
-
-    for (int r = 0; r < RPW; ++r) {
-        const int ly = wave * RPW + r;
-        if (ly >= th) break;
-        const int base = ly * TW;
-        const int64_t i0 = static_cast<int64_t>(gy0 + ly) * W + gx0 + lx0;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int s = lx0 + j;
-            if (s >= tw) continue;
-            const uint32_t code = (cc[r] >> (16 * j)) & 0xFFFFu;
-            int32_t R;
-            uint32_t st = 0;
-            if (code == CODE_BG) {
-                R = -1;
-            } else if (code < static_cast<uint32_t>(CAP)) {
-                R = Rb[code];
-                if constexpr (MODE == M_SW) st = Sb[code];
-                if constexpr (SIZES) atomicAdd(&Cb[code], 1);
+        const bool v0 = lx0 < tw, v1 = lx0 + 1 < tw;
+        if (a.labels) {
+            if (v1 && !(i0 & 1)) {
+                *reinterpret_cast<int2 *>(a.labels + i0) = make_int2(R[0], R[1]);
             } else {
-                const int slot = static_cast<int>(code) - CAP;
-                R = (gy0 + (slot >> 7)) * W + gx0 + (slot & (TW - 1));
-                if constexpr (MODE == M_SW) st = Si[slot];
-                if constexpr (SIZES) atomicAdd(&Ci[slot], 1);
+                if (v0) a.labels[i0] = R[0];
+                if (v1) a.labels[i0 + 1] = R[1];
             }
-            if (a.labels) a.labels[i0 + j] = R;
-            if constexpr (MODE == M_SW)
-                a.spins[i0 + j] = a.ising ? static_cast<uint8_t>(2 * st - 1) : static_cast<uint8_t>(st);
         }
-    }
-
-    {
-        const unsigned long long s = wave_sum(ncl);
-        if (lane == 0 && s) {
-            if constexpr (MODE == M_SW) {
-                if (a.stats) add_stat(&a.stats[ST_NCLUST], s);
+        if constexpr (MODE == M_SW) {
+            const uint32_t b0 = a.ising ? (2u * st[0] - 1u) & 0xFFu : st[0];
+            const uint32_t b1 = a.ising ? (2u * st[1] - 1u) & 0xFFu : st[1];
+            if (v1 && !(i0 & 1)) {
+                *reinterpret_cast<uint16_t *>(a.spins + i0) = static_cast<uint16_t>(b0 | (b1 << 8));
             } else {
-                if (a.n_clusters) atomicAdd(a.n_clusters, static_cast<int32_t>(s));
+                if (v0) a.spins[i0] = static_cast<uint8_t>(b0);
+                if (v1) a.spins[i0 + 1] = static_cast<uint8_t>(b1);
             }
         }
     }
@@ -679,10 +727,11 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
             if (Cb[k]) __hip_atomic_fetch_add(&a.gsize[Gid[k]], Cb[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // roots of this tile in raster order: per-row counts, then positions
         M128 rm[RPW];
+#pragma unroll
         for (int r = 0; r < RPW; ++r) {
-            const int ly = wave * RPW + r;
             rm[r] = M128{0ull, 0ull};
-            if (ly >= th) continue;
+            if (r >= nr) continue;
+            const int ly = ly0 + r;
             const int base = ly * TW;
             bool isr[2];
 #pragma unroll
@@ -713,9 +762,10 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
             rowc[th] = acc;
         }
         __syncthreads();
+#pragma unroll
         for (int r = 0; r < RPW; ++r) {
-            const int ly = wave * RPW + r;
-            if (ly >= th) break;
+            if (r >= nr) break;
+            const int ly = ly0 + r;
             const int base = ly * TW;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
@@ -731,6 +781,25 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
                                                                    : Ci[base + s];
             }
         }
+    }
+}
+
+// Sum of n per-tile int32 counters into *out64 and/or *out32 (one atomic per
+// workgroup; both outputs are cleared by the caller).
+__global__ __launch_bounds__(NT) void k_reduce_tiles(const int32_t *v, int n, unsigned long long *out64,
+                                                      int32_t *out32)
+{
+    __shared__ unsigned long long red[NWAVE];
+    unsigned long long acc = 0;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) acc += static_cast<unsigned>(v[i]);
+    acc = wave_sum(acc);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = red[0] + red[1] + red[2] + red[3];
+        if (out64) add_stat(out64, t);
+        if (out32 && t) atomicAdd(out32, static_cast<int32_t>(t));
     }
 }
 

@@ -4,6 +4,7 @@
 // of kernels.hpp on the caller's stream.  Allocates no device memory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -27,7 +28,7 @@ struct Layout {
     Grid g;
     bool sizes;
     int64_t nrow;  // H * ntx: entries of the per-(row, tile column) root counts
-    size_t codes, gkey, gparent, gsize, edges, xbits, nb, stats;
+    size_t codes, gkey, gparent, gsize, edges, xbits, nb, tile_act, tile_ncl, stats;
     size_t row_count, row_off, scan_tmp, rl_slot, rl_size;
     size_t total;
 };
@@ -75,7 +76,9 @@ Layout make_layout(int32_t W, int32_t H, bool sizes)
     L.edges = take(nt * EDGE * sizeof(uint16_t));
     L.xbits = take(nt * XW * sizeof(uint64_t));
     L.nb = take(nt * sizeof(int32_t));
-    L.stats = take(3 * ST_LEN * sizeof(unsigned long long));
+    L.tile_act = take(nt * sizeof(int32_t));
+    L.tile_ncl = take(nt * sizeof(int32_t));
+    L.stats = take(ST_LEN * sizeof(unsigned long long));
     if (sizes) {
         L.gsize = take(nt * CAP * sizeof(int32_t));
         L.row_count = take(static_cast<size_t>(L.nrow + 1) * sizeof(int32_t));
@@ -131,6 +134,7 @@ TileArgs tile_args(const Layout &L, void *ws, const uint8_t *in)
     a.edges = at<uint16_t>(ws, L.edges);
     a.xbits = at<uint64_t>(ws, L.xbits);
     a.nb = at<int32_t>(ws, L.nb);
+    a.tile_act = at<int32_t>(ws, L.tile_act);
     return a;
 }
 
@@ -153,6 +157,7 @@ FlatArgs flat_args(const Layout &L, void *ws)
     f.gkey = at<int32_t>(ws, L.gkey);
     f.gparent = at<int32_t>(ws, L.gparent);
     f.nb = at<int32_t>(ws, L.nb);
+    f.tile_ncl = at<int32_t>(ws, L.tile_ncl);
     if (L.sizes) {
         f.gsize = at<int32_t>(ws, L.gsize);
         f.row_count = at<int32_t>(ws, L.row_count);
@@ -181,7 +186,7 @@ struct sw_lattice {
     uint64_t T;
     uint64_t t;
     bool swept;       // at least one sweep since init / set_t
-    bool need_zero;   // per-sweep counters must be cleared before the next sweep
+    int32_t next_phase;  // SW_PHASE_* expected next
 };
 
 extern "C" {
@@ -224,13 +229,6 @@ size_t sw_workspace_bytes(const sw_params *p)
     return make_layout(p->W, p->H, false).total;
 }
 
-static sw_status zero_stats(sw_lattice *h, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s,
-                       at<unsigned long long>(h->b.workspace, h->L.stats), 3 * ST_LEN);
-    return launch_status("zero stats");
-}
-
 sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, void *stream)
 {
     if (!out || !b) return SW_ERR_ARG;
@@ -248,7 +246,7 @@ sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, voi
     h->T = threshold_of(p->K);
     h->t = 0;
     h->swept = false;
-    h->need_zero = false;
+    h->next_phase = SW_PHASE_TILE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t N = static_cast<int64_t>(p->W) * p->H;
     if (!(p->flags & SW_F_KEEP_SPINS)) {
@@ -263,59 +261,74 @@ sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, voi
             return st;
         }
     }
-    const sw_status st = zero_stats(h, s);
-    if (st != SW_OK) {
-        delete h;
-        return st;
-    }
     *out = h;
     return SW_OK;
 }
 
-sw_status sw_sweep(sw_lattice *h, int32_t n_sweeps, void *stream)
+// Enqueue one phase of sweep h->t.
+static sw_status launch_phase(sw_lattice *h, int32_t phase, hipStream_t s)
 {
-    if (!h || n_sweeps < 0) return SW_ERR_ARG;
-    if (h->t + static_cast<uint64_t>(n_sweeps) > 0xFFFFFFFFull) return SW_ERR_STATE;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     const Layout &L = h->L;
     void *ws = h->b.workspace;
-    unsigned long long *stats = at<unsigned long long>(ws, L.stats);
     const uint32_t k0 = static_cast<uint32_t>(h->p.seed), k1 = static_cast<uint32_t>(h->p.seed >> 32);
+    const uint32_t t = static_cast<uint32_t>(h->t);
     const dim3 grid(static_cast<unsigned>(L.g.ntiles)), block(NT);
-    if (n_sweeps > 0 && h->need_zero) {
-        const sw_status st = zero_stats(h, s);
-        if (st != SW_OK) return st;
-        h->need_zero = false;
+    if (phase == SW_PHASE_TILE) {
+        TileArgs ta = tile_args(L, ws, static_cast<const uint8_t *>(h->b.spins));
+        ta.bonds_out = h->b.bonds;
+        ta.T = h->T;
+        ta.k0 = k0;
+        ta.k1 = k1;
+        ta.t = t;
+        ta.sid = h->p.stream_id;
+        hipLaunchKernelGGL((k_tile<M_SW>), grid, block, 0, s, ta);
+        return launch_status("k_tile");
     }
-
-    TileArgs ta = tile_args(L, ws, static_cast<const uint8_t *>(h->b.spins));
-    ta.bonds_out = h->b.bonds;
-    ta.T = h->T;
-    ta.k0 = k0;
-    ta.k1 = k1;
-    ta.sid = h->p.stream_id;
-    const MergeArgs ma = merge_args(L, ws);
+    if (phase == SW_PHASE_MERGE) {
+        hipLaunchKernelGGL(k_merge, grid, block, 0, s, merge_args(L, ws));
+        return launch_status("k_merge");
+    }
     FlatArgs fa = flat_args(L, ws);
     fa.spins = static_cast<uint8_t *>(h->b.spins);
     fa.labels = h->b.labels;
     fa.q = static_cast<uint32_t>(h->p.q);
     fa.k0 = k0;
     fa.k1 = k1;
+    fa.t = t;
     fa.sid = h->p.stream_id;
     fa.ising = h->p.spin_kind == SW_SPIN_ISING_I8 ? 1 : 0;
+    hipLaunchKernelGGL((k_flatten<M_SW, false>), grid, block, 0, s, fa);
+    return launch_status("k_flatten");
+}
 
+sw_status sw_sweep_phase(sw_lattice *h, int32_t phase, void *stream)
+{
+    if (!h || phase < SW_PHASE_TILE || phase > SW_PHASE_FLIP) return SW_ERR_ARG;
+    if (phase != h->next_phase) return SW_ERR_STATE;
+    if (phase == SW_PHASE_TILE && h->t >= 0xFFFFFFFFull) return SW_ERR_STATE;
+    const sw_status st = launch_phase(h, phase, static_cast<hipStream_t>(stream));
+    if (st != SW_OK) return st;
+    if (phase == SW_PHASE_FLIP) {
+        h->next_phase = SW_PHASE_TILE;
+        h->t += 1;
+        h->swept = true;
+    } else {
+        h->next_phase = phase + 1;
+    }
+    return SW_OK;
+}
+
+sw_status sw_sweep(sw_lattice *h, int32_t n_sweeps, void *stream)
+{
+    if (!h || n_sweeps < 0) return SW_ERR_ARG;
+    if (h->next_phase != SW_PHASE_TILE) return SW_ERR_STATE;
+    if (h->t + static_cast<uint64_t>(n_sweeps) > 0xFFFFFFFFull) return SW_ERR_STATE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
     for (int32_t n = 0; n < n_sweeps; ++n) {
-        const uint32_t t = static_cast<uint32_t>(h->t);
-        ta.t = t;
-        ta.stats = stats + (t & 1u) * ST_LEN;
-        fa.t = t;
-        fa.stats = ta.stats;
-        fa.stats_next = stats + ((t + 1u) & 1u) * ST_LEN;
-        hipLaunchKernelGGL((k_tile<M_SW>), grid, block, 0, s, ta);
-        hipLaunchKernelGGL(k_merge, grid, block, 0, s, ma);
-        hipLaunchKernelGGL((k_flatten<M_SW, false>), grid, block, 0, s, fa);
-        const sw_status st = launch_status("sw_sweep");
-        if (st != SW_OK) return st;
+        for (int32_t ph = SW_PHASE_TILE; ph <= SW_PHASE_FLIP; ++ph) {
+            const sw_status st = launch_phase(h, ph, s);
+            if (st != SW_OK) return st;
+        }
         h->t += 1;
         h->swept = true;
     }
@@ -326,36 +339,37 @@ sw_status sw_observables(sw_lattice *h, sw_obs *out, void *stream)
 {
     if (!h || !out) return SW_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    unsigned long long *stats = at<unsigned long long>(h->b.workspace, h->L.stats);
-    unsigned long long *obs = stats + 2 * ST_LEN;
+    const Layout &L = h->L;
+    void *ws = h->b.workspace;
+    unsigned long long *obs = at<unsigned long long>(ws, L.stats);
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, obs, ST_LEN);
     const int64_t N = static_cast<int64_t>(h->p.W) * h->p.H;
-    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(cdiv(N, NT), 4096));
+    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(cdiv(N, NT), 1024));
     hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(NT), 0, s, static_cast<const uint8_t *>(h->b.spins),
                        h->p.W, h->p.H, static_cast<uint32_t>(h->p.q), h->p.spin_kind == SW_SPIN_ISING_I8 ? 1 : 0,
                        obs);
-    sw_status st = launch_status("k_observe");
+    if (h->swept) {
+        const unsigned rb = static_cast<unsigned>(std::min<int64_t>(cdiv(L.g.ntiles, NT), 64));
+        hipLaunchKernelGGL(k_reduce_tiles, dim3(rb), dim3(NT), 0, s, at<int32_t>(ws, L.tile_act), L.g.ntiles,
+                           obs + ST_ACTIVE, static_cast<int32_t *>(nullptr));
+        hipLaunchKernelGGL(k_reduce_tiles, dim3(rb), dim3(NT), 0, s, at<int32_t>(ws, L.tile_ncl), L.g.ntiles,
+                           obs + ST_NCLUST, static_cast<int32_t *>(nullptr));
+    }
+    sw_status st = launch_status("sw_observables");
     if (st != SW_OK) return st;
-    unsigned long long host[3 * ST_LEN];
-    st = device_status(hipMemcpyAsync(host, stats, sizeof(host), hipMemcpyDeviceToHost, s), "copy stats");
+    unsigned long long host[ST_LEN];
+    st = device_status(hipMemcpyAsync(host, obs, sizeof(host), hipMemcpyDeviceToHost, s), "copy observables");
     if (st != SW_OK) return st;
     st = device_status(hipStreamSynchronize(s), "sync");
     if (st != SW_OK) return st;
     std::memset(out, 0, sizeof(*out));
     out->t = h->t;
     out->threshold = h->T;
-    const unsigned long long *o = host + 2 * ST_LEN;
-    out->n_sat = static_cast<int64_t>(o[ST_NSAT]);
-    out->magnet = h->p.spin_kind == SW_SPIN_ISING_I8 ? static_cast<int64_t>(o[ST_MAGNET]) : 0;
-    for (int k = 0; k < 8; ++k) out->counts[k] = k < h->p.q ? static_cast<int64_t>(o[ST_COUNTS + k]) : 0;
-    if (h->swept) {
-        const unsigned long long *l = host + ((h->t - 1) & 1u) * ST_LEN;
-        out->n_active_bonds = static_cast<int64_t>(l[ST_ACTIVE]);
-        out->n_clusters = static_cast<int64_t>(l[ST_NCLUST]);
-    } else {
-        out->n_active_bonds = -1;
-        out->n_clusters = -1;
-    }
+    out->n_sat = static_cast<int64_t>(host[ST_NSAT]);
+    out->magnet = h->p.spin_kind == SW_SPIN_ISING_I8 ? static_cast<int64_t>(host[ST_MAGNET]) : 0;
+    for (int k = 0; k < 8; ++k) out->counts[k] = k < h->p.q ? static_cast<int64_t>(host[ST_COUNTS + k]) : 0;
+    out->n_active_bonds = h->swept ? static_cast<int64_t>(host[ST_ACTIVE]) : -1;
+    out->n_clusters = h->swept ? static_cast<int64_t>(host[ST_NCLUST]) : -1;
     return SW_OK;
 }
 
@@ -369,10 +383,9 @@ sw_status sw_get_t(const sw_lattice *h, uint64_t *t)
 sw_status sw_set_t(sw_lattice *h, uint64_t t)
 {
     if (!h) return SW_ERR_ARG;
-    if (t > 0xFFFFFFFFull) return SW_ERR_STATE;
+    if (t > 0xFFFFFFFFull || h->next_phase != SW_PHASE_TILE) return SW_ERR_STATE;
     h->t = t;
     h->swept = false;
-    h->need_zero = true;
     return SW_OK;
 }
 
@@ -407,7 +420,6 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
     hipStream_t s = static_cast<hipStream_t>(stream);
     const dim3 grid(static_cast<unsigned>(L.g.ntiles)), block(NT);
 
-    if (n_clusters) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, n_clusters, 1);
     const TileArgs ta = tile_args(L, workspace, in);
     switch (mode) {
     case CCL_BONDS_PERIODIC: hipLaunchKernelGGL((k_tile<M_BONDS_PERIODIC>), grid, block, 0, s, ta); break;
@@ -417,7 +429,6 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
     hipLaunchKernelGGL(k_merge, grid, block, 0, s, merge_args(L, workspace));
     FlatArgs fa = flat_args(L, workspace);
     fa.labels = labels;
-    fa.n_clusters = n_clusters;
     if (want_sizes) {
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, fa.row_count + L.nrow, 1);
         // the flatten mode only matters for M_SW; all labeling inputs share one path
@@ -435,6 +446,12 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
         hipLaunchKernelGGL(k_emit, grid, block, 0, s, ea);
     } else {
         hipLaunchKernelGGL((k_flatten<M_BONDS_PERIODIC, false>), grid, block, 0, s, fa);
+    }
+    if (n_clusters) {
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, n_clusters, 1);
+        const unsigned rb = static_cast<unsigned>(std::min<int64_t>(cdiv(L.g.ntiles, NT), 64));
+        hipLaunchKernelGGL(k_reduce_tiles, dim3(rb), dim3(NT), 0, s, fa.tile_ncl, L.g.ntiles,
+                           static_cast<unsigned long long *>(nullptr), n_clusters);
     }
     return launch_status("ccl_label");
 }
