@@ -5,18 +5,20 @@
 // with T_identify = T_local + T_global):
 //
 //   k_tile    one workgroup per 128x32 tile.  Bond activation (Sec. II.A) fused
-//             with tile labeling (Sec. II.B): the bonds of a tile row are
-//             ballots of the 64-lane wave; right bonds become row runs by bit
-//             scans of the ballot mask; down bonds join runs by a lock-free
-//             union-find with path halving in LDS.  Clusters that touch the
-//             tile border get a compact boundary id; every site's result is a
+//             with tile labeling (Sec. II.B): each lane of a 64-lane wave owns
+//             two sites of a tile row; the row's bonds become 128-bit masks by
+//             wave ballots, right bonds turn into row runs by a bit scan, and
+//             down bonds join runs by a lock-free union-find over run starts in
+//             LDS, fed from compacted per-wave lists of vertical contacts.
+//             Clusters that touch the tile border are claimed by their border
+//             sites and get a compact boundary id; every site's result is a
 //             16-bit code (boundary id, or CAP + the slot of its interior root).
 //   k_merge   tile consolidation (Sec. II.C) in one pass: every active bond
 //             that crosses a tile edge, the periodic wrap included, unites two
 //             boundary ids in a global union-find over the compact id space
-//             (CAS linking of the larger-key root under the smaller one, path
-//             halving).  Only ~2(TW+TH) ids per tile exist, so this structure
-//             stays small and cache resident.
+//             (CAS linking of the larger-key root under the smaller one).  Only
+//             ~2(TW+TH) ids per tile exist, so this structure stays small and
+//             cache resident.
 //   k_flatten resolves every boundary id to its root, whose key is the
 //             cluster's minimum site index (the canonical label), draws one new
 //             state per cluster from that root (Sec. II.D) and writes spins
@@ -41,8 +43,8 @@ constexpr int XW = 4;                 // crossing-bond words per tile: right row
 constexpr int NT = 256;               // threads per workgroup
 constexpr int NWAVE = NT / 64;
 constexpr int RPW = TH / NWAVE;       // tile rows per wave
+constexpr int WLIST = RPW * TW;       // per-wave work list capacity (one entry per site at most)
 constexpr uint16_t ID_NONE = 0xFFFF;
-constexpr uint16_t ID_MARK = 0xFFFE;
 constexpr uint16_t CODE_BG = 0xFFFF;
 static_assert(TH <= 64, "right-edge crossing bits are one 64-bit word");
 static_assert(CAP + TSITES < 0xFFFE, "codes are 16-bit");
@@ -51,7 +53,7 @@ static_assert(TW == 128, "a tile row is one wave of 64 lanes x 2 sites");
 enum : uint32_t { TAG_INIT = 0, TAG_BOND = 1, TAG_FLIP = 2 };
 enum Mode : int { M_SW = 0, M_BONDS_PERIODIC = 1, M_BONDS_OPEN = 2, M_SITES = 3 };
 
-// Per-sweep counters (unsigned 64-bit, two's complement for signed values).
+// Observable counters (unsigned 64-bit, two's complement for signed values).
 enum { ST_ACTIVE = 0, ST_NCLUST = 1, ST_NSAT = 2, ST_MAGNET = 3, ST_COUNTS = 4, ST_LEN = 16 };
 
 struct Grid {
@@ -69,46 +71,57 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
     return xcd * q + min(xcd, r) + local;
 }
 
-// Spread the low 32 bits of x to the even bit positions of a 64-bit word.
-__device__ __forceinline__ uint64_t spread32(uint64_t x)
+__device__ __forceinline__ uint64_t low_bits(int n)  // bits [0, n), n in [0, 64]
 {
-    x &= 0xFFFFFFFFull;
-    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
-    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
-    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
-    x = (x | (x << 2)) & 0x3333333333333333ull;
-    x = (x | (x << 1)) & 0x5555555555555555ull;
-    return x;
+    return n >= 64 ? ~0ull : ((1ull << n) - 1ull);
 }
 
+// A tile row of 128 sites in natural order: bit s of lo (s < 64) or of hi
+// (s >= 64) belongs to site s.
 struct M128 {
     uint64_t lo, hi;
 };
-
-// Lane L owns sites 2L and 2L+1 of a 128-site row: the ballots of the even
-// and odd sites interleave into the row's site mask.
-__device__ __forceinline__ M128 interleave(uint64_t ev, uint64_t od)
-{
-    return M128{spread32(ev) | (spread32(od) << 1), spread32(ev >> 32) | (spread32(od >> 32) << 1)};
-}
 
 __device__ __forceinline__ bool bit128(const M128 &m, int s)
 {
     return s < 64 ? ((m.lo >> s) & 1ull) : ((m.hi >> (s - 64)) & 1ull);
 }
 
-// Start of the row run containing site s: one past the highest j < s whose
-// bond j -> j+1 is absent (bit j of R clear), or 0.
+// Number of set bits below site s.
+__device__ __forceinline__ int rank128(const M128 &m, int s)
+{
+    return s < 64 ? __popcll(m.lo & low_bits(s)) : __popcll(m.lo) + __popcll(m.hi & low_bits(s - 64));
+}
+
+// Lane L holds, in bits 2k and 2k+1 of `f`, flag k of its sites 2L and 2L+1.
+// Returns flag k of every site of the row as a natural-order 128-bit mask:
+// lane t fetches the flags of sites t and 64+t from their owners (a lane
+// permute through the LDS crossbar), then two ballots.
+template <int NF>
+__device__ __forceinline__ void row_masks(uint32_t f, int lane, M128 (&out)[NF])
+{
+    const uint32_t g0 = static_cast<uint32_t>(__shfl(static_cast<int>(f), lane >> 1));
+    const uint32_t g1 = static_cast<uint32_t>(__shfl(static_cast<int>(f), 32 + (lane >> 1)));
+    const int sh = lane & 1;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+        out[k].lo = __ballot((g0 >> (2 * k + sh)) & 1u);
+        out[k].hi = __ballot((g1 >> (2 * k + sh)) & 1u);
+    }
+}
+
+// Start of the row run containing site s: one past the last site j < s whose
+// bond j -> j+1 (bit j of R) is absent, or 0.
 __device__ __forceinline__ int run_start(const M128 &R, int s)
 {
     if (s < 64) {
-        const uint64_t z = ~R.lo & ((1ull << s) - 1ull);
+        const uint64_t z = ~R.lo & low_bits(s);
         return z ? 64 - __builtin_clzll(z) : 0;
     }
-    const uint64_t z = ~R.hi & ((1ull << (s - 64)) - 1ull);
+    const uint64_t z = ~R.hi & low_bits(s - 64);
     if (z) return 128 - __builtin_clzll(z);
     if (!((R.lo >> 63) & 1ull)) return 64;
-    const uint64_t z0 = ~R.lo & 0x7FFFFFFFFFFFFFFFull;
+    const uint64_t z0 = ~R.lo & low_bits(63);
     return z0 ? 64 - __builtin_clzll(z0) : 0;
 }
 
@@ -136,6 +149,16 @@ __device__ __forceinline__ int lfind(int *P, int x)
     }
 }
 
+// Root of x without writes (for use once all unions are done).
+__device__ __forceinline__ int lroot(int *P, int x)
+{
+    for (;;) {
+        const int p = lds_ld(&P[x]);
+        if (p == x) return x;
+        x = p;
+    }
+}
+
 // Union: the larger root index is linked below the smaller, so every root is
 // the minimum (local, hence global) index of its tree.
 __device__ __forceinline__ void lunite(int *P, int a, int b)
@@ -156,36 +179,28 @@ __device__ __forceinline__ void lunite(int *P, int a, int b)
     }
 }
 
-// ---- global union-find over boundary ids (agent scope: 8 XCDs, 8 L2s) ----
-__device__ __forceinline__ int g_ld(int *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void g_st(int *p, int v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ int gfind(int *G, int x)
+// ---- global union-find over boundary ids ----
+//
+// Parents only move towards smaller keys, so a stale (older) parent read from
+// a non-coherent L2 is still an ancestor: finds may use plain loads.  Every
+// change of a root goes through a device-scope CAS; a failed CAS returns the
+// node's current parent, from which the union continues.  Keys are the global
+// site indices of the tile-local roots, so every final root's key is the
+// minimum site index of its cluster.
+__device__ __forceinline__ int gfind(const int *G, int x)
 {
     for (;;) {
-        const int p = g_ld(&G[x]);
+        const int p = __hip_atomic_load(const_cast<int *>(&G[x]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (p == x) return x;
-        const int g = g_ld(&G[p]);
-        if (g == p) return p;
-        g_st(&G[x], g);
-        x = g;
+        x = p;
     }
 }
 
-// Keys are the global site indices of the tile-local roots; linking the root
-// with the larger key below the smaller one makes every final root's key the
-// minimum site index of its cluster.
 __device__ __forceinline__ void gunite(int *G, const int *key, int a, int b)
 {
+    a = gfind(G, a);
+    b = gfind(G, b);
     for (;;) {
-        a = gfind(G, a);
-        b = gfind(G, b);
         if (a == b) return;
         if (key[a] < key[b]) {
             const int t = a;
@@ -196,6 +211,8 @@ __device__ __forceinline__ void gunite(int *G, const int *key, int a, int b)
         if (__hip_atomic_compare_exchange_strong(&G[a], &expect, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT))
             return;
+        a = gfind(G, expect);  // a was linked meanwhile: continue from its parent
+        b = gfind(G, b);
     }
 }
 
@@ -209,6 +226,13 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
 __device__ __forceinline__ void add_stat(unsigned long long *p, unsigned long long v)
 {
     if (v) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Keep the compiler from moving LDS accesses of one wave across this point
+// (the DS unit executes one wave's LDS operations in order).
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
 // ----------------------------------------------------------------- init ----
@@ -257,22 +281,27 @@ struct TileArgs {
     uint64_t *xbits;          // [ntiles][XW]
     int32_t *nb;              // [ntiles]
     int32_t *tile_act;        // [ntiles]: active bonds owned by the tile (M_SW)
-    uint64_t T;
+    uint32_t tm1;             // M_SW: a bond is active iff its word r <= tm1 ...
+    uint32_t tany;            // ... and tany (threshold T > 0); tm1 = T - 1
     uint32_t k0, k1, t, sid;
 };
+
+// Claimed roots: P[root] = CLAIMING while the id is allocated, then
+// -(k + 2) for boundary id k.
+constexpr int CLAIMING = -1;
 
 template <int MODE>
 __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
 {
     constexpr bool NEED_DOWN = MODE == M_SW || MODE == M_SITES;  // bonds from two rows
     constexpr bool NEED_HALO = MODE == M_SW || MODE == M_SITES;  // column right of the tile
-    __shared__ int P[TSITES];
-    __shared__ uint16_t ID[TSITES];
-    __shared__ M128 Rm[TH];  // in-tile right bonds per row
-    __shared__ M128 Dm[TH];  // in-tile down bonds per row
-    __shared__ M128 Om[TH];  // occupied sites per row (all valid sites unless M_SITES)
-    __shared__ unsigned long long xr_w[NWAVE];  // right crossing bonds, per wave's rows
-    __shared__ M128 xd_s;
+    __shared__ int P[TSITES];             // union-find parent per site slot
+    __shared__ M128 Rm[TH];               // in-tile right bonds per row
+    __shared__ M128 Dm[TH];               // in-tile down bonds per row
+    __shared__ M128 Om[TH];               // occupied sites per row
+    __shared__ uint16_t wl[NWAVE][WLIST]; // per-wave work list (contacts, then run starts)
+    __shared__ unsigned long long xr_w[NWAVE];  // right crossing bonds of each wave's rows
+    __shared__ M128 xd_s;                 // bottom crossing bonds
     __shared__ int nb_s;
     __shared__ int act_w[NWAVE];
 
@@ -290,6 +319,7 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     const bool bottom_is_wrap = (gy0 + th == H);
     const int ly0 = wave * RPW;
     const int nr = max(0, min(RPW, th - ly0));  // tile rows owned by this wave
+    uint16_t *mylist = wl[wave];
 
     if (threadIdx.x == 0) nb_s = 0;  // first used after the barrier closing phase A
 
@@ -317,7 +347,7 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         }
     }
 
-    // ---- A1: bonds of each row, row masks, row-run parents ----
+    // ---- A1: bonds of each row, row masks, run-start parents ----
     unsigned long long nact = 0, xr = 0;
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
@@ -350,13 +380,19 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
                 r1R = b2.v0;
                 r1D = b2.v1;
             }
-            bR0 = v0 && s0 == sr0 && static_cast<uint64_t>(r0R) < a.T;
-            bD0 = v0 && s0 == d0 && static_cast<uint64_t>(r0D) < a.T;
-            bR1 = v1 && s1 == sr1 && static_cast<uint64_t>(r1R) < a.T;
-            bD1 = v1 && s1 == d1 && static_cast<uint64_t>(r1D) < a.T;
+            const bool on = a.tany != 0;
+            bR0 = on && v0 && s0 == sr0 && r0R <= a.tm1;
+            bD0 = on && v0 && s0 == d0 && r0D <= a.tm1;
+            bR1 = on && v1 && s1 == sr1 && r1R <= a.tm1;
+            bD1 = on && v1 && s1 == d1 && r1D <= a.tm1;
             if (a.bonds_out) {
-                if (v0) a.bonds_out[i0] = static_cast<uint8_t>(bR0 | (bD0 << 1));
-                if (v1) a.bonds_out[i0 + 1] = static_cast<uint8_t>(bR1 | (bD1 << 1));
+                const uint32_t b0 = bR0 | (bD0 << 1), b1 = bR1 | (bD1 << 1);
+                if (v1 && !(i0 & 1)) {
+                    *reinterpret_cast<uint16_t *>(a.bonds_out + i0) = static_cast<uint16_t>(b0 | (b1 << 8));
+                } else {
+                    if (v0) a.bonds_out[i0] = static_cast<uint8_t>(b0);
+                    if (v1) a.bonds_out[i0 + 1] = static_cast<uint8_t>(b1);
+                }
             }
             nact += static_cast<unsigned>(bR0) + bD0 + bR1 + bD1;
         } else if constexpr (MODE == M_BONDS_PERIODIC || MODE == M_BONDS_OPEN) {
@@ -389,25 +425,21 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         // last row's down bonds.  They are merged by k_merge.
         const bool cross = (last0 && bR0) || (last1 && bR1);
         if (__ballot(cross)) xr |= 1ull << ly;
-        const M128 Rrow = interleave(__ballot(bR0 && !last0), __ballot(bR1 && !last1));
-        M128 Drow = M128{0ull, 0ull};
-        const M128 Dall = interleave(__ballot(bD0), __ballot(bD1));
-        if (ly == th - 1) {
-            if (lane == 0) xd_s = Dall;
-        } else {
-            Drow = Dall;
-        }
-        const M128 Orow = interleave(__ballot(o0), __ballot(o1));
+        const bool inR0 = bR0 && !last0, inR1 = bR1 && !last1;
+        // flags: 0 in-tile right bond, 1 down bond, 2 occupied
+        const uint32_t f = inR0 | (inR1 << 1) | (bD0 << 2) | (bD1 << 3) | (o0 << 4) | (o1 << 5);
+        M128 m[3];
+        row_masks<3>(f, lane, m);
         if (lane == 0) {
-            Rm[ly] = Rrow;
-            Dm[ly] = Drow;
-            Om[ly] = Orow;
+            Rm[ly] = m[0];
+            Dm[ly] = (ly == th - 1) ? M128{0ull, 0ull} : m[1];
+            Om[ly] = m[2];
+            if (ly == th - 1) xd_s = m[1];
         }
         const int base = ly * TW;
-        P[base + lx0] = base + (v0 ? run_start(Rrow, lx0) : lx0);
-        P[base + lx1] = base + (v1 ? run_start(Rrow, lx1) : lx1);
-        ID[base + lx0] = ID_NONE;
-        ID[base + lx1] = ID_NONE;
+        const int rs0 = v0 ? run_start(m[0], lx0) : lx0;
+        const int rs1 = (v1 && inR0) ? rs0 : lx1;
+        *reinterpret_cast<int2 *>(&P[base + lx0]) = make_int2(base + rs0, base + rs1);
     }
     if (lane == 0) xr_w[wave] = xr;
     if constexpr (MODE == M_SW) {
@@ -416,59 +448,84 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     }
     __syncthreads();
 
-    // ---- B: down bonds join row runs; one union per vertical contact ----
+    // ---- B: down bonds join runs.  One union per vertical contact segment:
+    // site s repeats the contact of s-1 when s-1 has a down bond and both rows
+    // continue from s-1 to s.  Contacts of the wave's rows are compacted into
+    // its list, then united in dense rounds of 64.
+    int ncon = 0;
     for (int r = 0; r < RPW; ++r) {
         const int ly = ly0 + r;
         if (ly + 1 >= th) break;
         const M128 D = Dm[ly], Ra = Rm[ly], Rb = Rm[ly + 1];
-        // Site s repeats the contact of s-1 when s-1 has a down bond and both
-        // rows continue from s-1 to s.
         const M128 X = M128{D.lo & Ra.lo & Rb.lo, D.hi & Ra.hi & Rb.hi};
-        const M128 Xs = M128{X.lo << 1, (X.hi << 1) | (X.lo >> 63)};
-        const M128 F = M128{D.lo & ~Xs.lo, D.hi & ~Xs.hi};
+        const M128 F = M128{D.lo & ~(X.lo << 1), D.hi & ~((X.hi << 1) | (X.lo >> 63))};
         const int base = ly * TW;
-        if (bit128(F, lx0)) lunite(P, base + lx0, base + TW + lx0);
-        if (bit128(F, lx1)) lunite(P, base + lx1, base + TW + lx1);
+        if (bit128(F, lx0)) mylist[ncon + rank128(F, lx0)] = static_cast<uint16_t>(base + lx0);
+        if (bit128(F, lx1)) mylist[ncon + rank128(F, lx1)] = static_cast<uint16_t>(base + lx1);
+        ncon += __popcll(F.lo) + __popcll(F.hi);
+    }
+    wave_lds_fence();
+    for (int i = lane; i < ncon; i += 64) {
+        const int c = mylist[i];
+        lunite(P, c, c + TW);
     }
     __syncthreads();
 
-    // ---- C: full path compression ----
-    for (int r = 0; r < nr; ++r) {
-        const int base = (ly0 + r) * TW;
-        if (v0) lds_st(&P[base + lx0], lfind(P, base + lx0));
-        if (v1) lds_st(&P[base + lx1], lfind(P, base + lx1));
-    }
-    __syncthreads();
-
-    // ---- D: mark roots of clusters that touch the tile border ----
+    // ---- C: compress run starts (the only sites unions ever touch) ----
+    int nrs = 0;
     for (int r = 0; r < nr; ++r) {
         const int ly = ly0 + r;
-        const M128 O = Om[ly];
+        const M128 R = Rm[ly], O = Om[ly];
+        // run start: occupied, valid, and no bond from the left neighbour
+        M128 S = M128{O.lo & ~(R.lo << 1), O.hi & ~((R.hi << 1) | (R.lo >> 63))};
         const int base = ly * TW;
-        const bool edge_row = (ly == 0) || (ly == th - 1);
-        if (v0 && bit128(O, lx0) && (edge_row || lx0 == 0 || last0)) ID[P[base + lx0]] = ID_MARK;
-        if (v1 && bit128(O, lx1) && (edge_row || last1)) ID[P[base + lx1]] = ID_MARK;
+        if (bit128(S, lx0)) mylist[nrs + rank128(S, lx0)] = static_cast<uint16_t>(base + lx0);
+        if (bit128(S, lx1)) mylist[nrs + rank128(S, lx1)] = static_cast<uint16_t>(base + lx1);
+        nrs += __popcll(S.lo) + __popcll(S.hi);
     }
-    __syncthreads();
-
-    // ---- E: compact boundary ids ----
-    for (int r = 0; r < nr; ++r) {
-        const int ly = ly0 + r;
-        const int base = ly * TW;
+    wave_lds_fence();
+    // Roots are found read-only first and written after a barrier: a halving
+    // store racing with another wave's compression could otherwise put an
+    // older ancestor back over a root that was already written.
+    int rr[WLIST / 64];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int s = lx0 + j;
-            const bool isb = (s < tw) && P[base + s] == base + s && ID[base + s] == ID_MARK;
-            const uint64_t m = __ballot(isb);
-            if (m) {
-                int first = 0;
-                if (lane == 0) first = atomicAdd(&nb_s, __popcll(m));
-                first = __shfl(first, 0);
-                if (isb) {
-                    const int k = first + __popcll(m & ((1ull << lane) - 1ull));
-                    ID[base + s] = static_cast<uint16_t>(k);
+    for (int j = 0; j < WLIST / 64; ++j) {
+        const int i = lane + 64 * j;
+        rr[j] = i < nrs ? lroot(P, mylist[i]) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < WLIST / 64; ++j) {
+        const int i = lane + 64 * j;
+        if (i < nrs) P[mylist[i]] = rr[j];
+    }
+    __syncthreads();
+    // From here on the root of site s is P[P[s]].
+
+    // ---- D: border sites claim their cluster's root and allocate its id ----
+    {
+        const bool top = ly0 == 0, bot = (ly0 <= th - 1) && (th - 1 < ly0 + RPW);
+        for (int r = 0; r < nr; ++r) {
+            const int ly = ly0 + r;
+            const M128 O = Om[ly];
+            const int base = ly * TW;
+            const bool edge_row = (top && r == 0) || (bot && ly == th - 1);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int s = lx0 + j;
+                const bool border = s < tw && (edge_row || s == 0 || s == tw - 1) && bit128(O, s);
+                if (!border) continue;
+                const int p = lds_ld(&P[base + s]);
+                if (p < 0) continue;  // s is a root already claimed
+                const int root = lds_ld(&P[p]);
+                if (root < 0) continue;  // p is the root, already claimed
+                int expect = root;
+                if (__hip_atomic_compare_exchange_strong(&P[root], &expect, CLAIMING, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                    const int k = atomicAdd(&nb_s, 1);
+                    lds_st(&P[root], -(k + 2));
                     const int id = tile * CAP + k;
-                    a.gkey[id] = (gy0 + ly) * W + gx0 + s;
+                    a.gkey[id] = (gy0 + (root >> 7)) * W + gx0 + (root & (TW - 1));
                     a.gparent[id] = id;
                     if (a.gsize) a.gsize[id] = 0;
                 }
@@ -484,16 +541,30 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         const int ly = ly0 + r;
         const M128 O = Om[ly];
         const int base = ly * TW;
+        const int2 pp = *reinterpret_cast<const int2 *>(&P[base + lx0]);
         uint16_t c[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int s = lx0 + j;
             uint16_t code = CODE_BG, eid = ID_NONE;
             if (s < tw && bit128(O, s)) {
-                const int root = P[base + s];
-                const uint16_t k = ID[root];
-                eid = k;
-                code = (k != ID_NONE) ? k : static_cast<uint16_t>(CAP + root);
+                const int p = j ? pp.y : pp.x;
+                int v = p;  // walk s -> run start -> root until a claim or a root
+                if (v >= 0) {
+                    const int q = P[v];
+                    if (q < 0 || q == v) {
+                        v = q < 0 ? q : v;
+                    } else {
+                        const int u = P[q];
+                        v = u < 0 ? u : q;
+                    }
+                }
+                if (v < 0) {
+                    code = static_cast<uint16_t>(-v - 2);
+                    eid = code;
+                } else {
+                    code = static_cast<uint16_t>(CAP + v);
+                }
             }
             c[j] = code;
             if (s < tw) {
@@ -507,11 +578,9 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     }
     if (threadIdx.x == 0) {
         uint64_t *xb = a.xbits + static_cast<int64_t>(tile) * XW;
-        unsigned long long xrt = 0;
-        for (int w = 0; w < NWAVE; ++w) xrt |= xr_w[w];
-        xb[0] = xrt;
-        xb[1] = th > 0 ? xd_s.lo : 0ull;
-        xb[2] = th > 0 ? xd_s.hi : 0ull;
+        xb[0] = xr_w[0] | xr_w[1] | xr_w[2] | xr_w[3];
+        xb[1] = xd_s.lo;
+        xb[2] = xd_s.hi;
         a.nb[tile] = nb_s;
         if (MODE == M_SW && a.tile_act) a.tile_act[tile] = act_w[0] + act_w[1] + act_w[2] + act_w[3];
     }
@@ -527,36 +596,40 @@ struct MergeArgs {
     int32_t *gparent;
 };
 
-// One thread per bond crossing the right edge (TH rows) or the bottom edge
-// (TW columns) of a tile; consecutive crossing bonds that join the same pair
-// of boundary ids are skipped.
+constexpr int MERGE_TILES = NWAVE;  // tiles per workgroup: one wave each
+
+// A wave per tile: its lanes walk the bonds crossing the tile's right edge
+// (TH rows) and bottom edge (TW columns).  Consecutive crossing bonds that
+// join the same pair of boundary ids are skipped.
 __global__ __launch_bounds__(NT) void k_merge(MergeArgs a)
 {
-    const int tile = xcd_remap(blockIdx.x, a.g.ntiles);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tile = blockIdx.x * MERGE_TILES + wave;
+    if (tile >= a.g.ntiles) return;
     const int tx = tile % a.g.ntx, ty = tile / a.g.ntx;
     const int tw = min(TW, a.g.W - tx * TW), th = min(TH, a.g.H - ty * TH);
-    const int j = threadIdx.x;
     const uint16_t *e = a.edges + static_cast<int64_t>(tile) * EDGE;
-    if (j < TH) {
-        if (j >= th) return;
-        const uint64_t xr = a.xbits[static_cast<int64_t>(tile) * XW];
-        if (!((xr >> j) & 1ull)) return;
-        const int nt = ty * a.g.ntx + (tx + 1 == a.g.ntx ? 0 : tx + 1);
-        const uint16_t *en = a.edges + static_cast<int64_t>(nt) * EDGE;
-        const uint16_t ka = e[2 * TW + TH + j], kb = en[2 * TW + j];
-        if (j > 0 && ((xr >> (j - 1)) & 1ull) && e[2 * TW + TH + j - 1] == ka && en[2 * TW + j - 1] == kb) return;
-        gunite(a.gparent, a.gkey, tile * CAP + ka, nt * CAP + kb);
-    } else if (j < TH + TW) {
-        const int x = j - TH;
-        if (x >= tw) return;
-        const uint64_t *xb = a.xbits + static_cast<int64_t>(tile) * XW + 1;
-        if (!((xb[x >> 6] >> (x & 63)) & 1ull)) return;
-        const int nt = (ty + 1 == a.g.nty ? 0 : ty + 1) * a.g.ntx + tx;
-        const uint16_t *en = a.edges + static_cast<int64_t>(nt) * EDGE;
-        const uint16_t ka = e[TW + x], kb = en[x];
-        if (x > 0 && ((xb[(x - 1) >> 6] >> ((x - 1) & 63)) & 1ull) && e[TW + x - 1] == ka && en[x - 1] == kb)
-            return;
-        gunite(a.gparent, a.gkey, tile * CAP + ka, nt * CAP + kb);
+    const uint64_t *xb = a.xbits + static_cast<int64_t>(tile) * XW;
+    const int ntR = ty * a.g.ntx + (tx + 1 == a.g.ntx ? 0 : tx + 1);
+    const int ntD = (ty + 1 == a.g.nty ? 0 : ty + 1) * a.g.ntx + tx;
+    const uint16_t *eR = a.edges + static_cast<int64_t>(ntR) * EDGE;
+    const uint16_t *eD = a.edges + static_cast<int64_t>(ntD) * EDGE;
+    const uint64_t xr = xb[0];
+    const M128 xd = M128{xb[1], xb[2]};
+    for (int j = lane; j < TH + TW; j += 64) {
+        if (j < TH) {
+            if (j >= th || !((xr >> j) & 1ull)) continue;
+            const uint16_t ka = e[2 * TW + TH + j], kb = eR[2 * TW + j];
+            if (j > 0 && ((xr >> (j - 1)) & 1ull) && e[2 * TW + TH + j - 1] == ka && eR[2 * TW + j - 1] == kb)
+                continue;
+            gunite(a.gparent, a.gkey, tile * CAP + ka, ntR * CAP + kb);
+        } else {
+            const int x = j - TH;
+            if (x >= tw || !bit128(xd, x)) continue;
+            const uint16_t ka = e[TW + x], kb = eD[x];
+            if (x > 0 && bit128(xd, x - 1) && e[TW + x - 1] == ka && eD[x - 1] == kb) continue;
+            gunite(a.gparent, a.gkey, tile * CAP + ka, ntD * CAP + kb);
+        }
     }
 }
 
@@ -744,7 +817,9 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
                           (code < static_cast<uint32_t>(CAP) && Gid[code] == tile * CAP + static_cast<int>(code) &&
                            Rb[code] == self));
             }
-            rm[r] = interleave(__ballot(isr[0]), __ballot(isr[1]));
+            M128 mk[1];
+            row_masks<1>(static_cast<uint32_t>(isr[0]) | (static_cast<uint32_t>(isr[1]) << 1), lane, mk);
+            rm[r] = mk[0];
             if (lane == 0) {
                 const int n = __popcll(rm[r].lo) + __popcll(rm[r].hi);
                 rowc[ly] = n;
@@ -771,9 +846,7 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
             for (int j = 0; j < 2; ++j) {
                 const int s = lx0 + j;
                 if (!bit128(rm[r], s)) continue;
-                const int below = (s < 64) ? __popcll(rm[r].lo & ((1ull << s) - 1ull))
-                                           : __popcll(rm[r].lo) + __popcll(rm[r].hi & ((1ull << (s - 64)) - 1ull));
-                const int pos = rowc[ly] + below;
+                const int pos = rowc[ly] + rank128(rm[r], s);
                 const uint32_t code = (cc[r] >> (16 * j)) & 0xFFFFu;
                 const int64_t o = static_cast<int64_t>(tile) * TSITES + pos;
                 a.rl_slot[o] = base + s;

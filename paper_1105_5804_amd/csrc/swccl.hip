@@ -149,6 +149,8 @@ MergeArgs merge_args(const Layout &L, void *ws)
     return m;
 }
 
+dim3 merge_grid(const Layout &L) { return dim3(static_cast<unsigned>(cdiv(L.g.ntiles, MERGE_TILES))); }
+
 FlatArgs flat_args(const Layout &L, void *ws)
 {
     FlatArgs f{};
@@ -276,7 +278,8 @@ static sw_status launch_phase(sw_lattice *h, int32_t phase, hipStream_t s)
     if (phase == SW_PHASE_TILE) {
         TileArgs ta = tile_args(L, ws, static_cast<const uint8_t *>(h->b.spins));
         ta.bonds_out = h->b.bonds;
-        ta.T = h->T;
+        ta.tany = h->T > 0 ? 1u : 0u;
+        ta.tm1 = h->T > 0 ? static_cast<uint32_t>(h->T - 1) : 0u;
         ta.k0 = k0;
         ta.k1 = k1;
         ta.t = t;
@@ -285,7 +288,7 @@ static sw_status launch_phase(sw_lattice *h, int32_t phase, hipStream_t s)
         return launch_status("k_tile");
     }
     if (phase == SW_PHASE_MERGE) {
-        hipLaunchKernelGGL(k_merge, grid, block, 0, s, merge_args(L, ws));
+        hipLaunchKernelGGL(k_merge, merge_grid(L), block, 0, s, merge_args(L, ws));
         return launch_status("k_merge");
     }
     FlatArgs fa = flat_args(L, ws);
@@ -426,7 +429,7 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
     case CCL_BONDS_OPEN: hipLaunchKernelGGL((k_tile<M_BONDS_OPEN>), grid, block, 0, s, ta); break;
     default: hipLaunchKernelGGL((k_tile<M_SITES>), grid, block, 0, s, ta); break;
     }
-    hipLaunchKernelGGL(k_merge, grid, block, 0, s, merge_args(L, workspace));
+    hipLaunchKernelGGL(k_merge, merge_grid(L), block, 0, s, merge_args(L, workspace));
     FlatArgs fa = flat_args(L, workspace);
     fa.labels = labels;
     if (want_sizes) {

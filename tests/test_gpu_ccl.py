@@ -89,3 +89,17 @@ def test_percolation_16384():
     assert np.array_equal(sizes.cpu().numpy(), s_ref)
     # exact density of bond-percolation clusters at p = 1/2 is (3 sqrt3 - 5)/2
     assert abs(n / L**2 - (3 * np.sqrt(3) - 5) / 2) < 1e-3
+
+
+def test_percolation_16384_repeated():
+    """Eight labelings of the same full-size input all equal the oracle (race guard)."""
+    L = 16384
+    inp = wl.percolation_bonds(L, L, seed=wl.SEED_BASE | 3)
+    want, _ = oracle.label_bonds(L, L, inp.reshape(-1), oracle.PERIODIC)
+    want = torch.from_numpy(want.reshape(L, L)).cuda()
+    g = torch.from_numpy(inp).cuda()
+    ws = torch.empty(sw.ccl_workspace_bytes(L, L) + 256, dtype=torch.uint8, device="cuda")
+    for rep in range(8):
+        lab = sw.ccl_label(g, "bonds_periodic", workspace=ws)
+        bad = int((lab != want).sum().item())
+        assert bad == 0, (rep, bad)

@@ -174,3 +174,52 @@ def test_invalid_spins_buffer():
         sw.SWLattice(64, 64, q=2, spins=torch.zeros((64, 64), dtype=torch.uint8, device="cuda"))
     with pytest.raises(sw.SwccLError):
         sw.SWLattice(1, 64, q=2)
+
+
+@pytest.mark.parametrize("W,H,q,ising,n", [(2048, 2048, 2, True, 40), (1000, 1030, 3, False, 40)])
+def test_long_trajectory(W, H, q, ising, n):
+    """Many sweeps at a critical coupling: the whole trajectory stays bit-exact."""
+    K = wl.K_ISING_C if q == 2 else wl.K_POTTS3_C
+    seed = wl.SEED_BASE | 0xA1
+    print(f"long W={W} H={H} q={q} n={n}", flush=True)
+    T = oracle.threshold(K)
+    lat = sw.SWLattice(W, H, q=q, K=K, seed=seed, ising=ising)
+    st = oracle.init_states(W, H, q, seed)
+    st, rec = oracle.sw_run(W, H, q, T, seed, 0, 0, n, st)
+    for t in range(n):
+        lat.sweep(1)
+        if t % 5 == 4 or t == n - 1:
+            o = lat.observables()
+            assert o["n_clusters"] == rec[t, oracle.REC_NCLUST], t
+            assert o["n_sat"] == rec[t, oracle.REC_NSAT], t
+    torch.cuda.synchronize()
+    assert np.array_equal(_state(lat), st)
+
+
+def test_potts16384_deterministic():
+    """Two runs of 30 full-size sweeps from one seed give identical spins."""
+    c = wl.CONFIGS["potts16384"]
+    out = []
+    for _ in range(2):
+        lat = sw.SWLattice(c.W, c.H, q=3, K=c.K, seed=c.seed, ising=False)
+        lat.sweep(30)
+        torch.cuda.synchronize()
+        out.append((lat.spins.clone(), lat.observables()))
+        del lat
+    assert out[0][1] == out[1][1]
+    assert torch.equal(out[0][0], out[1][0])
+
+
+def test_potts16384_three_sweeps():
+    """Full-size q=3 Potts: spins and counters after each of the first 3 sweeps."""
+    c = wl.CONFIGS["potts16384"]
+    T = oracle.threshold(c.K)
+    lat = sw.SWLattice(c.W, c.H, q=3, K=c.K, seed=c.seed, ising=False)
+    st = oracle.init_states(c.W, c.H, 3, c.seed)
+    for t in range(3):
+        lat.sweep(1)
+        st, _b, _l, rec = oracle.sw_sweep(c.W, c.H, 3, T, c.seed, 0, t, st)
+        o = lat.observables()
+        assert o["n_clusters"] == rec[oracle.REC_NCLUST], t
+        assert o["n_active_bonds"] == rec[oracle.REC_ACTIVE], t
+        assert np.array_equal(_state(lat), st), t
