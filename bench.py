@@ -46,6 +46,8 @@ def _args():
     ap.add_argument("--workload", default="potts16384")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ccl", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this size first (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -72,6 +74,13 @@ def main() -> int:
     N = cfg.W * cfg.H
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     lat = sw.SWLattice(cfg.W, cfg.H, q=cfg.q, K=cfg.K, seed=cfg.seed, ising=cfg.ising,
                        keep_bonds=cfg.keep_bonds)
     for _ in range(args.warmup):

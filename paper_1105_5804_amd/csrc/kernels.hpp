@@ -149,16 +149,6 @@ __device__ __forceinline__ int lfind(int *P, int x)
     }
 }
 
-// Root of x without writes (for use once all unions are done).
-__device__ __forceinline__ int lroot(int *P, int x)
-{
-    for (;;) {
-        const int p = lds_ld(&P[x]);
-        if (p == x) return x;
-        x = p;
-    }
-}
-
 // Union: the larger root index is linked below the smaller, so every root is
 // the minimum (local, hence global) index of its tree.
 __device__ __forceinline__ void lunite(int *P, int a, int b)
@@ -286,8 +276,79 @@ struct TileArgs {
     uint32_t k0, k1, t, sid;
 };
 
+// A tile row as two wave ballots: lane L owns sites 2L and 2L+1, bit L of `e`
+// belongs to site 2L and bit L of `o` to site 2L+1.  The masks stay in scalar
+// registers; the natural-order shift s -> s+1 is (o << 1, e).
+struct EO {
+    uint64_t e, o;
+};
+
+__device__ __forceinline__ EO eo_and(EO a, EO b) { return EO{a.e & b.e, a.o & b.o}; }
+__device__ __forceinline__ EO eo_andnot(EO a, EO b) { return EO{a.e & ~b.e, a.o & ~b.o}; }
+__device__ __forceinline__ EO eo_shift1(EO m) { return EO{m.o << 1, m.e}; }
+
+// Set bits of m at lanes below the calling lane.
+__device__ __forceinline__ int lanes_below(uint64_t m)
+{
+    return static_cast<int>(__builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u)));
+}
+
+// Append the sites set in m (row starting at slot `base`) to a wave list in
+// ascending order; n is the wave-uniform list length.
+__device__ __forceinline__ void eo_append(uint16_t *list, int &n, EO m, int lane, int base)
+{
+    const int r0 = n + lanes_below(m.e) + lanes_below(m.o);
+    const int b0 = static_cast<int>((m.e >> lane) & 1ull);
+    if (b0) list[r0] = static_cast<uint16_t>(base + 2 * lane);
+    if ((m.o >> lane) & 1ull) list[r0 + b0] = static_cast<uint16_t>(base + 2 * lane + 1);
+    n += __popcll(m.e) + __popcll(m.o);
+}
+
+// Start of the row run containing the even site 2L: one past the last missing
+// right bond before it (e bits are bonds 2m -> 2m+1, o bits 2m+1 -> 2m+2).
+__device__ __forceinline__ int run_start_even(EO R, int L)
+{
+    const uint64_t below = low_bits(L);
+    const uint64_t ze = ~R.e & below, zo = ~R.o & below;
+    const int ce = ze ? 2 * (63 - __builtin_clzll(ze)) + 1 : 0;
+    const int co = zo ? 2 * (63 - __builtin_clzll(zo)) + 2 : 0;
+    return max(ce, co);
+}
+
+// Wave-uniform copy of a mask read from LDS.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+__device__ __forceinline__ EO uniform_eo(EO m) { return EO{uniform64(m.e), uniform64(m.o)}; }
+
+// Root of x once all unions are done; a claimed root (negative entry) is a root.
+__device__ __forceinline__ int lroot(int *P, int x)
+{
+    for (;;) {
+        const int p = lds_ld(&P[x]);
+        if (p == x || p < 0) return x;
+        x = p;
+    }
+}
+
+// Border position t of a tile in the layout of the edge arrays: top row,
+// bottom row, left column, right column.  Returns the slot, or -1 if the
+// position lies outside a ragged tile.
+__device__ __forceinline__ int border_slot(int t, int tw, int th)
+{
+    if (t < TW) return t < tw ? t : -1;
+    if (t < 2 * TW) return (t - TW) < tw ? (th - 1) * TW + (t - TW) : -1;
+    if (t < 2 * TW + TH) return (t - 2 * TW) < th ? (t - 2 * TW) * TW : -1;
+    return (t - 2 * TW - TH) < th ? (t - 2 * TW - TH) * TW + tw - 1 : -1;
+}
+
 // Claimed roots: P[root] = CLAIMING while the id is allocated, then
-// -(k + 2) for boundary id k.
+// -(k + 2) for boundary id k.  After the codes are resolved every occupied run
+// start x holds P[x] = -(code + 1).
 constexpr int CLAIMING = -1;
 
 template <int MODE>
@@ -296,12 +357,11 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     constexpr bool NEED_DOWN = MODE == M_SW || MODE == M_SITES;  // bonds from two rows
     constexpr bool NEED_HALO = MODE == M_SW || MODE == M_SITES;  // column right of the tile
     __shared__ int P[TSITES];             // union-find parent per site slot
-    __shared__ M128 Rm[TH];               // in-tile right bonds per row
-    __shared__ M128 Dm[TH];               // in-tile down bonds per row
-    __shared__ M128 Om[TH];               // occupied sites per row
+    __shared__ EO Rm[TH];                 // in-tile right bonds per row
+    __shared__ EO Om[TH];                 // occupied sites per row
     __shared__ uint16_t wl[NWAVE][WLIST]; // per-wave work list (contacts, then run starts)
     __shared__ unsigned long long xr_w[NWAVE];  // right crossing bonds of each wave's rows
-    __shared__ M128 xd_s;                 // bottom crossing bonds
+    __shared__ EO xd_s;                   // bottom crossing bonds
     __shared__ int nb_s;
     __shared__ int act_w[NWAVE];
 
@@ -320,6 +380,7 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     const int ly0 = wave * RPW;
     const int nr = max(0, min(RPW, th - ly0));  // tile rows owned by this wave
     uint16_t *mylist = wl[wave];
+    const EO valid = EO{__ballot(v0), __ballot(v1)};
 
     if (threadIdx.x == 0) nb_s = 0;  // first used after the barrier closing phase A
 
@@ -347,8 +408,13 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         }
     }
 
-    // ---- A1: bonds of each row, row masks, run-start parents ----
+    // ---- A1: bonds, row masks, run-start parents, and the vertical contacts
+    // of the previous row pair.  Site s repeats the contact of s-1 when s-1 has
+    // a down bond and both rows continue from s-1 to s: one union per contact
+    // segment suffices.
     unsigned long long nact = 0, xr = 0;
+    int ncon = 0;
+    EO prevR = EO{0ull, 0ull}, prevD = EO{0ull, 0ull};
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         if (r >= nr) break;
@@ -423,23 +489,29 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
 
         // Crossing bonds leave the tile: the last column's right bond and the
         // last row's down bonds.  They are merged by k_merge.
-        const bool cross = (last0 && bR0) || (last1 && bR1);
-        if (__ballot(cross)) xr |= 1ull << ly;
+        if (__ballot((last0 && bR0) || (last1 && bR1))) xr |= 1ull << ly;
         const bool inR0 = bR0 && !last0, inR1 = bR1 && !last1;
-        // flags: 0 in-tile right bond, 1 down bond, 2 occupied
-        const uint32_t f = inR0 | (inR1 << 1) | (bD0 << 2) | (bD1 << 3) | (o0 << 4) | (o1 << 5);
-        M128 m[3];
-        row_masks<3>(f, lane, m);
+        const EO R = EO{__ballot(inR0), __ballot(inR1)};
+        EO D = EO{__ballot(bD0), __ballot(bD1)};
+        const EO O = (MODE == M_SITES) ? EO{__ballot(o0), __ballot(o1)} : valid;
+        if (ly == th - 1) {
+            if (lane == 0) xd_s = D;
+            D = EO{0ull, 0ull};
+        }
         if (lane == 0) {
-            Rm[ly] = m[0];
-            Dm[ly] = (ly == th - 1) ? M128{0ull, 0ull} : m[1];
-            Om[ly] = m[2];
-            if (ly == th - 1) xd_s = m[1];
+            Rm[ly] = R;
+            Om[ly] = O;
         }
         const int base = ly * TW;
-        const int rs0 = v0 ? run_start(m[0], lx0) : lx0;
-        const int rs1 = (v1 && inR0) ? rs0 : lx1;
+        const int rs0 = v0 ? run_start_even(R, lane) : lx0;
+        const int rs1 = inR0 ? rs0 : lx1;
         *reinterpret_cast<int2 *>(&P[base + lx0]) = make_int2(base + rs0, base + rs1);
+        if (r > 0) {
+            const EO X = eo_and(eo_and(prevD, prevR), R);
+            eo_append(mylist, ncon, eo_andnot(prevD, eo_shift1(X)), lane, base - TW);
+        }
+        prevR = R;
+        prevD = D;
     }
     if (lane == 0) xr_w[wave] = xr;
     if constexpr (MODE == M_SW) {
@@ -448,21 +520,11 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     }
     __syncthreads();
 
-    // ---- B: down bonds join runs.  One union per vertical contact segment:
-    // site s repeats the contact of s-1 when s-1 has a down bond and both rows
-    // continue from s-1 to s.  Contacts of the wave's rows are compacted into
-    // its list, then united in dense rounds of 64.
-    int ncon = 0;
-    for (int r = 0; r < RPW; ++r) {
-        const int ly = ly0 + r;
-        if (ly + 1 >= th) break;
-        const M128 D = Dm[ly], Ra = Rm[ly], Rb = Rm[ly + 1];
-        const M128 X = M128{D.lo & Ra.lo & Rb.lo, D.hi & Ra.hi & Rb.hi};
-        const M128 F = M128{D.lo & ~(X.lo << 1), D.hi & ~((X.hi << 1) | (X.lo >> 63))};
-        const int base = ly * TW;
-        if (bit128(F, lx0)) mylist[ncon + rank128(F, lx0)] = static_cast<uint16_t>(base + lx0);
-        if (bit128(F, lx1)) mylist[ncon + rank128(F, lx1)] = static_cast<uint16_t>(base + lx1);
-        ncon += __popcll(F.lo) + __popcll(F.hi);
+    // ---- B: contacts with the next wave's first row, then all unions ----
+    if (nr > 0 && ly0 + nr < th) {
+        const EO Rn = uniform_eo(Rm[ly0 + nr]);
+        const EO X = eo_and(eo_and(prevD, prevR), Rn);
+        eo_append(mylist, ncon, eo_andnot(prevD, eo_shift1(X)), lane, (ly0 + nr - 1) * TW);
     }
     wave_lds_fence();
     for (int i = lane; i < ncon; i += 64) {
@@ -471,116 +533,92 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     }
     __syncthreads();
 
-    // ---- C: compress run starts (the only sites unions ever touch) ----
+    // ---- C: roots of the occupied run starts (read-only), and claims of the
+    // clusters that touch the tile border (one thread per border position).
     int nrs = 0;
     for (int r = 0; r < nr; ++r) {
         const int ly = ly0 + r;
-        const M128 R = Rm[ly], O = Om[ly];
-        // run start: occupied, valid, and no bond from the left neighbour
-        M128 S = M128{O.lo & ~(R.lo << 1), O.hi & ~((R.hi << 1) | (R.lo >> 63))};
-        const int base = ly * TW;
-        if (bit128(S, lx0)) mylist[nrs + rank128(S, lx0)] = static_cast<uint16_t>(base + lx0);
-        if (bit128(S, lx1)) mylist[nrs + rank128(S, lx1)] = static_cast<uint16_t>(base + lx1);
-        nrs += __popcll(S.lo) + __popcll(S.hi);
+        const EO R = uniform_eo(Rm[ly]), O = uniform_eo(Om[ly]);
+        eo_append(mylist, nrs, eo_andnot(O, eo_shift1(R)), lane, ly * TW);
     }
     wave_lds_fence();
-    // Roots are found read-only first and written after a barrier: a halving
-    // store racing with another wave's compression could otherwise put an
-    // older ancestor back over a root that was already written.
     int rr[WLIST / 64];
 #pragma unroll
     for (int j = 0; j < WLIST / 64; ++j) {
         const int i = lane + 64 * j;
         rr[j] = i < nrs ? lroot(P, mylist[i]) : 0;
     }
+    for (int t = threadIdx.x; t < EDGE; t += NT) {
+        const int slot = border_slot(t, tw, th);
+        if (slot < 0) continue;
+        const EO O = Om[slot >> 7];
+        const int s = slot & (TW - 1);
+        if (!(((s & 1) ? O.o : O.e) >> (s >> 1) & 1ull)) continue;
+        const int root = lroot(P, slot);
+        int expect = root;
+        if (__hip_atomic_compare_exchange_strong(&P[root], &expect, CLAIMING, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            const int k = atomicAdd(&nb_s, 1);
+            lds_st(&P[root], -(k + 2));
+            const int id = tile * CAP + k;
+            a.gkey[id] = (gy0 + (root >> 7)) * W + gx0 + (root & (TW - 1));
+            a.gparent[id] = id;
+            if (a.gsize) a.gsize[id] = 0;
+        }
+    }
+    __syncthreads();
+
+    // ---- D: the code of every occupied run start (boundary id, or CAP + the
+    // slot of its interior root), then stored in place as -(code + 1).
+#pragma unroll
+    for (int j = 0; j < WLIST / 64; ++j) {
+        const int i = lane + 64 * j;
+        if (i < nrs) {
+            const int pr_root = lds_ld(&P[rr[j]]);
+            rr[j] = pr_root < 0 ? -pr_root - 2 : CAP + rr[j];
+        }
+    }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < WLIST / 64; ++j) {
         const int i = lane + 64 * j;
-        if (i < nrs) P[mylist[i]] = rr[j];
-    }
-    __syncthreads();
-    // From here on the root of site s is P[P[s]].
-
-    // ---- D: border sites claim their cluster's root and allocate its id ----
-    {
-        const bool top = ly0 == 0, bot = (ly0 <= th - 1) && (th - 1 < ly0 + RPW);
-        for (int r = 0; r < nr; ++r) {
-            const int ly = ly0 + r;
-            const M128 O = Om[ly];
-            const int base = ly * TW;
-            const bool edge_row = (top && r == 0) || (bot && ly == th - 1);
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int s = lx0 + j;
-                const bool border = s < tw && (edge_row || s == 0 || s == tw - 1) && bit128(O, s);
-                if (!border) continue;
-                const int p = lds_ld(&P[base + s]);
-                if (p < 0) continue;  // s is a root already claimed
-                const int root = lds_ld(&P[p]);
-                if (root < 0) continue;  // p is the root, already claimed
-                int expect = root;
-                if (__hip_atomic_compare_exchange_strong(&P[root], &expect, CLAIMING, __ATOMIC_RELAXED,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-                    const int k = atomicAdd(&nb_s, 1);
-                    lds_st(&P[root], -(k + 2));
-                    const int id = tile * CAP + k;
-                    a.gkey[id] = (gy0 + (root >> 7)) * W + gx0 + (root & (TW - 1));
-                    a.gparent[id] = id;
-                    if (a.gsize) a.gsize[id] = 0;
-                }
-            }
-        }
+        if (i < nrs) P[mylist[i]] = -(rr[j] + 1);
     }
     __syncthreads();
 
-    // ---- F: codes, edge ids, crossing bits ----
+    // ---- E: per-site codes, edge ids, crossing bits ----
     uint32_t *codes32 = reinterpret_cast<uint32_t *>(a.codes + static_cast<int64_t>(tile) * TSITES);
-    uint16_t *edg = a.edges + static_cast<int64_t>(tile) * EDGE;
     for (int r = 0; r < nr; ++r) {
         const int ly = ly0 + r;
-        const M128 O = Om[ly];
+        const EO O = Om[ly];
         const int base = ly * TW;
         const int2 pp = *reinterpret_cast<const int2 *>(&P[base + lx0]);
-        uint16_t c[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int s = lx0 + j;
-            uint16_t code = CODE_BG, eid = ID_NONE;
-            if (s < tw && bit128(O, s)) {
-                const int p = j ? pp.y : pp.x;
-                int v = p;  // walk s -> run start -> root until a claim or a root
-                if (v >= 0) {
-                    const int q = P[v];
-                    if (q < 0 || q == v) {
-                        v = q < 0 ? q : v;
-                    } else {
-                        const int u = P[q];
-                        v = u < 0 ? u : q;
-                    }
-                }
-                if (v < 0) {
-                    code = static_cast<uint16_t>(-v - 2);
-                    eid = code;
-                } else {
-                    code = static_cast<uint16_t>(CAP + v);
-                }
-            }
-            c[j] = code;
-            if (s < tw) {
-                if (ly == 0) edg[s] = eid;
-                if (ly == th - 1) edg[TW + s] = eid;
-                if (s == 0) edg[2 * TW + ly] = eid;
-                if (s == tw - 1) edg[2 * TW + TH + ly] = eid;
+        // a run start holds its code; any other site points at a run start
+        const int c0 = pp.x < 0 ? pp.x : P[max(pp.x, 0)];
+        const int c1 = pp.y < 0 ? pp.y : P[max(pp.y, 0)];
+        const uint32_t code0 = ((O.e >> lane) & 1ull) ? static_cast<uint32_t>(-c0 - 1) : CODE_BG;
+        const uint32_t code1 = ((O.o >> lane) & 1ull) ? static_cast<uint32_t>(-c1 - 1) : CODE_BG;
+        codes32[(base + lx0) >> 1] = code0 | (code1 << 16);
+    }
+    uint16_t *edg = a.edges + static_cast<int64_t>(tile) * EDGE;
+    for (int t = threadIdx.x; t < EDGE; t += NT) {
+        const int slot = border_slot(t, tw, th);
+        uint16_t eid = ID_NONE;
+        if (slot >= 0) {
+            const EO O = Om[slot >> 7];
+            const int s = slot & (TW - 1);
+            if (((s & 1) ? O.o : O.e) >> (s >> 1) & 1ull) {
+                const int p = P[slot];
+                eid = static_cast<uint16_t>(-(p < 0 ? p : P[p]) - 1);
             }
         }
-        codes32[(base + lx0) >> 1] = static_cast<uint32_t>(c[0]) | (static_cast<uint32_t>(c[1]) << 16);
+        edg[t] = eid;
     }
     if (threadIdx.x == 0) {
         uint64_t *xb = a.xbits + static_cast<int64_t>(tile) * XW;
         xb[0] = xr_w[0] | xr_w[1] | xr_w[2] | xr_w[3];
-        xb[1] = xd_s.lo;
-        xb[2] = xd_s.hi;
+        xb[1] = xd_s.e;  // bottom crossing bonds of even columns
+        xb[2] = xd_s.o;  // ... and of odd columns
         a.nb[tile] = nb_s;
         if (MODE == M_SW && a.tile_act) a.tile_act[tile] = act_w[0] + act_w[1] + act_w[2] + act_w[3];
     }
@@ -615,7 +653,8 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a)
     const uint16_t *eR = a.edges + static_cast<int64_t>(ntR) * EDGE;
     const uint16_t *eD = a.edges + static_cast<int64_t>(ntD) * EDGE;
     const uint64_t xr = xb[0];
-    const M128 xd = M128{xb[1], xb[2]};
+    const uint64_t xde = xb[1], xdo = xb[2];  // bottom crossing bonds, even / odd columns
+    auto xd_bit = [&](int x) { return (((x & 1) ? xdo : xde) >> (x >> 1)) & 1ull; };
     for (int j = lane; j < TH + TW; j += 64) {
         if (j < TH) {
             if (j >= th || !((xr >> j) & 1ull)) continue;
@@ -625,9 +664,9 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a)
             gunite(a.gparent, a.gkey, tile * CAP + ka, ntR * CAP + kb);
         } else {
             const int x = j - TH;
-            if (x >= tw || !bit128(xd, x)) continue;
+            if (x >= tw || !xd_bit(x)) continue;
             const uint16_t ka = e[TW + x], kb = eD[x];
-            if (x > 0 && bit128(xd, x - 1) && e[TW + x - 1] == ka && eD[x - 1] == kb) continue;
+            if (x > 0 && xd_bit(x - 1) && e[TW + x - 1] == ka && eD[x - 1] == kb) continue;
             gunite(a.gparent, a.gkey, tile * CAP + ka, ntD * CAP + kb);
         }
     }
