@@ -351,7 +351,21 @@ __device__ __forceinline__ int border_slot(int t, int tw, int th)
 // start x holds P[x] = -(code + 1).
 constexpr int CLAIMING = -1;
 
-template <int MODE>
+// Lane masks: bit L describes lane L (uicmp yields the mask of one compare).
+constexpr int CMP_EQ = 32, CMP_NE = 33, CMP_ULT = 36, CMP_ULE = 37;
+__device__ __forceinline__ uint64_t lanes_eq(uint32_t x, uint32_t y) { return __builtin_amdgcn_uicmp(x, y, CMP_EQ); }
+__device__ __forceinline__ uint64_t lanes_ne(uint32_t x, uint32_t y) { return __builtin_amdgcn_uicmp(x, y, CMP_NE); }
+__device__ __forceinline__ uint64_t lanes_lt(uint32_t x, uint32_t y) { return __builtin_amdgcn_uicmp(x, y, CMP_ULT); }
+__device__ __forceinline__ uint64_t lanes_le(uint32_t x, uint32_t y) { return __builtin_amdgcn_uicmp(x, y, CMP_ULE); }
+__device__ __forceinline__ bool lane_bit(uint64_t m, int lane) { return (m >> lane) & 1ull; }
+
+// Value of x held by the next lane (DPP wave shift; the last lane gets 0).
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t x)
+{
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x130, 0xF, 0xF, false));
+}
+
+template <int MODE, bool EVENW>
 __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
 {
     constexpr bool NEED_DOWN = MODE == M_SW || MODE == M_SITES;  // bonds from two rows
@@ -373,67 +387,68 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx0 = 2 * lane, lx1 = lx0 + 1;
     const bool v0 = lx0 < tw, v1 = lx1 < tw;
-    const bool last0 = lx0 == tw - 1, last1 = lx1 == tw - 1;
     const int hx = (gx0 + tw == W) ? 0 : gx0 + tw;  // column right of the tile
     const bool right_is_wrap = (gx0 + tw == W);
     const bool bottom_is_wrap = (gy0 + th == H);
     const int ly0 = wave * RPW;
     const int nr = max(0, min(RPW, th - ly0));  // tile rows owned by this wave
     uint16_t *mylist = wl[wave];
-    const EO valid = EO{__ballot(v0), __ballot(v1)};
+    // wave-uniform lane masks
+    const uint64_t V0 = lanes_lt(lx0, tw), V1 = lanes_lt(lx1, tw);
+    const uint64_t L0 = lanes_eq(lx0, tw - 1), L1 = lanes_eq(lx1, tw - 1);  // last column
+    const EO valid = EO{V0, V1};
 
     if (threadIdx.x == 0) nb_s = 0;  // first used after the barrier closing phase A
 
-    // ---- A0: issue every load of the wave's rows (and the row below) up front.
+    // ---- A0: issue every load of the wave's rows (and the row below) up front,
+    // branch-free within the wave: invalid lanes read a clamped valid address.
     // pr[r] holds the bytes of sites lx0 (bits 0-7) and lx1 (bits 8-15).
+    const int col = gx0 + (v0 ? lx0 : 0);
     uint32_t pr[RPW + 1];
-    uint8_t hl[RPW];
+    uint32_t hl[RPW];
 #pragma unroll
     for (int r = 0; r <= RPW; ++r) {
         pr[r] = 0;
         if (r < RPW) hl[r] = 0;
-        const bool want = nr > 0 && (r < nr || (NEED_DOWN && r == nr));
-        if (want) {
+        if (nr > 0 && (r < nr || (NEED_DOWN && r == nr))) {
             int gy = gy0 + ly0 + r;
             if (gy == H) gy = 0;  // ly0 + r <= th, so at most one wrap
-            const int64_t rowb = static_cast<int64_t>(gy) * W;
-            const int64_t i0 = rowb + gx0 + lx0;
-            if (v1 && !(i0 & 1)) {
-                pr[r] = *reinterpret_cast<const uint16_t *>(a.in + i0);
+            const uint8_t *row = a.in + static_cast<int64_t>(gy) * W;
+            if constexpr (EVENW) {
+                pr[r] = *reinterpret_cast<const uint16_t *>(row + col);
             } else {
-                if (v0) pr[r] = a.in[i0];
-                if (v1) pr[r] |= static_cast<uint32_t>(a.in[i0 + 1]) << 8;
+                pr[r] = static_cast<uint32_t>(row[col]) | (static_cast<uint32_t>(row[col + (v1 ? 1 : 0)]) << 8);
             }
-            if (NEED_HALO && r < nr && (last0 || last1)) hl[r] = a.in[rowb + hx];
+            if (NEED_HALO && r < nr) hl[r] = row[hx];  // same byte for every lane
         }
     }
 
-    // ---- A1: bonds, row masks, run-start parents, and the vertical contacts
-    // of the previous row pair.  Site s repeats the contact of s-1 when s-1 has
-    // a down bond and both rows continue from s-1 to s: one union per contact
-    // segment suffices.
+    // ---- A1: bonds as lane masks, row masks, run-start parents, and the
+    // vertical contacts of the previous row pair.  Site s repeats the contact
+    // of s-1 when s-1 has a down bond and both rows continue from s-1 to s:
+    // one union per contact segment suffices.
     unsigned long long nact = 0, xr = 0;
     int ncon = 0;
     EO prevR = EO{0ull, 0ull}, prevD = EO{0ull, 0ull};
+    const uint64_t below = low_bits(lane);
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         if (r >= nr) break;
         const int ly = ly0 + r;
         const int gy = gy0 + ly;
-        const int64_t rowb = static_cast<int64_t>(gy) * W;
-        const int64_t i0 = rowb + gx0 + lx0;
         const uint32_t cur = pr[r], dn = pr[r + 1];
-        bool bR0 = false, bR1 = false, bD0 = false, bD1 = false, o0 = v0, o1 = v1;
+        uint64_t mR0, mR1, mD0, mD1, O0 = V0, O1 = V1;
 
         if constexpr (MODE == M_SW) {
             const uint32_t s0 = cur & 0xFFu, s1 = (cur >> 8) & 0xFFu;
             const uint32_t d0 = dn & 0xFFu, d1 = (dn >> 8) & 0xFFu;
-            const uint32_t nxt = static_cast<uint32_t>(__shfl_down(static_cast<int>(s0), 1));
-            const uint32_t sr0 = last0 ? hl[r] : s1;
-            const uint32_t sr1 = last1 ? hl[r] : nxt;
+            const uint32_t nxt = from_next_lane(s0);
+            const uint32_t sr0 = (!EVENW && lx0 == tw - 1) ? hl[r] : s1;
+            const uint32_t sr1 = (lx1 == tw - 1) ? hl[r] : nxt;
+            const int64_t i0 = static_cast<int64_t>(gy) * W + gx0 + lx0;
             uint32_t r0R, r0D, r1R, r1D;
             const U4 blk = philox4x32_10(static_cast<uint32_t>(i0 >> 1), a.t, TAG_BOND, a.sid, a.k0, a.k1);
-            if ((rowb & 1) == 0) {  // the pair (i0, i0+1) shares one block
+            if (EVENW || (i0 & 1) == 0) {  // the pair (i0, i0+1) shares one block
                 r0R = blk.v0;
                 r0D = blk.v1;
                 r1R = blk.v2;
@@ -446,65 +461,69 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
                 r1R = b2.v0;
                 r1D = b2.v1;
             }
-            const bool on = a.tany != 0;
-            bR0 = on && v0 && s0 == sr0 && r0R <= a.tm1;
-            bD0 = on && v0 && s0 == d0 && r0D <= a.tm1;
-            bR1 = on && v1 && s1 == sr1 && r1R <= a.tm1;
-            bD1 = on && v1 && s1 == d1 && r1D <= a.tm1;
+            const uint64_t on0 = a.tany ? V0 : 0ull, on1 = a.tany ? V1 : 0ull;
+            mR0 = lanes_eq(s0, sr0) & lanes_le(r0R, a.tm1) & on0;
+            mD0 = lanes_eq(s0, d0) & lanes_le(r0D, a.tm1) & on0;
+            mR1 = lanes_eq(s1, sr1) & lanes_le(r1R, a.tm1) & on1;
+            mD1 = lanes_eq(s1, d1) & lanes_le(r1D, a.tm1) & on1;
             if (a.bonds_out) {
-                const uint32_t b0 = bR0 | (bD0 << 1), b1 = bR1 | (bD1 << 1);
-                if (v1 && !(i0 & 1)) {
+                const uint32_t b0 = lane_bit(mR0, lane) | (lane_bit(mD0, lane) << 1);
+                const uint32_t b1 = lane_bit(mR1, lane) | (lane_bit(mD1, lane) << 1);
+                if (v1 && (EVENW || !(i0 & 1))) {
                     *reinterpret_cast<uint16_t *>(a.bonds_out + i0) = static_cast<uint16_t>(b0 | (b1 << 8));
                 } else {
                     if (v0) a.bonds_out[i0] = static_cast<uint8_t>(b0);
                     if (v1) a.bonds_out[i0 + 1] = static_cast<uint8_t>(b1);
                 }
             }
-            nact += static_cast<unsigned>(bR0) + bD0 + bR1 + bD1;
+            nact += __popcll(mR0) + __popcll(mD0) + __popcll(mR1) + __popcll(mD1);
         } else if constexpr (MODE == M_BONDS_PERIODIC || MODE == M_BONDS_OPEN) {
-            bR0 = cur & 1u;
-            bD0 = (cur >> 1) & 1u;
-            bR1 = (cur >> 8) & 1u;
-            bD1 = (cur >> 9) & 1u;
+            mR0 = lanes_ne(cur & 0x001u, 0u) & V0;
+            mD0 = lanes_ne(cur & 0x002u, 0u) & V0;
+            mR1 = lanes_ne(cur & 0x100u, 0u) & V1;
+            mD1 = lanes_ne(cur & 0x200u, 0u) & V1;
             if (MODE == M_BONDS_OPEN) {
                 if (right_is_wrap) {
-                    bR0 = bR0 && !last0;
-                    bR1 = bR1 && !last1;
+                    mR0 &= ~L0;
+                    mR1 &= ~L1;
                 }
-                if (bottom_is_wrap && ly == th - 1) bD0 = bD1 = false;
+                if (bottom_is_wrap && ly == th - 1) mD0 = mD1 = 0ull;
             }
         } else {  // M_SITES: 4-connected occupied pixels, open boundary
-            o0 = v0 && (cur & 0xFFu) != 0;
-            o1 = v1 && (cur & 0xFF00u) != 0;
-            const bool has_down = gy + 1 < H;
-            const bool d0 = has_down && (dn & 0xFFu) != 0;
-            const bool d1 = has_down && (dn & 0xFF00u) != 0;
-            const bool nxt = __shfl_down(static_cast<int>(o0), 1) != 0;
-            const bool halo = !right_is_wrap && hl[r] != 0;
-            bR0 = o0 && (last0 ? halo : o1);
-            bR1 = o1 && (last1 ? halo : nxt);
-            bD0 = o0 && d0;
-            bD1 = o1 && d1;
+            O0 = lanes_ne(cur & 0x00FFu, 0u) & V0;
+            O1 = lanes_ne(cur & 0xFF00u, 0u) & V1;
+            const uint64_t below_occ = (gy + 1 < H) ? ~0ull : 0ull;
+            const uint64_t Dn0 = lanes_ne(dn & 0x00FFu, 0u) & below_occ;
+            const uint64_t Dn1 = lanes_ne(dn & 0xFF00u, 0u) & below_occ;
+            const uint64_t Hh = (!right_is_wrap && hl[r] != 0) ? ~0ull : 0ull;  // hl is lane-uniform
+            mR0 = O0 & ((O1 & ~L0) | (Hh & L0));
+            mR1 = O1 & (((O0 >> 1) & ~L1) | (Hh & L1));
+            mD0 = O0 & Dn0;
+            mD1 = O1 & Dn1;
         }
 
         // Crossing bonds leave the tile: the last column's right bond and the
         // last row's down bonds.  They are merged by k_merge.
-        if (__ballot((last0 && bR0) || (last1 && bR1))) xr |= 1ull << ly;
-        const bool inR0 = bR0 && !last0, inR1 = bR1 && !last1;
-        const EO R = EO{__ballot(inR0), __ballot(inR1)};
-        EO D = EO{__ballot(bD0), __ballot(bD1)};
-        const EO O = (MODE == M_SITES) ? EO{__ballot(o0), __ballot(o1)} : valid;
+        if ((mR0 & L0) | (mR1 & L1)) xr |= 1ull << ly;
+        const EO R = EO{mR0 & ~L0, mR1 & ~L1};
+        EO D = EO{mD0, mD1};
         if (ly == th - 1) {
             if (lane == 0) xd_s = D;
             D = EO{0ull, 0ull};
         }
         if (lane == 0) {
             Rm[ly] = R;
-            Om[ly] = O;
+            Om[ly] = EO{O0, O1};
         }
         const int base = ly * TW;
-        const int rs0 = v0 ? run_start_even(R, lane) : lx0;
-        const int rs1 = inR0 ? rs0 : lx1;
+        int rs0 = lx0;
+        if (v0) {  // run start of site 2L: one past the last missing right bond before it
+            const uint64_t ze = ~R.e & below, zo = ~R.o & below;
+            const int ce = ze ? 2 * (63 - __builtin_clzll(ze)) + 1 : 0;
+            const int co = zo ? 2 * (63 - __builtin_clzll(zo)) + 2 : 0;
+            rs0 = max(ce, co);
+        }
+        const int rs1 = lane_bit(R.e, lane) ? rs0 : lx1;
         *reinterpret_cast<int2 *>(&P[base + lx0]) = make_int2(base + rs0, base + rs1);
         if (r > 0) {
             const EO X = eo_and(eo_and(prevD, prevR), R);
@@ -513,10 +532,9 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         prevR = R;
         prevD = D;
     }
-    if (lane == 0) xr_w[wave] = xr;
-    if constexpr (MODE == M_SW) {
-        const unsigned long long s = wave_sum(nact);
-        if (lane == 0) act_w[wave] = static_cast<int>(s);
+    if (lane == 0) {
+        xr_w[wave] = xr;
+        act_w[wave] = static_cast<int>(nact);
     }
     __syncthreads();
 

@@ -149,6 +149,17 @@ MergeArgs merge_args(const Layout &L, void *ws)
     return m;
 }
 
+// Even W keeps every row start even: one 16-bit load per lane pair.
+template <int MODE>
+void launch_tile(const Layout &L, const TileArgs &ta, hipStream_t s)
+{
+    const dim3 grid(static_cast<unsigned>(L.g.ntiles)), block(NT);
+    if (L.g.W % 2 == 0)
+        hipLaunchKernelGGL((k_tile<MODE, true>), grid, block, 0, s, ta);
+    else
+        hipLaunchKernelGGL((k_tile<MODE, false>), grid, block, 0, s, ta);
+}
+
 dim3 merge_grid(const Layout &L) { return dim3(static_cast<unsigned>(cdiv(L.g.ntiles, MERGE_TILES))); }
 
 FlatArgs flat_args(const Layout &L, void *ws)
@@ -284,7 +295,7 @@ static sw_status launch_phase(sw_lattice *h, int32_t phase, hipStream_t s)
         ta.k1 = k1;
         ta.t = t;
         ta.sid = h->p.stream_id;
-        hipLaunchKernelGGL((k_tile<M_SW>), grid, block, 0, s, ta);
+        launch_tile<M_SW>(L, ta, s);
         return launch_status("k_tile");
     }
     if (phase == SW_PHASE_MERGE) {
@@ -425,9 +436,9 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
 
     const TileArgs ta = tile_args(L, workspace, in);
     switch (mode) {
-    case CCL_BONDS_PERIODIC: hipLaunchKernelGGL((k_tile<M_BONDS_PERIODIC>), grid, block, 0, s, ta); break;
-    case CCL_BONDS_OPEN: hipLaunchKernelGGL((k_tile<M_BONDS_OPEN>), grid, block, 0, s, ta); break;
-    default: hipLaunchKernelGGL((k_tile<M_SITES>), grid, block, 0, s, ta); break;
+    case CCL_BONDS_PERIODIC: launch_tile<M_BONDS_PERIODIC>(L, ta, s); break;
+    case CCL_BONDS_OPEN: launch_tile<M_BONDS_OPEN>(L, ta, s); break;
+    default: launch_tile<M_SITES>(L, ta, s); break;
     }
     hipLaunchKernelGGL(k_merge, merge_grid(L), block, 0, s, merge_args(L, workspace));
     FlatArgs fa = flat_args(L, workspace);
