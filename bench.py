@@ -34,8 +34,6 @@ SWEEP_BYTES_PER_SITE = 10
 TILE_BYTES_PER_SITE = 5   # spin in (1) + label out (4)
 FLIP_BYTES_PER_SITE = 5   # label in (4) + spin out (1)
 CCL_BYTES_PER_SITE = 13   # input (1) + label write, read and canonical write (3 x 4)
-# Philox4x32-10 per site for the bonds: half a block = 10 32x32->64 multiplies.
-MULS_PER_SITE_TILE = 10
 
 
 def _args():
@@ -51,9 +49,26 @@ def _args():
     return ap.parse_args()
 
 
-def _mul64_peak_tops(rate: float) -> float:
-    """Peak 32x32->64 multiplies per second if one issues every 1/rate lane-slots."""
-    return CUS * LANES_PER_CU_CLK * CLOCK_GHZ * 1e9 * rate / 1e12
+VALU_ISSUE_PEAK = CUS * CLOCK_GHZ * 1e9  # wave64 VALU instructions per second (1 per CU per clock)
+
+
+def _profile(kernel: str):
+    """Counter figures for `kernel` from the committed rocprofv3 summary, or None
+    when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_potts16384.json")
+    src = os.path.join(ROOT, "paper_1105_5804_amd", "csrc", "kernels.hpp")
+    try:
+        prof = json.load(open(path))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except (OSError, ValueError):
+        return None
+    if prof.get("kernels_hpp_sha256_16") != h:
+        return None
+    for name, v in prof.get("kernels", {}).items():
+        if name.startswith(kernel):
+            return v
+    return None
 
 
 def main() -> int:
@@ -115,23 +130,27 @@ def main() -> int:
 
     dom = int(np.argmax(phase_ms))
     dom_ms = phase_ms[dom]
+    kname = {0: "swccl::k_tile<0", 1: "swccl::k_merge", 2: "swccl::k_flatten<0"}[dom]
     dom_bytes = [TILE_BYTES_PER_SITE, 0, FLIP_BYTES_PER_SITE][dom] * N
     achieved_gbs = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_bytes else 0.0
+    prof = _profile(kname)
     roofline = {
-        "kernel": {0: "k_tile", 1: "k_merge", 2: "k_flatten"}[dom],
+        "kernel": kname.split("::")[-1].split("<")[0],
         "bound": "hbm",
         "achieved": round(achieved_gbs, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": (prof["fetch_bytes"] + prof["write_bytes"]) if prof else None,
         "bytes_per_site": [TILE_BYTES_PER_SITE, 0, FLIP_BYTES_PER_SITE][dom],
         "sweep_frac_of_hbm_roofline": round(SWEEP_BYTES_PER_SITE * N / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
+    if prof and prof.get("valu_insts"):
+        # issued wave64 VALU instructions per launch (counters) over this launch time
+        roofline["valu_issue_frac"] = round(prof["valu_insts"] / (dom_ms * 1e-3) / VALU_ISSUE_PEAK, 4)
     if dom == 0:
-        muls = MULS_PER_SITE_TILE * N / (dom_ms * 1e-3) / 1e12
-        roofline["alu_mul64_tops"] = round(muls, 3)
-        roofline["alu_mul64_peak_tops_quarter_rate"] = round(_mul64_peak_tops(0.25), 3)
+        # the bond RNG alone: half a Philox4x32-10 block per site at ~62 lane-cycles per block
+        roofline["philox_floor_ms"] = round(N * 31 / (CUS * LANES_PER_CU_CLK * CLOCK_GHZ * 1e9) * 1e3, 4)
 
     out = {
         "metric": "ns/spin per SW sweep at L=16384; labeled sites/s; batched/served vs plain",
