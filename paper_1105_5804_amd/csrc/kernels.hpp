@@ -180,7 +180,7 @@ __device__ __forceinline__ void lunite(int *P, int a, int b)
 __device__ __forceinline__ int gfind(const int *G, int x)
 {
     for (;;) {
-        const int p = __hip_atomic_load(const_cast<int *>(&G[x]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int p = G[x];
         if (p == x) return x;
         x = p;
     }
@@ -721,15 +721,14 @@ __device__ __forceinline__ uint8_t flip_state(uint32_t R, const FlatArgs &a)
 template <int MODE, bool SIZES>
 __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
 {
-    __shared__ int32_t Rb[CAP];     // canonical root (site index) per boundary id
-    __shared__ int32_t Gid[CAP];    // root id per boundary id
-    __shared__ uint8_t Sb[CAP];     // new state per boundary id
-    __shared__ uint8_t Si[TSITES];  // new state per interior root slot
-    __shared__ uint16_t rlist[TSITES];  // interior root slots
-    __shared__ int nroot_s;
+    constexpr int NCODE = CAP + TSITES;
+    __shared__ uint8_t ST[MODE == M_SW ? NCODE : 1];  // new state per code (boundary id or CAP + slot)
+    __shared__ int32_t Rb[CAP];                        // canonical root (site index) per boundary id
+    __shared__ int32_t Gid[CAP];                       // root id per boundary id
+    __shared__ uint16_t rl[NWAVE][WLIST];              // interior roots of each wave's rows
     __shared__ int ncl_w[NWAVE];
-    __shared__ int32_t Ci[SIZES ? TSITES : 1];  // sizes of interior clusters
-    __shared__ int32_t Cb[SIZES ? CAP : 1];     // per-tile part of boundary clusters
+    __shared__ int32_t Ci[SIZES ? TSITES : 1];         // sizes of interior clusters
+    __shared__ int32_t Cb[SIZES ? CAP : 1];            // per-tile part of boundary clusters
     __shared__ int32_t rowc[TH + 1];
 
     const int W = a.g.W;
@@ -743,7 +742,6 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
     const int nr = max(0, min(RPW, th - ly0));
     const int nbt = a.nb[tile];
 
-    if (threadIdx.x == 0) nroot_s = 0;
     if constexpr (SIZES) {
         for (int k = threadIdx.x; k < TSITES; k += NT) Ci[k] = 0;
         for (int k = threadIdx.x; k < CAP; k += NT) Cb[k] = 0;
@@ -752,85 +750,74 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
     const uint32_t *codes32 = reinterpret_cast<const uint32_t *>(a.codes + static_cast<int64_t>(tile) * TSITES);
 #pragma unroll
     for (int r = 0; r < RPW; ++r) cc[r] = r < nr ? codes32[((ly0 + r) * TW + lx0) >> 1] : 0xFFFFFFFFu;
-    __syncthreads();
 
-    // interior roots (code = CAP + own slot) into a compact list
-#pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-        if (r >= nr) break;
+    // interior roots (code = CAP + own slot) of the wave's rows, compacted
+    int nroot = 0;
+    uint16_t *mylist = rl[wave];
+    for (int r = 0; r < nr; ++r) {
         const int base = (ly0 + r) * TW;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int s = lx0 + j;
-            const uint32_t code = (cc[r] >> (16 * j)) & 0xFFFFu;
-            const bool isr = s < tw && code == static_cast<uint32_t>(CAP + base + s);
-            const uint64_t m = __ballot(isr);
-            if (m) {
-                int first = 0;
-                if (lane == 0) first = atomicAdd(&nroot_s, __popcll(m));
-                first = __shfl(first, 0);
-                if (isr) rlist[first + __popcll(m & ((1ull << lane) - 1ull))] = static_cast<uint16_t>(base + s);
-            }
+        const EO m = EO{lanes_eq(cc[r] & 0xFFFFu, static_cast<uint32_t>(CAP + base + lx0)),
+                        lanes_eq(cc[r] >> 16, static_cast<uint32_t>(CAP + base + lx0 + 1))};
+        eo_append(mylist, nroot, m, lane, base);
+    }
+    wave_lds_fence();
+    if constexpr (MODE == M_SW) {
+        for (int i = lane; i < nroot; i += 64) {
+            const int slot = mylist[i];
+            ST[CAP + slot] = flip_state(static_cast<uint32_t>((gy0 + (slot >> 7)) * W + gx0 + (slot & (TW - 1))), a);
         }
     }
-
-    // boundary ids: resolve to the global root; the root's key is the
-    // cluster's minimum site index
+    // boundary ids: resolve to the global root, whose key is the cluster's
+    // minimum site index (the union-find is final: plain loads suffice)
     int nbr = 0;
     for (int k = threadIdx.x; k < nbt; k += NT) {
         const int id = tile * CAP + k;
-        const int root = gfind(a.gparent, id);
+        int root = id;
+        for (int p = a.gparent[root]; p != root; p = a.gparent[root]) root = p;
         const int R = a.gkey[root];
         Rb[k] = R;
         Gid[k] = root;
         nbr += root == id;
-        if constexpr (MODE == M_SW) Sb[k] = flip_state(static_cast<uint32_t>(R), a);
+        if constexpr (MODE == M_SW) ST[k] = flip_state(static_cast<uint32_t>(R), a);
     }
     {
         const unsigned long long s = wave_sum(static_cast<unsigned long long>(nbr));
-        if (lane == 0) ncl_w[wave] = static_cast<int>(s);
+        if (lane == 0) ncl_w[wave] = static_cast<int>(s) + nroot;
     }
     __syncthreads();
-    const int nroot = nroot_s;
-    if constexpr (MODE == M_SW) {
-        for (int j = threadIdx.x; j < nroot; j += NT) {
-            const int slot = rlist[j];
-            Si[slot] = flip_state(static_cast<uint32_t>((gy0 + (slot >> 7)) * W + gx0 + (slot & (TW - 1))), a);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && a.tile_ncl) a.tile_ncl[tile] = nroot + ncl_w[0] + ncl_w[1] + ncl_w[2] + ncl_w[3];
+    if (threadIdx.x == 0 && a.tile_ncl) a.tile_ncl[tile] = ncl_w[0] + ncl_w[1] + ncl_w[2] + ncl_w[3];
 
+    const bool v0 = lx0 < tw, v1 = lx0 + 1 < tw;
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         if (r >= nr) break;
         const int ly = ly0 + r;
-        const int base = ly * TW;
         const int64_t i0 = static_cast<int64_t>(gy0 + ly) * W + gx0 + lx0;
-        int32_t R[2];
-        uint32_t st[2] = {0u, 0u};
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const uint32_t code = (cc[r] >> (16 * j)) & 0xFFFFu;
-            if (code == CODE_BG) {
-                R[j] = -1;
-            } else if (code < static_cast<uint32_t>(CAP)) {
-                R[j] = Rb[code];
-                if constexpr (MODE == M_SW) st[j] = Sb[code];
-                if constexpr (SIZES) {
-                    if (lx0 + j < tw) atomicAdd(&Cb[code], 1);
-                }
+        const uint32_t c0 = cc[r] & 0xFFFFu, c1 = cc[r] >> 16;
+        if constexpr (MODE == M_SW) {
+            // sites past a ragged tile edge carry CODE_BG: clamp the lookup, never store
+            const uint32_t st0 = ST[min(c0, static_cast<uint32_t>(NCODE - 1))];
+            const uint32_t st1 = ST[min(c1, static_cast<uint32_t>(NCODE - 1))];
+            const uint32_t b0 = a.ising ? (2u * st0 - 1u) & 0xFFu : st0;
+            const uint32_t b1 = a.ising ? (2u * st1 - 1u) & 0xFFu : st1;
+            if (v1 && !(i0 & 1)) {
+                *reinterpret_cast<uint16_t *>(a.spins + i0) = static_cast<uint16_t>(b0 | (b1 << 8));
             } else {
-                const int slot = static_cast<int>(code) - CAP;
-                R[j] = (gy0 + (slot >> 7)) * W + gx0 + (slot & (TW - 1));
-                if constexpr (MODE == M_SW) st[j] = Si[slot];
-                if constexpr (SIZES) {
-                    if (lx0 + j < tw) atomicAdd(&Ci[slot], 1);
-                }
+                if (v0) a.spins[i0] = static_cast<uint8_t>(b0);
+                if (v1) a.spins[i0 + 1] = static_cast<uint8_t>(b1);
             }
         }
-        const bool v0 = lx0 < tw, v1 = lx0 + 1 < tw;
         if (a.labels) {
+            int32_t R[2];
+            const uint32_t cs[2] = {c0, c1};
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const uint32_t c = cs[j];
+                const int slot = static_cast<int>(c) - CAP;
+                R[j] = c == CODE_BG ? -1
+                     : c < static_cast<uint32_t>(CAP) ? Rb[c]
+                                                       : (gy0 + (slot >> 7)) * W + gx0 + (slot & (TW - 1));
+            }
             if (v1 && !(i0 & 1)) {
                 *reinterpret_cast<int2 *>(a.labels + i0) = make_int2(R[0], R[1]);
             } else {
@@ -838,15 +825,9 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
                 if (v1) a.labels[i0 + 1] = R[1];
             }
         }
-        if constexpr (MODE == M_SW) {
-            const uint32_t b0 = a.ising ? (2u * st[0] - 1u) & 0xFFu : st[0];
-            const uint32_t b1 = a.ising ? (2u * st[1] - 1u) & 0xFFu : st[1];
-            if (v1 && !(i0 & 1)) {
-                *reinterpret_cast<uint16_t *>(a.spins + i0) = static_cast<uint16_t>(b0 | (b1 << 8));
-            } else {
-                if (v0) a.spins[i0] = static_cast<uint8_t>(b0);
-                if (v1) a.spins[i0 + 1] = static_cast<uint8_t>(b1);
-            }
+        if constexpr (SIZES) {
+            if (v0 && c0 != CODE_BG) atomicAdd(c0 < static_cast<uint32_t>(CAP) ? &Cb[c0] : &Ci[c0 - CAP], 1);
+            if (v1 && c1 != CODE_BG) atomicAdd(c1 < static_cast<uint32_t>(CAP) ? &Cb[c1] : &Ci[c1 - CAP], 1);
         }
     }
 
@@ -855,11 +836,11 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
         // boundary clusters: add this tile's part at the global root id
         for (int k = threadIdx.x; k < nbt; k += NT)
             if (Cb[k]) __hip_atomic_fetch_add(&a.gsize[Gid[k]], Cb[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // roots of this tile in raster order: per-row counts, then positions
-        M128 rm[RPW];
+        // canonical roots of this tile in raster order: per-row counts, then positions
+        EO rm[RPW];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
-            rm[r] = M128{0ull, 0ull};
+            rm[r] = EO{0ull, 0ull};
             if (r >= nr) continue;
             const int ly = ly0 + r;
             const int base = ly * TW;
@@ -874,11 +855,9 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
                           (code < static_cast<uint32_t>(CAP) && Gid[code] == tile * CAP + static_cast<int>(code) &&
                            Rb[code] == self));
             }
-            M128 mk[1];
-            row_masks<1>(static_cast<uint32_t>(isr[0]) | (static_cast<uint32_t>(isr[1]) << 1), lane, mk);
-            rm[r] = mk[0];
+            rm[r] = EO{__ballot(isr[0]), __ballot(isr[1])};
             if (lane == 0) {
-                const int n = __popcll(rm[r].lo) + __popcll(rm[r].hi);
+                const int n = __popcll(rm[r].e) + __popcll(rm[r].o);
                 rowc[ly] = n;
                 a.row_count[static_cast<int64_t>(gy0 + ly) * a.g.ntx + tx] = n;
             }
@@ -899,11 +878,14 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
             if (r >= nr) break;
             const int ly = ly0 + r;
             const int base = ly * TW;
+            // ascending site order within the row: even sites below 2L+j, odd sites below
+            const int below = lanes_below(rm[r].e) + lanes_below(rm[r].o);
+            const int be = static_cast<int>((rm[r].e >> lane) & 1ull);
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
+                if (!(((j ? rm[r].o : rm[r].e) >> lane) & 1ull)) continue;
                 const int s = lx0 + j;
-                if (!bit128(rm[r], s)) continue;
-                const int pos = rowc[ly] + rank128(rm[r], s);
+                const int pos = rowc[ly] + below + (j ? be : 0);
                 const uint32_t code = (cc[r] >> (16 * j)) & 0xFFFFu;
                 const int64_t o = static_cast<int64_t>(tile) * TSITES + pos;
                 a.rl_slot[o] = base + s;
@@ -1017,44 +999,59 @@ __global__ __launch_bounds__(NT) void k_emit(EmitArgs a)
 // ----------------------------------------------------------- observables ---
 
 // Satisfied bonds, magnetisation (Ising) and state counts of the spins
-// (Eq. potts_hamiltonian: -H/J = number of satisfied bonds).
+// (Eq. potts_hamiltonian: -H/J = number of satisfied bonds).  Blocks take whole
+// rows; a thread takes 4 consecutive sites per step.  State counts go to
+// packed 16-bit counters (states 0-3 and 4-7), flushed after every row.
 __global__ __launch_bounds__(NT) void k_observe(const uint8_t *s, int W, int H, uint32_t q, int ising,
                                                 unsigned long long *out)
 {
     __shared__ unsigned long long red[NWAVE][10];
-    const int64_t N = static_cast<int64_t>(W) * H;
     unsigned long long nsat = 0, cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    long long mag = 0;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; i < N;
-         i += static_cast<int64_t>(gridDim.x) * NT) {
-        const int x = static_cast<int>(i % W);
-        const int64_t y = i / W;
-        const uint8_t v = s[i];
-        const uint8_t vr = s[y * W + (x + 1 == W ? 0 : x + 1)];
-        const uint8_t vd = s[(y + 1 == H ? 0 : y + 1) * static_cast<int64_t>(W) + x];
-        nsat += (v == vr) + (v == vd);
-        if (ising) {
-            mag += static_cast<int8_t>(v);
-            cnt[v == 1 ? 1 : 0]++;
-        } else if (v < 8) {
-            cnt[v]++;
+    for (int y = blockIdx.x; y < H; y += gridDim.x) {
+        const uint8_t *row = s + static_cast<int64_t>(y) * W;
+        const uint8_t *dwn = s + static_cast<int64_t>(y + 1 == H ? 0 : y + 1) * W;
+        uint64_t h03 = 0, h47 = 0;
+        for (int x = threadIdx.x * 4; x < W; x += NT * 4) {
+            uint32_t v[5], d[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int xj = min(x + j, W - 1);
+                v[j] = row[xj];
+                d[j] = dwn[xj];
+            }
+            v[4] = row[x + 4 < W ? x + 4 : (x + 4 == W ? 0 : W - 1)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (x + j >= W) break;
+                const uint32_t vr = (x + j + 1 == W) ? row[0] : v[j + 1];
+                nsat += (v[j] == vr) + (v[j] == d[j]);
+                const uint32_t st = ising ? (v[j] == 1u ? 1u : 0u) : v[j];
+                if (st < 4) h03 += 1ull << (16 * st);
+                else if (st < 8) h47 += 1ull << (16 * (st - 4));
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            cnt[k] += (h03 >> (16 * k)) & 0xFFFFull;
+            cnt[k + 4] += (h47 >> (16 * k)) & 0xFFFFull;
         }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long vals[10];
     vals[0] = nsat;
-    vals[1] = static_cast<unsigned long long>(mag);
+    vals[1] = 0;
     for (int k = 0; k < 8; ++k) vals[2 + k] = cnt[k];
     for (int k = 0; k < 10; ++k) {
         const unsigned long long w = wave_sum(vals[k]);
         if (lane == 0) red[wave][k] = w;
     }
     __syncthreads();
-    if (threadIdx.x < 10) {
+    // the magnetisation of the Ising case follows from the counts on the host
+    if (threadIdx.x < 10 && threadIdx.x != 1) {
         unsigned long long t = 0;
         for (int w = 0; w < NWAVE; ++w) t += red[w][threadIdx.x];
-        const int slot = threadIdx.x == 0 ? ST_NSAT : threadIdx.x == 1 ? ST_MAGNET : ST_COUNTS + threadIdx.x - 2;
-        __hip_atomic_fetch_add(&out[slot], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int slot = threadIdx.x == 0 ? ST_NSAT : ST_COUNTS + threadIdx.x - 2;
+        add_stat(&out[slot], t);
     }
     (void)q;
 }

@@ -358,7 +358,7 @@ sw_status sw_observables(sw_lattice *h, sw_obs *out, void *stream)
     unsigned long long *obs = at<unsigned long long>(ws, L.stats);
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, obs, ST_LEN);
     const int64_t N = static_cast<int64_t>(h->p.W) * h->p.H;
-    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(cdiv(N, NT), 1024));
+    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(h->p.H, 2048));
     hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(NT), 0, s, static_cast<const uint8_t *>(h->b.spins),
                        h->p.W, h->p.H, static_cast<uint32_t>(h->p.q), h->p.spin_kind == SW_SPIN_ISING_I8 ? 1 : 0,
                        obs);
@@ -380,8 +380,8 @@ sw_status sw_observables(sw_lattice *h, sw_obs *out, void *stream)
     out->t = h->t;
     out->threshold = h->T;
     out->n_sat = static_cast<int64_t>(host[ST_NSAT]);
-    out->magnet = h->p.spin_kind == SW_SPIN_ISING_I8 ? static_cast<int64_t>(host[ST_MAGNET]) : 0;
     for (int k = 0; k < 8; ++k) out->counts[k] = k < h->p.q ? static_cast<int64_t>(host[ST_COUNTS + k]) : 0;
+    out->magnet = h->p.spin_kind == SW_SPIN_ISING_I8 ? 2 * out->counts[1] - N : 0;
     out->n_active_bonds = h->swept ? static_cast<int64_t>(host[ST_ACTIVE]) : -1;
     out->n_clusters = h->swept ? static_cast<int64_t>(host[ST_NCLUST]) : -1;
     return SW_OK;
