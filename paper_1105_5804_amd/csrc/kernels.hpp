@@ -4,7 +4,7 @@
 // A sweep is three launches (Sec. II: T_SW = T_activate + T_identify + T_flip,
 // with T_identify = T_local + T_global):
 //
-//   k_tile    one workgroup per 128x32 tile.  Bond activation (Sec. II.A) fused
+//   k_tile    one workgroup per 128x64 tile.  Bond activation (Sec. II.A) fused
 //             with tile labeling (Sec. II.B): each lane of a 64-lane wave owns
 //             two sites of a tile row; the row's bonds become 128-bit masks by
 //             wave ballots, right bonds turn into row runs by a bit scan, and
@@ -35,12 +35,12 @@
 namespace swccl {
 
 constexpr int TW = 128;               // tile width: a wave covers a tile row, 2 sites per lane
-constexpr int TH = 32;                // tile height
+constexpr int TH = 64;                // tile height
 constexpr int TSITES = TW * TH;       // sites per tile
 constexpr int CAP = 2 * (TW + TH);    // boundary ids per tile (>= border sites)
 constexpr int EDGE = 2 * TW + 2 * TH; // edge id entries per tile: top, bottom, left, right
 constexpr int XW = 4;                 // crossing-bond words per tile: right rows, bottom cols (2)
-constexpr int NT = 256;               // threads per workgroup
+constexpr int NT = 512;               // threads per workgroup
 constexpr int NWAVE = NT / 64;
 constexpr int RPW = TH / NWAVE;       // tile rows per wave
 constexpr int WLIST = RPW * TW;       // per-wave work list capacity (one entry per site at most)
@@ -634,11 +634,17 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     }
     if (threadIdx.x == 0) {
         uint64_t *xb = a.xbits + static_cast<int64_t>(tile) * XW;
-        xb[0] = xr_w[0] | xr_w[1] | xr_w[2] | xr_w[3];
+        unsigned long long xrt = 0;
+        int act = 0;
+        for (int w = 0; w < NWAVE; ++w) {
+            xrt |= xr_w[w];
+            act += act_w[w];
+        }
+        xb[0] = xrt;
         xb[1] = xd_s.e;  // bottom crossing bonds of even columns
         xb[2] = xd_s.o;  // ... and of odd columns
         a.nb[tile] = nb_s;
-        if (MODE == M_SW && a.tile_act) a.tile_act[tile] = act_w[0] + act_w[1] + act_w[2] + act_w[3];
+        if (MODE == M_SW && a.tile_act) a.tile_act[tile] = act;
     }
 }
 
@@ -785,7 +791,11 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
         if (lane == 0) ncl_w[wave] = static_cast<int>(s) + nroot;
     }
     __syncthreads();
-    if (threadIdx.x == 0 && a.tile_ncl) a.tile_ncl[tile] = ncl_w[0] + ncl_w[1] + ncl_w[2] + ncl_w[3];
+    if (threadIdx.x == 0 && a.tile_ncl) {
+        int n = 0;
+        for (int w = 0; w < NWAVE; ++w) n += ncl_w[w];
+        a.tile_ncl[tile] = n;
+    }
 
     const bool v0 = lx0 < tw, v1 = lx0 + 1 < tw;
 #pragma unroll
@@ -909,7 +919,8 @@ __global__ __launch_bounds__(NT) void k_reduce_tiles(const int32_t *v, int n, un
     if (lane == 0) red[wave] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned long long t = red[0] + red[1] + red[2] + red[3];
+        unsigned long long t = 0;
+        for (int w = 0; w < NWAVE; ++w) t += red[w];
         if (out64) add_stat(out64, t);
         if (out32 && t) atomicAdd(out32, static_cast<int32_t>(t));
     }
