@@ -73,6 +73,10 @@ def _load():
         lib.orc_sw_run.argtypes = [c_i32, c_i32, c_i32, c_u64, c_u64, c_u32, c_u32, c_i32,
                                    u8p, i64p]
         lib.orc_sw_run.restype = None
+        lib.orc_digest_u8.argtypes = [c_i64, u8p]
+        lib.orc_digest_u8.restype = c_u64
+        lib.orc_digest_i32.argtypes = [c_i64, i32p]
+        lib.orc_digest_i32.restype = c_u64
         _lib = lib
     return _lib
 
@@ -151,6 +155,19 @@ def cluster_sizes(labels):
     mx = np.zeros(1, dtype=np.int64)
     n = _load().orc_cluster_sizes(N, _i32(lab), _i32(roots), _i32(sizes), _i64(mx))
     return roots[:n].copy(), sizes[:n].copy(), int(mx[0])
+
+
+def digest(a) -> int:
+    """Check-sum of an array: sum of lo64(Philox((i, a_i, 0xD16E57, 0), key 0)) mod 2^64.
+    uint8 arrays (states, bond bytes) and int32 arrays (labels) are accepted."""
+    a = np.asarray(a).reshape(-1)
+    if a.dtype == np.uint8:
+        a = np.ascontiguousarray(a)
+        return int(_load().orc_digest_u8(a.size, _u8(a)))
+    if a.dtype == np.int32:
+        a = np.ascontiguousarray(a)
+        return int(_load().orc_digest_i32(a.size, _i32(a)))
+    raise TypeError(f"digest of {a.dtype} arrays is not defined")
 
 
 def flip(W, H, q, labels, state, seed, t, sid=0) -> np.ndarray:

@@ -249,6 +249,33 @@ void orc_flip(int32_t W, int32_t H, int32_t q, const int32_t *labels, uint64_t s
     free(root_state);
 }
 
+/* --------------------------------------------------------------- digest -- */
+
+/* Check-sum of an array, defined in the header: one Philox block per element,
+ * keyed by the element's index and value, summed with 64-bit wrap-around. */
+static uint64_t digest_term(uint32_t i, uint32_t v)
+{
+    const uint32_t ctr[4] = {i, v, ORC_DIGEST_TAG, 0u};
+    const uint32_t key[2] = {0u, 0u};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return (uint64_t)out[0] | ((uint64_t)out[1] << 32);
+}
+
+uint64_t orc_digest_u8(int64_t N, const uint8_t *a)
+{
+    uint64_t d = 0;
+    for (int64_t i = 0; i < N; ++i) d += digest_term((uint32_t)i, a[i]);
+    return d;
+}
+
+uint64_t orc_digest_i32(int64_t N, const int32_t *a)
+{
+    uint64_t d = 0;
+    for (int64_t i = 0; i < N; ++i) d += digest_term((uint32_t)i, (uint32_t)a[i]);
+    return d;
+}
+
 /* ---------------------------------------------------------- observables -- */
 
 /* Number of satisfied bonds, i.e. -H/J of Eq. potts_hamiltonian. */

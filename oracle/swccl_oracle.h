@@ -88,6 +88,15 @@ void orc_sw_sweep(int32_t W, int32_t H, int32_t q, uint64_t T, uint64_t seed,
                   uint32_t sid, uint32_t t, uint8_t *state, uint8_t *bonds,
                   int32_t *labels, int64_t *rec);
 
+/* Order-independent digest of an array of N values a_i (a check-sum for
+ * comparing large arrays without copying them):
+ *   sum over i of lo64(Philox4x32-10(ctr = (i, a_i, ORC_DIGEST_TAG, 0), key = (0, 0)))
+ * modulo 2^64, where lo64 = word0 | word1 << 32.  Values are taken as uint32
+ * (int32 labels by their two's-complement bits). */
+enum { ORC_DIGEST_TAG = 0xD16E57 };
+uint64_t orc_digest_u8(int64_t N, const uint8_t *a);
+uint64_t orc_digest_i32(int64_t N, const int32_t *a);
+
 /* n sweeps t0..t0+n-1, one record per sweep into rec[n][ORC_REC_LEN]. */
 void orc_sw_run(int32_t W, int32_t H, int32_t q, uint64_t T, uint64_t seed,
                 uint32_t sid, uint32_t t0, int32_t n, uint8_t *state, int64_t *rec);
