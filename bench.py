@@ -44,6 +44,7 @@ def _args():
     ap.add_argument("--workload", default="potts16384")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ccl", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -199,6 +200,41 @@ def main() -> int:
                       "bytes_per_site": CCL_BYTES_PER_SITE, "achieved_gbs": round(gbs, 1),
                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
         del inp, ws, labels
+
+    # ---- batched sweeps of 256 mixed-size lattices vs one launch sequence each ----
+    if not args.no_batch:
+        specs = wl.batch_specs()
+        nsite = sum(sp["W"] * sp["H"] for sp in specs)
+        reps = max(5, args.steps // 2)
+        b = sw.SWBatch(specs)
+        b.sweep(2)
+        torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        b.sweep(reps)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        ms_b = c0.elapsed_time(c1) / reps
+        del b
+        lats = [sw.SWLattice(sp["W"], sp["H"], q=2, K=sp["K"], seed=sp["seed"], stream_id=sp["stream_id"])
+                for sp in specs]
+        for lat in lats:
+            lat.sweep(2)
+        torch.cuda.synchronize()
+        c0.record(stream)
+        for _ in range(reps):
+            for lat in lats:
+                lat.sweep(1)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        ms_p = c0.elapsed_time(c1) / reps
+        del lats
+        torch.cuda.empty_cache()
+        out["batched"] = {"workload": f"{len(specs)} Ising lattices, L in 32..1024, {nsite} sites",
+                          "ms_per_sweep": round(ms_b, 4), "spins_per_s": round(nsite / (ms_b * 1e-3), 1),
+                          "plain_ms_per_sweep": round(ms_p, 4),
+                          "plain_spins_per_s": round(nsite / (ms_p * 1e-3), 1),
+                          "speedup_vs_plain": round(ms_p / ms_b, 3)}
 
     # ---- CPU oracle on the host: one sweep of the same lattice ----
     if not args.no_cpu_baseline:

@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define SWCCL_ABI_VERSION 1
+#define SWCCL_ABI_VERSION 2
 
 typedef int32_t sw_status;
 enum {
@@ -78,8 +78,13 @@ enum {
 enum { SW_SPIN_ISING_I8 = 0, SW_SPIN_POTTS_U8 = 1 };
 
 /* sw_params.flags */
-enum { SW_F_KEEP_SPINS = 1u << 0 }; /* sw_init: do not draw initial spins; use the
-                                       caller's (restart from a saved state) */
+enum {
+    SW_F_KEEP_SPINS = 1u << 0, /* sw_init: do not draw initial spins; use the
+                                  caller's (restart from a saved state)       */
+    SW_F_SIZES = 1u << 1       /* every sweep also lists its clusters: roots
+                                  (ascending) and sizes into sw_buffers.roots /
+                                  .sizes, and the largest size (sw_obs)       */
+};
 
 /* Input kinds of ccl_label. */
 enum {
@@ -106,6 +111,11 @@ typedef struct sw_buffers {
     int32_t *labels;        /* N int32 or NULL: canonical labels of the last
                                sweep's bond configuration                   */
     uint8_t *bonds;         /* N bytes or NULL: packed bonds of the last sweep */
+    int32_t *roots;         /* N int32 with SW_F_SIZES (else ignored): the last
+                               sweep's canonical roots in ascending order, in
+                               the first n_clusters entries                 */
+    int32_t *sizes;         /* N int32 with SW_F_SIZES: sizes[k] is the size of
+                               the cluster rooted at roots[k]               */
     void *workspace;        /* sw_workspace_bytes() bytes, 256-byte aligned  */
     size_t workspace_bytes;
 } sw_buffers;
@@ -119,6 +129,17 @@ typedef struct sw_obs {
     int64_t counts[8];       /* sites in state k, k < min(q, 8)                 */
     int64_t n_active_bonds;  /* active bonds of the last sweep (-1: none yet)   */
     int64_t n_clusters;      /* clusters of the last sweep (-1: none yet)       */
+    int64_t max_cluster;     /* largest cluster of the last sweep (-1: none yet,
+                                or SW_F_SIZES not set)                          */
+    /* Order-independent check-sums of the arrays, for comparing runs without
+     * copying them: sum over i of lo64(Philox4x32-10(ctr = (i, a_i, 0xD16E57, 0),
+     * key = (0, 0))) mod 2^64 with lo64 = word0 | word1 << 32.  a_i is the state
+     * 0..q-1 of site i (Ising: +1 -> 1, -1 -> 0), the label bits as uint32, or
+     * the bond byte.  Labels / bonds digests are 0 when the buffer is absent or
+     * before the first sweep. */
+    uint64_t digest_spins;
+    uint64_t digest_labels;
+    uint64_t digest_bonds;
 } sw_obs;
 
 typedef struct sw_lattice sw_lattice;
@@ -133,11 +154,13 @@ const char *sw_last_error(void);
  * bond's 32-bit uniform must stay below (Sec. II.A activation rule). */
 uint64_t sw_threshold(double K);
 
-/* Workspace bytes needed by a lattice with these parameters (0 if invalid). */
+/* Workspace bytes needed by a lattice with these parameters, SW_F_SIZES
+ * included (0 if invalid). */
 size_t sw_workspace_bytes(const sw_params *p);
 
 /* Create a lattice handle over caller-owned buffers and, unless
  * SW_F_KEEP_SPINS is set, draw the initial spins (t = 0, Philox tag 0).
+ * SW_F_SIZES needs b->roots and b->sizes (else SW_ERR_ARG).
  * The handle keeps copies of p and b; the buffers must outlive it.
  * Returns SW_ERR_ARG / SW_ERR_SIZE / SW_ERR_WORKSPACE before enqueuing
  * anything. */
@@ -158,8 +181,9 @@ sw_status sw_sweep(sw_lattice *h, int32_t n_sweeps, void *stream);
 enum { SW_PHASE_TILE = 0, SW_PHASE_MERGE = 1, SW_PHASE_FLIP = 2 };
 sw_status sw_sweep_phase(sw_lattice *h, int32_t phase, void *stream);
 
-/* Measure the current spins and the last sweep's counters; waits for the
- * stream. */
+/* Measure the current spins (satisfied bonds, state counts, digests) and the
+ * last sweep's counters (active bonds, clusters, largest cluster); waits for
+ * the stream. */
 sw_status sw_observables(sw_lattice *h, sw_obs *out, void *stream);
 
 /* Checkpointing: the full state of a lattice is (spins, t); a restart is
@@ -169,6 +193,38 @@ sw_status sw_set_t(sw_lattice *h, uint64_t t);
 
 /* Free the host handle (device buffers stay with the caller). */
 sw_status sw_destroy(sw_lattice *h);
+
+/* ---- Batches: many independent lattices advanced together, one launch per
+ * phase for the whole batch (the SW update of Sec. II, steps 1-3, on each
+ * lattice).  Lattice j evolves exactly as a single lattice created with p[j]
+ * and swept as often would: same spins, bonds, labels and counters.  The
+ * lattices share one sweep counter t, starting at 0.  Small lattices occupy
+ * one tile each; large ones are tiled as single lattices are. */
+typedef struct swb_batch swb_batch;
+
+/* Workspace bytes of a batch of n >= 1 lattices (0 if a parameter set is
+ * invalid, or asks for SW_F_SIZES, which batches do not support). */
+size_t swb_workspace_bytes(const sw_params *p, int32_t n);
+
+/* Create a batch over n caller-owned lattices: p[j] and b[j] as for sw_init
+ * (b[j].workspace is ignored; b[j].roots and .sizes must be NULL); one
+ * 256-byte aligned workspace of swb_workspace_bytes() bytes serves the whole
+ * batch.  Draws the initial spins of every lattice without SW_F_KEEP_SPINS.
+ * The arrays p and b are copied.  Errors as for sw_init; SW_ERR_UNSUPPORTED
+ * for SW_F_SIZES. */
+sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int32_t n, void *workspace,
+                   size_t workspace_bytes, void *stream);
+
+/* Enqueue n_sweeps sweeps of every lattice (asynchronous). */
+sw_status swb_sweep(swb_batch *h, int32_t n_sweeps, void *stream);
+
+/* Observables of lattice j, 0 <= j < n, as sw_observables (max_cluster is
+ * always -1); waits for the stream. */
+sw_status swb_observables(swb_batch *h, int32_t j, sw_obs *out, void *stream);
+
+/* Sweeps done so far; free the host handle. */
+sw_status swb_get_t(const swb_batch *h, uint64_t *t);
+sw_status swb_destroy(swb_batch *h);
 
 /* Workspace bytes needed by ccl_label for this shape (0 if invalid). */
 size_t ccl_workspace_bytes(int32_t W, int32_t H, int32_t mode);

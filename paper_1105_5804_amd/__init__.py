@@ -22,6 +22,7 @@ from ._lib import (  # noqa: F401
 
 __all__ = [
     "SWLattice",
+    "SWBatch",
     "ccl_label",
     "ccl_workspace_bytes",
     "threshold",
@@ -73,17 +74,41 @@ def _workspace(torch, nbytes: int, device):
     return buf, p + ((-p) % 256)
 
 
+def _obs_dict(o, N: int, q: int, ising: bool) -> dict:
+    d = {
+        "t": int(o.t),
+        "threshold": int(o.threshold),
+        "n_sat": int(o.n_sat),
+        "magnet": int(o.magnet),
+        "counts": [int(c) for c in o.counts][: min(q, 8)],
+        "n_active_bonds": int(o.n_active_bonds),
+        "n_clusters": int(o.n_clusters),
+        "max_cluster": int(o.max_cluster),
+        "digest_spins": int(o.digest_spins),
+        "digest_labels": int(o.digest_labels),
+        "digest_bonds": int(o.digest_bonds),
+    }
+    if ising:
+        d["energy_per_site"] = -(2.0 * d["n_sat"] - 2.0 * N) / N
+        d["abs_m"] = abs(d["magnet"]) / N
+    else:
+        d["energy_per_site"] = -d["n_sat"] / N
+    return d
+
+
 class SWLattice:
     """One periodic W x H lattice advanced by Swendsen-Wang sweeps on the GPU.
 
     ``spins`` is an (H, W) int8 (Ising, +-1) or uint8 (Potts, 0..q-1) tensor.
     With ``keep_labels`` / ``keep_bonds`` the canonical labels / packed bonds of
-    the last sweep are kept in ``labels`` / ``bonds``.
+    the last sweep are kept in ``labels`` / ``bonds``; with ``sizes`` every sweep
+    also lists its clusters (``cluster_sizes()``) and their largest size.
     """
 
     def __init__(self, W: int, H: int, q: int = 2, K: float | None = None, seed: int = 0,
                  stream_id: int = 0, ising: bool | None = None, keep_labels: bool = False,
-                 keep_bonds: bool = False, spins=None, t: int = 0, device: str = "cuda"):
+                 keep_bonds: bool = False, sizes: bool = False, spins=None, t: int = 0,
+                 device: str = "cuda"):
         torch = _torch()
         L = _lib.lib()
         if ising is None:
@@ -94,7 +119,8 @@ class SWLattice:
         self.seed, self.stream_id, self.ising = int(seed), int(stream_id), bool(ising)
         self.device = torch.device(device)
         p = _lib.SwParams(self.W, self.H, self.q, _lib.SW_SPIN_ISING_I8 if ising else _lib.SW_SPIN_POTTS_U8,
-                          self.K, self.seed & (2**64 - 1), self.stream_id, 0)
+                          self.K, self.seed & (2**64 - 1), self.stream_id,
+                          _lib.SW_F_SIZES if sizes else 0)
         ws = L.sw_workspace_bytes(ctypes.byref(p))
         if ws == 0:
             _lib.check(_lib.SW_ERR_ARG if self.W >= 2 and self.H >= 2 else _lib.SW_ERR_SIZE, "sw_workspace_bytes")
@@ -103,16 +129,21 @@ class SWLattice:
             if spins.shape != (self.H, self.W) or spins.dtype != dt or spins.device.type != "cuda":
                 raise ValueError(f"spins must be a ({self.H}, {self.W}) {dt} GPU tensor")
             self.spins = spins.contiguous()
-            p.flags = _lib.SW_F_KEEP_SPINS
+            p.flags |= _lib.SW_F_KEEP_SPINS
         else:
             self.spins = torch.empty((self.H, self.W), dtype=dt, device=self.device)
         self.labels = torch.empty((self.H, self.W), dtype=torch.int32, device=self.device) if keep_labels else None
         self.bonds = torch.empty((self.H, self.W), dtype=torch.uint8, device=self.device) if keep_bonds else None
+        N = self.W * self.H
+        self.roots = torch.empty(N, dtype=torch.int32, device=self.device) if sizes else None
+        self.sizes = torch.empty(N, dtype=torch.int32, device=self.device) if sizes else None
         self._ws_buf, ws_ptr = _workspace(torch, ws, self.device)
         self._bufs = _lib.SwBuffers(
             self.spins.data_ptr(),
             self.labels.data_ptr() if self.labels is not None else None,
             self.bonds.data_ptr() if self.bonds is not None else None,
+            self.roots.data_ptr() if self.roots is not None else None,
+            self.sizes.data_ptr() if self.sizes is not None else None,
             ws_ptr,
             ws,
         )
@@ -152,22 +183,17 @@ class SWLattice:
         torch = _torch()
         o = _lib.SwObs()
         _lib.check(_lib.lib().sw_observables(self._h, ctypes.byref(o), _stream(torch, stream)), "sw_observables")
-        N = self.W * self.H
-        d = {
-            "t": int(o.t),
-            "threshold": int(o.threshold),
-            "n_sat": int(o.n_sat),
-            "magnet": int(o.magnet),
-            "counts": [int(c) for c in o.counts][: min(self.q, 8)],
-            "n_active_bonds": int(o.n_active_bonds),
-            "n_clusters": int(o.n_clusters),
-        }
-        if self.ising:
-            d["energy_per_site"] = -(2.0 * d["n_sat"] - 2.0 * N) / N
-            d["abs_m"] = abs(d["magnet"]) / N
-        else:
-            d["energy_per_site"] = -d["n_sat"] / N
-        return d
+        return _obs_dict(o, self.W * self.H, self.q, self.ising)
+
+    def cluster_sizes(self, stream=None):
+        """(roots ascending, sizes) of the last sweep's clusters (needs ``sizes=True``;
+        waits for the stream)."""
+        if self.roots is None:
+            raise ValueError("lattice was created without sizes=True")
+        n = self.observables(stream)["n_clusters"]
+        if n < 0:
+            raise ValueError("no sweep yet")
+        return self.roots[:n], self.sizes[:n]
 
     def state(self):
         """(spins copy, t): everything needed to resume bit-exactly."""
@@ -176,6 +202,85 @@ class SWLattice:
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.lib().sw_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SWBatch:
+    """Many independent lattices advanced together, one launch per sweep phase.
+
+    ``specs`` is a sequence of dicts with keys W, H and optionally q, K, seed,
+    stream_id, ising (defaults as in ``SWLattice``).  Lattice j evolves exactly
+    as ``SWLattice(**specs[j])`` would.  ``spins[j]`` (and ``labels[j]`` /
+    ``bonds[j]`` with ``keep_labels`` / ``keep_bonds``) are its tensors.
+    """
+
+    def __init__(self, specs, keep_labels: bool = False, keep_bonds: bool = False, device: str = "cuda"):
+        torch = _torch()
+        L = _lib.lib()
+        self.device = torch.device(device)
+        n = len(specs)
+        if n < 1:
+            raise ValueError("a batch needs at least one lattice")
+        P = (_lib.SwParams * n)()
+        B = (_lib.SwBuffers * n)()
+        self.specs, self.spins, self.labels, self.bonds = [], [], [], []
+        for j, sp in enumerate(specs):
+            W, H = int(sp["W"]), int(sp["H"])
+            q = int(sp.get("q", 2))
+            ising = bool(sp.get("ising", q == 2))
+            K = sp.get("K")
+            if K is None:
+                K = ising_K(BETA_C_ISING) if q == 2 else math.log1p(math.sqrt(q))
+            seed, sid = int(sp.get("seed", 0)), int(sp.get("stream_id", 0))
+            self.specs.append(dict(W=W, H=H, q=q, K=float(K), seed=seed, stream_id=sid, ising=ising))
+            P[j] = _lib.SwParams(W, H, q, _lib.SW_SPIN_ISING_I8 if ising else _lib.SW_SPIN_POTTS_U8, float(K),
+                                 seed & (2**64 - 1), sid, 0)
+            dt = torch.int8 if ising else torch.uint8
+            sp_t = torch.empty((H, W), dtype=dt, device=self.device)
+            lab = torch.empty((H, W), dtype=torch.int32, device=self.device) if keep_labels else None
+            bnd = torch.empty((H, W), dtype=torch.uint8, device=self.device) if keep_bonds else None
+            self.spins.append(sp_t)
+            self.labels.append(lab)
+            self.bonds.append(bnd)
+            B[j] = _lib.SwBuffers(spins=sp_t.data_ptr(), labels=lab.data_ptr() if lab is not None else None,
+                                  bonds=bnd.data_ptr() if bnd is not None else None)
+        ws = L.swb_workspace_bytes(P, n)
+        if ws == 0:
+            _lib.check(_lib.SW_ERR_ARG, "swb_workspace_bytes")
+        self._ws_buf, ws_ptr = _workspace(torch, ws, self.device)
+        self._P, self._B = P, B
+        self._h = ctypes.c_void_p()
+        _lib.check(L.swb_init(ctypes.byref(self._h), P, B, n, ws_ptr, ws, _stream(torch)), "swb_init")
+        self.n = n
+
+    @property
+    def t(self) -> int:
+        v = ctypes.c_uint64()
+        _lib.check(_lib.lib().swb_get_t(self._h, ctypes.byref(v)), "swb_get_t")
+        return int(v.value)
+
+    def sweep(self, n: int = 1, stream=None) -> None:
+        """Enqueue n sweeps of every lattice; does not wait."""
+        torch = _torch()
+        _lib.check(_lib.lib().swb_sweep(self._h, int(n), _stream(torch, stream)), "swb_sweep")
+
+    def observables(self, j: int, stream=None) -> dict:
+        """Counters of lattice j (waits for the stream)."""
+        torch = _torch()
+        o = _lib.SwObs()
+        _lib.check(_lib.lib().swb_observables(self._h, int(j), ctypes.byref(o), _stream(torch, stream)),
+                   "swb_observables")
+        return _obs_dict(o, self.specs[j]["W"] * self.specs[j]["H"], self.specs[j]["q"], self.specs[j]["ising"])
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().swb_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

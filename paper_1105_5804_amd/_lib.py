@@ -7,10 +7,12 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libswccl.so")
 
+ABI_VERSION = 2  # the SWCCL_ABI_VERSION these declarations follow
+
 # status codes
 SW_OK, SW_ERR_ARG, SW_ERR_SIZE, SW_ERR_WORKSPACE, SW_ERR_DEVICE, SW_ERR_STATE, SW_ERR_UNSUPPORTED = range(7)
 SW_SPIN_ISING_I8, SW_SPIN_POTTS_U8 = 0, 1
-SW_F_KEEP_SPINS = 1
+SW_F_KEEP_SPINS, SW_F_SIZES = 1, 2
 CCL_BONDS_PERIODIC, CCL_BONDS_OPEN, CCL_SITES_OPEN = 0, 1, 2
 SW_PHASE_TILE, SW_PHASE_MERGE, SW_PHASE_FLIP = 0, 1, 2
 
@@ -33,6 +35,8 @@ class SwBuffers(ctypes.Structure):
         ("spins", ctypes.c_void_p),
         ("labels", ctypes.c_void_p),
         ("bonds", ctypes.c_void_p),
+        ("roots", ctypes.c_void_p),
+        ("sizes", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
     ]
@@ -47,6 +51,10 @@ class SwObs(ctypes.Structure):
         ("counts", ctypes.c_int64 * 8),
         ("n_active_bonds", ctypes.c_int64),
         ("n_clusters", ctypes.c_int64),
+        ("max_cluster", ctypes.c_int64),
+        ("digest_spins", ctypes.c_uint64),
+        ("digest_labels", ctypes.c_uint64),
+        ("digest_bonds", ctypes.c_uint64),
     ]
 
 
@@ -71,6 +79,14 @@ SIGNATURES = {
     "sw_get_t": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "sw_set_t": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64]),
     "sw_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "swb_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SwParams), ctypes.c_int32]),
+    "swb_init": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SwParams),
+                                  ctypes.POINTER(SwBuffers), ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p]),
+    "swb_sweep": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "swb_observables": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(SwObs), ctypes.c_void_p]),
+    "swb_get_t": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "swb_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "ccl_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "ccl_label": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -91,6 +107,8 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        if L.swccl_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI {L.swccl_abi_version()}, expected {ABI_VERSION}: rebuild it")
         _lib = L
     return _lib
 

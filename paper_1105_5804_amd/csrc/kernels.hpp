@@ -54,10 +54,32 @@ enum : uint32_t { TAG_INIT = 0, TAG_BOND = 1, TAG_FLIP = 2 };
 enum Mode : int { M_SW = 0, M_BONDS_PERIODIC = 1, M_BONDS_OPEN = 2, M_SITES = 3 };
 
 // Observable counters (unsigned 64-bit, two's complement for signed values).
-enum { ST_ACTIVE = 0, ST_NCLUST = 1, ST_NSAT = 2, ST_MAGNET = 3, ST_COUNTS = 4, ST_LEN = 16 };
+enum { ST_ACTIVE = 0, ST_NCLUST = 1, ST_NSAT = 2, ST_MAGNET = 3, ST_COUNTS = 4, ST_DIGEST = 12, ST_LEN = 16 };
 
 struct Grid {
     int W, H, ntx, nty, ntiles;
+};
+
+// One lattice of a batched launch (many independent lattices swept by one
+// launch per phase): its shape, buffers and random-number parameters, and the
+// first of its tiles in the batch's tile arrays.
+struct LatticeDesc {
+    Grid g;
+    int32_t tile0;
+    uint8_t *spins;
+    uint8_t *bonds;    // packed bonds of the sweep, or nullptr
+    int32_t *labels;   // canonical labels, or nullptr
+    uint32_t tm1, tany, k0, k1, sid, q;
+    int32_t ising;
+};
+
+// How a batched launch finds the lattice of a tile.  Tile-indexed arrays
+// (codes, ids, edges, ...) are concatenated over the batch and indexed by the
+// batch tile; geometry uses the tile's index inside its lattice.
+struct Batch {
+    const LatticeDesc *lat;
+    const int32_t *lat_of_tile;  // batch tile -> lattice
+    int32_t tile_base, ntiles;   // this launch covers tiles [tile_base, tile_base + ntiles)
 };
 
 // ---------------------------------------------------------------- helpers --
@@ -213,6 +235,22 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
     return v;
 }
 
+// Index of the calling wave in its workgroup, as a wave-uniform (scalar)
+// value: everything derived from it (rows, row pointers, loop bounds) then
+// stays in scalar registers and branches on it need no exec masking.
+__device__ __forceinline__ int wave_id()
+{
+    return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+}
+
+// Maximum over the wave (valid in lane 0).
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_down(v, off));
+    return v;
+}
+
 __device__ __forceinline__ void add_stat(unsigned long long *p, unsigned long long v)
 {
     if (v) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -274,6 +312,7 @@ struct TileArgs {
     uint32_t tm1;             // M_SW: a bond is active iff its word r <= tm1 ...
     uint32_t tany;            // ... and tany (threshold T > 0); tm1 = T - 1
     uint32_t k0, k1, t, sid;
+    Batch b;                  // batched launches only
 };
 
 // A tile row as two wave ballots: lane L owns sites 2L and 2L+1, bit L of `e`
@@ -365,7 +404,7 @@ __device__ __forceinline__ uint32_t from_next_lane(uint32_t x)
     return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x130, 0xF, 0xF, false));
 }
 
-template <int MODE, bool EVENW>
+template <int MODE, bool EVENW, bool BATCH = false>
 __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
 {
     constexpr bool NEED_DOWN = MODE == M_SW || MODE == M_SITES;  // bonds from two rows
@@ -379,12 +418,27 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     __shared__ int nb_s;
     __shared__ int act_w[NWAVE];
 
+    int tile, lt;  // tile in the arrays, tile inside its lattice
+    if constexpr (BATCH) {
+        tile = a.b.tile_base + xcd_remap(blockIdx.x, a.b.ntiles);
+        const LatticeDesc &L = a.b.lat[a.b.lat_of_tile[tile]];
+        a.g = L.g;
+        a.in = L.spins;
+        a.bonds_out = L.bonds;
+        a.tm1 = L.tm1;
+        a.tany = L.tany;
+        a.k0 = L.k0;
+        a.k1 = L.k1;
+        a.sid = L.sid;
+        lt = tile - L.tile0;
+    } else {
+        tile = lt = xcd_remap(blockIdx.x, a.g.ntiles);
+    }
     const int W = a.g.W, H = a.g.H;
-    const int tile = xcd_remap(blockIdx.x, a.g.ntiles);
-    const int tx = tile % a.g.ntx, ty = tile / a.g.ntx;
+    const int tx = lt % a.g.ntx, ty = lt / a.g.ntx;
     const int gx0 = tx * TW, gy0 = ty * TH;
     const int tw = min(TW, W - gx0), th = min(TH, H - gy0);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const int lx0 = 2 * lane, lx1 = lx0 + 1;
     const bool v0 = lx0 < tw, v1 = lx1 < tw;
     const int hx = (gx0 + tw == W) ? 0 : gx0 + tw;  // column right of the tile
@@ -447,7 +501,11 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
             const uint32_t sr1 = (lx1 == tw - 1) ? hl[r] : nxt;
             const int64_t i0 = static_cast<int64_t>(gy) * W + gx0 + lx0;
             uint32_t r0R, r0D, r1R, r1D;
-            const U4 blk = philox4x32_10(static_cast<uint32_t>(i0 >> 1), a.t, TAG_BOND, a.sid, a.k0, a.k1);
+            // the key schedule is recomputed per row (scalar adds) rather than
+            // held in 20 scalar registers across the unrolled row loop
+            uint32_t k0 = a.k0, k1 = a.k1;
+            asm volatile("" : "+s"(k0), "+s"(k1));
+            const U4 blk = philox4x32_10(static_cast<uint32_t>(i0 >> 1), a.t, TAG_BOND, a.sid, k0, k1);
             if (EVENW || (i0 & 1) == 0) {  // the pair (i0, i0+1) shares one block
                 r0R = blk.v0;
                 r0D = blk.v1;
@@ -457,7 +515,7 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
                 r0R = blk.v2;
                 r0D = blk.v3;
                 const U4 b2 = philox4x32_10(static_cast<uint32_t>((i0 + 1) >> 1), a.t, TAG_BOND, a.sid,
-                                            a.k0, a.k1);
+                                            k0, k1);
                 r1R = b2.v0;
                 r1D = b2.v1;
             }
@@ -506,14 +564,14 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         // last row's down bonds.  They are merged by k_merge.
         if ((mR0 & L0) | (mR1 & L1)) xr |= 1ull << ly;
         const EO R = EO{mR0 & ~L0, mR1 & ~L1};
-        EO D = EO{mD0, mD1};
-        if (ly == th - 1) {
-            if (lane == 0) xd_s = D;
-            D = EO{0ull, 0ull};
-        }
+        // the last tile row's down bonds cross the tile; selected on a uniform
+        // condition so the masks stay in scalar registers
+        const bool last = ly == th - 1;
+        const EO D = last ? EO{0ull, 0ull} : EO{mD0, mD1};
         if (lane == 0) {
+            if (last) xd_s = EO{mD0, mD1};
             Rm[ly] = R;
-            Om[ly] = EO{O0, O1};
+            if (MODE == M_SITES) Om[ly] = EO{O0, O1};
         }
         const int base = ly * TW;
         int rs0 = lx0;
@@ -551,12 +609,25 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     }
     __syncthreads();
 
+    // Occupancy of a tile slot: images keep per-row masks, every site of a
+    // bond input is a lattice site.
+    auto occupied = [&](int slot) {
+        if constexpr (MODE == M_SITES) {
+            const EO O = Om[slot >> 7];
+            const int x = slot & (TW - 1);
+            return (((x & 1) ? O.o : O.e) >> (x >> 1) & 1ull) != 0;
+        } else {
+            return true;
+        }
+    };
+
     // ---- C: roots of the occupied run starts (read-only), and claims of the
     // clusters that touch the tile border (one thread per border position).
     int nrs = 0;
     for (int r = 0; r < nr; ++r) {
         const int ly = ly0 + r;
-        const EO R = uniform_eo(Rm[ly]), O = uniform_eo(Om[ly]);
+        const EO R = uniform_eo(Rm[ly]);
+        const EO O = MODE == M_SITES ? uniform_eo(Om[ly]) : valid;
         eo_append(mylist, nrs, eo_andnot(O, eo_shift1(R)), lane, ly * TW);
     }
     wave_lds_fence();
@@ -568,10 +639,7 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     }
     for (int t = threadIdx.x; t < EDGE; t += NT) {
         const int slot = border_slot(t, tw, th);
-        if (slot < 0) continue;
-        const EO O = Om[slot >> 7];
-        const int s = slot & (TW - 1);
-        if (!(((s & 1) ? O.o : O.e) >> (s >> 1) & 1ull)) continue;
+        if (slot < 0 || !occupied(slot)) continue;
         const int root = lroot(P, slot);
         int expect = root;
         if (__hip_atomic_compare_exchange_strong(&P[root], &expect, CLAIMING, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
@@ -608,7 +676,7 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     uint32_t *codes32 = reinterpret_cast<uint32_t *>(a.codes + static_cast<int64_t>(tile) * TSITES);
     for (int r = 0; r < nr; ++r) {
         const int ly = ly0 + r;
-        const EO O = Om[ly];
+        const EO O = MODE == M_SITES ? Om[ly] : valid;
         const int base = ly * TW;
         const int2 pp = *reinterpret_cast<const int2 *>(&P[base + lx0]);
         // a run start holds its code; any other site points at a run start
@@ -622,13 +690,9 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     for (int t = threadIdx.x; t < EDGE; t += NT) {
         const int slot = border_slot(t, tw, th);
         uint16_t eid = ID_NONE;
-        if (slot >= 0) {
-            const EO O = Om[slot >> 7];
-            const int s = slot & (TW - 1);
-            if (((s & 1) ? O.o : O.e) >> (s >> 1) & 1ull) {
-                const int p = P[slot];
-                eid = static_cast<uint16_t>(-(p < 0 ? p : P[p]) - 1);
-            }
+        if (slot >= 0 && occupied(slot)) {
+            const int p = P[slot];
+            eid = static_cast<uint16_t>(-(p < 0 ? p : P[p]) - 1);
         }
         edg[t] = eid;
     }
@@ -656,6 +720,7 @@ struct MergeArgs {
     const uint64_t *xbits;
     const int32_t *gkey;
     int32_t *gparent;
+    Batch b;                  // batched launches only
 };
 
 constexpr int MERGE_TILES = NWAVE;  // tiles per workgroup: one wave each
@@ -663,17 +728,28 @@ constexpr int MERGE_TILES = NWAVE;  // tiles per workgroup: one wave each
 // A wave per tile: its lanes walk the bonds crossing the tile's right edge
 // (TH rows) and bottom edge (TW columns).  Consecutive crossing bonds that
 // join the same pair of boundary ids are skipped.
+template <bool BATCH = false>
 __global__ __launch_bounds__(NT) void k_merge(MergeArgs a)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tile = blockIdx.x * MERGE_TILES + wave;
-    if (tile >= a.g.ntiles) return;
-    const int tx = tile % a.g.ntx, ty = tile / a.g.ntx;
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    int tile = blockIdx.x * MERGE_TILES + wave;
+    int tile0 = 0;  // first tile of the lattice in the arrays
+    if constexpr (BATCH) {
+        if (tile >= a.b.ntiles) return;
+        tile += a.b.tile_base;
+        const LatticeDesc &L = a.b.lat[a.b.lat_of_tile[tile]];
+        a.g = L.g;
+        tile0 = L.tile0;
+    } else {
+        if (tile >= a.g.ntiles) return;
+    }
+    const int lt = tile - tile0;
+    const int tx = lt % a.g.ntx, ty = lt / a.g.ntx;
     const int tw = min(TW, a.g.W - tx * TW), th = min(TH, a.g.H - ty * TH);
     const uint16_t *e = a.edges + static_cast<int64_t>(tile) * EDGE;
     const uint64_t *xb = a.xbits + static_cast<int64_t>(tile) * XW;
-    const int ntR = ty * a.g.ntx + (tx + 1 == a.g.ntx ? 0 : tx + 1);
-    const int ntD = (ty + 1 == a.g.nty ? 0 : ty + 1) * a.g.ntx + tx;
+    const int ntR = tile0 + ty * a.g.ntx + (tx + 1 == a.g.ntx ? 0 : tx + 1);
+    const int ntD = tile0 + (ty + 1 == a.g.nty ? 0 : ty + 1) * a.g.ntx + tx;
     const uint16_t *eR = a.edges + static_cast<int64_t>(ntR) * EDGE;
     const uint16_t *eD = a.edges + static_cast<int64_t>(ntD) * EDGE;
     const uint64_t xr = xb[0];
@@ -714,6 +790,7 @@ struct FlatArgs {
     int32_t *rl_size;         // size, or -(root id + 1) for boundary clusters
     uint32_t q, k0, k1, t, sid;
     int ising;
+    Batch b;                  // batched launches only
 };
 
 // New state of the cluster whose canonical root is R (Sec. II.D: one uniform
@@ -724,7 +801,7 @@ __device__ __forceinline__ uint8_t flip_state(uint32_t R, const FlatArgs &a)
     return static_cast<uint8_t>(draw_state(pick(b, R & 3u), a.q));
 }
 
-template <int MODE, bool SIZES>
+template <int MODE, bool SIZES, bool BATCH = false>
 __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
 {
     constexpr int NCODE = CAP + TSITES;
@@ -737,12 +814,27 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
     __shared__ int32_t Cb[SIZES ? CAP : 1];            // per-tile part of boundary clusters
     __shared__ int32_t rowc[TH + 1];
 
+    int tile, lt;  // tile in the arrays, tile inside its lattice
+    if constexpr (BATCH) {
+        tile = a.b.tile_base + xcd_remap(blockIdx.x, a.b.ntiles);
+        const LatticeDesc &L = a.b.lat[a.b.lat_of_tile[tile]];
+        a.g = L.g;
+        a.spins = L.spins;
+        a.labels = L.labels;
+        a.q = L.q;
+        a.k0 = L.k0;
+        a.k1 = L.k1;
+        a.sid = L.sid;
+        a.ising = L.ising;
+        lt = tile - L.tile0;
+    } else {
+        tile = lt = xcd_remap(blockIdx.x, a.g.ntiles);
+    }
     const int W = a.g.W;
-    const int tile = xcd_remap(blockIdx.x, a.g.ntiles);
-    const int tx = tile % a.g.ntx, ty = tile / a.g.ntx;
+    const int tx = lt % a.g.ntx, ty = lt / a.g.ntx;
     const int gx0 = tx * TW, gy0 = ty * TH;
     const int tw = min(TW, W - gx0), th = min(TH, a.g.H - gy0);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const int lx0 = 2 * lane;
     const int ly0 = wave * RPW;
     const int nr = max(0, min(RPW, th - ly0));
@@ -915,7 +1007,7 @@ __global__ __launch_bounds__(NT) void k_reduce_tiles(const int32_t *v, int n, un
     unsigned long long acc = 0;
     for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) acc += static_cast<unsigned>(v[i]);
     acc = wave_sum(acc);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     if (lane == 0) red[wave] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -974,6 +1066,7 @@ struct EmitArgs {
     const int32_t *gsize;
     int32_t *roots;
     int32_t *sizes;
+    int32_t *max_size;        // largest size (atomic max), or nullptr
 };
 
 // Write each tile's roots (ascending site index within a row) at their global
@@ -996,14 +1089,57 @@ __global__ __launch_bounds__(NT) void k_emit(EmitArgs a)
     }
     __syncthreads();
     const int n = rstart[th];
+    int mx = 0;
     for (int j = threadIdx.x; j < n; j += NT) {
         const int64_t o = static_cast<int64_t>(tile) * TSITES + j;
         const int slot = a.rl_slot[o];
         const int ly = slot >> 7;
         const int pos = a.row_off[static_cast<int64_t>(gy0 + ly) * a.g.ntx + tx] + (j - rstart[ly]);
         const int sz = a.rl_size[o];
+        const int size = sz >= 0 ? sz : a.gsize[-sz - 1];
         a.roots[pos] = (gy0 + ly) * a.g.W + gx0 + (slot & (TW - 1));
-        a.sizes[pos] = sz >= 0 ? sz : a.gsize[-sz - 1];
+        a.sizes[pos] = size;
+        mx = max(mx, size);
+    }
+    if (a.max_size) {
+        mx = wave_max(mx);
+        if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(a.max_size, mx);
+    }
+}
+
+// --------------------------------------------------------------- digest ---
+
+// Check-sum of an array: the sum over i of the low 64 bits of the Philox block
+// at counter (i, a_i, DIGEST_TAG, 0) under the zero key, modulo 2^64.  The sum
+// is order-independent, so the grid-stride partial sums may add in any order.
+constexpr uint32_t DIGEST_TAG = 0xD16E57u;
+enum { DIG_U8 = 0, DIG_ISING_I8 = 1, DIG_I32 = 2 };  // a_i: byte, Ising state (+1 -> 1), int32 bits
+
+template <int KIND>
+__global__ __launch_bounds__(NT) void k_digest(const void *v, int64_t n, unsigned long long *out)
+{
+    __shared__ unsigned long long red[NWAVE];
+    unsigned long long acc = 0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * NT) {
+        uint32_t x;
+        if constexpr (KIND == DIG_I32) {
+            x = static_cast<const uint32_t *>(v)[i];
+        } else {
+            const uint32_t b = static_cast<const uint8_t *>(v)[i];
+            x = KIND == DIG_ISING_I8 ? (b == 1u ? 1u : 0u) : b;
+        }
+        const U4 r = philox4x32_10(static_cast<uint32_t>(i), x, DIGEST_TAG, 0u, 0u, 0u);
+        acc += static_cast<unsigned long long>(r.v0) | (static_cast<unsigned long long>(r.v1) << 32);
+    }
+    acc = wave_sum(acc);
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    if (lane == 0) red[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < NWAVE; ++w) t += red[w];
+        add_stat(out, t);
     }
 }
 
@@ -1047,7 +1183,7 @@ __global__ __launch_bounds__(NT) void k_observe(const uint8_t *s, int W, int H, 
             cnt[k + 4] += (h47 >> (16 * k)) & 0xFFFFull;
         }
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     unsigned long long vals[10];
     vals[0] = nsat;
     vals[1] = 0;

@@ -16,6 +16,15 @@ struct U4 {
     uint32_t v0, v1, v2, v3;
 };
 
+// a ^ b ^ k in one gfx950 three-input bit operation (truth table 0x96 is the
+// parity of the three inputs); k is wave-uniform.
+__device__ __forceinline__ uint32_t xor3_vvs(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
 __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                             uint32_t k0, uint32_t k1)
 {
@@ -23,8 +32,14 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     for (int r = 0; r < 10; ++r) {
         const uint64_t a = static_cast<uint64_t>(0xD2511F53u) * c0;  // one v_mad_u64_u32
         const uint64_t b = static_cast<uint64_t>(0xCD9E8D57u) * c2;
-        const uint32_t n0 = static_cast<uint32_t>(b >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = static_cast<uint32_t>(a >> 32) ^ c3 ^ k1;
+        uint32_t n0, n2;
+        if (r == 0) {  // c1..c3 may still be wave-uniform: leave the first round to the compiler
+            n0 = static_cast<uint32_t>(b >> 32) ^ c1 ^ k0;
+            n2 = static_cast<uint32_t>(a >> 32) ^ c3 ^ k1;
+        } else {
+            n0 = xor3_vvs(static_cast<uint32_t>(b >> 32), c1, k0);
+            n2 = xor3_vvs(static_cast<uint32_t>(a >> 32), c3, k1);
+        }
         c1 = static_cast<uint32_t>(b);
         c3 = static_cast<uint32_t>(a);
         c0 = n0;

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/swccl.h"
 #include "kernels.hpp"
@@ -30,6 +31,7 @@ struct Layout {
     int64_t nrow;  // H * ntx: entries of the per-(row, tile column) root counts
     size_t codes, gkey, gparent, gsize, edges, xbits, nb, tile_act, tile_ncl, stats;
     size_t row_count, row_off, scan_tmp, rl_slot, rl_size;
+    size_t lat_desc, lat_of_tile;  // batches only
     size_t total;
 };
 
@@ -53,17 +55,9 @@ bool valid_shape(int32_t W, int32_t H, int32_t min_side)
     return static_cast<int64_t>(W) * H < (static_cast<int64_t>(1) << 31);
 }
 
-Layout make_layout(int32_t W, int32_t H, bool sizes)
+// Per-tile arrays shared by single lattices and batches; returns the bytes used.
+size_t carve_tiles(Layout &L, size_t nt)
 {
-    Layout L{};
-    L.g.W = W;
-    L.g.H = H;
-    L.g.ntx = static_cast<int>(cdiv(W, TW));
-    L.g.nty = static_cast<int>(cdiv(H, TH));
-    L.g.ntiles = L.g.ntx * L.g.nty;
-    L.sizes = sizes;
-    L.nrow = static_cast<int64_t>(H) * L.g.ntx;
-    const size_t nt = static_cast<size_t>(L.g.ntiles);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -79,9 +73,30 @@ Layout make_layout(int32_t W, int32_t H, bool sizes)
     L.tile_act = take(nt * sizeof(int32_t));
     L.tile_ncl = take(nt * sizeof(int32_t));
     L.stats = take(ST_LEN * sizeof(unsigned long long));
+    return off;
+}
+
+Layout make_layout(int32_t W, int32_t H, bool sizes)
+{
+    Layout L{};
+    L.g.W = W;
+    L.g.H = H;
+    L.g.ntx = static_cast<int>(cdiv(W, TW));
+    L.g.nty = static_cast<int>(cdiv(H, TH));
+    L.g.ntiles = L.g.ntx * L.g.nty;
+    L.sizes = sizes;
+    L.nrow = static_cast<int64_t>(H) * L.g.ntx;
+    size_t off = carve_tiles(L, static_cast<size_t>(L.g.ntiles));
+    const size_t nt = static_cast<size_t>(L.g.ntiles);
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align_up(bytes);
+        return at;
+    };
     if (sizes) {
         L.gsize = take(nt * CAP * sizeof(int32_t));
-        L.row_count = take(static_cast<size_t>(L.nrow + 1) * sizeof(int32_t));
+        // per-(row, tile column) root counts, their total, then the largest size
+        L.row_count = take(static_cast<size_t>(L.nrow + 2) * sizeof(int32_t));
         L.row_off = take(static_cast<size_t>(L.nrow + 1) * sizeof(int32_t));
         L.scan_tmp = take(scan_tmp_bytes(L.nrow + 1));
         L.rl_slot = take(nt * TSITES * sizeof(int32_t));
@@ -90,6 +105,22 @@ Layout make_layout(int32_t W, int32_t H, bool sizes)
     L.total = off;
     return L;
 }
+
+// Workspace of a batch of lattices: the tile arrays over all their tiles,
+// then the lattice descriptors and the tile -> lattice table.
+Layout make_batch_layout(int64_t ntiles, int32_t nlat)
+{
+    Layout L{};
+    L.g.ntiles = static_cast<int>(ntiles);
+    size_t off = carve_tiles(L, static_cast<size_t>(ntiles));
+    L.lat_desc = off;
+    off += align_up(static_cast<size_t>(nlat) * sizeof(LatticeDesc));
+    L.lat_of_tile = off;
+    off += align_up(static_cast<size_t>(ntiles) * sizeof(int32_t));
+    L.total = off;
+    return L;
+}
+
 
 template <typename T>
 T *at(void *ws, size_t off)
@@ -180,6 +211,25 @@ FlatArgs flat_args(const Layout &L, void *ws)
     return f;
 }
 
+// Roots in ascending order and their sizes from a flatten pass with sizes:
+// scan the per-(row, tile column) root counts, then place each tile's roots.
+void emit_sizes(const Layout &L, void *ws, const FlatArgs &fa, int32_t *roots, int32_t *sizes, int32_t *max_size,
+                hipStream_t s)
+{
+    int32_t *row_off = at<int32_t>(ws, L.row_off);
+    scan_i32(fa.row_count, row_off, L.nrow + 1, at<char>(ws, L.scan_tmp), s);
+    EmitArgs ea{};
+    ea.g = L.g;
+    ea.row_off = row_off;
+    ea.rl_slot = fa.rl_slot;
+    ea.rl_size = fa.rl_size;
+    ea.gsize = fa.gsize;
+    ea.roots = roots;
+    ea.sizes = sizes;
+    ea.max_size = max_size;
+    hipLaunchKernelGGL(k_emit, dim3(static_cast<unsigned>(L.g.ntiles)), dim3(NT), 0, s, ea);
+}
+
 uint64_t threshold_of(double K)
 {
     if (!(K > 0.0)) return 0;
@@ -232,14 +282,14 @@ static sw_status check_params(const sw_params *p)
     if (p->spin_kind != SW_SPIN_ISING_I8 && p->spin_kind != SW_SPIN_POTTS_U8) return SW_ERR_ARG;
     if (p->spin_kind == SW_SPIN_ISING_I8 && p->q != 2) return SW_ERR_ARG;
     if (std::isnan(p->K)) return SW_ERR_ARG;
-    if (p->flags & ~static_cast<uint32_t>(SW_F_KEEP_SPINS)) return SW_ERR_ARG;
+    if (p->flags & ~static_cast<uint32_t>(SW_F_KEEP_SPINS | SW_F_SIZES)) return SW_ERR_ARG;
     return SW_OK;
 }
 
 size_t sw_workspace_bytes(const sw_params *p)
 {
     if (check_params(p) != SW_OK) return 0;
-    return make_layout(p->W, p->H, false).total;
+    return make_layout(p->W, p->H, (p->flags & SW_F_SIZES) != 0).total;
 }
 
 sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, void *stream)
@@ -248,7 +298,9 @@ sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, voi
     const sw_status ps = check_params(p);
     if (ps != SW_OK) return ps;
     if (!b->spins) return SW_ERR_ARG;
-    const Layout L = make_layout(p->W, p->H, false);
+    const bool sizes = (p->flags & SW_F_SIZES) != 0;
+    if (sizes && (!b->roots || !b->sizes)) return SW_ERR_ARG;
+    const Layout L = make_layout(p->W, p->H, sizes);
     if (!b->workspace || b->workspace_bytes < L.total) return SW_ERR_WORKSPACE;
     if (reinterpret_cast<uintptr_t>(b->workspace) % ALIGN) return SW_ERR_WORKSPACE;
     sw_lattice *h = new (std::nothrow) sw_lattice();
@@ -311,7 +363,13 @@ static sw_status launch_phase(sw_lattice *h, int32_t phase, hipStream_t s)
     fa.t = t;
     fa.sid = h->p.stream_id;
     fa.ising = h->p.spin_kind == SW_SPIN_ISING_I8 ? 1 : 0;
-    hipLaunchKernelGGL((k_flatten<M_SW, false>), grid, block, 0, s, fa);
+    if (!L.sizes) {
+        hipLaunchKernelGGL((k_flatten<M_SW, false>), grid, block, 0, s, fa);
+        return launch_status("k_flatten");
+    }
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, fa.row_count + L.nrow, 2);
+    hipLaunchKernelGGL((k_flatten<M_SW, true>), grid, block, 0, s, fa);
+    emit_sizes(L, ws, fa, h->b.roots, h->b.sizes, fa.row_count + L.nrow + 1, s);
     return launch_status("k_flatten");
 }
 
@@ -349,42 +407,70 @@ sw_status sw_sweep(sw_lattice *h, int32_t n_sweeps, void *stream)
     return SW_OK;
 }
 
-sw_status sw_observables(sw_lattice *h, sw_obs *out, void *stream)
+// Observables of one lattice (spins, digests, and the last sweep's per-tile
+// counters tile_act / tile_ncl of its ntiles tiles); waits for the stream.
+static sw_status measure(const sw_params &p, const sw_buffers &b, bool swept, const int32_t *tile_act,
+                         const int32_t *tile_ncl, int ntiles, unsigned long long *obs, const int32_t *max_size_dev,
+                         uint64_t T, uint64_t t, sw_obs *out, hipStream_t s)
 {
-    if (!h || !out) return SW_ERR_ARG;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout &L = h->L;
-    void *ws = h->b.workspace;
-    unsigned long long *obs = at<unsigned long long>(ws, L.stats);
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, obs, ST_LEN);
-    const int64_t N = static_cast<int64_t>(h->p.W) * h->p.H;
-    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(h->p.H, 2048));
-    hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(NT), 0, s, static_cast<const uint8_t *>(h->b.spins),
-                       h->p.W, h->p.H, static_cast<uint32_t>(h->p.q), h->p.spin_kind == SW_SPIN_ISING_I8 ? 1 : 0,
-                       obs);
-    if (h->swept) {
-        const unsigned rb = static_cast<unsigned>(std::min<int64_t>(cdiv(L.g.ntiles, NT), 64));
-        hipLaunchKernelGGL(k_reduce_tiles, dim3(rb), dim3(NT), 0, s, at<int32_t>(ws, L.tile_act), L.g.ntiles,
-                           obs + ST_ACTIVE, static_cast<int32_t *>(nullptr));
-        hipLaunchKernelGGL(k_reduce_tiles, dim3(rb), dim3(NT), 0, s, at<int32_t>(ws, L.tile_ncl), L.g.ntiles,
-                           obs + ST_NCLUST, static_cast<int32_t *>(nullptr));
+    const int64_t N = static_cast<int64_t>(p.W) * p.H;
+    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(p.H, 2048));
+    const int ising = p.spin_kind == SW_SPIN_ISING_I8 ? 1 : 0;
+    hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(NT), 0, s, static_cast<const uint8_t *>(b.spins), p.W, p.H,
+                       static_cast<uint32_t>(p.q), ising, obs);
+    if (swept) {
+        const unsigned rb = static_cast<unsigned>(std::min<int64_t>(cdiv(ntiles, NT), 64));
+        hipLaunchKernelGGL(k_reduce_tiles, dim3(rb), dim3(NT), 0, s, tile_act, ntiles, obs + ST_ACTIVE,
+                           static_cast<int32_t *>(nullptr));
+        hipLaunchKernelGGL(k_reduce_tiles, dim3(rb), dim3(NT), 0, s, tile_ncl, ntiles, obs + ST_NCLUST,
+                           static_cast<int32_t *>(nullptr));
     }
-    sw_status st = launch_status("sw_observables");
+    const unsigned db = static_cast<unsigned>(std::min<int64_t>(cdiv(N, NT), 4096));
+    if (ising)
+        hipLaunchKernelGGL(k_digest<DIG_ISING_I8>, dim3(db), dim3(NT), 0, s, b.spins, N, obs + ST_DIGEST);
+    else
+        hipLaunchKernelGGL(k_digest<DIG_U8>, dim3(db), dim3(NT), 0, s, b.spins, N, obs + ST_DIGEST);
+    if (swept && b.labels)
+        hipLaunchKernelGGL(k_digest<DIG_I32>, dim3(db), dim3(NT), 0, s, b.labels, N, obs + ST_DIGEST + 1);
+    if (swept && b.bonds)
+        hipLaunchKernelGGL(k_digest<DIG_U8>, dim3(db), dim3(NT), 0, s, b.bonds, N, obs + ST_DIGEST + 2);
+    sw_status st = launch_status("observables");
     if (st != SW_OK) return st;
     unsigned long long host[ST_LEN];
+    int32_t max_size = -1;
     st = device_status(hipMemcpyAsync(host, obs, sizeof(host), hipMemcpyDeviceToHost, s), "copy observables");
     if (st != SW_OK) return st;
+    if (max_size_dev && swept) {
+        st = device_status(hipMemcpyAsync(&max_size, max_size_dev, sizeof(max_size), hipMemcpyDeviceToHost, s),
+                           "copy max size");
+        if (st != SW_OK) return st;
+    }
     st = device_status(hipStreamSynchronize(s), "sync");
     if (st != SW_OK) return st;
     std::memset(out, 0, sizeof(*out));
-    out->t = h->t;
-    out->threshold = h->T;
+    out->t = t;
+    out->threshold = T;
     out->n_sat = static_cast<int64_t>(host[ST_NSAT]);
-    for (int k = 0; k < 8; ++k) out->counts[k] = k < h->p.q ? static_cast<int64_t>(host[ST_COUNTS + k]) : 0;
-    out->magnet = h->p.spin_kind == SW_SPIN_ISING_I8 ? 2 * out->counts[1] - N : 0;
-    out->n_active_bonds = h->swept ? static_cast<int64_t>(host[ST_ACTIVE]) : -1;
-    out->n_clusters = h->swept ? static_cast<int64_t>(host[ST_NCLUST]) : -1;
+    for (int k = 0; k < 8; ++k) out->counts[k] = k < p.q ? static_cast<int64_t>(host[ST_COUNTS + k]) : 0;
+    out->magnet = ising ? 2 * out->counts[1] - N : 0;
+    out->n_active_bonds = swept ? static_cast<int64_t>(host[ST_ACTIVE]) : -1;
+    out->n_clusters = swept ? static_cast<int64_t>(host[ST_NCLUST]) : -1;
+    out->max_cluster = (max_size_dev && swept) ? max_size : -1;
+    out->digest_spins = host[ST_DIGEST];
+    out->digest_labels = host[ST_DIGEST + 1];
+    out->digest_bonds = host[ST_DIGEST + 2];
     return SW_OK;
+}
+
+sw_status sw_observables(sw_lattice *h, sw_obs *out, void *stream)
+{
+    if (!h || !out) return SW_ERR_ARG;
+    const Layout &L = h->L;
+    void *ws = h->b.workspace;
+    const int32_t *max_dev = L.sizes ? at<int32_t>(ws, L.row_count) + L.nrow + 1 : nullptr;
+    return measure(h->p, h->b, h->swept, at<int32_t>(ws, L.tile_act), at<int32_t>(ws, L.tile_ncl), L.g.ntiles,
+                   at<unsigned long long>(ws, L.stats), max_dev, h->T, h->t, out, static_cast<hipStream_t>(stream));
 }
 
 sw_status sw_get_t(const sw_lattice *h, uint64_t *t)
@@ -447,17 +533,7 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, fa.row_count + L.nrow, 1);
         // the flatten mode only matters for M_SW; all labeling inputs share one path
         hipLaunchKernelGGL((k_flatten<M_BONDS_PERIODIC, true>), grid, block, 0, s, fa);
-        int32_t *row_off = at<int32_t>(workspace, L.row_off);
-        scan_i32(fa.row_count, row_off, L.nrow + 1, at<char>(workspace, L.scan_tmp), s);
-        EmitArgs ea{};
-        ea.g = L.g;
-        ea.row_off = row_off;
-        ea.rl_slot = fa.rl_slot;
-        ea.rl_size = fa.rl_size;
-        ea.gsize = fa.gsize;
-        ea.roots = roots;
-        ea.sizes = sizes;
-        hipLaunchKernelGGL(k_emit, grid, block, 0, s, ea);
+        emit_sizes(L, workspace, fa, roots, sizes, nullptr, s);
     } else {
         hipLaunchKernelGGL((k_flatten<M_BONDS_PERIODIC, false>), grid, block, 0, s, fa);
     }
@@ -468,6 +544,197 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
                            static_cast<unsigned long long *>(nullptr), n_clusters);
     }
     return launch_status("ccl_label");
+}
+
+
+// ------------------------------------------------------------------ batches --
+
+struct swb_batch {
+    int32_t n;
+    std::vector<sw_params> p;
+    std::vector<sw_buffers> b;
+    std::vector<uint64_t> T;
+    std::vector<LatticeDesc> desc;     // host copies of what the device tables hold
+    std::vector<int32_t> lat_of_tile;
+    Layout L;
+    void *ws;
+    int32_t tiles_even;  // tiles of even-width lattices come first
+    uint64_t t;
+    bool swept;
+};
+
+static sw_status check_batch(const sw_params *p, const sw_buffers *b, int32_t n, int64_t *ntiles)
+{
+    if (!p || !b || n < 1) return SW_ERR_ARG;
+    int64_t nt = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        const sw_status st = check_params(&p[j]);
+        if (st != SW_OK) return st;
+        if (p[j].flags & SW_F_SIZES) return SW_ERR_UNSUPPORTED;
+        if (!b[j].spins || b[j].roots || b[j].sizes) return SW_ERR_ARG;
+        nt += cdiv(p[j].W, TW) * cdiv(p[j].H, TH);
+    }
+    // tile ids times CAP must stay in int32
+    if (nt * CAP >= (static_cast<int64_t>(1) << 31)) return SW_ERR_SIZE;
+    *ntiles = nt;
+    return SW_OK;
+}
+
+size_t swb_workspace_bytes(const sw_params *p, int32_t n)
+{
+    int64_t nt = 0;
+    std::vector<sw_buffers> dummy(n > 0 ? static_cast<size_t>(n) : 0);
+    for (auto &d : dummy) d.spins = reinterpret_cast<void *>(1);
+    if (n < 1 || check_batch(p, dummy.data(), n, &nt) != SW_OK) return 0;
+    return make_batch_layout(nt, n).total;
+}
+
+sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int32_t n, void *workspace,
+                   size_t workspace_bytes, void *stream)
+{
+    if (!out) return SW_ERR_ARG;
+    int64_t nt = 0;
+    const sw_status cs = check_batch(p, b, n, &nt);
+    if (cs != SW_OK) return cs;
+    const Layout L = make_batch_layout(nt, n);
+    if (!workspace || workspace_bytes < L.total) return SW_ERR_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return SW_ERR_WORKSPACE;
+    swb_batch *h = new (std::nothrow) swb_batch();
+    if (!h) return SW_ERR_ARG;
+    h->n = n;
+    h->p.assign(p, p + n);
+    h->b.assign(b, b + n);
+    h->L = L;
+    h->ws = workspace;
+    h->t = 0;
+    h->swept = false;
+    h->desc.resize(static_cast<size_t>(n));
+    h->lat_of_tile.resize(static_cast<size_t>(nt));
+    // even widths first (one tile-kernel launch per width parity)
+    int32_t tile = 0;
+    for (int parity = 0; parity < 2; ++parity) {
+        for (int32_t j = 0; j < n; ++j) {
+            if ((p[j].W & 1) != parity) continue;
+            LatticeDesc &d = h->desc[static_cast<size_t>(j)];
+            d.g.W = p[j].W;
+            d.g.H = p[j].H;
+            d.g.ntx = static_cast<int>(cdiv(p[j].W, TW));
+            d.g.nty = static_cast<int>(cdiv(p[j].H, TH));
+            d.g.ntiles = d.g.ntx * d.g.nty;
+            d.tile0 = tile;
+            d.spins = static_cast<uint8_t *>(b[j].spins);
+            d.bonds = b[j].bonds;
+            d.labels = b[j].labels;
+            const uint64_t T = threshold_of(p[j].K);
+            d.tany = T > 0 ? 1u : 0u;
+            d.tm1 = T > 0 ? static_cast<uint32_t>(T - 1) : 0u;
+            d.k0 = static_cast<uint32_t>(p[j].seed);
+            d.k1 = static_cast<uint32_t>(p[j].seed >> 32);
+            d.sid = p[j].stream_id;
+            d.q = static_cast<uint32_t>(p[j].q);
+            d.ising = p[j].spin_kind == SW_SPIN_ISING_I8 ? 1 : 0;
+            for (int k = 0; k < d.g.ntiles; ++k) h->lat_of_tile[static_cast<size_t>(tile + k)] = j;
+            tile += d.g.ntiles;
+        }
+        if (parity == 0) h->tiles_even = tile;
+    }
+    for (int32_t j = 0; j < n; ++j) h->T.push_back(threshold_of(p[j].K));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    sw_status st = device_status(hipMemcpyAsync(at<LatticeDesc>(workspace, L.lat_desc), h->desc.data(),
+                                                h->desc.size() * sizeof(LatticeDesc), hipMemcpyHostToDevice, s),
+                                 "copy lattice table");
+    if (st == SW_OK)
+        st = device_status(hipMemcpyAsync(at<int32_t>(workspace, L.lat_of_tile), h->lat_of_tile.data(),
+                                          h->lat_of_tile.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+                           "copy tile table");
+    for (int32_t j = 0; j < n && st == SW_OK; ++j) {
+        if (p[j].flags & SW_F_KEEP_SPINS) continue;
+        const int64_t N = static_cast<int64_t>(p[j].W) * p[j].H;
+        hipLaunchKernelGGL(k_init, dim3(static_cast<unsigned>(cdiv(cdiv(N, 4), NT))), dim3(NT), 0, s,
+                           static_cast<uint8_t *>(b[j].spins), N, static_cast<uint32_t>(p[j].q),
+                           p[j].spin_kind == SW_SPIN_ISING_I8 ? 1 : 0, static_cast<uint32_t>(p[j].seed),
+                           static_cast<uint32_t>(p[j].seed >> 32), p[j].stream_id);
+        st = launch_status("k_init");
+    }
+    // the tables are read by later launches on this stream; the host copies stay
+    // alive in the handle, so a pageable-copy staging delay is harmless
+    if (st != SW_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return SW_OK;
+}
+
+sw_status swb_sweep(swb_batch *h, int32_t n_sweeps, void *stream)
+{
+    if (!h || n_sweeps < 0) return SW_ERR_ARG;
+    if (h->t + static_cast<uint64_t>(n_sweeps) > 0xFFFFFFFFull) return SW_ERR_STATE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout &L = h->L;
+    void *ws = h->ws;
+    Batch bt{};
+    bt.lat = at<LatticeDesc>(ws, L.lat_desc);
+    bt.lat_of_tile = at<int32_t>(ws, L.lat_of_tile);
+    const int32_t total = L.g.ntiles, even = h->tiles_even;
+    for (int32_t k = 0; k < n_sweeps; ++k) {
+        const uint32_t t = static_cast<uint32_t>(h->t);
+        TileArgs ta = tile_args(L, ws, nullptr);
+        ta.t = t;
+        ta.b = bt;
+        if (even > 0) {
+            ta.b.tile_base = 0;
+            ta.b.ntiles = even;
+            hipLaunchKernelGGL((k_tile<M_SW, true, true>), dim3(static_cast<unsigned>(even)), dim3(NT), 0, s, ta);
+        }
+        if (total > even) {
+            ta.b.tile_base = even;
+            ta.b.ntiles = total - even;
+            hipLaunchKernelGGL((k_tile<M_SW, false, true>), dim3(static_cast<unsigned>(total - even)), dim3(NT), 0,
+                               s, ta);
+        }
+        MergeArgs ma = merge_args(L, ws);
+        ma.b = bt;
+        ma.b.tile_base = 0;
+        ma.b.ntiles = total;
+        hipLaunchKernelGGL(k_merge<true>, dim3(static_cast<unsigned>(cdiv(total, MERGE_TILES))), dim3(NT), 0, s, ma);
+        FlatArgs fa = flat_args(L, ws);
+        fa.t = t;
+        fa.b = bt;
+        fa.b.tile_base = 0;
+        fa.b.ntiles = total;
+        hipLaunchKernelGGL((k_flatten<M_SW, false, true>), dim3(static_cast<unsigned>(total)), dim3(NT), 0, s, fa);
+        const sw_status st = launch_status("swb_sweep");
+        if (st != SW_OK) return st;
+        h->t += 1;
+        h->swept = true;
+    }
+    return SW_OK;
+}
+
+sw_status swb_observables(swb_batch *h, int32_t j, sw_obs *out, void *stream)
+{
+    if (!h || !out || j < 0 || j >= h->n) return SW_ERR_ARG;
+    const Layout &L = h->L;
+    const LatticeDesc &d = h->desc[static_cast<size_t>(j)];
+    return measure(h->p[static_cast<size_t>(j)], h->b[static_cast<size_t>(j)], h->swept,
+                   at<int32_t>(h->ws, L.tile_act) + d.tile0, at<int32_t>(h->ws, L.tile_ncl) + d.tile0, d.g.ntiles,
+                   at<unsigned long long>(h->ws, L.stats), nullptr, h->T[static_cast<size_t>(j)], h->t, out,
+                   static_cast<hipStream_t>(stream));
+}
+
+sw_status swb_get_t(const swb_batch *h, uint64_t *t)
+{
+    if (!h || !t) return SW_ERR_ARG;
+    *t = h->t;
+    return SW_OK;
+}
+
+sw_status swb_destroy(swb_batch *h)
+{
+    if (!h) return SW_ERR_ARG;
+    delete h;
+    return SW_OK;
 }
 
 }  // extern "C"

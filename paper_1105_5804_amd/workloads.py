@@ -10,6 +10,9 @@ percolation on periodic square lattices):
   ising4096    q=2 Ising, L=4096, beta_c, packed bonds kept, 200 + 1000 sweeps
   potts16384   q=3 Potts, L=16384, beta_c = ln(1+sqrt3) (Potts normalisation),
                100 sweeps; plus a labeling pass on bond percolation at p = 1/2
+  batch256     256 independent Ising lattices of mixed size L in {32, ..., 1024}
+               and couplings near beta_c (replicas / temperatures), swept
+               together
 """
 from __future__ import annotations
 
@@ -43,6 +46,20 @@ CONFIGS = {
     "ising4096": SWConfig("ising4096", 4096, 4096, 2, True, K_ISING_C, SEED_BASE | 2, 1000, 200, True),
     "potts16384": SWConfig("potts16384", 16384, 16384, 3, False, K_POTTS3_C, SEED_BASE | 3, 100),
 }
+
+
+def batch_specs(n: int = 256, seed: int = SEED_BASE | 4) -> list[dict]:
+    """Lattice specs of the batched workload: lattice j has side L_j uniform over
+    {32, 64, ..., 1024}, beta_j = beta_c (0.9 + 0.2 u_j) (K = 2 beta J for +-1
+    spins), its own 64-bit seed and stream id j."""
+    g = rng(seed)
+    sides = 32 << g.integers(0, 6, size=n)
+    u = g.random(n)
+    seeds = g.integers(0, 2**63, size=n, dtype=np.int64)
+    beta_c = 0.5 * K_ISING_C
+    return [dict(W=int(L), H=int(L), q=2, ising=True, K=2.0 * beta_c * (0.9 + 0.2 * float(uj)),
+                 seed=int(sd), stream_id=j)
+            for j, (L, uj, sd) in enumerate(zip(sides, u, seeds))]
 
 
 def rng(seed: int) -> np.random.Generator:

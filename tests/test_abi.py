@@ -34,7 +34,9 @@ def test_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
         assert n in _lib.SIGNATURES, n
-    assert L.swccl_abi_version() == 1
+    hdr = open(os.path.join(ROOT, "include", "swccl.h")).read()
+    ver = int(re.search(r"#define SWCCL_ABI_VERSION (\d+)", hdr).group(1))
+    assert L.swccl_abi_version() == ver == _lib.ABI_VERSION
 
 
 def test_status_strings():
@@ -56,6 +58,10 @@ def _params(W=64, H=64, q=2, kind=0, K=0.88, flags=0):
     return _lib.SwParams(W, H, q, kind, K, 1, 0, flags)
 
 
+def _bufs(spins, ws, nbytes, roots=None, sizes=None):
+    return _lib.SwBuffers(spins=spins, workspace=ws, workspace_bytes=nbytes, roots=roots, sizes=sizes)
+
+
 @pytest.mark.parametrize("kw", [
     dict(W=1), dict(H=1), dict(W=0), dict(W=-5), dict(W=65536, H=32768),
     dict(q=1), dict(q=256), dict(kind=0, q=3), dict(kind=7), dict(K=float("nan")), dict(flags=8),
@@ -65,7 +71,7 @@ def test_bad_params_rejected(kw):
     p = _params(**kw)
     assert L.sw_workspace_bytes(ctypes.byref(p)) == 0
     h = ctypes.c_void_p()
-    buf = _lib.SwBuffers(0x1000, None, None, 0x100000, 1 << 30)
+    buf = _bufs(0x1000, 0x100000, 1 << 30)
     st = L.sw_init(ctypes.byref(h), ctypes.byref(p), ctypes.byref(buf), None)
     assert st in (_lib.SW_ERR_ARG, _lib.SW_ERR_SIZE)
 
@@ -86,14 +92,23 @@ def test_init_argument_errors():
     need = L.sw_workspace_bytes(ctypes.byref(p))
     h = ctypes.c_void_p()
     assert L.sw_init(None, ctypes.byref(p), None, None) == _lib.SW_ERR_ARG
-    buf = _lib.SwBuffers(None, None, None, 0x100000, need)
+    buf = _bufs(None, 0x100000, need)
     assert L.sw_init(ctypes.byref(h), ctypes.byref(p), ctypes.byref(buf), None) == _lib.SW_ERR_ARG
-    buf = _lib.SwBuffers(0x1000, None, None, 0x100000, need - 1)
+    buf = _bufs(0x1000, 0x100000, need - 1)
     assert L.sw_init(ctypes.byref(h), ctypes.byref(p), ctypes.byref(buf), None) == _lib.SW_ERR_WORKSPACE
-    buf = _lib.SwBuffers(0x1000, None, None, 0x100010, need)
+    buf = _bufs(0x1000, 0x100010, need)
     assert L.sw_init(ctypes.byref(h), ctypes.byref(p), ctypes.byref(buf), None) == _lib.SW_ERR_WORKSPACE
-    buf = _lib.SwBuffers(0x1000, None, None, None, need)
+    buf = _bufs(0x1000, None, need)
     assert L.sw_init(ctypes.byref(h), ctypes.byref(p), ctypes.byref(buf), None) == _lib.SW_ERR_WORKSPACE
+    # cluster sizes need both output arrays and a larger workspace
+    ps = _params(flags=_lib.SW_F_SIZES)
+    need_s = L.sw_workspace_bytes(ctypes.byref(ps))
+    assert need_s > need
+    for r, z in ((None, None), (0x200000, None), (None, 0x300000)):
+        buf = _bufs(0x1000, 0x100000, need_s, roots=r, sizes=z)
+        assert L.sw_init(ctypes.byref(h), ctypes.byref(ps), ctypes.byref(buf), None) == _lib.SW_ERR_ARG
+    buf = _bufs(0x1000, 0x100000, need_s - 1, roots=0x200000, sizes=0x300000)
+    assert L.sw_init(ctypes.byref(h), ctypes.byref(ps), ctypes.byref(buf), None) == _lib.SW_ERR_WORKSPACE
     assert L.sw_sweep(None, 1, None) == _lib.SW_ERR_ARG
     assert L.sw_observables(None, None, None) == _lib.SW_ERR_ARG
     assert L.sw_get_t(None, None) == _lib.SW_ERR_ARG
@@ -122,3 +137,34 @@ def test_ccl_argument_errors():
     assert call(inp, W, H, 0, lab, 0x50000000, 0x60000000, None, ws, need - 1, None) == _lib.SW_ERR_WORKSPACE
     assert call(inp, W, H, 0, lab, None, None, None, None, need, None) == _lib.SW_ERR_WORKSPACE
     assert call(inp, W, H, 0, lab, None, None, None, ws + 4, need, None) == _lib.SW_ERR_WORKSPACE
+
+
+def test_batch_argument_errors():
+    L = _lib.lib()
+    P = (_lib.SwParams * 3)(_params(), _params(W=100, H=37, q=3, kind=1), _params(W=2, H=2))
+    need = L.swb_workspace_bytes(P, 3)
+    assert need > 0
+    assert L.swb_workspace_bytes(P, 0) == 0
+    assert L.swb_workspace_bytes(None, 3) == 0
+    bad = (_lib.SwParams * 2)(_params(), _params(W=1))
+    assert L.swb_workspace_bytes(bad, 2) == 0
+    h = ctypes.c_void_p()
+    B = (_lib.SwBuffers * 3)(_bufs(0x1000, None, 0), _bufs(0x2000, None, 0), _bufs(0x3000, None, 0))
+    ws = 0x100000
+    assert L.swb_init(None, P, B, 3, ws, need, None) == _lib.SW_ERR_ARG
+    assert L.swb_init(ctypes.byref(h), P, B, 0, ws, need, None) == _lib.SW_ERR_ARG
+    assert L.swb_init(ctypes.byref(h), P, B, 3, ws, need - 1, None) == _lib.SW_ERR_WORKSPACE
+    assert L.swb_init(ctypes.byref(h), P, B, 3, ws + 8, need, None) == _lib.SW_ERR_WORKSPACE
+    assert L.swb_init(ctypes.byref(h), P, B, 3, None, need, None) == _lib.SW_ERR_WORKSPACE
+    B2 = (_lib.SwBuffers * 3)(_bufs(0x1000, None, 0), _bufs(None, None, 0), _bufs(0x3000, None, 0))
+    assert L.swb_init(ctypes.byref(h), P, B2, 3, ws, need, None) == _lib.SW_ERR_ARG
+    B3 = (_lib.SwBuffers * 3)(_bufs(0x1000, None, 0, roots=0x5000, sizes=0x6000), _bufs(0x2000, None, 0),
+                              _bufs(0x3000, None, 0))
+    assert L.swb_init(ctypes.byref(h), P, B3, 3, ws, need, None) == _lib.SW_ERR_ARG
+    PS = (_lib.SwParams * 1)(_params(flags=_lib.SW_F_SIZES))
+    assert L.swb_workspace_bytes(PS, 1) == 0
+    assert L.swb_init(ctypes.byref(h), PS, B, 1, ws, need, None) == _lib.SW_ERR_UNSUPPORTED
+    assert L.swb_sweep(None, 1, None) == _lib.SW_ERR_ARG
+    assert L.swb_observables(None, 0, None, None) == _lib.SW_ERR_ARG
+    assert L.swb_get_t(None, None) == _lib.SW_ERR_ARG
+    assert L.swb_destroy(None) == _lib.SW_ERR_ARG

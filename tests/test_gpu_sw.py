@@ -223,3 +223,77 @@ def test_potts16384_three_sweeps():
         assert o["n_clusters"] == rec[oracle.REC_NCLUST], t
         assert o["n_active_bonds"] == rec[oracle.REC_ACTIVE], t
         assert np.array_equal(_state(lat), st), t
+
+
+SIZE_CASES = [
+    (64, 64, 2, True, wl.K_ISING_C),
+    (257, 95, 2, True, wl.K_ISING_C),
+    (2, 2, 2, True, wl.K_ISING_C),
+    (300, 3, 4, False, 1.1),
+    (383, 161, 5, False, 1.2),
+    (200, 200, 3, False, float("inf")),
+    (515, 260, 3, False, wl.K_POTTS3_C),
+]
+
+
+@pytest.mark.parametrize("W,H,q,ising,K", SIZE_CASES)
+def test_sizes_and_digests(W, H, q, ising, K):
+    """Cluster list (roots ascending, sizes), largest size and array digests per sweep."""
+    print(f"sizes W={W} H={H} q={q} ising={ising} K={K}", flush=True)
+    seed, sid = wl.SEED_BASE | 0x5E, 1
+    lat = sw.SWLattice(W, H, q=q, K=K, seed=seed, stream_id=sid, ising=ising, keep_labels=True,
+                       keep_bonds=True, sizes=True)
+    T = oracle.threshold(K)
+    st = oracle.init_states(W, H, q, seed, sid)
+    o = lat.observables()
+    assert o["max_cluster"] == -1 and o["n_clusters"] == -1
+    assert o["digest_spins"] == oracle.digest(st)
+    assert o["digest_labels"] == 0 and o["digest_bonds"] == 0
+    for t in range(3):
+        lat.sweep(1)
+        st, bonds, labels, rec = oracle.sw_sweep(W, H, q, T, seed, sid, t, st)
+        roots, sizes = lat.cluster_sizes()
+        r_ref, s_ref, mx = oracle.cluster_sizes(labels)
+        assert np.array_equal(roots.cpu().numpy(), r_ref), t
+        assert np.array_equal(sizes.cpu().numpy(), s_ref), t
+        o = lat.observables()
+        assert o["max_cluster"] == mx == rec[oracle.REC_MAXCL], t
+        assert o["n_clusters"] == len(r_ref)
+        assert o["digest_spins"] == oracle.digest(st), t
+        assert o["digest_labels"] == oracle.digest(labels), t
+        assert o["digest_bonds"] == oracle.digest(bonds), t
+        assert np.array_equal(_state(lat), st), t
+
+
+def test_sizes_by_phase():
+    """The per-phase calls with sizes give the same cluster list as sw_sweep."""
+    W, H, q = 700, 300, 3
+    a = sw.SWLattice(W, H, q=q, seed=11, ising=False, sizes=True)
+    b = sw.SWLattice(W, H, q=q, seed=11, ising=False, sizes=True)
+    for _ in range(3):
+        a.sweep(1)
+        for ph in range(3):
+            b.sweep_phase(ph)
+    ra, sa = a.cluster_sizes()
+    rb, sb = b.cluster_sizes()
+    assert torch.equal(ra, rb) and torch.equal(sa, sb)
+    assert a.observables() == b.observables()
+
+
+def test_potts16384_sizes():
+    """Full size with the cluster list: roots, sizes, largest cluster and the spin digest."""
+    c = wl.CONFIGS["potts16384"]
+    T = oracle.threshold(c.K)
+    lat = sw.SWLattice(c.W, c.H, q=3, K=c.K, seed=c.seed, ising=False, sizes=True)
+    st = oracle.init_states(c.W, c.H, 3, c.seed)
+    lat.sweep(1)
+    new, _b, labels, rec = oracle.sw_sweep(c.W, c.H, 3, T, c.seed, 0, 0, st)
+    del _b
+    r_ref, s_ref, mx = oracle.cluster_sizes(labels)
+    del labels
+    roots, sizes = lat.cluster_sizes()
+    assert np.array_equal(roots.cpu().numpy(), r_ref)
+    assert np.array_equal(sizes.cpu().numpy(), s_ref)
+    o = lat.observables()
+    assert o["max_cluster"] == mx == rec[oracle.REC_MAXCL]
+    assert o["digest_spins"] == oracle.digest(new)
