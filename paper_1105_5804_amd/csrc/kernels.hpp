@@ -157,38 +157,25 @@ __device__ __forceinline__ void lds_st(int *p, int v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Root of x with path halving.  Parents only ever move to ancestors, and a
-// root is only changed by the CAS in lunite, so concurrent halving is safe.
-__device__ __forceinline__ int lfind(int *P, int x)
+// One step of a union of the trees holding a and b, with a straight-line body
+// (nested find/link loops cost more in exec-mask bookkeeping than in LDS
+// traffic).  A step climbs both nodes one level; when both are roots the
+// larger is linked below the smaller with an atomic min, so every root is the
+// minimum (local, hence global) index of its tree.  If the larger root had
+// meanwhile been linked elsewhere, the min leaves it below its old parent or
+// below the smaller root, and the union goes on with that old parent, so no
+// link is lost and every parent stays below its child.  done is set when the
+// two trees are one.
+__device__ __forceinline__ void unite_step(int *P, int &a, int &b, int &done)
 {
-    for (;;) {
-        const int p = lds_ld(&P[x]);
-        if (p == x) return x;
-        const int g = lds_ld(&P[p]);
-        if (g == p) return p;
-        lds_st(&P[x], g);
-        x = g;
-    }
-}
-
-// Union: the larger root index is linked below the smaller, so every root is
-// the minimum (local, hence global) index of its tree.
-__device__ __forceinline__ void lunite(int *P, int a, int b)
-{
-    for (;;) {
-        a = lfind(P, a);
-        b = lfind(P, b);
-        if (a == b) return;
-        if (a < b) {
-            const int t = a;
-            a = b;
-            b = t;
-        }
-        int expect = a;
-        if (__hip_atomic_compare_exchange_strong(&P[a], &expect, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
-            return;
-    }
+    const int pa = lds_ld(&P[a]), pb = lds_ld(&P[b]);
+    const bool roots = pa == a && pb == b;
+    const int hi = max(a, b), lo = min(a, b);
+    int old = hi;
+    if (roots && a != b) old = __hip_atomic_fetch_min(&P[hi], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    done = roots && old == hi;
+    a = roots ? old : pa;
+    b = roots ? lo : pb;
 }
 
 // ---- global union-find over boundary ids ----
@@ -386,8 +373,7 @@ __device__ __forceinline__ int border_slot(int t, int tw, int th)
 }
 
 // Claimed roots: P[root] = CLAIMING while the id is allocated, then
-// -(k + 2) for boundary id k.  After the codes are resolved every occupied run
-// start x holds P[x] = -(code + 1).
+// -(k + 2) for boundary id k.
 constexpr int CLAIMING = -1;
 
 // Lane masks: bit L describes lane L (uicmp yields the mask of one compare).
@@ -603,9 +589,28 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         eo_append(mylist, ncon, eo_andnot(prevD, eo_shift1(X)), lane, (ly0 + nr - 1) * TW);
     }
     wave_lds_fence();
-    for (int i = lane; i < ncon; i += 64) {
-        const int c = mylist[i];
-        lunite(P, c, c + TW);
+    // Lane L unites contacts L, L+64, ... of the list; a lane whose union is
+    // done takes its next contact at once, so one deep union does not hold up
+    // the other lanes of its round.
+    {
+        int i = lane, a = 0, b = 0;
+        if (i < ncon) {
+            const int c = mylist[i];
+            a = lds_ld(&P[c]);
+            b = lds_ld(&P[c + TW]);
+        }
+        while (i < ncon) {
+            int done;
+            unite_step(P, a, b, done);
+            if (done) {
+                i += 64;
+                if (i < ncon) {
+                    const int c = mylist[i];
+                    a = lds_ld(&P[c]);
+                    b = lds_ld(&P[c + TW]);
+                }
+            }
+        }
     }
     __syncthreads();
 
@@ -621,8 +626,10 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         }
     };
 
-    // ---- C: roots of the occupied run starts (read-only), and claims of the
-    // clusters that touch the tile border (one thread per border position).
+    // ---- C: every occupied run start is pointed straight at its root, and
+    // the clusters that touch the tile border are claimed (one thread per
+    // border position).  A compressed entry only ever replaces a parent by an
+    // ancestor, and a root's own entry is left to the claims.
     int nrs = 0;
     for (int r = 0; r < nr; ++r) {
         const int ly = ly0 + r;
@@ -631,11 +638,21 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         eo_append(mylist, nrs, eo_andnot(O, eo_shift1(R)), lane, ly * TW);
     }
     wave_lds_fence();
-    int rr[WLIST / 64];
-#pragma unroll
-    for (int j = 0; j < WLIST / 64; ++j) {
-        const int i = lane + 64 * j;
-        rr[j] = i < nrs ? lroot(P, mylist[i]) : 0;
+    {
+        // lane L takes run starts L, L+64, ...; a lane whose walk is done takes
+        // its next run start at once
+        int i = lane, s0 = 0, x = 0;
+        if (i < nrs) s0 = x = mylist[i];
+        while (i < nrs) {
+            const int p = lds_ld(&P[x]);
+            if (p >= 0 && p != x) {
+                x = p;
+            } else {
+                if (x != s0) lds_st(&P[s0], x);
+                i += 64;
+                if (i < nrs) s0 = x = mylist[i];
+            }
+        }
     }
     for (int t = threadIdx.x; t < EDGE; t += NT) {
         const int slot = border_slot(t, tw, th);
@@ -654,46 +671,31 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     }
     __syncthreads();
 
-    // ---- D: the code of every occupied run start (boundary id, or CAP + the
-    // slot of its interior root), then stored in place as -(code + 1).
-#pragma unroll
-    for (int j = 0; j < WLIST / 64; ++j) {
-        const int i = lane + 64 * j;
-        if (i < nrs) {
-            const int pr_root = lds_ld(&P[rr[j]]);
-            rr[j] = pr_root < 0 ? -pr_root - 2 : CAP + rr[j];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < WLIST / 64; ++j) {
-        const int i = lane + 64 * j;
-        if (i < nrs) P[mylist[i]] = -(rr[j] + 1);
-    }
-    __syncthreads();
-
-    // ---- E: per-site codes, edge ids, crossing bits ----
+    // ---- E: per-site codes (boundary id of a claimed root, else CAP + the
+    // root's slot), edge ids, crossing bits.  A site reaches its root in at
+    // most two steps: site -> run start -> root.
+    auto code_of = [&](int x) {
+        int p = P[x];
+        x = (p >= 0 && p != x) ? p : x;
+        p = P[max(x, 0)];
+        const int y = (p >= 0 && p != x) ? p : x;
+        p = (y != x) ? P[y] : p;
+        return p < 0 ? static_cast<uint32_t>(-p - 2) : static_cast<uint32_t>(CAP + y);
+    };
     uint32_t *codes32 = reinterpret_cast<uint32_t *>(a.codes + static_cast<int64_t>(tile) * TSITES);
     for (int r = 0; r < nr; ++r) {
         const int ly = ly0 + r;
         const EO O = MODE == M_SITES ? Om[ly] : valid;
         const int base = ly * TW;
-        const int2 pp = *reinterpret_cast<const int2 *>(&P[base + lx0]);
-        // a run start holds its code; any other site points at a run start
-        const int c0 = pp.x < 0 ? pp.x : P[max(pp.x, 0)];
-        const int c1 = pp.y < 0 ? pp.y : P[max(pp.y, 0)];
-        const uint32_t code0 = ((O.e >> lane) & 1ull) ? static_cast<uint32_t>(-c0 - 1) : CODE_BG;
-        const uint32_t code1 = ((O.o >> lane) & 1ull) ? static_cast<uint32_t>(-c1 - 1) : CODE_BG;
+        const uint32_t code0 = ((O.e >> lane) & 1ull) ? code_of(base + lx0) : CODE_BG;
+        const uint32_t code1 = ((O.o >> lane) & 1ull) ? code_of(base + lx0 + 1) : CODE_BG;
         codes32[(base + lx0) >> 1] = code0 | (code1 << 16);
     }
     uint16_t *edg = a.edges + static_cast<int64_t>(tile) * EDGE;
     for (int t = threadIdx.x; t < EDGE; t += NT) {
         const int slot = border_slot(t, tw, th);
         uint16_t eid = ID_NONE;
-        if (slot >= 0 && occupied(slot)) {
-            const int p = P[slot];
-            eid = static_cast<uint16_t>(-(p < 0 ? p : P[p]) - 1);
-        }
+        if (slot >= 0 && occupied(slot)) eid = static_cast<uint16_t>(code_of(slot));
         edg[t] = eid;
     }
     if (threadIdx.x == 0) {
