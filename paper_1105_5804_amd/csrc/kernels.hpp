@@ -93,6 +93,14 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
     return xcd * q + min(xcd, r) + local;
 }
 
+// Bit `lane` of a wave-uniform mask m, for the calling lane: the mask is used
+// as the lane condition directly (no per-lane shift).
+__device__ __forceinline__ bool lane_bit(uint64_t m, int lane)
+{
+    (void)lane;
+    return __builtin_amdgcn_inverse_ballot_w64(m);
+}
+
 __device__ __forceinline__ uint64_t low_bits(int n)  // bits [0, n), n in [0, 64]
 {
     return n >= 64 ? ~0ull : ((1ull << n) - 1ull);
@@ -325,9 +333,9 @@ __device__ __forceinline__ int lanes_below(uint64_t m)
 __device__ __forceinline__ void eo_append(uint16_t *list, int &n, EO m, int lane, int base)
 {
     const int r0 = n + lanes_below(m.e) + lanes_below(m.o);
-    const int b0 = static_cast<int>((m.e >> lane) & 1ull);
+    const int b0 = lane_bit(m.e, lane) ? 1 : 0;
     if (b0) list[r0] = static_cast<uint16_t>(base + 2 * lane);
-    if ((m.o >> lane) & 1ull) list[r0 + b0] = static_cast<uint16_t>(base + 2 * lane + 1);
+    if (lane_bit(m.o, lane)) list[r0 + b0] = static_cast<uint16_t>(base + 2 * lane + 1);
     n += __popcll(m.e) + __popcll(m.o);
 }
 
@@ -382,7 +390,6 @@ __device__ __forceinline__ uint64_t lanes_eq(uint32_t x, uint32_t y) { return __
 __device__ __forceinline__ uint64_t lanes_ne(uint32_t x, uint32_t y) { return __builtin_amdgcn_uicmp(x, y, CMP_NE); }
 __device__ __forceinline__ uint64_t lanes_lt(uint32_t x, uint32_t y) { return __builtin_amdgcn_uicmp(x, y, CMP_ULT); }
 __device__ __forceinline__ uint64_t lanes_le(uint32_t x, uint32_t y) { return __builtin_amdgcn_uicmp(x, y, CMP_ULE); }
-__device__ __forceinline__ bool lane_bit(uint64_t m, int lane) { return (m >> lane) & 1ull; }
 
 // Value of x held by the next lane (DPP wave shift; the last lane gets 0).
 __device__ __forceinline__ uint32_t from_next_lane(uint32_t x)
@@ -687,8 +694,8 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         const int ly = ly0 + r;
         const EO O = MODE == M_SITES ? Om[ly] : valid;
         const int base = ly * TW;
-        const uint32_t code0 = ((O.e >> lane) & 1ull) ? code_of(base + lx0) : CODE_BG;
-        const uint32_t code1 = ((O.o >> lane) & 1ull) ? code_of(base + lx0 + 1) : CODE_BG;
+        const uint32_t code0 = lane_bit(O.e, lane) ? code_of(base + lx0) : CODE_BG;
+        const uint32_t code1 = lane_bit(O.o, lane) ? code_of(base + lx0 + 1) : CODE_BG;
         codes32[(base + lx0) >> 1] = code0 | (code1 << 16);
     }
     uint16_t *edg = a.edges + static_cast<int64_t>(tile) * EDGE;
@@ -984,10 +991,10 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
             const int base = ly * TW;
             // ascending site order within the row: even sites below 2L+j, odd sites below
             const int below = lanes_below(rm[r].e) + lanes_below(rm[r].o);
-            const int be = static_cast<int>((rm[r].e >> lane) & 1ull);
+            const int be = lane_bit(rm[r].e, lane) ? 1 : 0;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                if (!(((j ? rm[r].o : rm[r].e) >> lane) & 1ull)) continue;
+                if (!lane_bit(j ? rm[r].o : rm[r].e, lane)) continue;
                 const int s = lx0 + j;
                 const int pos = rowc[ly] + below + (j ? be : 0);
                 const uint32_t code = (cc[r] >> (16 * j)) & 0xFFFFu;
