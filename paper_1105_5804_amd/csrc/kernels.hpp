@@ -781,6 +781,26 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a)
     }
 }
 
+// After the merge: every boundary id is pointed straight at its root and
+// takes its root's key, so the flatten pass needs one load of each per id.
+// Roots keep their entries; a walk that reads an entry being compressed sees
+// its old parent or the root, both ancestors.  One wave per tile.
+__global__ __launch_bounds__(NT) void k_resolve(const int32_t *nb, int32_t *gparent, int32_t *gkey, int ntiles)
+{
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int tile = blockIdx.x * MERGE_TILES + wave;
+    if (tile >= ntiles) return;
+    const int n = nb[tile];
+    for (int k = lane; k < n; k += 64) {
+        const int id = tile * CAP + k;
+        const int root = gfind(gparent, id);
+        if (root != id) {
+            gparent[id] = root;
+            gkey[id] = gkey[root];
+        }
+    }
+}
+
 // -------------------------------------------------------------- flatten ----
 
 struct FlatArgs {
@@ -848,6 +868,13 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
     const int ly0 = wave * RPW;
     const int nr = max(0, min(RPW, th - ly0));
     const int nbt = a.nb[tile];
+    static_assert(CAP <= NT, "one boundary id per thread");
+    // after k_resolve every boundary id holds its root and the root's key
+    int broot = 0, bR = 0;
+    if (threadIdx.x < nbt) {
+        broot = a.gparent[tile * CAP + threadIdx.x];
+        bR = a.gkey[tile * CAP + threadIdx.x];
+    }
 
     if constexpr (SIZES) {
         for (int k = threadIdx.x; k < TSITES; k += NT) Ci[k] = 0;
@@ -874,18 +901,15 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
             ST[CAP + slot] = flip_state(static_cast<uint32_t>((gy0 + (slot >> 7)) * W + gx0 + (slot & (TW - 1))), a);
         }
     }
-    // boundary ids: resolve to the global root, whose key is the cluster's
-    // minimum site index (the union-find is final: plain loads suffice)
+    // boundary ids: the root and its key (the cluster's minimum site index),
+    // loaded at the start; one id per thread since nb <= CAP <= NT
     int nbr = 0;
-    for (int k = threadIdx.x; k < nbt; k += NT) {
-        const int id = tile * CAP + k;
-        int root = id;
-        for (int p = a.gparent[root]; p != root; p = a.gparent[root]) root = p;
-        const int R = a.gkey[root];
-        Rb[k] = R;
-        Gid[k] = root;
-        nbr += root == id;
-        if constexpr (MODE == M_SW) ST[k] = flip_state(static_cast<uint32_t>(R), a);
+    if (threadIdx.x < nbt) {
+        const int k = threadIdx.x;
+        Rb[k] = bR;
+        Gid[k] = broot;
+        nbr = broot == tile * CAP + k;
+        if constexpr (MODE == M_SW) ST[k] = flip_state(static_cast<uint32_t>(bR), a);
     }
     {
         const unsigned long long s = wave_sum(static_cast<unsigned long long>(nbr));
