@@ -242,6 +242,56 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
                     int32_t *roots, int32_t *sizes, int32_t *n_clusters, void *workspace,
                     size_t workspace_bytes, void *stream);
 
+/* ---- Served labeling: requests labeled as they arrive (ccl_label on each),
+ * over one caller-owned device arena.  An admitted request takes one arena
+ * block of ccl_server_footprint() bytes (its input, labels, optional roots
+ * and sizes, and labeling workspace), so the number in flight is bounded by
+ * memory, not by a fixed slot size; a request that does not fit is refused
+ * with SW_ERR_STATE and waits in the caller's queue until blocks are
+ * released.  Requests go round-robin to the caller's streams, so copies and
+ * labeling of different requests overlap.  The server allocates no device
+ * memory and is driven from one host thread. */
+typedef struct ccl_server ccl_server;
+typedef struct ccl_server_params {
+    int32_t mode;          /* CCL_* input kind of every request               */
+    int32_t sizes;         /* 1: also roots and sizes per request, 0: labels  */
+    int32_t max_inflight;  /* requests admitted at once, 1..4096              */
+    int32_t n_streams;     /* streams passed to ccl_server_create, 1..64      */
+} ccl_server_params;
+
+/* Arena bytes one W x H request takes (0 if the shape or p is invalid). */
+size_t ccl_server_footprint(int32_t W, int32_t H, const ccl_server_params *p);
+
+/* Create a server over arena (device, 256-byte aligned, arena_bytes) and
+ * p->n_streams caller streams (hipStream_t as void*). */
+sw_status ccl_server_create(ccl_server **out, const ccl_server_params *p, void *arena, size_t arena_bytes,
+                            void *const *streams);
+
+/* Admit one request: copy the W x H image (host memory, row pitch in bytes;
+ * pinned memory lets the copy run asynchronously; it must stay unchanged
+ * until the request completes) to the arena and enqueue its labeling.
+ * *slot identifies the request until it is released.  SW_ERR_STATE: no
+ * arena block or request slot is free now (nothing enqueued); SW_ERR_SIZE:
+ * the request can never fit or its shape is invalid. */
+sw_status ccl_server_submit(ccl_server *s, const uint8_t *image, int32_t W, int32_t H, size_t pitch, uint64_t tag,
+                            int32_t *slot);
+
+/* Completed requests not reported before (non-blocking): up to max pairs
+ * (slot, tag) and their number *n. */
+sw_status ccl_server_poll(ccl_server *s, int32_t *slots, uint64_t *tags, int32_t max, int32_t *n);
+
+/* Device pointers of a request's outputs (as ccl_label writes them): labels
+ * (W x H), roots and sizes (NULL without sizes) and the cluster count.  Valid
+ * until the request is released. */
+sw_status ccl_server_result(ccl_server *s, int32_t slot, int32_t **labels, int32_t **roots, int32_t **sizes,
+                            int32_t **n_clusters);
+
+/* Return a request's arena block (waits for the request if it still runs). */
+sw_status ccl_server_release(ccl_server *s, int32_t slot);
+
+/* Wait for requests still running and free the host object. */
+sw_status ccl_server_destroy(ccl_server *s);
+
 #ifdef __cplusplus
 }
 #endif

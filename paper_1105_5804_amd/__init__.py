@@ -338,3 +338,8 @@ def ccl_label(inp, mode: str | int = "bonds_periodic", sizes: bool = False, work
         return labels
     n = int(ncl.item())
     return labels, roots[:n], szs[:n], n
+
+
+from .server import CCLServer  # noqa: E402  (needs the helpers above)
+
+__all__.append("CCLServer")

@@ -58,6 +58,15 @@ class SwObs(ctypes.Structure):
     ]
 
 
+class CclServerParams(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_int32),
+        ("sizes", ctypes.c_int32),
+        ("max_inflight", ctypes.c_int32),
+        ("n_streams", ctypes.c_int32),
+    ]
+
+
 class SwccLError(RuntimeError):
     """A non-zero sw_status from the library."""
 
@@ -88,6 +97,19 @@ SIGNATURES = {
     "swb_get_t": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "swb_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "ccl_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "ccl_server_footprint": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(CclServerParams)]),
+    "ccl_server_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(CclServerParams),
+                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]),
+    "ccl_server_submit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_size_t, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
+    "ccl_server_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32)]),
+    "ccl_server_result": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p)]),
+    "ccl_server_release": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "ccl_server_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "ccl_label": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),

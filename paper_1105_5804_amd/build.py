@@ -7,7 +7,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "swccl.hip")
+SRCS = [os.path.join(HERE, "csrc", "swccl.hip"), os.path.join(HERE, "csrc", "server.hip")]
 LIB = os.path.join(HERE, "libswccl.so")
 
 # -packed-fp32-ops keeps the compiler away from packed fp32 instructions.
@@ -29,7 +29,7 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     """Always recompile (the build check must exercise the compiler)."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPFLAGS, "-o", tmp, SRC]
+    cmd = [hipcc(), *HIPFLAGS, "-o", tmp, *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

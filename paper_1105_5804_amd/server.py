@@ -1,0 +1,122 @@
+"""Served connected-component labeling: a thin layer over the ``ccl_server_*``
+C ABI (argument marshalling only).
+
+Requests are host images labeled as they arrive.  The library admits a request
+when its footprint fits in the device arena (``SW_ERR_STATE`` otherwise: the
+request waits here, in submission order), spreads requests over the given
+streams, and reports completions through ``poll``.
+"""
+from __future__ import annotations
+
+import collections
+import ctypes
+
+from . import _lib
+from . import _MODES, _torch
+
+_STATE = _lib.SW_ERR_STATE
+
+
+class CCLServer:
+    """Label host images (``(H, W)`` uint8 CPU tensors, ideally pinned) on the GPU.
+
+    arena_bytes of device memory hold the requests in flight; ``sizes`` adds
+    the sorted roots and sizes of every request's clusters.
+    """
+
+    def __init__(self, arena_bytes: int, mode: str | int = "sites_open", sizes: bool = True,
+                 max_inflight: int = 256, n_streams: int = 4, device: str = "cuda"):
+        torch = _torch()
+        L = _lib.lib()
+        self.mode = _MODES[mode] if isinstance(mode, str) else int(mode)
+        self.sizes = bool(sizes)
+        self.params = _lib.CclServerParams(self.mode, 1 if sizes else 0, int(max_inflight), int(n_streams))
+        self.device = torch.device(device)
+        # streams at the default priority
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
+        self._arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=self.device)
+        base = self._arena.data_ptr()
+        self._arena_ptr = base + ((-base) % 256)
+        self._arena_off = self._arena_ptr - base
+        arr = (ctypes.c_void_p * n_streams)(*[s.cuda_stream for s in self.streams])
+        self._h = ctypes.c_void_p()
+        _lib.check(L.ccl_server_create(ctypes.byref(self._h), ctypes.byref(self.params), self._arena_ptr,
+                                       int(arena_bytes), arr), "ccl_server_create")
+        self._queue = collections.deque()   # (tag, image) waiting for admission
+        self._inflight = {}                 # slot -> (tag, image, W, H)
+        cap = int(max_inflight)
+        self._pslots = (ctypes.c_int32 * cap)()
+        self._ptags = (ctypes.c_uint64 * cap)()
+
+    def footprint(self, W: int, H: int) -> int:
+        return int(_lib.lib().ccl_server_footprint(int(W), int(H), ctypes.byref(self.params)))
+
+    def _try_submit(self, tag: int, img) -> bool:
+        H, W = img.shape
+        slot = ctypes.c_int32()
+        st = _lib.lib().ccl_server_submit(self._h, img.data_ptr(), W, H, img.stride(0), tag, ctypes.byref(slot))
+        if st == _STATE:
+            return False
+        _lib.check(st, "ccl_server_submit")
+        self._inflight[slot.value] = (tag, img, W, H)
+        return True
+
+    def submit(self, tag: int, img) -> None:
+        """Queue a request; it is admitted at once if the arena has room."""
+        if img.dim() != 2 or img.dtype.itemsize != 1 or img.device.type != "cpu" or img.stride(1) != 1:
+            raise ValueError("a request is a 2D uint8 CPU tensor with unit column stride")
+        if self._queue or not self._try_submit(tag, img):
+            self._queue.append((tag, img))
+
+    def pump(self) -> None:
+        """Admit queued requests, in order, while they fit."""
+        while self._queue and self._try_submit(*self._queue[0]):
+            self._queue.popleft()
+
+    def poll(self) -> list:
+        """[(slot, tag)] of requests completed since the last poll (non-blocking)."""
+        n = ctypes.c_int32()
+        cap = len(self._pslots)
+        _lib.check(_lib.lib().ccl_server_poll(self._h, self._pslots, self._ptags, cap, ctypes.byref(n)),
+                   "ccl_server_poll")
+        return [(int(self._pslots[i]), int(self._ptags[i])) for i in range(n.value)]
+
+    def result(self, slot: int):
+        """(labels (H, W), roots, sizes, n) of a completed request as views of the
+        arena (valid until release); roots and sizes are None without sizes."""
+        torch = _torch()
+        ptrs = [ctypes.c_void_p() for _ in range(4)]
+        _lib.check(_lib.lib().ccl_server_result(self._h, int(slot), *[ctypes.byref(p) for p in ptrs]),
+                   "ccl_server_result")
+        _, _, W, H = self._inflight[slot]
+        N = W * H
+
+        def view(ptr, count, shape=None):
+            off = ptr - self._arena_ptr + self._arena_off
+            t = self._arena[off:off + 4 * count].view(torch.int32)
+            return t.view(shape) if shape else t
+
+        ncl = int(view(ptrs[3].value, 1).item())
+        labels = view(ptrs[0].value, N, (H, W))
+        if not self.sizes:
+            return labels, None, None, ncl
+        return labels, view(ptrs[1].value, ncl), view(ptrs[2].value, ncl), ncl
+
+    def release(self, slot: int) -> None:
+        _lib.check(_lib.lib().ccl_server_release(self._h, int(slot)), "ccl_server_release")
+        del self._inflight[slot]
+
+    @property
+    def pending(self) -> int:
+        return len(self._queue) + len(self._inflight)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().ccl_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

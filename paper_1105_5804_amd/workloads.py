@@ -13,6 +13,10 @@ percolation on periodic square lattices):
   batch256     256 independent Ising lattices of mixed size L in {32, ..., 1024}
                and couplings near beta_c (replicas / temperatures), swept
                together
+  served       image-segmentation requests (Sec. I): square binary images of
+               side N log-uniform in [64, 8192], site occupancy p uniform in
+               [0.40, 0.70] (straddling site percolation, p_c ~ 0.5927),
+               Poisson arrivals
 """
 from __future__ import annotations
 
@@ -60,6 +64,35 @@ def batch_specs(n: int = 256, seed: int = SEED_BASE | 4) -> list[dict]:
     return [dict(W=int(L), H=int(L), q=2, ising=True, K=2.0 * beta_c * (0.9 + 0.2 * float(uj)),
                  seed=int(sd), stream_id=j)
             for j, (L, uj, sd) in enumerate(zip(sides, u, seeds))]
+
+
+SERVED_POOL_SIDE = 8192
+SERVED_POOL_LEVELS = 8
+
+
+def served_pool_p(level: int) -> float:
+    """Occupancy of pool image `level`: SERVED_POOL_LEVELS values spanning [0.40, 0.70]."""
+    return 0.40 + 0.30 * (level + 0.5) / SERVED_POOL_LEVELS
+
+
+def served_requests(n: int, seed: int = SEED_BASE | 5) -> list[dict]:
+    """Parameters of n served requests: side N = round(exp(ln 64 + ln 128 u)),
+    an occupancy level (a pool buffer of SERVED_POOL_SIDE^2 pixels of that p),
+    the offset of the request's N*N pixels in that buffer (taken as a
+    contiguous N x N image), and a unit-rate exponential inter-arrival gap
+    (scaled by 1/lambda by the caller).  Every pool pixel is occupied
+    independently, so every request is an i.i.d. site-percolation image."""
+    g = rng(seed)
+    u = g.random((n, 4))
+    out = []
+    total = SERVED_POOL_SIDE * SERVED_POOL_SIDE
+    for r in range(n):
+        N = int(round(math.exp(math.log(64) + math.log(128) * u[r, 0])))
+        N = min(max(N, 1), SERVED_POOL_SIDE)
+        lev = min(int(u[r, 1] * SERVED_POOL_LEVELS), SERVED_POOL_LEVELS - 1)
+        span = total - N * N
+        out.append(dict(N=N, level=lev, offset=int(u[r, 2] * (span + 1)), gap=-math.log1p(-u[r, 3])))
+    return out
 
 
 def rng(seed: int) -> np.random.Generator:

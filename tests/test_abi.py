@@ -168,3 +168,30 @@ def test_batch_argument_errors():
     assert L.swb_observables(None, 0, None, None) == _lib.SW_ERR_ARG
     assert L.swb_get_t(None, None) == _lib.SW_ERR_ARG
     assert L.swb_destroy(None) == _lib.SW_ERR_ARG
+
+
+def test_server_argument_errors():
+    L = _lib.lib()
+    P = _lib.CclServerParams(2, 1, 8, 2)
+    assert L.ccl_server_footprint(100, 50, ctypes.byref(P)) >= 100 * 50 * 13
+    assert L.ccl_server_footprint(0, 50, ctypes.byref(P)) == 0
+    for bad in (_lib.CclServerParams(3, 1, 8, 2), _lib.CclServerParams(2, 2, 8, 2),
+                _lib.CclServerParams(2, 1, 0, 2), _lib.CclServerParams(2, 1, 8, 0),
+                _lib.CclServerParams(2, 1, 8, 65)):
+        assert L.ccl_server_footprint(100, 50, ctypes.byref(bad)) == 0
+        h = ctypes.c_void_p()
+        streams = (ctypes.c_void_p * 2)(None, None)
+        assert L.ccl_server_create(ctypes.byref(h), ctypes.byref(bad), 0x100000, 1 << 20, streams) == _lib.SW_ERR_ARG
+    h = ctypes.c_void_p()
+    streams = (ctypes.c_void_p * 2)(None, None)
+    assert L.ccl_server_create(None, ctypes.byref(P), 0x100000, 1 << 20, streams) == _lib.SW_ERR_ARG
+    assert L.ccl_server_create(ctypes.byref(h), ctypes.byref(P), 0x100000, 1 << 20, None) == _lib.SW_ERR_ARG
+    assert L.ccl_server_create(ctypes.byref(h), ctypes.byref(P), 0x100010, 1 << 20, streams) == _lib.SW_ERR_WORKSPACE
+    assert L.ccl_server_create(ctypes.byref(h), ctypes.byref(P), None, 1 << 20, streams) == _lib.SW_ERR_WORKSPACE
+    slot = ctypes.c_int32()
+    assert L.ccl_server_submit(None, 0x1000, 4, 4, 4, 0, ctypes.byref(slot)) == _lib.SW_ERR_ARG
+    n = ctypes.c_int32()
+    assert L.ccl_server_poll(None, None, None, 0, ctypes.byref(n)) == _lib.SW_ERR_ARG
+    assert L.ccl_server_result(None, 0, None, None, None, None) == _lib.SW_ERR_ARG
+    assert L.ccl_server_release(None, 0) == _lib.SW_ERR_ARG
+    assert L.ccl_server_destroy(None) == _lib.SW_ERR_ARG
