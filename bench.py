@@ -304,6 +304,29 @@ def main() -> int:
                           "plain_spins_per_s": round(nsite / (ms_p * 1e-3), 1),
                           "speedup_vs_plain": round(ms_p / ms_b, 3)}
 
+    # ---- a one-tile lattice (Ising L=64, 1000 sweeps): fused launch vs tiled path ----
+    if not args.no_batch:
+        c = wl.CONFIGS["ising64"]
+        res = {}
+        for name in ("fused", "tiled"):
+            lat = sw.SWLattice(c.W, c.H, q=2, K=c.K, seed=c.seed)
+            torch.cuda.synchronize()
+            c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            c0.record(stream)
+            if name == "fused":
+                lat.sweep_history(c.sweeps)
+            else:
+                for _ in range(c.sweeps):
+                    for ph in range(3):
+                        lat.sweep_phase(ph)
+            c1.record(stream)
+            torch.cuda.synchronize()
+            res[name] = c0.elapsed_time(c1) * 1e3 / c.sweeps
+            del lat
+        out["small"] = {"workload": f"Ising {c.W}x{c.H}, {c.sweeps} sweeps with per-sweep records",
+                        "us_per_sweep": round(res["fused"], 3),
+                        "us_per_sweep_tiled_launches": round(res["tiled"], 3)}
+
     # ---- served labeling ----
     if not args.no_serve:
         out["served"] = _served(args, torch, sw, wl)

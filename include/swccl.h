@@ -172,6 +172,21 @@ sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, voi
  * flip.  n_sweeps = 0 is a no-op. */
 sw_status sw_sweep(sw_lattice *h, int32_t n_sweeps, void *stream);
 
+/* Per-sweep records of sw_sweep_history (int64 each). */
+enum {
+    SW_HIST_ACTIVE = 0,  /* active bonds of the sweep                         */
+    SW_HIST_NCLUST = 1,  /* clusters of the sweep                             */
+    SW_HIST_MAXCL = 2,   /* largest cluster (with SW_F_SIZES), else -1        */
+    SW_HIST_NSAT = 3,    /* satisfied bonds of the spins after the flip       */
+    SW_HIST_COUNTS = 4,  /* 8 entries: sites in state k after the flip, k < 8 */
+    SW_HIST_LEN = 12
+};
+
+/* sw_sweep plus one record per sweep into history (device, n_sweeps x
+ * SW_HIST_LEN int64, row k for sweep t + k), written on the stream without
+ * waiting: a measurement series needs no host round trip per sweep. */
+sw_status sw_sweep_history(sw_lattice *h, int32_t n_sweeps, int64_t *history, void *stream);
+
 /* One phase of a sweep, for per-phase timing (Sec. II.E decomposes T_SW into
  * activation + local labeling, consolidation across tiles, and flipping):
  * SW_PHASE_TILE, SW_PHASE_MERGE, SW_PHASE_FLIP in this order make one sweep,

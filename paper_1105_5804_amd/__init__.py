@@ -173,6 +173,16 @@ class SWLattice:
         torch = _torch()
         _lib.check(_lib.lib().sw_sweep(self._h, int(n), _stream(torch, stream)), "sw_sweep")
 
+    def sweep_history(self, n: int, stream=None):
+        """Enqueue n sweeps and return their per-sweep records, an (n, 12) int64
+        device tensor (columns: active bonds, clusters, largest cluster or -1,
+        satisfied bonds and counts[8] of the new spins); does not wait."""
+        torch = _torch()
+        hist = torch.empty((max(int(n), 1), _lib.SW_HIST_LEN), dtype=torch.int64, device=self.device)
+        _lib.check(_lib.lib().sw_sweep_history(self._h, int(n), hist.data_ptr(), _stream(torch, stream)),
+                   "sw_sweep_history")
+        return hist[: int(n)]
+
     def sweep_phase(self, phase: int, stream=None) -> None:
         """Enqueue one phase (0 tile, 1 merge, 2 flip) of the next sweep."""
         torch = _torch()

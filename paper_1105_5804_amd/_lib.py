@@ -15,6 +15,7 @@ SW_SPIN_ISING_I8, SW_SPIN_POTTS_U8 = 0, 1
 SW_F_KEEP_SPINS, SW_F_SIZES = 1, 2
 CCL_BONDS_PERIODIC, CCL_BONDS_OPEN, CCL_SITES_OPEN = 0, 1, 2
 SW_PHASE_TILE, SW_PHASE_MERGE, SW_PHASE_FLIP = 0, 1, 2
+SW_HIST_ACTIVE, SW_HIST_NCLUST, SW_HIST_MAXCL, SW_HIST_NSAT, SW_HIST_COUNTS, SW_HIST_LEN = 0, 1, 2, 3, 4, 12
 
 
 class SwParams(ctypes.Structure):
@@ -84,6 +85,7 @@ SIGNATURES = {
                                  ctypes.POINTER(SwBuffers), ctypes.c_void_p]),
     "sw_sweep": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "sw_sweep_phase": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "sw_sweep_history": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sw_observables": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(SwObs), ctypes.c_void_p]),
     "sw_get_t": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "sw_set_t": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64]),

@@ -1140,6 +1140,184 @@ __global__ __launch_bounds__(NT) void k_emit(EmitArgs a)
     }
 }
 
+// ------------------------------------------------------- small lattices ---
+//
+// A lattice of one tile (W <= TW, H <= TH) is swept entirely inside one
+// workgroup: spins, union-find parents and the new state of every root stay in
+// LDS for all n sweeps of one launch, so a sweep costs neither launches nor an
+// HBM round trip (a 64 x 64 lattice is launch-latency bound otherwise).  The
+// bonds, canonical labels and new states are those of the tiled path; every
+// bond, wrap bonds included, is a union inside the workgroup.
+
+// Per-sweep record of sw_sweep_history: active bonds, clusters, largest cluster
+// (-1: not measured), satisfied bonds and state counts of the new spins.
+enum { HIST_ACTIVE = 0, HIST_NCLUST = 1, HIST_MAXCL = 2, HIST_NSAT = 3, HIST_COUNTS = 4, HIST_LEN = 12 };
+
+struct SmallArgs {
+    int W, H;
+    uint8_t *spins;       // read at the start, written at the end
+    uint8_t *bonds_out;   // packed bonds of the last sweep, or nullptr
+    int32_t *labels;      // canonical labels of the last sweep, or nullptr
+    int64_t *hist;        // [n][HIST_LEN] per-sweep records, or nullptr
+    int32_t *tile_act;    // [1]: active bonds of the last sweep
+    int32_t *tile_ncl;    // [1]: clusters of the last sweep
+    uint32_t tm1, tany, k0, k1, sid, q, t0;
+    int ising, n;
+};
+
+// Row of site i < 2^13 in a lattice of width W <= 128: the float quotient is
+// at least 0.5 / W away from the next integer, far above its rounding error.
+__device__ __forceinline__ int small_row(int i, float inv_w) { return static_cast<int>((i + 0.5f) * inv_w); }
+
+constexpr int SMALL_NT = 1024;  // 16 waves: more LDS round trips in flight on the one CU
+
+__global__ __launch_bounds__(SMALL_NT) void k_small(SmallArgs a)
+{
+    constexpr int NT = SMALL_NT, NWAVE = SMALL_NT / 64;
+    constexpr int PAIRS_PER_THREAD = TSITES / 2 / NT;  // site pairs 2p, 2p+1 with p = tid + NT m
+    __shared__ int P[TSITES];
+    __shared__ uint8_t S[TSITES];   // states 0..q-1
+    __shared__ uint8_t NS[TSITES];  // new state, at root slots
+    __shared__ unsigned long long red[NWAVE][11];
+    const int W = a.W, H = a.H, N = W * H;
+    const float inv_w = 1.0f / static_cast<float>(W);
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    auto right_of = [&](int i) {
+        const int y = small_row(i, inv_w), x = i - y * W;
+        return y * W + (x + 1 == W ? 0 : x + 1);
+    };
+    auto down_of = [&](int i) {
+        const int y = small_row(i, inv_w);
+        return y + 1 == H ? i - y * W : i + W;
+    };
+    for (int i = threadIdx.x; i < N; i += NT) {
+        const uint32_t b = a.spins[i];
+        S[i] = static_cast<uint8_t>(a.ising ? (b == 1u ? 1u : 0u) : b);
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < a.n; ++sweep) {
+        const uint32_t t = a.t0 + static_cast<uint32_t>(sweep);
+        const bool last = sweep + 1 == a.n;
+        for (int i = threadIdx.x; i < N; i += NT) P[i] = i;
+        // bonds of the thread's site pairs (one Philox block per pair): bit
+        // 4m + 2j + k of `bonds` is bond k (0 right, 1 down) of site 2p + j
+        uint32_t bonds = 0;
+#pragma unroll
+        for (int m = 0; m < PAIRS_PER_THREAD; ++m) {
+            const int p = threadIdx.x + NT * m;
+            if (2 * p >= N) break;
+            const U4 blk = philox4x32_10(static_cast<uint32_t>(p), t, TAG_BOND, a.sid, a.k0, a.k1);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int i = 2 * p + j;
+                if (i >= N) break;
+                const uint32_t wr = j ? blk.v2 : blk.v0, wd = j ? blk.v3 : blk.v1;
+                const bool br = a.tany && S[i] == S[right_of(i)] && wr <= a.tm1;
+                const bool bd = a.tany && S[i] == S[down_of(i)] && wd <= a.tm1;
+                bonds |= (br ? 1u : 0u) << (4 * m + 2 * j);
+                bonds |= (bd ? 1u : 0u) << (4 * m + 2 * j + 1);
+                if (last && a.bonds_out) a.bonds_out[i] = static_cast<uint8_t>((br ? 1 : 0) | (bd ? 2 : 0));
+            }
+        }
+        const unsigned long long act = static_cast<unsigned>(__popc(bonds));
+        __syncthreads();
+        // unions of the thread's active bonds, one flat loop: a finished union
+        // takes the next bond at once
+        {
+            uint32_t todo = bonds;
+            int u = 0, v = 0, busy = 0;
+            while (busy || todo) {
+                if (!busy) {
+                    const int b = __ffs(todo) - 1;
+                    todo &= todo - 1;
+                    const int i = 2 * (threadIdx.x + NT * (b >> 2)) + ((b >> 1) & 1);
+                    u = i;
+                    v = (b & 1) ? down_of(i) : right_of(i);
+                    busy = 1;
+                }
+                int done;
+                unite_step(P, u, v, done);
+                busy = !done;
+            }
+        }
+        __syncthreads();
+        // every site straight to its root (replacing a parent by an ancestor)
+        for (int i = threadIdx.x; i < N; i += NT) {
+            int x = i, px = lds_ld(&P[x]);
+            while (px != x) {
+                x = px;
+                px = lds_ld(&P[x]);
+            }
+            if (x != i) lds_st(&P[i], x);
+        }
+        __syncthreads();
+        // one draw per cluster at its canonical (minimum) root
+        unsigned long long ncl = 0;
+        for (int i = threadIdx.x; i < N; i += NT) {
+            if (P[i] != i) continue;
+            const U4 b = philox4x32_10(static_cast<uint32_t>(i) >> 2, t, TAG_FLIP, a.sid, a.k0, a.k1);
+            NS[i] = static_cast<uint8_t>(draw_state(pick(b, static_cast<uint32_t>(i) & 3u), a.q));
+            ++ncl;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < N; i += NT) {
+            S[i] = NS[P[i]];
+            if (last && a.labels) a.labels[i] = P[i];
+        }
+        __syncthreads();
+        if (a.hist || last) {
+            // counters of the new spins
+            unsigned long long v[11];
+            v[0] = act;
+            v[1] = ncl;
+            for (int k = 2; k < 11; ++k) v[k] = 0;
+            for (int i = threadIdx.x; i < N; i += NT) {
+                const uint32_t si = S[i];
+                v[2] += static_cast<unsigned>(si == S[right_of(i)]) + static_cast<unsigned>(si == S[down_of(i)]);
+                if (si < 8) v[3 + si] += 1;
+            }
+            for (int k = 0; k < 11; ++k) {
+                const unsigned long long w = wave_sum(v[k]);
+                if (lane == 0) red[wave][k] = w;
+            }
+            __syncthreads();
+            if (threadIdx.x < 11) {
+                unsigned long long tot = 0;
+                for (int w = 0; w < NWAVE; ++w) tot += red[w][threadIdx.x];
+                const int k = threadIdx.x;
+                if (a.hist) {
+                    int64_t *row = a.hist + static_cast<int64_t>(sweep) * HIST_LEN;
+                    const int col = k == 0 ? HIST_ACTIVE : k == 1 ? HIST_NCLUST : k == 2 ? HIST_NSAT : HIST_COUNTS + k - 3;
+                    row[col] = static_cast<int64_t>(tot);
+                    if (k == 0) row[HIST_MAXCL] = -1;
+                }
+                if (last && k == 0) a.tile_act[0] = static_cast<int32_t>(tot);
+                if (last && k == 1) a.tile_ncl[0] = static_cast<int32_t>(tot);
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < N; i += NT) {
+        const uint32_t st = S[i];
+        a.spins[i] = static_cast<uint8_t>(a.ising ? 2u * st - 1u : st);
+    }
+}
+
+// One per-sweep record from the observable slots (after k_observe and the
+// per-tile reductions of the sweep).
+__global__ void k_hist_row(const unsigned long long *st, const int32_t *max_size, int64_t *row)
+{
+    const int k = threadIdx.x;
+    if (k >= HIST_LEN) return;
+    int64_t v;
+    if (k == HIST_ACTIVE) v = static_cast<int64_t>(st[ST_ACTIVE]);
+    else if (k == HIST_NCLUST) v = static_cast<int64_t>(st[ST_NCLUST]);
+    else if (k == HIST_MAXCL) v = max_size ? static_cast<int64_t>(*max_size) : -1;
+    else if (k == HIST_NSAT) v = static_cast<int64_t>(st[ST_NSAT]);
+    else v = static_cast<int64_t>(st[ST_COUNTS + k - HIST_COUNTS]);
+    row[k] = v;
+}
+
 // --------------------------------------------------------------- digest ---
 
 // Check-sum of an array: the sum over i of the low 64 bits of the Philox block

@@ -398,12 +398,49 @@ sw_status sw_sweep_phase(sw_lattice *h, int32_t phase, void *stream)
     return SW_OK;
 }
 
+// A lattice of one tile is swept by k_small, all sweeps in one launch (the
+// per-phase entry point keeps the tiled path; both give the same results).
+static bool small_path(const sw_lattice *h) { return h->L.g.ntiles == 1 && !h->L.sizes; }
+
+static sw_status launch_small(sw_lattice *h, int32_t n, int64_t *hist, hipStream_t s)
+{
+    const Layout &L = h->L;
+    void *ws = h->b.workspace;
+    SmallArgs a{};
+    a.W = h->p.W;
+    a.H = h->p.H;
+    a.spins = static_cast<uint8_t *>(h->b.spins);
+    a.bonds_out = h->b.bonds;
+    a.labels = h->b.labels;
+    a.hist = hist;
+    a.tile_act = at<int32_t>(ws, L.tile_act);
+    a.tile_ncl = at<int32_t>(ws, L.tile_ncl);
+    a.tany = h->T > 0 ? 1u : 0u;
+    a.tm1 = h->T > 0 ? static_cast<uint32_t>(h->T - 1) : 0u;
+    a.k0 = static_cast<uint32_t>(h->p.seed);
+    a.k1 = static_cast<uint32_t>(h->p.seed >> 32);
+    a.sid = h->p.stream_id;
+    a.q = static_cast<uint32_t>(h->p.q);
+    a.t0 = static_cast<uint32_t>(h->t);
+    a.ising = h->p.spin_kind == SW_SPIN_ISING_I8 ? 1 : 0;
+    a.n = n;
+    hipLaunchKernelGGL(k_small, dim3(1), dim3(SMALL_NT), 0, s, a);
+    return launch_status("k_small");
+}
+
 sw_status sw_sweep(sw_lattice *h, int32_t n_sweeps, void *stream)
 {
     if (!h || n_sweeps < 0) return SW_ERR_ARG;
     if (h->next_phase != SW_PHASE_TILE) return SW_ERR_STATE;
     if (h->t + static_cast<uint64_t>(n_sweeps) > 0xFFFFFFFFull) return SW_ERR_STATE;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n_sweeps > 0 && small_path(h)) {
+        const sw_status st = launch_small(h, n_sweeps, nullptr, s);
+        if (st != SW_OK) return st;
+        h->t += static_cast<uint64_t>(n_sweeps);
+        h->swept = true;
+        return SW_OK;
+    }
     for (int32_t n = 0; n < n_sweeps; ++n) {
         for (int32_t ph = SW_PHASE_TILE; ph <= SW_PHASE_FLIP; ++ph) {
             const sw_status st = launch_phase(h, ph, s);
@@ -479,6 +516,47 @@ sw_status sw_observables(sw_lattice *h, sw_obs *out, void *stream)
     const int32_t *max_dev = L.sizes ? at<int32_t>(ws, L.row_count) + L.nrow + 1 : nullptr;
     return measure(h->p, h->b, h->swept, at<int32_t>(ws, L.tile_act), at<int32_t>(ws, L.tile_ncl), L.g.ntiles,
                    at<unsigned long long>(ws, L.stats), max_dev, h->T, h->t, out, static_cast<hipStream_t>(stream));
+}
+
+sw_status sw_sweep_history(sw_lattice *h, int32_t n_sweeps, int64_t *history, void *stream)
+{
+    if (!h || n_sweeps < 0 || (n_sweeps > 0 && !history)) return SW_ERR_ARG;
+    if (h->next_phase != SW_PHASE_TILE) return SW_ERR_STATE;
+    if (h->t + static_cast<uint64_t>(n_sweeps) > 0xFFFFFFFFull) return SW_ERR_STATE;
+    if (n_sweeps == 0) return SW_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (small_path(h)) {
+        const sw_status st = launch_small(h, n_sweeps, history, s);
+        if (st != SW_OK) return st;
+        h->t += static_cast<uint64_t>(n_sweeps);
+        h->swept = true;
+        return SW_OK;
+    }
+    const Layout &L = h->L;
+    void *ws = h->b.workspace;
+    unsigned long long *obs = at<unsigned long long>(ws, L.stats);
+    const int32_t *max_dev = L.sizes ? at<int32_t>(ws, L.row_count) + L.nrow + 1 : nullptr;
+    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(h->p.H, 2048));
+    const unsigned rb = static_cast<unsigned>(std::min<int64_t>(cdiv(L.g.ntiles, NT), 64));
+    for (int32_t n = 0; n < n_sweeps; ++n) {
+        for (int32_t ph = SW_PHASE_TILE; ph <= SW_PHASE_FLIP; ++ph) {
+            const sw_status st = launch_phase(h, ph, s);
+            if (st != SW_OK) return st;
+        }
+        h->t += 1;
+        h->swept = true;
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, obs, ST_LEN);
+        hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(NT), 0, s, static_cast<const uint8_t *>(h->b.spins), h->p.W,
+                           h->p.H, static_cast<uint32_t>(h->p.q), h->p.spin_kind == SW_SPIN_ISING_I8 ? 1 : 0, obs);
+        hipLaunchKernelGGL(k_reduce_tiles, dim3(rb), dim3(NT), 0, s, at<int32_t>(ws, L.tile_act), L.g.ntiles,
+                           obs + ST_ACTIVE, static_cast<int32_t *>(nullptr));
+        hipLaunchKernelGGL(k_reduce_tiles, dim3(rb), dim3(NT), 0, s, at<int32_t>(ws, L.tile_ncl), L.g.ntiles,
+                           obs + ST_NCLUST, static_cast<int32_t *>(nullptr));
+        hipLaunchKernelGGL(k_hist_row, dim3(1), dim3(64), 0, s, obs, max_dev, history + static_cast<int64_t>(n) * HIST_LEN);
+        const sw_status st = launch_status("sw_sweep_history");
+        if (st != SW_OK) return st;
+    }
+    return SW_OK;
 }
 
 sw_status sw_get_t(const sw_lattice *h, uint64_t *t)

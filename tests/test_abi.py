@@ -110,6 +110,7 @@ def test_init_argument_errors():
     buf = _bufs(0x1000, 0x100000, need_s - 1, roots=0x200000, sizes=0x300000)
     assert L.sw_init(ctypes.byref(h), ctypes.byref(ps), ctypes.byref(buf), None) == _lib.SW_ERR_WORKSPACE
     assert L.sw_sweep(None, 1, None) == _lib.SW_ERR_ARG
+    assert L.sw_sweep_history(None, 1, 0x1000, None) == _lib.SW_ERR_ARG
     assert L.sw_observables(None, None, None) == _lib.SW_ERR_ARG
     assert L.sw_get_t(None, None) == _lib.SW_ERR_ARG
     assert L.sw_set_t(None, 0) == _lib.SW_ERR_ARG

@@ -297,3 +297,38 @@ def test_potts16384_sizes():
     o = lat.observables()
     assert o["max_cluster"] == mx == rec[oracle.REC_MAXCL]
     assert o["digest_spins"] == oracle.digest(new)
+
+
+@pytest.mark.parametrize("W,H,q,ising,n", [(64, 64, 2, True, 1000), (2, 2, 2, True, 50), (128, 64, 3, False, 200),
+                                           (97, 33, 5, False, 100), (300, 170, 3, False, 12)])
+def test_sweep_history(W, H, q, ising, n):
+    """Per-sweep records (one launch for one-tile lattices) equal the oracle's records."""
+    K = wl.K_ISING_C if q == 2 else math.log1p(math.sqrt(q))
+    seed = wl.SEED_BASE | 0x1
+    print(f"history W={W} H={H} q={q} n={n}", flush=True)
+    lat = sw.SWLattice(W, H, q=q, K=K, seed=seed, ising=ising)
+    hist = lat.sweep_history(n).cpu().numpy()
+    T = oracle.threshold(K)
+    st = oracle.init_states(W, H, q, seed)
+    st, rec = oracle.sw_run(W, H, q, T, seed, 0, 0, n, st)
+    cols = [oracle.REC_ACTIVE, oracle.REC_NCLUST, oracle.REC_NSAT] + [oracle.REC_COUNTS + k for k in range(min(q, 8))]
+    assert np.array_equal(hist[:, cols], rec[:, cols])
+    assert np.all(hist[:, 2] == -1)
+    assert np.array_equal(_state(lat), st)
+    o = lat.observables()
+    assert o["t"] == n and o["n_clusters"] == rec[-1, oracle.REC_NCLUST]
+
+
+def test_small_path_matches_tiled_path():
+    """One-tile lattices: the fused launch and the per-phase (tiled) path agree."""
+    for (W, H, q) in [(64, 64, 2), (128, 64, 3), (33, 17, 4), (2, 64, 2)]:
+        a = sw.SWLattice(W, H, q=q, seed=5, ising=(q == 2), keep_labels=True, keep_bonds=True)
+        b = sw.SWLattice(W, H, q=q, seed=5, ising=(q == 2), keep_labels=True, keep_bonds=True)
+        for _ in range(4):
+            a.sweep(1)
+            for ph in range(3):
+                b.sweep_phase(ph)
+        torch.cuda.synchronize()
+        assert torch.equal(a.spins, b.spins), (W, H)
+        assert torch.equal(a.labels, b.labels) and torch.equal(a.bonds, b.bonds), (W, H)
+        assert a.observables() == b.observables()
