@@ -637,12 +637,17 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     // the clusters that touch the tile border are claimed (one thread per
     // border position).  A compressed entry only ever replaces a parent by an
     // ancestor, and a root's own entry is left to the claims.
+    // Only run starts whose parent is not themselves need a walk.
     int nrs = 0;
     for (int r = 0; r < nr; ++r) {
         const int ly = ly0 + r;
+        const int base = ly * TW;
         const EO R = uniform_eo(Rm[ly]);
         const EO O = MODE == M_SITES ? uniform_eo(Om[ly]) : valid;
-        eo_append(mylist, nrs, eo_andnot(O, eo_shift1(R)), lane, ly * TW);
+        const int2 pp = *reinterpret_cast<const int2 *>(&P[base + lx0]);
+        const EO linked = EO{lanes_ne(static_cast<uint32_t>(pp.x), static_cast<uint32_t>(base + lx0)),
+                             lanes_ne(static_cast<uint32_t>(pp.y), static_cast<uint32_t>(base + lx0 + 1))};
+        eo_append(mylist, nrs, eo_and(eo_andnot(O, eo_shift1(R)), linked), lane, base);
     }
     wave_lds_fence();
     {
@@ -681,8 +686,7 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     // ---- E: per-site codes (boundary id of a claimed root, else CAP + the
     // root's slot), edge ids, crossing bits.  A site reaches its root in at
     // most two steps: site -> run start -> root.
-    auto code_of = [&](int x) {
-        int p = P[x];
+    auto code_of = [&](int x, int p) {  // p = P[x]
         x = (p >= 0 && p != x) ? p : x;
         p = P[max(x, 0)];
         const int y = (p >= 0 && p != x) ? p : x;
@@ -694,15 +698,16 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         const int ly = ly0 + r;
         const EO O = MODE == M_SITES ? Om[ly] : valid;
         const int base = ly * TW;
-        const uint32_t code0 = lane_bit(O.e, lane) ? code_of(base + lx0) : CODE_BG;
-        const uint32_t code1 = lane_bit(O.o, lane) ? code_of(base + lx0 + 1) : CODE_BG;
+        const int2 pp = *reinterpret_cast<const int2 *>(&P[base + lx0]);
+        const uint32_t code0 = lane_bit(O.e, lane) ? code_of(base + lx0, pp.x) : CODE_BG;
+        const uint32_t code1 = lane_bit(O.o, lane) ? code_of(base + lx0 + 1, pp.y) : CODE_BG;
         codes32[(base + lx0) >> 1] = code0 | (code1 << 16);
     }
     uint16_t *edg = a.edges + static_cast<int64_t>(tile) * EDGE;
     for (int t = threadIdx.x; t < EDGE; t += NT) {
         const int slot = border_slot(t, tw, th);
         uint16_t eid = ID_NONE;
-        if (slot >= 0 && occupied(slot)) eid = static_cast<uint16_t>(code_of(slot));
+        if (slot >= 0 && occupied(slot)) eid = static_cast<uint16_t>(code_of(slot, P[slot]));
         edg[t] = eid;
     }
     if (threadIdx.x == 0) {
