@@ -203,13 +203,26 @@ __device__ __forceinline__ int gfind(const int *G, int x)
     }
 }
 
+// Roots of a and b, both chains walked at once (their loads overlap); the
+// body is straight-line, a finished chain just reloads its root.
+__device__ __forceinline__ void gfind2(const int *G, int &a, int &b)
+{
+    int pa = G[a], pb = G[b];
+    while (pa != a || pb != b) {
+        a = pa;
+        b = pb;
+        pa = G[a];
+        pb = G[b];
+    }
+}
+
 __device__ __forceinline__ void gunite(int *G, const int *key, int a, int b)
 {
-    a = gfind(G, a);
-    b = gfind(G, b);
+    gfind2(G, a, b);
     for (;;) {
         if (a == b) return;
-        if (key[a] < key[b]) {
+        const int ka = key[a], kb = key[b];
+        if (ka < kb) {
             const int t = a;
             a = b;
             b = t;
@@ -218,8 +231,8 @@ __device__ __forceinline__ void gunite(int *G, const int *key, int a, int b)
         if (__hip_atomic_compare_exchange_strong(&G[a], &expect, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT))
             return;
-        a = gfind(G, expect);  // a was linked meanwhile: continue from its parent
-        b = gfind(G, b);
+        a = expect;  // a was linked meanwhile: continue from its parent
+        gfind2(G, a, b);
     }
 }
 
