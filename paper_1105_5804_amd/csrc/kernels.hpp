@@ -410,6 +410,21 @@ __device__ __forceinline__ uint32_t from_next_lane(uint32_t x)
     return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x130, 0xF, 0xF, false));
 }
 
+// Maximum of v over the lanes below the calling one (0 for lane 0), v >= 0:
+// an inclusive max-scan by row shifts and row broadcasts, then a shift by one
+// lane.  Out-of-row sources read 0, the identity; rows outside a broadcast's
+// row mask keep their value.
+__device__ __forceinline__ int wave_max_below(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast:15 (rows 1, 3)
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast:31 (rows 2, 3)
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true);         // wave_shr:1, lane 0 reads 0
+}
+
 template <int MODE, bool EVENW, bool BATCH = false>
 __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
 {
@@ -580,14 +595,14 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
             if (MODE == M_SITES) Om[ly] = EO{O0, O1};
         }
         const int base = ly * TW;
-        int rs0 = lx0;
-        if (v0) {  // run start of site 2L: one past the last missing right bond before it
-            const uint64_t ze = ~R.e & below, zo = ~R.o & below;
-            const int ce = ze ? 2 * (63 - __builtin_clzll(ze)) + 1 : 0;
-            const int co = zo ? 2 * (63 - __builtin_clzll(zo)) + 2 : 0;
-            rs0 = max(ce, co);
-        }
-        const int rs1 = lane_bit(R.e, lane) ? rs0 : lx1;
+        // Run starts: site 2L starts a run unless bond 2L-1 -> 2L is present,
+        // site 2L+1 unless bond 2L -> 2L+1 is; the run start of 2L is the last
+        // start at or before it (a max-scan over the lanes below).
+        const bool e_start = lane_bit(~(R.o << 1), lane);
+        const bool o_start = lane_bit(~R.e, lane);
+        const int below_start = wave_max_below(o_start ? lx1 + 1 : (e_start ? lx0 + 1 : 0));
+        const int rs0 = e_start ? lx0 : ((below_start - 1) & (TW - 1));
+        const int rs1 = o_start ? lx1 : rs0;
         *reinterpret_cast<int2 *>(&P[base + lx0]) = make_int2(base + rs0, base + rs1);
         if (r > 0) {
             const EO X = eo_and(eo_and(prevD, prevR), R);
