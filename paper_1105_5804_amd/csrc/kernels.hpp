@@ -101,59 +101,6 @@ __device__ __forceinline__ bool lane_bit(uint64_t m, int lane)
     return __builtin_amdgcn_inverse_ballot_w64(m);
 }
 
-__device__ __forceinline__ uint64_t low_bits(int n)  // bits [0, n), n in [0, 64]
-{
-    return n >= 64 ? ~0ull : ((1ull << n) - 1ull);
-}
-
-// A tile row of 128 sites in natural order: bit s of lo (s < 64) or of hi
-// (s >= 64) belongs to site s.
-struct M128 {
-    uint64_t lo, hi;
-};
-
-__device__ __forceinline__ bool bit128(const M128 &m, int s)
-{
-    return s < 64 ? ((m.lo >> s) & 1ull) : ((m.hi >> (s - 64)) & 1ull);
-}
-
-// Number of set bits below site s.
-__device__ __forceinline__ int rank128(const M128 &m, int s)
-{
-    return s < 64 ? __popcll(m.lo & low_bits(s)) : __popcll(m.lo) + __popcll(m.hi & low_bits(s - 64));
-}
-
-// Lane L holds, in bits 2k and 2k+1 of `f`, flag k of its sites 2L and 2L+1.
-// Returns flag k of every site of the row as a natural-order 128-bit mask:
-// lane t fetches the flags of sites t and 64+t from their owners (a lane
-// permute through the LDS crossbar), then two ballots.
-template <int NF>
-__device__ __forceinline__ void row_masks(uint32_t f, int lane, M128 (&out)[NF])
-{
-    const uint32_t g0 = static_cast<uint32_t>(__shfl(static_cast<int>(f), lane >> 1));
-    const uint32_t g1 = static_cast<uint32_t>(__shfl(static_cast<int>(f), 32 + (lane >> 1)));
-    const int sh = lane & 1;
-#pragma unroll
-    for (int k = 0; k < NF; ++k) {
-        out[k].lo = __ballot((g0 >> (2 * k + sh)) & 1u);
-        out[k].hi = __ballot((g1 >> (2 * k + sh)) & 1u);
-    }
-}
-
-// Start of the row run containing site s: one past the last site j < s whose
-// bond j -> j+1 (bit j of R) is absent, or 0.
-__device__ __forceinline__ int run_start(const M128 &R, int s)
-{
-    if (s < 64) {
-        const uint64_t z = ~R.lo & low_bits(s);
-        return z ? 64 - __builtin_clzll(z) : 0;
-    }
-    const uint64_t z = ~R.hi & low_bits(s - 64);
-    if (z) return 128 - __builtin_clzll(z);
-    if (!((R.lo >> 63) & 1ull)) return 64;
-    const uint64_t z0 = ~R.lo & low_bits(63);
-    return z0 ? 64 - __builtin_clzll(z0) : 0;
-}
 
 // ---- LDS union-find (workgroup scope) ----
 __device__ __forceinline__ int lds_ld(int *p)
@@ -352,17 +299,6 @@ __device__ __forceinline__ void eo_append(uint16_t *list, int &n, EO m, int lane
     n += __popcll(m.e) + __popcll(m.o);
 }
 
-// Start of the row run containing the even site 2L: one past the last missing
-// right bond before it (e bits are bonds 2m -> 2m+1, o bits 2m+1 -> 2m+2).
-__device__ __forceinline__ int run_start_even(EO R, int L)
-{
-    const uint64_t below = low_bits(L);
-    const uint64_t ze = ~R.e & below, zo = ~R.o & below;
-    const int ce = ze ? 2 * (63 - __builtin_clzll(ze)) + 1 : 0;
-    const int co = zo ? 2 * (63 - __builtin_clzll(zo)) + 2 : 0;
-    return max(ce, co);
-}
-
 // Wave-uniform copy of a mask read from LDS.
 __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 {
@@ -505,7 +441,6 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     unsigned long long nact = 0, xr = 0;
     int ncon = 0;
     EO prevR = EO{0ull, 0ull}, prevD = EO{0ull, 0ull};
-    const uint64_t below = low_bits(lane);
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         if (r >= nr) break;
