@@ -837,9 +837,10 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
     const int nr = max(0, min(RPW, th - ly0));
     const int nbt = a.nb[tile];
     static_assert(CAP <= NT, "one boundary id per thread");
-    // after k_resolve every boundary id holds its root and the root's key
+    // after k_resolve every boundary id holds its root and the root's key; the
+    // loads are issued with the count's (entries past nb are read, not used)
     int broot = 0, bR = 0;
-    if (threadIdx.x < nbt) {
+    if (threadIdx.x < CAP) {
         broot = a.gparent[tile * CAP + threadIdx.x];
         bR = a.gkey[tile * CAP + threadIdx.x];
     }
@@ -856,7 +857,9 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
     // interior roots (code = CAP + own slot) of the wave's rows, compacted
     int nroot = 0;
     uint16_t *mylist = rl[wave];
-    for (int r = 0; r < nr; ++r) {
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        if (r >= nr) break;  // unrolled: cc[] stays indexed by constants
         const int base = (ly0 + r) * TW;
         const EO m = EO{lanes_eq(cc[r] & 0xFFFFu, static_cast<uint32_t>(CAP + base + lx0)),
                         lanes_eq(cc[r] >> 16, static_cast<uint32_t>(CAP + base + lx0 + 1))};

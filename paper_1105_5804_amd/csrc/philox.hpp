@@ -50,9 +50,11 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     return U4{c0, c1, c2, c3};
 }
 
+// Word j (0..3) of a block, by selects rather than branches.
 __device__ __forceinline__ uint32_t pick(const U4 &b, uint32_t j)
 {
-    return j == 0 ? b.v0 : j == 1 ? b.v1 : j == 2 ? b.v2 : b.v3;
+    const uint32_t lo = (j & 1u) ? b.v1 : b.v0, hi = (j & 1u) ? b.v3 : b.v2;
+    return (j & 2u) ? hi : lo;
 }
 
 // floor(w * q / 2^32): one uniform state in 0..q-1 from a 32-bit word.
