@@ -732,21 +732,24 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a)
     const uint64_t xr = xb[0];
     const uint64_t xde = xb[1], xdo = xb[2];  // bottom crossing bonds, even / odd columns
     auto xd_bit = [&](int x) { return (((x & 1) ? xdo : xde) >> (x >> 1)) & 1ull; };
-    for (int j = lane; j < TH + TW; j += 64) {
-        if (j < TH) {
-            if (j >= th || !((xr >> j) & 1ull)) continue;
-            const uint16_t ka = e[2 * TW + TH + j], kb = eR[2 * TW + j];
-            if (j > 0 && ((xr >> (j - 1)) & 1ull) && e[2 * TW + TH + j - 1] == ka && eR[2 * TW + j - 1] == kb)
-                continue;
-            gunite(a.gparent, a.gkey, tile * CAP + ka, ntR * CAP + kb);
-        } else {
-            const int x = j - TH;
-            if (x >= tw || !xd_bit(x)) continue;
-            const uint16_t ka = e[TW + x], kb = eD[x];
-            if (x > 0 && xd_bit(x - 1) && e[TW + x - 1] == ka && eD[x - 1] == kb) continue;
-            gunite(a.gparent, a.gkey, tile * CAP + ka, ntD * CAP + kb);
-        }
-    }
+    // Three 64-lane passes: the right edge (TH rows), then the bottom edge in
+    // two halves (TW columns).  Every edge entry a lane needs, and the one
+    // before it (for skipping repeats), is loaded up front; all lie inside
+    // the tiles' edge arrays.
+    static_assert(TH == 64 && TW == 128, "one pass per 64 edge positions");
+    const int lm = max(lane - 1, 0);
+    const uint16_t *er = e + 2 * TW + TH, *el = eR + 2 * TW, *eb = e + TW;
+    const uint16_t r_a = er[lane], r_b = el[lane], r_ap = er[lm], r_bp = el[lm];
+    const uint16_t b1_a = eb[lane], b1_b = eD[lane], b1_ap = eb[lm], b1_bp = eD[lm];
+    const uint16_t b2_a = eb[64 + lane], b2_b = eD[64 + lane], b2_ap = eb[63 + lane], b2_bp = eD[63 + lane];
+    if (lane < th && ((xr >> lane) & 1ull) &&
+        !(lane > 0 && ((xr >> (lane - 1)) & 1ull) && r_ap == r_a && r_bp == r_b))
+        gunite(a.gparent, a.gkey, tile * CAP + r_a, ntR * CAP + r_b);
+    if (lane < tw && xd_bit(lane) && !(lane > 0 && xd_bit(lane - 1) && b1_ap == b1_a && b1_bp == b1_b))
+        gunite(a.gparent, a.gkey, tile * CAP + b1_a, ntD * CAP + b1_b);
+    const int x2 = 64 + lane;
+    if (x2 < tw && xd_bit(x2) && !(xd_bit(x2 - 1) && b2_ap == b2_a && b2_bp == b2_b))
+        gunite(a.gparent, a.gkey, tile * CAP + b2_a, ntD * CAP + b2_b);
 }
 
 // After the merge: every boundary id is pointed straight at its root and
