@@ -44,6 +44,8 @@ constexpr int NT = 512;               // threads per workgroup
 constexpr int NWAVE = NT / 64;
 constexpr int RPW = TH / NWAVE;       // tile rows per wave
 constexpr int WLIST = RPW * TW;       // per-wave work list capacity (one entry per site at most)
+constexpr int TLIST = 3 * TW;         // k_tile's per-wave lists: a row adds at most TW entries, a
+                                      // fuller list is worked off first (keeps 4 workgroups per CU)
 constexpr uint16_t ID_NONE = 0xFFFF;
 constexpr uint16_t CODE_BG = 0xFFFF;
 static_assert(TH <= 64, "right-edge crossing bits are one 64-bit word");
@@ -361,15 +363,18 @@ __device__ __forceinline__ int wave_max_below(int v)
     return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true);         // wave_shr:1, lane 0 reads 0
 }
 
+// Four workgroups per CU (8 waves per SIMD): the LDS use stays under 40 KB
+// and the registers are held to what 8 waves allow (some scalar registers
+// spill to vector lanes; the extra latency hiding is worth more).
 template <int MODE, bool EVENW, bool BATCH = false>
-__global__ __launch_bounds__(NT) void k_tile(TileArgs a)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_tile(TileArgs a)
 {
     constexpr bool NEED_DOWN = MODE == M_SW || MODE == M_SITES;  // bonds from two rows
     constexpr bool NEED_HALO = MODE == M_SW || MODE == M_SITES;  // column right of the tile
     __shared__ int P[TSITES];             // union-find parent per site slot
     __shared__ EO Rm[TH];                 // in-tile right bonds per row
     __shared__ EO Om[TH];                 // occupied sites per row
-    __shared__ uint16_t wl[NWAVE][WLIST]; // per-wave work list (contacts, then run starts)
+    __shared__ uint16_t wl[NWAVE][TLIST]; // per-wave work list (contacts, then run starts)
     __shared__ unsigned long long xr_w[NWAVE];  // right crossing bonds of each wave's rows
     __shared__ EO xd_s;                   // bottom crossing bonds
     __shared__ int nb_s;
@@ -404,6 +409,32 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     const int ly0 = wave * RPW;
     const int nr = max(0, min(RPW, th - ly0));  // tile rows owned by this wave
     uint16_t *mylist = wl[wave];
+    // Unite the n contacts of the wave's list (contact c joins slots c and
+    // c + TW).  Lane L takes contacts L, L+64, ...; a lane whose union is done
+    // takes its next contact at once, so one deep union does not hold up the
+    // other lanes of its round.
+    auto unite_list = [&](int n) {
+        wave_lds_fence();
+        int i = lane, a = 0, b = 0;
+        if (i < n) {
+            const int c = mylist[i];
+            a = lds_ld(&P[c]);
+            b = lds_ld(&P[c + TW]);
+        }
+        while (i < n) {
+            int done;
+            unite_step(P, a, b, done);
+            if (done) {
+                i += 64;
+                if (i < n) {
+                    const int c = mylist[i];
+                    a = lds_ld(&P[c]);
+                    b = lds_ld(&P[c + TW]);
+                }
+            }
+        }
+        wave_lds_fence();
+    };
     // wave-uniform lane masks
     const uint64_t V0 = lanes_lt(lx0, tw), V1 = lanes_lt(lx1, tw);
     const uint64_t L0 = lanes_eq(lx0, tw - 1), L1 = lanes_eq(lx1, tw - 1);  // last column
@@ -540,6 +571,12 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
         const int rs1 = o_start ? lx1 : rs0;
         *reinterpret_cast<int2 *>(&P[base + lx0]) = make_int2(base + rs0, base + rs1);
         if (r > 0) {
+            // contacts between this wave's own rows: a full list is united at
+            // once (only rows this wave has initialised are involved)
+            if (ncon > TLIST - TW) {
+                unite_list(ncon);
+                ncon = 0;
+            }
             const EO X = eo_and(eo_and(prevD, prevR), R);
             eo_append(mylist, ncon, eo_andnot(prevD, eo_shift1(X)), lane, base - TW);
         }
@@ -554,34 +591,15 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
 
     // ---- B: contacts with the next wave's first row, then all unions ----
     if (nr > 0 && ly0 + nr < th) {
+        if (ncon > TLIST - TW) {
+            unite_list(ncon);
+            ncon = 0;
+        }
         const EO Rn = uniform_eo(Rm[ly0 + nr]);
         const EO X = eo_and(eo_and(prevD, prevR), Rn);
         eo_append(mylist, ncon, eo_andnot(prevD, eo_shift1(X)), lane, (ly0 + nr - 1) * TW);
     }
-    wave_lds_fence();
-    // Lane L unites contacts L, L+64, ... of the list; a lane whose union is
-    // done takes its next contact at once, so one deep union does not hold up
-    // the other lanes of its round.
-    {
-        int i = lane, a = 0, b = 0;
-        if (i < ncon) {
-            const int c = mylist[i];
-            a = lds_ld(&P[c]);
-            b = lds_ld(&P[c + TW]);
-        }
-        while (i < ncon) {
-            int done;
-            unite_step(P, a, b, done);
-            if (done) {
-                i += 64;
-                if (i < ncon) {
-                    const int c = mylist[i];
-                    a = lds_ld(&P[c]);
-                    b = lds_ld(&P[c + TW]);
-                }
-            }
-        }
-    }
+    unite_list(ncon);
     __syncthreads();
 
     // Occupancy of a tile slot: images keep per-row masks, every site of a
@@ -601,10 +619,32 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
     // border position).  A compressed entry only ever replaces a parent by an
     // ancestor, and a root's own entry is left to the claims.
     // Only run starts whose parent is not themselves need a walk.
+    // Lane L walks run starts L, L+64, ... of the list; a lane whose walk is
+    // done takes its next run start at once.
+    auto compress_list = [&](int n) {
+        wave_lds_fence();
+        int i = lane, s0 = 0, x = 0;
+        if (i < n) s0 = x = mylist[i];
+        while (i < n) {
+            const int p = lds_ld(&P[x]);
+            if (p >= 0 && p != x) {
+                x = p;
+            } else {
+                if (x != s0) lds_st(&P[s0], x);
+                i += 64;
+                if (i < n) s0 = x = mylist[i];
+            }
+        }
+        wave_lds_fence();
+    };
     int nrs = 0;
     for (int r = 0; r < nr; ++r) {
         const int ly = ly0 + r;
         const int base = ly * TW;
+        if (nrs > TLIST - TW) {
+            compress_list(nrs);
+            nrs = 0;
+        }
         const EO R = uniform_eo(Rm[ly]);
         const EO O = MODE == M_SITES ? uniform_eo(Om[ly]) : valid;
         const int2 pp = *reinterpret_cast<const int2 *>(&P[base + lx0]);
@@ -612,23 +652,7 @@ __global__ __launch_bounds__(NT) void k_tile(TileArgs a)
                              lanes_ne(static_cast<uint32_t>(pp.y), static_cast<uint32_t>(base + lx0 + 1))};
         eo_append(mylist, nrs, eo_and(eo_andnot(O, eo_shift1(R)), linked), lane, base);
     }
-    wave_lds_fence();
-    {
-        // lane L takes run starts L, L+64, ...; a lane whose walk is done takes
-        // its next run start at once
-        int i = lane, s0 = 0, x = 0;
-        if (i < nrs) s0 = x = mylist[i];
-        while (i < nrs) {
-            const int p = lds_ld(&P[x]);
-            if (p >= 0 && p != x) {
-                x = p;
-            } else {
-                if (x != s0) lds_st(&P[s0], x);
-                i += 64;
-                if (i < nrs) s0 = x = mylist[i];
-            }
-        }
-    }
+    compress_list(nrs);
     for (int t = threadIdx.x; t < EDGE; t += NT) {
         const int slot = border_slot(t, tw, th);
         if (slot < 0 || !occupied(slot)) continue;
