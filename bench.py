@@ -47,6 +47,8 @@ def _args():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--study", action="store_true",
+                    help="instead of the bench line: sweep time and phases over couplings and q at L=16384")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -140,6 +142,44 @@ def _served(args, torch, sw, wl) -> dict:
             "labeled_px_per_s": round(sum(px) / wall, 1), "wall_s": round(wall, 3)}
 
 
+def _study(args) -> int:
+    """Sweep time and per-phase split of the tiled path over the paper's variant
+    axes: coupling off the critical point (0.6, 1.0, 1.4 x beta_c) and the
+    number of states (q = 2, 3, 4), L = 16384, after equilibration."""
+    import numpy as np
+    import torch
+
+    import paper_1105_5804_amd as sw
+
+    L = 16384
+    rows = []
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    for q in (2, 3, 4):
+        kc = math.log1p(math.sqrt(q))
+        for f in (0.6, 1.0, 1.4):
+            lat = sw.SWLattice(L, L, q=q, K=kc * f, seed=(0x1105580400000000 | 0x57) + q, ising=False)
+            lat.sweep(max(args.warmup, 20))
+            torch.cuda.synchronize()
+            evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+            for k in range(args.steps):
+                evs[k][0].record(stream)
+                for ph in range(3):
+                    lat.sweep_phase(ph)
+                    evs[k][ph + 1].record(stream)
+            torch.cuda.synchronize()
+            ph_ms = [float(np.mean([evs[k][p].elapsed_time(evs[k][p + 1]) for k in range(args.steps)])) for p in range(3)]
+            o = lat.observables()
+            rows.append({"q": q, "beta_over_beta_c": f, "K": round(kc * f, 6), "ms_per_sweep": round(sum(ph_ms), 4),
+                         "tile_ms": round(ph_ms[0], 4), "merge_ms": round(ph_ms[1], 4), "flip_ms": round(ph_ms[2], 4),
+                         "clusters_per_site": round(o["n_clusters"] / (L * L), 5),
+                         "active_bonds_per_site": round(o["n_active_bonds"] / (L * L), 5)})
+            print(json.dumps(rows[-1]), flush=True)
+            del lat
+            torch.cuda.empty_cache()
+    return 0
+
+
 def main() -> int:
     args = _args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -147,6 +187,9 @@ def main() -> int:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(a lattice would shard by row strips; see the design notes)", file=sys.stderr)
         return 2
+
+    if args.study:
+        return _study(args)
 
     import numpy as np
     import torch

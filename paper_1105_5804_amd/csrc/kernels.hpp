@@ -469,7 +469,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     // vertical contacts of the previous row pair.  Site s repeats the contact
     // of s-1 when s-1 has a down bond and both rows continue from s-1 to s:
     // one union per contact segment suffices.
-    unsigned long long nact = 0, xr = 0;
+    unsigned long long xr = 0;
+    int nact = 0;  // at most 2 * TSITES
     int ncon = 0;
     EO prevR = EO{0ull, 0ull}, prevD = EO{0ull, 0ull};
 #pragma unroll
@@ -521,7 +522,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                     if (v1) a.bonds_out[i0 + 1] = static_cast<uint8_t>(b1);
                 }
             }
-            nact += __popcll(mR0) + __popcll(mD0) + __popcll(mR1) + __popcll(mD1);
+            nact += __popcll(mR0) + __popcll(mD0) + __popcll(mR1) + __popcll(mD1);  // 32-bit sums
         } else if constexpr (MODE == M_BONDS_PERIODIC || MODE == M_BONDS_OPEN) {
             mR0 = lanes_ne(cur & 0x001u, 0u) & V0;
             mD0 = lanes_ne(cur & 0x002u, 0u) & V0;
@@ -585,7 +586,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     }
     if (lane == 0) {
         xr_w[wave] = xr;
-        act_w[wave] = static_cast<int>(nact);
+        act_w[wave] = nact;
     }
     __syncthreads();
 
