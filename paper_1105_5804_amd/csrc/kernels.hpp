@@ -154,12 +154,18 @@ __device__ __forceinline__ int gfind(const int *G, int x)
 
 // Roots of a and b, both chains walked at once (their loads overlap); the
 // body is straight-line, a finished chain just reloads its root.
-__device__ __forceinline__ void gfind2(const int *G, int &a, int &b)
+__device__ __forceinline__ void gfind2(int *G, int &a, int &b)
 {
+    // path halving: a node passed over is pointed at its grandparent (an
+    // ancestor, so concurrent walks stay valid), which keeps the trees of
+    // clusters that span many tiles shallow
     int pa = G[a], pb = G[b];
     while (pa != a || pb != b) {
-        a = pa;
-        b = pb;
+        const int ga = G[pa], gb = G[pb];
+        if (ga != pa) G[a] = ga;
+        if (gb != pb) G[b] = gb;
+        a = ga;
+        b = gb;
         pa = G[a];
         pb = G[b];
     }
