@@ -122,17 +122,29 @@ __device__ __forceinline__ void lds_st(int *p, int v)
 // meanwhile been linked elsewhere, the min leaves it below its old parent or
 // below the smaller root, and the union goes on with that old parent, so no
 // link is lost and every parent stays below its child.  done is set when the
-// two trees are one.
+// two trees are one.  Entries only ever decrease, so a lane with nothing to
+// link applies min(P[a], P[a]-as-read), which changes nothing: every lane
+// issues the atomic and the step needs no branch.
+// With BYTES the node values are byte offsets of the entries (4 x index), so
+// a value is directly an LDS address.
+template <bool BYTES = false>
+__device__ __forceinline__ int *lds_entry(int *P, int v)
+{
+    return BYTES ? reinterpret_cast<int *>(reinterpret_cast<char *>(P) + v) : &P[v];
+}
+
+template <bool BYTES = false>
 __device__ __forceinline__ void unite_step(int *P, int &a, int &b, int &done)
 {
-    const int pa = lds_ld(&P[a]), pb = lds_ld(&P[b]);
+    const int pa = lds_ld(lds_entry<BYTES>(P, a)), pb = lds_ld(lds_entry<BYTES>(P, b));
     const bool roots = pa == a && pb == b;
+    const bool link = roots && a != b;
     const int hi = max(a, b), lo = min(a, b);
-    int old = hi;
-    if (roots && a != b) old = __hip_atomic_fetch_min(&P[hi], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    done = roots && old == hi;
-    a = roots ? old : pa;
-    b = roots ? lo : pb;
+    const int old = __hip_atomic_fetch_min(lds_entry<BYTES>(P, link ? hi : a), link ? lo : pa, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    done = roots && (!link || old == hi);
+    a = link ? old : pa;
+    b = link ? lo : pb;
 }
 
 // ---- global union-find over boundary ids ----
@@ -316,11 +328,12 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 }
 __device__ __forceinline__ EO uniform_eo(EO m) { return EO{uniform64(m.e), uniform64(m.o)}; }
 
-// Root of x once all unions are done; a claimed root (negative entry) is a root.
+// Root of x (a byte offset, as the tile kernel's parents) once all unions are
+// done; a claimed root (negative entry) is a root.
 __device__ __forceinline__ int lroot(int *P, int x)
 {
     for (;;) {
-        const int p = lds_ld(&P[x]);
+        const int p = lds_ld(lds_entry<true>(P, x));
         if (p == x || p < 0) return x;
         x = p;
     }
@@ -377,7 +390,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 {
     constexpr bool NEED_DOWN = MODE == M_SW || MODE == M_SITES;  // bonds from two rows
     constexpr bool NEED_HALO = MODE == M_SW || MODE == M_SITES;  // column right of the tile
-    __shared__ int P[TSITES];             // union-find parent per site slot
+    __shared__ int P[TSITES];             // union-find parent per site slot, as 4 x slot
     __shared__ EO Rm[TH];                 // in-tile right bonds per row
     __shared__ EO Om[TH];                 // occupied sites per row
     __shared__ uint16_t wl[NWAVE][TLIST]; // per-wave work list (contacts, then run starts)
@@ -429,7 +442,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         }
         while (i < n) {
             int done;
-            unite_step(P, a, b, done);
+            unite_step<true>(P, a, b, done);
             if (done) {
                 i += 64;
                 if (i < n) {
@@ -576,7 +589,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         const int below_start = wave_max_below(o_start ? lx1 + 1 : (e_start ? lx0 + 1 : 0));
         const int rs0 = e_start ? lx0 : ((below_start - 1) & (TW - 1));
         const int rs1 = o_start ? lx1 : rs0;
-        *reinterpret_cast<int2 *>(&P[base + lx0]) = make_int2(base + rs0, base + rs1);
+        *reinterpret_cast<int2 *>(&P[base + lx0]) = make_int2(4 * (base + rs0), 4 * (base + rs1));
         if (r > 0) {
             // contacts between this wave's own rows: a full list is united at
             // once (only rows this wave has initialised are involved)
@@ -631,15 +644,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     auto compress_list = [&](int n) {
         wave_lds_fence();
         int i = lane, s0 = 0, x = 0;
-        if (i < n) s0 = x = mylist[i];
+        if (i < n) s0 = x = 4 * mylist[i];
         while (i < n) {
-            const int p = lds_ld(&P[x]);
+            const int p = lds_ld(lds_entry<true>(P, x));
             if (p >= 0 && p != x) {
                 x = p;
             } else {
-                if (x != s0) lds_st(&P[s0], x);
+                if (x != s0) lds_st(lds_entry<true>(P, s0), x);
                 i += 64;
-                if (i < n) s0 = x = mylist[i];
+                if (i < n) s0 = x = 4 * mylist[i];
             }
         }
         wave_lds_fence();
@@ -655,20 +668,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         const EO R = uniform_eo(Rm[ly]);
         const EO O = MODE == M_SITES ? uniform_eo(Om[ly]) : valid;
         const int2 pp = *reinterpret_cast<const int2 *>(&P[base + lx0]);
-        const EO linked = EO{lanes_ne(static_cast<uint32_t>(pp.x), static_cast<uint32_t>(base + lx0)),
-                             lanes_ne(static_cast<uint32_t>(pp.y), static_cast<uint32_t>(base + lx0 + 1))};
+        const EO linked = EO{lanes_ne(static_cast<uint32_t>(pp.x), static_cast<uint32_t>(4 * (base + lx0))),
+                             lanes_ne(static_cast<uint32_t>(pp.y), static_cast<uint32_t>(4 * (base + lx0 + 1)))};
         eo_append(mylist, nrs, eo_and(eo_andnot(O, eo_shift1(R)), linked), lane, base);
     }
     compress_list(nrs);
     for (int t = threadIdx.x; t < EDGE; t += NT) {
         const int slot = border_slot(t, tw, th);
         if (slot < 0 || !occupied(slot)) continue;
-        const int root = lroot(P, slot);
-        int expect = root;
-        if (__hip_atomic_compare_exchange_strong(&P[root], &expect, CLAIMING, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP)) {
+        const int root4 = lroot(P, 4 * slot), root = root4 >> 2;
+        int expect = root4;
+        if (__hip_atomic_compare_exchange_strong(lds_entry<true>(P, root4), &expect, CLAIMING, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
             const int k = atomicAdd(&nb_s, 1);
-            lds_st(&P[root], -(k + 2));
+            lds_st(lds_entry<true>(P, root4), -(k + 2));
             const int id = tile * CAP + k;
             a.gkey[id] = (gy0 + (root >> 7)) * W + gx0 + (root & (TW - 1));
             a.gparent[id] = id;
@@ -680,12 +693,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     // ---- E: per-site codes (boundary id of a claimed root, else CAP + the
     // root's slot), edge ids, crossing bits.  A site reaches its root in at
     // most two steps: site -> run start -> root.
-    auto code_of = [&](int x, int p) {  // p = P[x]
+    auto code_of = [&](int x, int p) {  // x a slot, p = P[x]; the walk runs on byte offsets
+        x *= 4;
         x = (p >= 0 && p != x) ? p : x;
-        p = P[max(x, 0)];
+        p = *lds_entry<true>(P, x);
         const int y = (p >= 0 && p != x) ? p : x;
-        p = (y != x) ? P[y] : p;
-        return p < 0 ? static_cast<uint32_t>(-p - 2) : static_cast<uint32_t>(CAP + y);
+        p = (y != x) ? *lds_entry<true>(P, y) : p;
+        return p < 0 ? static_cast<uint32_t>(-p - 2) : static_cast<uint32_t>(CAP + (y >> 2));
     };
     uint32_t *codes32 = reinterpret_cast<uint32_t *>(a.codes + static_cast<int64_t>(tile) * TSITES);
     for (int r = 0; r < nr; ++r) {
