@@ -640,7 +640,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     // ancestor, and a root's own entry is left to the claims.
     // Only run starts whose parent is not themselves need a walk.
     // Lane L walks run starts L, L+64, ... of the list; a lane whose walk is
-    // done takes its next run start at once.
+    // done takes its next run start at once.  Claims of waves that are done
+    // compressing run concurrently, so a root already claimed (its entry
+    // negative, no longer its own offset) can be listed: its walk ends where
+    // it starts and its entry must not be written.
     auto compress_list = [&](int n) {
         wave_lds_fence();
         int i = lane, s0 = 0, x = 0;
@@ -787,13 +790,18 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a)
     const uint16_t r_a = er[lane], r_b = el[lane], r_ap = er[lm], r_bp = el[lm];
     const uint16_t b1_a = eb[lane], b1_b = eD[lane], b1_ap = eb[lm], b1_bp = eD[lm];
     const uint16_t b2_a = eb[64 + lane], b2_b = eD[64 + lane], b2_ap = eb[63 + lane], b2_bp = eD[63 + lane];
+    // Both ends of a crossing bond are border sites, whose codes are boundary
+    // ids (< CAP); the bound keeps any other entry from addressing memory
+    // outside the tiles' tables.
+    auto ids = [](uint16_t u, uint16_t v) { return u < CAP && v < CAP; };
     if (lane < th && ((xr >> lane) & 1ull) &&
-        !(lane > 0 && ((xr >> (lane - 1)) & 1ull) && r_ap == r_a && r_bp == r_b))
+        !(lane > 0 && ((xr >> (lane - 1)) & 1ull) && r_ap == r_a && r_bp == r_b) && ids(r_a, r_b))
         gunite(a.gparent, a.gkey, tile * CAP + r_a, ntR * CAP + r_b);
-    if (lane < tw && xd_bit(lane) && !(lane > 0 && xd_bit(lane - 1) && b1_ap == b1_a && b1_bp == b1_b))
+    if (lane < tw && xd_bit(lane) && !(lane > 0 && xd_bit(lane - 1) && b1_ap == b1_a && b1_bp == b1_b) &&
+        ids(b1_a, b1_b))
         gunite(a.gparent, a.gkey, tile * CAP + b1_a, ntD * CAP + b1_b);
     const int x2 = 64 + lane;
-    if (x2 < tw && xd_bit(x2) && !(xd_bit(x2 - 1) && b2_ap == b2_a && b2_bp == b2_b))
+    if (x2 < tw && xd_bit(x2) && !(xd_bit(x2 - 1) && b2_ap == b2_a && b2_bp == b2_b) && ids(b2_a, b2_b))
         gunite(a.gparent, a.gkey, tile * CAP + b2_a, ntD * CAP + b2_b);
 }
 
