@@ -498,6 +498,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         const int ly = ly0 + r;
         const int gy = gy0 + ly;
         const uint32_t cur = pr[r], dn = pr[r + 1];
+        // lane masks are recomputed per row (one compare each) instead of
+        // being held in scalar registers across the unrolled rows, where
+        // they would spill
+        uint32_t twr = static_cast<uint32_t>(tw);
+        int lane_r = lane;
+        asm volatile("" : "+s"(twr), "+v"(lane_r));
+        const uint64_t V0 = lanes_lt(lx0, twr), V1 = lanes_lt(lx1, twr);
+        const uint64_t L0 = lanes_eq(lx0, twr - 1), L1 = lanes_eq(lx1, twr - 1);
         uint64_t mR0, mR1, mD0, mD1, O0 = V0, O1 = V1;
 
         if constexpr (MODE == M_SW) {
@@ -575,7 +583,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         // condition so the masks stay in scalar registers
         const bool last = ly == th - 1;
         const EO D = last ? EO{0ull, 0ull} : EO{mD0, mD1};
-        if (lane == 0) {
+        if (lane_r == 0) {
             if (last) xd_s = EO{mD0, mD1};
             Rm[ly] = R;
             if (MODE == M_SITES) Om[ly] = EO{O0, O1};
