@@ -512,8 +512,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             const uint32_t s0 = cur & 0xFFu, s1 = (cur >> 8) & 0xFFu;
             const uint32_t d0 = dn & 0xFFu, d1 = (dn >> 8) & 0xFFu;
             const uint32_t nxt = from_next_lane(s0);
-            const uint32_t sr0 = (!EVENW && lx0 == tw - 1) ? hl[r] : s1;
-            const uint32_t sr1 = (lx1 == tw - 1) ? hl[r] : nxt;
+            const uint32_t sr0 = (!EVENW && lx0 == static_cast<int>(twr) - 1) ? hl[r] : s1;
+            const uint32_t sr1 = (lx1 == static_cast<int>(twr) - 1) ? hl[r] : nxt;
             const int64_t i0 = static_cast<int64_t>(gy) * W + gx0 + lx0;
             uint32_t r0R, r0D, r1R, r1D;
             // the key schedule is recomputed per row (scalar adds) rather than
@@ -534,19 +534,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                 r1R = b2.v0;
                 r1D = b2.v1;
             }
-            const uint64_t on0 = a.tany ? V0 : 0ull, on1 = a.tany ? V1 : 0ull;
+            // uniform flags are re-read per row as well (held across rows
+            // as lane masks, they too would spill)
+            uint32_t tany = a.tany;
+            uint8_t *bonds_out = a.bonds_out;
+            asm volatile("" : "+s"(tany), "+s"(bonds_out));
+            const uint64_t on0 = tany ? V0 : 0ull, on1 = tany ? V1 : 0ull;
             mR0 = lanes_eq(s0, sr0) & lanes_le(r0R, a.tm1) & on0;
             mD0 = lanes_eq(s0, d0) & lanes_le(r0D, a.tm1) & on0;
             mR1 = lanes_eq(s1, sr1) & lanes_le(r1R, a.tm1) & on1;
             mD1 = lanes_eq(s1, d1) & lanes_le(r1D, a.tm1) & on1;
-            if (a.bonds_out) {
+            if (bonds_out) {
                 const uint32_t b0 = lane_bit(mR0, lane) | (lane_bit(mD0, lane) << 1);
                 const uint32_t b1 = lane_bit(mR1, lane) | (lane_bit(mD1, lane) << 1);
-                if (v1 && (EVENW || !(i0 & 1))) {
-                    *reinterpret_cast<uint16_t *>(a.bonds_out + i0) = static_cast<uint16_t>(b0 | (b1 << 8));
+                const bool w0 = lx0 < static_cast<int>(twr), w1 = lx1 < static_cast<int>(twr);
+                if (w1 && (EVENW || !(i0 & 1))) {
+                    *reinterpret_cast<uint16_t *>(bonds_out + i0) = static_cast<uint16_t>(b0 | (b1 << 8));
                 } else {
-                    if (v0) a.bonds_out[i0] = static_cast<uint8_t>(b0);
-                    if (v1) a.bonds_out[i0 + 1] = static_cast<uint8_t>(b1);
+                    if (w0) bonds_out[i0] = static_cast<uint8_t>(b0);
+                    if (w1) bonds_out[i0 + 1] = static_cast<uint8_t>(b1);
                 }
             }
             nact += __popcll(mR0) + __popcll(mD0) + __popcll(mR1) + __popcll(mD1);  // 32-bit sums
