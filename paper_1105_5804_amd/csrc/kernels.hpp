@@ -819,26 +819,6 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a)
         gunite(a.gparent, a.gkey, tile * CAP + b2_a, ntD * CAP + b2_b);
 }
 
-// After the merge: every boundary id is pointed straight at its root and
-// takes its root's key, so the flatten pass needs one load of each per id.
-// Roots keep their entries; a walk that reads an entry being compressed sees
-// its old parent or the root, both ancestors.  One wave per tile.
-__global__ __launch_bounds__(NT) void k_resolve(const int32_t *nb, int32_t *gparent, int32_t *gkey, int ntiles)
-{
-    const int lane = threadIdx.x & 63, wave = wave_id();
-    const int tile = blockIdx.x * MERGE_TILES + wave;
-    if (tile >= ntiles) return;
-    const int n = nb[tile];
-    for (int k = lane; k < n; k += 64) {
-        const int id = tile * CAP + k;
-        const int root = gfind(gparent, id);
-        if (root != id) {
-            gparent[id] = root;
-            gkey[id] = gkey[root];
-        }
-    }
-}
-
 // -------------------------------------------------------------- flatten ----
 
 struct FlatArgs {
@@ -907,8 +887,8 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
     const int nr = max(0, min(RPW, th - ly0));
     const int nbt = a.nb[tile];
     static_assert(CAP <= NT, "one boundary id per thread");
-    // after k_resolve every boundary id holds its root and the root's key; the
-    // loads are issued with the count's (entries past nb are read, not used)
+    // each boundary id's parent and key, issued with the count's loads (entries
+    // past nb are read, not used); a root's key is its cluster's canonical label
     int broot = 0, bR = 0;
     if (threadIdx.x < CAP) {
         broot = a.gparent[tile * CAP + threadIdx.x];
@@ -946,10 +926,14 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
     // loaded at the start; one id per thread since nb <= CAP <= NT
     int nbr = 0;
     if (threadIdx.x < nbt) {
-        const int k = threadIdx.x;
+        const int k = threadIdx.x, id = tile * CAP + k;
+        if (broot != id) {  // below a root (the merge keeps trees shallow): walk up, take the root's key
+            broot = gfind(a.gparent, broot);
+            bR = a.gkey[broot];
+        }
         Rb[k] = bR;
         Gid[k] = broot;
-        nbr = broot == tile * CAP + k;
+        nbr = broot == id;
         if constexpr (MODE == M_SW) ST[k] = flip_state(static_cast<uint32_t>(bR), a);
     }
     {

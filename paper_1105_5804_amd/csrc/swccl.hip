@@ -193,13 +193,6 @@ void launch_tile(const Layout &L, const TileArgs &ta, hipStream_t s)
 
 dim3 merge_grid(const Layout &L) { return dim3(static_cast<unsigned>(cdiv(L.g.ntiles, MERGE_TILES))); }
 
-// Point every boundary id at its root after the merge (all tiles of L).
-void launch_resolve(const Layout &L, void *ws, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_resolve, merge_grid(L), dim3(NT), 0, s, at<int32_t>(ws, L.nb), at<int32_t>(ws, L.gparent),
-                       at<int32_t>(ws, L.gkey), L.g.ntiles);
-}
-
 FlatArgs flat_args(const Layout &L, void *ws)
 {
     FlatArgs f{};
@@ -359,7 +352,6 @@ static sw_status launch_phase(sw_lattice *h, int32_t phase, hipStream_t s)
     }
     if (phase == SW_PHASE_MERGE) {
         hipLaunchKernelGGL(k_merge<false>, merge_grid(L), block, 0, s, merge_args(L, ws));
-        launch_resolve(L, ws, s);
         return launch_status("k_merge");
     }
     FlatArgs fa = flat_args(L, ws);
@@ -613,7 +605,6 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
     default: launch_tile<M_SITES>(L, ta, s); break;
     }
     hipLaunchKernelGGL(k_merge<false>, merge_grid(L), block, 0, s, merge_args(L, workspace));
-    launch_resolve(L, workspace, s);
     FlatArgs fa = flat_args(L, workspace);
     fa.labels = labels;
     if (want_sizes) {
@@ -785,7 +776,6 @@ sw_status swb_sweep(swb_batch *h, int32_t n_sweeps, void *stream)
         ma.b.tile_base = 0;
         ma.b.ntiles = total;
         hipLaunchKernelGGL(k_merge<true>, dim3(static_cast<unsigned>(cdiv(total, MERGE_TILES))), dim3(NT), 0, s, ma);
-        launch_resolve(L, ws, s);
         FlatArgs fa = flat_args(L, ws);
         fa.t = t;
         fa.b = bt;
