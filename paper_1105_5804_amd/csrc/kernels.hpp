@@ -309,13 +309,14 @@ __device__ __forceinline__ int lanes_below(uint64_t m)
 }
 
 // Append the sites set in m (row starting at slot `base`) to a wave list in
-// ascending order; n is the wave-uniform list length.
+// ascending order, as slot << SH; n is the wave-uniform list length.
+template <int SH = 0>
 __device__ __forceinline__ void eo_append(uint16_t *list, int &n, EO m, int lane, int base)
 {
     const int r0 = n + lanes_below(m.e) + lanes_below(m.o);
     const int b0 = lane_bit(m.e, lane) ? 1 : 0;
-    if (b0) list[r0] = static_cast<uint16_t>(base + 2 * lane);
-    if (lane_bit(m.o, lane)) list[r0 + b0] = static_cast<uint16_t>(base + 2 * lane + 1);
+    if (b0) list[r0] = static_cast<uint16_t>((base + 2 * lane) << SH);
+    if (lane_bit(m.o, lane)) list[r0 + b0] = static_cast<uint16_t>((base + 2 * lane + 1) << SH);
     n += __popcll(m.e) + __popcll(m.o);
 }
 
@@ -393,7 +394,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     __shared__ int P[TSITES];             // union-find parent per site slot, as 4 x slot
     __shared__ EO Rm[TH];                 // in-tile right bonds per row
     __shared__ EO Om[TH];                 // occupied sites per row
-    __shared__ uint16_t wl[NWAVE][TLIST]; // per-wave work list (contacts, then run starts)
+    // the image mode's extra occupancy masks are paid for by slightly shorter
+    // lists, so every mode stays under 40 KB of LDS (four workgroups per CU)
+    constexpr int TL = MODE == M_SITES ? TLIST - 8 : TLIST;
+    __shared__ uint16_t wl[NWAVE][TL];    // per-wave work list (contacts, then run starts)
     __shared__ unsigned long long xr_w[NWAVE];  // right crossing bonds of each wave's rows
     __shared__ EO xd_s;                   // bottom crossing bonds
     __shared__ int nb_s;
@@ -429,16 +433,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const int nr = max(0, min(RPW, th - ly0));  // tile rows owned by this wave
     uint16_t *mylist = wl[wave];
     // Unite the n contacts of the wave's list (contact c joins slots c and
-    // c + TW).  Lane L takes contacts L, L+64, ...; a lane whose union is done
+    // c + TW; the list holds their byte offsets).  Lane L takes contacts L, L+64, ...; a lane whose union is done
     // takes its next contact at once, so one deep union does not hold up the
     // other lanes of its round.
     auto unite_list = [&](int n) {
         wave_lds_fence();
         int i = lane, a = 0, b = 0;
         if (i < n) {
-            const int c = mylist[i];
-            a = lds_ld(&P[c]);
-            b = lds_ld(&P[c + TW]);
+            const int c = mylist[i];  // byte offset of the upper site
+            a = lds_ld(lds_entry<true>(P, c));
+            b = lds_ld(lds_entry<true>(P, c + 4 * TW));
         }
         while (i < n) {
             int done;
@@ -447,8 +451,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                 i += 64;
                 if (i < n) {
                     const int c = mylist[i];
-                    a = lds_ld(&P[c]);
-                    b = lds_ld(&P[c + TW]);
+                    a = lds_ld(lds_entry<true>(P, c));
+                    b = lds_ld(lds_entry<true>(P, c + 4 * TW));
                 }
             }
         }
@@ -607,12 +611,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         if (r > 0) {
             // contacts between this wave's own rows: a full list is united at
             // once (only rows this wave has initialised are involved)
-            if (ncon > TLIST - TW) {
+            if (ncon > TL - TW) {
                 unite_list(ncon);
                 ncon = 0;
             }
             const EO X = eo_and(eo_and(prevD, prevR), R);
-            eo_append(mylist, ncon, eo_andnot(prevD, eo_shift1(X)), lane, base - TW);
+            eo_append<2>(mylist, ncon, eo_andnot(prevD, eo_shift1(X)), lane, base - TW);
         }
         prevR = R;
         prevD = D;
@@ -625,13 +629,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 
     // ---- B: contacts with the next wave's first row, then all unions ----
     if (nr > 0 && ly0 + nr < th) {
-        if (ncon > TLIST - TW) {
+        if (ncon > TL - TW) {
             unite_list(ncon);
             ncon = 0;
         }
         const EO Rn = uniform_eo(Rm[ly0 + nr]);
         const EO X = eo_and(eo_and(prevD, prevR), Rn);
-        eo_append(mylist, ncon, eo_andnot(prevD, eo_shift1(X)), lane, (ly0 + nr - 1) * TW);
+        eo_append<2>(mylist, ncon, eo_andnot(prevD, eo_shift1(X)), lane, (ly0 + nr - 1) * TW);
     }
     unite_list(ncon);
     __syncthreads();
@@ -661,7 +665,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     auto compress_list = [&](int n) {
         wave_lds_fence();
         int i = lane, s0 = 0, x = 0;
-        if (i < n) s0 = x = 4 * mylist[i];
+        if (i < n) s0 = x = mylist[i];
         while (i < n) {
             const int p = lds_ld(lds_entry<true>(P, x));
             if (p >= 0 && p != x) {
@@ -669,7 +673,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
             } else {
                 if (x != s0) lds_st(lds_entry<true>(P, s0), x);
                 i += 64;
-                if (i < n) s0 = x = 4 * mylist[i];
+                if (i < n) s0 = x = mylist[i];
             }
         }
         wave_lds_fence();
@@ -678,7 +682,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     for (int r = 0; r < nr; ++r) {
         const int ly = ly0 + r;
         const int base = ly * TW;
-        if (nrs > TLIST - TW) {
+        if (nrs > TL - TW) {
             compress_list(nrs);
             nrs = 0;
         }
@@ -687,7 +691,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         const int2 pp = *reinterpret_cast<const int2 *>(&P[base + lx0]);
         const EO linked = EO{lanes_ne(static_cast<uint32_t>(pp.x), static_cast<uint32_t>(4 * (base + lx0))),
                              lanes_ne(static_cast<uint32_t>(pp.y), static_cast<uint32_t>(4 * (base + lx0 + 1)))};
-        eo_append(mylist, nrs, eo_and(eo_andnot(O, eo_shift1(R)), linked), lane, base);
+        eo_append<2>(mylist, nrs, eo_and(eo_andnot(O, eo_shift1(R)), linked), lane, base);
     }
     compress_list(nrs);
     for (int t = threadIdx.x; t < EDGE; t += NT) {
