@@ -378,9 +378,20 @@ __device__ __forceinline__ int wave_max_below(int v)
     v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false));  // row_shr:2
     v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false));  // row_shr:4
     v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false));  // row_shr:8
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast:15 (rows 1, 3)
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast:31 (rows 2, 3)
-    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true);         // wave_shr:1, lane 0 reads 0
+    // The row broadcasts write only the rows in their masks (1 and 3, then 2
+    // and 3) and leave the others as they are: with the destination as the
+    // second source that is one max per step (the compiler emits a copy, a
+    // broadcast and a max).  s_nop 1 gives each DPP read of a just-written
+    // register its two wait states.
+    int out;
+    asm("s_nop 1\n\t"
+        "v_max_i32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_max_i32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_mov_b32_dpp %1, %0 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"  // lane 0 reads 0
+        : "+v"(v), "=v"(out));
+    return out;
 }
 
 // Four workgroups per CU (8 waves per SIMD): the LDS use stays under 40 KB
@@ -424,7 +435,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const int gx0 = tx * TW, gy0 = ty * TH;
     const int tw = min(TW, W - gx0), th = min(TH, H - gy0);
     const int lane = threadIdx.x & 63, wave = wave_id();
-    const int lx0 = 2 * lane, lx1 = lx0 + 1;
+    const int lx0 = 2 * lane, lx1 = lx0 + 1, x4 = 4 * lx0;
     const bool v0 = lx0 < tw, v1 = lx1 < tw;
     const int hx = (gx0 + tw == W) ? 0 : gx0 + tw;  // column right of the tile
     const bool right_is_wrap = (gx0 + tw == W);
@@ -602,12 +613,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         // Run starts: site 2L starts a run unless bond 2L-1 -> 2L is present,
         // site 2L+1 unless bond 2L -> 2L+1 is; the run start of 2L is the last
         // start at or before it (a max-scan over the lanes below).
+        // Scanned in byte offsets within the row (x4 = 4 lx0); lane 0's even
+        // site always starts a run, so every other lane finds a start below.
         const bool e_start = lane_bit(~(R.o << 1), lane);
         const bool o_start = lane_bit(~R.e, lane);
-        const int below_start = wave_max_below(o_start ? lx1 + 1 : (e_start ? lx0 + 1 : 0));
-        const int rs0 = e_start ? lx0 : ((below_start - 1) & (TW - 1));
-        const int rs1 = o_start ? lx1 : rs0;
-        *reinterpret_cast<int2 *>(&P[base + lx0]) = make_int2(4 * (base + rs0), 4 * (base + rs1));
+        const int below4 = wave_max_below(o_start ? x4 + 8 : (e_start ? x4 + 4 : 0));
+        const int rs0 = e_start ? x4 : below4 - 4;
+        const int rs1 = o_start ? x4 + 4 : rs0;
+        *reinterpret_cast<int2 *>(&P[base + lx0]) = make_int2(4 * base + rs0, 4 * base + rs1);
         if (r > 0) {
             // contacts between this wave's own rows: a full list is united at
             // once (only rows this wave has initialised are involved)
