@@ -132,6 +132,18 @@ def _served(args, torch, sw, wl) -> dict:
     lat, wall = run(list(range(len(reqs))), arr)
     srv.close()
     ms = np.array([lat[k] for k in range(len(reqs))]) * 1e3
+    # the host -> device link alone: one pool image (1 byte per pixel) copied
+    # from pinned memory, the bound on pixels per second of any served mix
+    dst = torch.empty_like(pool[0], device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dst.copy_(pool[0], non_blocking=True)
+    ev0.record()
+    for _ in range(5):
+        dst.copy_(pool[0], non_blocking=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    h2d_gbs = 5 * pool[0].numel() / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del dst
     return {"workload": f"{len(reqs)} site-percolation images, side 64..8192 log-uniform, p 0.40..0.70, "
                         f"Poisson arrivals at 0.8 x closed-loop capacity; H2D from pinned host memory included",
             "closed_loop_req_per_s": round(cap, 1),
@@ -139,7 +151,8 @@ def _served(args, torch, sw, wl) -> dict:
             "offered_req_per_s": round(lam, 1),
             "p50_ms": round(float(np.percentile(ms, 50)), 4), "p99_ms": round(float(np.percentile(ms, 99)), 4),
             "mean_ms": round(float(ms.mean()), 4),
-            "labeled_px_per_s": round(sum(px) / wall, 1), "wall_s": round(wall, 3)}
+            "labeled_px_per_s": round(sum(px) / wall, 1), "wall_s": round(wall, 3),
+            "h2d_pinned_gbs": round(h2d_gbs, 1)}
 
 
 def _study(args) -> int:
