@@ -271,8 +271,14 @@ def main() -> int:
         "sweep_frac_of_hbm_roofline": round(SWEEP_BYTES_PER_SITE * N / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
     if prof and prof.get("valu_insts"):
-        # issued wave64 VALU instructions per launch (counters) over this launch time
-        roofline["valu_issue_frac"] = round(prof["valu_insts"] / (dom_ms * 1e-3) / VALU_ISSUE_PEAK, 4)
+        # the secondary (instruction-issue) ceiling: wave64 VALU instructions per
+        # launch from the counters over this launch's time, against one per CU
+        # per clock; valu_busy is the counters' own busy fraction
+        rate = prof["valu_insts"] / (dom_ms * 1e-3)
+        roofline["alu"] = {"achieved": round(rate / 1e9, 1), "peak": round(VALU_ISSUE_PEAK / 1e9, 1),
+                           "unit": "G wave64 VALU instr/s", "frac": round(rate / VALU_ISSUE_PEAK, 4),
+                           "valu_busy": prof.get("valu_busy")}
+        roofline["binds"] = "alu" if rate / VALU_ISSUE_PEAK > roofline["frac"] else "hbm"
     if dom == 0:
         # the bond RNG alone: half a Philox4x32-10 block per site at ~62 lane-cycles per block
         roofline["philox_floor_ms"] = round(N * 31 / (CUS * LANES_PER_CU_CLK * CLOCK_GHZ * 1e9) * 1e3, 4)
