@@ -345,6 +345,14 @@ def main() -> int:
         c1.record(stream)
         torch.cuda.synchronize()
         ms_b = c0.elapsed_time(c1) / reps
+        # the same sweeps replayed from a captured graph (first call captures)
+        b.sweep(1, graph=True)
+        torch.cuda.synchronize()
+        c0.record(stream)
+        b.sweep(reps, graph=True)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        ms_g = c0.elapsed_time(c1) / reps
         del b
         lats = [sw.SWLattice(sp["W"], sp["H"], q=2, K=sp["K"], seed=sp["seed"], stream_id=sp["stream_id"])
                 for sp in specs]
@@ -362,6 +370,7 @@ def main() -> int:
         torch.cuda.empty_cache()
         out["batched"] = {"workload": f"{len(specs)} Ising lattices, L in 32..1024, {nsite} sites",
                           "ms_per_sweep": round(ms_b, 4), "spins_per_s": round(nsite / (ms_b * 1e-3), 1),
+                          "graph_ms_per_sweep": round(ms_g, 4),
                           "plain_ms_per_sweep": round(ms_p, 4),
                           "plain_spins_per_s": round(nsite / (ms_p * 1e-3), 1),
                           "speedup_vs_plain": round(ms_p / ms_b, 3)}

@@ -230,8 +230,19 @@ size_t swb_workspace_bytes(const sw_params *p, int32_t n);
 sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int32_t n, void *workspace,
                    size_t workspace_bytes, void *stream);
 
-/* Enqueue n_sweeps sweeps of every lattice (asynchronous). */
+/* Enqueue n_sweeps sweeps of every lattice (asynchronous).  The kernels read
+ * the sweep index t from a counter in the workspace, which each sweep
+ * advances on the device. */
 sw_status swb_sweep(swb_batch *h, int32_t n_sweeps, void *stream);
+
+/* As swb_sweep, but each sweep is one launch of a HIP graph holding the
+ * sweep's kernels (Sec. II steps 1-3 for every lattice of the batch), captured
+ * on the first call on a stream of the library's own and replayed afterwards;
+ * the same trajectory as swb_sweep, and the two may be mixed.  The graph holds
+ * no memset nodes.  Errors: SW_ERR_ARG, SW_ERR_STATE (t would pass 2^32 - 1),
+ * SW_ERR_DEVICE if capture, instantiation or launch fails (sw_last_error()
+ * says which).  Released by swb_destroy. */
+sw_status swb_sweep_graph(swb_batch *h, int32_t n_sweeps, void *stream);
 
 /* Observables of lattice j, 0 <= j < n, as sw_observables (max_cluster is
  * always -1); waits for the stream. */

@@ -275,10 +275,12 @@ class SWBatch:
         _lib.check(_lib.lib().swb_get_t(self._h, ctypes.byref(v)), "swb_get_t")
         return int(v.value)
 
-    def sweep(self, n: int = 1, stream=None) -> None:
-        """Enqueue n sweeps of every lattice; does not wait."""
+    def sweep(self, n: int = 1, stream=None, graph: bool = False) -> None:
+        """Enqueue n sweeps of every lattice; does not wait.  With graph=True
+        each sweep is one replay of a captured HIP graph (same trajectory)."""
         torch = _torch()
-        _lib.check(_lib.lib().swb_sweep(self._h, int(n), _stream(torch, stream)), "swb_sweep")
+        fn = _lib.lib().swb_sweep_graph if graph else _lib.lib().swb_sweep
+        _lib.check(fn(self._h, int(n), _stream(torch, stream)), "swb_sweep_graph" if graph else "swb_sweep")
 
     def observables(self, j: int, stream=None) -> dict:
         """Counters of lattice j (waits for the stream)."""

@@ -95,6 +95,7 @@ SIGNATURES = {
                                   ctypes.POINTER(SwBuffers), ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p]),
     "swb_sweep": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "swb_sweep_graph": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "swb_observables": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(SwObs), ctypes.c_void_p]),
     "swb_get_t": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "swb_destroy": (ctypes.c_int32, [ctypes.c_void_p]),

@@ -81,6 +81,7 @@ struct LatticeDesc {
 struct Batch {
     const LatticeDesc *lat;
     const int32_t *lat_of_tile;  // batch tile -> lattice
+    const uint32_t *t;           // the batch's sweep counter, read on the device (graph replays)
     int32_t tile_base, ntiles;   // this launch covers tiles [tile_base, tile_base + ntiles)
 };
 
@@ -270,6 +271,12 @@ __global__ void k_zero_i32(int32_t *p, int n)
     if (i < n) p[i] = 0;
 }
 
+// Advance a device-side sweep counter (the last launch of a batched sweep).
+__global__ void k_bump_u32(uint32_t *p)
+{
+    if (threadIdx.x == 0) p[0] += 1u;
+}
+
 // ----------------------------------------------------------------- tile ----
 
 struct TileArgs {
@@ -426,6 +433,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         a.k0 = L.k0;
         a.k1 = L.k1;
         a.sid = L.sid;
+        a.t = *a.b.t;
         lt = tile - L.tile0;
     } else {
         tile = lt = xcd_remap(blockIdx.x, a.g.ntiles);
@@ -890,6 +898,7 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
         a.k1 = L.k1;
         a.sid = L.sid;
         a.ising = L.ising;
+        a.t = *a.b.t;
         lt = tile - L.tile0;
     } else {
         tile = lt = xcd_remap(blockIdx.x, a.g.ntiles);

@@ -31,7 +31,7 @@ struct Layout {
     int64_t nrow;  // H * ntx: entries of the per-(row, tile column) root counts
     size_t codes, gkey, gparent, gsize, edges, xbits, nb, tile_act, tile_ncl, stats;
     size_t row_count, row_off, scan_tmp, rl_slot, rl_size;
-    size_t lat_desc, lat_of_tile;  // batches only
+    size_t lat_desc, lat_of_tile, t_dev;  // batches only
     size_t total;
 };
 
@@ -117,6 +117,8 @@ Layout make_batch_layout(int64_t ntiles, int32_t nlat)
     off += align_up(static_cast<size_t>(nlat) * sizeof(LatticeDesc));
     L.lat_of_tile = off;
     off += align_up(static_cast<size_t>(ntiles) * sizeof(int32_t));
+    L.t_dev = off;
+    off += align_up(sizeof(uint32_t));
     L.total = off;
     return L;
 }
@@ -637,8 +639,12 @@ struct swb_batch {
     Layout L;
     void *ws;
     int32_t tiles_even;  // tiles of even-width lattices come first
-    uint64_t t;
+    uint64_t t;          // host mirror of the device sweep counter
     bool swept;
+    // one sweep captured as a graph (swb_sweep_graph), made on first use
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 static sw_status check_batch(const sw_params *p, const sw_buffers *b, int32_t n, int64_t *ntiles)
@@ -725,6 +731,10 @@ sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int
         st = device_status(hipMemcpyAsync(at<int32_t>(workspace, L.lat_of_tile), h->lat_of_tile.data(),
                                           h->lat_of_tile.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
                            "copy tile table");
+    if (st == SW_OK) {
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, at<int32_t>(workspace, L.t_dev), 1);
+        st = launch_status("k_zero_i32");
+    }
     for (int32_t j = 0; j < n && st == SW_OK; ++j) {
         if (p[j].flags & SW_F_KEEP_SPINS) continue;
         const int64_t N = static_cast<int64_t>(p[j].W) * p[j].H;
@@ -744,45 +754,103 @@ sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int
     return SW_OK;
 }
 
-sw_status swb_sweep(swb_batch *h, int32_t n_sweeps, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Enqueue one batched sweep: tile launches (per width parity), merge, flatten,
+// and the bump of the device sweep counter the kernels read t from.
+void enqueue_batch_sweep(const swb_batch *h, hipStream_t s)
 {
-    if (!h || n_sweeps < 0) return SW_ERR_ARG;
-    if (h->t + static_cast<uint64_t>(n_sweeps) > 0xFFFFFFFFull) return SW_ERR_STATE;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     const Layout &L = h->L;
     void *ws = h->ws;
     Batch bt{};
     bt.lat = at<LatticeDesc>(ws, L.lat_desc);
     bt.lat_of_tile = at<int32_t>(ws, L.lat_of_tile);
+    bt.t = at<uint32_t>(ws, L.t_dev);
     const int32_t total = L.g.ntiles, even = h->tiles_even;
+    TileArgs ta = tile_args(L, ws, nullptr);
+    ta.b = bt;
+    if (even > 0) {
+        ta.b.tile_base = 0;
+        ta.b.ntiles = even;
+        hipLaunchKernelGGL((k_tile<M_SW, true, true>), dim3(static_cast<unsigned>(even)), dim3(NT), 0, s, ta);
+    }
+    if (total > even) {
+        ta.b.tile_base = even;
+        ta.b.ntiles = total - even;
+        hipLaunchKernelGGL((k_tile<M_SW, false, true>), dim3(static_cast<unsigned>(total - even)), dim3(NT), 0, s,
+                           ta);
+    }
+    MergeArgs ma = merge_args(L, ws);
+    ma.b = bt;
+    ma.b.tile_base = 0;
+    ma.b.ntiles = total;
+    hipLaunchKernelGGL(k_merge<true>, dim3(static_cast<unsigned>(cdiv(total, MERGE_TILES))), dim3(NT), 0, s, ma);
+    FlatArgs fa = flat_args(L, ws);
+    fa.b = bt;
+    fa.b.tile_base = 0;
+    fa.b.ntiles = total;
+    hipLaunchKernelGGL((k_flatten<M_SW, false, true>), dim3(static_cast<unsigned>(total)), dim3(NT), 0, s, fa);
+    hipLaunchKernelGGL(k_bump_u32, dim3(1), dim3(64), 0, s, at<uint32_t>(ws, L.t_dev));
+}
+
+void drop_graph(swb_batch *h)
+{
+    if (h->exec) (void)hipGraphExecDestroy(h->exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    h->exec = nullptr;
+    h->graph = nullptr;
+    h->cap = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+sw_status swb_sweep(swb_batch *h, int32_t n_sweeps, void *stream)
+{
+    if (!h || n_sweeps < 0) return SW_ERR_ARG;
+    if (h->t + static_cast<uint64_t>(n_sweeps) > 0xFFFFFFFFull) return SW_ERR_STATE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
     for (int32_t k = 0; k < n_sweeps; ++k) {
-        const uint32_t t = static_cast<uint32_t>(h->t);
-        TileArgs ta = tile_args(L, ws, nullptr);
-        ta.t = t;
-        ta.b = bt;
-        if (even > 0) {
-            ta.b.tile_base = 0;
-            ta.b.ntiles = even;
-            hipLaunchKernelGGL((k_tile<M_SW, true, true>), dim3(static_cast<unsigned>(even)), dim3(NT), 0, s, ta);
-        }
-        if (total > even) {
-            ta.b.tile_base = even;
-            ta.b.ntiles = total - even;
-            hipLaunchKernelGGL((k_tile<M_SW, false, true>), dim3(static_cast<unsigned>(total - even)), dim3(NT), 0,
-                               s, ta);
-        }
-        MergeArgs ma = merge_args(L, ws);
-        ma.b = bt;
-        ma.b.tile_base = 0;
-        ma.b.ntiles = total;
-        hipLaunchKernelGGL(k_merge<true>, dim3(static_cast<unsigned>(cdiv(total, MERGE_TILES))), dim3(NT), 0, s, ma);
-        FlatArgs fa = flat_args(L, ws);
-        fa.t = t;
-        fa.b = bt;
-        fa.b.tile_base = 0;
-        fa.b.ntiles = total;
-        hipLaunchKernelGGL((k_flatten<M_SW, false, true>), dim3(static_cast<unsigned>(total)), dim3(NT), 0, s, fa);
+        enqueue_batch_sweep(h, s);
         const sw_status st = launch_status("swb_sweep");
+        if (st != SW_OK) return st;
+        h->t += 1;
+        h->swept = true;
+    }
+    return SW_OK;
+}
+
+sw_status swb_sweep_graph(swb_batch *h, int32_t n_sweeps, void *stream)
+{
+    if (!h || n_sweeps < 0) return SW_ERR_ARG;
+    if (h->t + static_cast<uint64_t>(n_sweeps) > 0xFFFFFFFFull) return SW_ERR_STATE;
+    if (n_sweeps == 0) return SW_OK;
+    if (!h->exec) {
+        // capture on a stream of the library's own: capture runs nothing, and
+        // the caller's stream may be one that cannot be captured
+        sw_status st = device_status(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking), "create capture stream");
+        if (st == SW_OK)
+            st = device_status(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (st == SW_OK) {
+            enqueue_batch_sweep(h, h->cap);
+            const hipError_t le = hipGetLastError();
+            const hipError_t ee = hipStreamEndCapture(h->cap, &h->graph);
+            st = device_status(le != hipSuccess ? le : ee, "capture batched sweep");
+        }
+        if (st == SW_OK) st = device_status(hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0),
+                                            "instantiate batched sweep");
+        if (st != SW_OK) {
+            drop_graph(h);
+            return st;
+        }
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int32_t k = 0; k < n_sweeps; ++k) {
+        const sw_status st = device_status(hipGraphLaunch(h->exec, s), "launch batched sweep graph");
         if (st != SW_OK) return st;
         h->t += 1;
         h->swept = true;
@@ -811,6 +879,7 @@ sw_status swb_get_t(const swb_batch *h, uint64_t *t)
 sw_status swb_destroy(swb_batch *h)
 {
     if (!h) return SW_ERR_ARG;
+    drop_graph(h);
     delete h;
     return SW_OK;
 }

@@ -166,6 +166,7 @@ def test_batch_argument_errors():
     assert L.swb_workspace_bytes(PS, 1) == 0
     assert L.swb_init(ctypes.byref(h), PS, B, 1, ws, need, None) == _lib.SW_ERR_UNSUPPORTED
     assert L.swb_sweep(None, 1, None) == _lib.SW_ERR_ARG
+    assert L.swb_sweep_graph(None, 1, None) == _lib.SW_ERR_ARG
     assert L.swb_observables(None, 0, None, None) == _lib.SW_ERR_ARG
     assert L.swb_get_t(None, None) == _lib.SW_ERR_ARG
     assert L.swb_destroy(None) == _lib.SW_ERR_ARG

@@ -79,3 +79,28 @@ def test_batch256():
             o = b.observables(j)
             assert o["n_clusters"] == rec[1, oracle.REC_NCLUST], j
             assert o["n_sat"] == rec[1, oracle.REC_NSAT], j
+
+
+def test_batch_graph_replays():
+    """Sweeps replayed from a captured HIP graph, mixed with eager sweeps and
+    with eager work and synchronisations between the replays: every sweep of
+    every lattice matches the oracle."""
+    specs = [dict(sp, stream_id=j) for j, sp in enumerate(MIX)]
+    b = sw.SWBatch(specs, keep_labels=True, keep_bonds=True)
+    st = [oracle.init_states(sp["W"], sp["H"], sp["q"], sp["seed"], sp["stream_id"]) for sp in b.specs]
+    for t, graph in enumerate([True, True, False, True, True]):
+        print(f"batch graph replay t={t} graph={graph}", flush=True)
+        b.sweep(1, graph=graph)
+        torch.cuda.synchronize()
+        for j, sp in enumerate(b.specs):
+            W, H, q = sp["W"], sp["H"], sp["q"]
+            T = oracle.threshold(sp["K"])
+            new, bonds, labels, rec = oracle.sw_sweep(W, H, q, T, sp["seed"], sp["stream_id"], t, st[j])
+            assert np.array_equal(b.bonds[j].cpu().numpy().reshape(-1), bonds), (j, t)
+            assert np.array_equal(b.labels[j].cpu().numpy().reshape(-1), labels), (j, t)
+            assert np.array_equal(_state(b.spins[j], sp["ising"]), new), (j, t)
+            o = b.observables(j)  # eager work between the replays
+            assert o["t"] == t + 1
+            assert o["n_clusters"] == rec[oracle.REC_NCLUST]
+            st[j] = new
+    assert b.t == 5
