@@ -1229,7 +1229,8 @@ __global__ __launch_bounds__(SMALL_NT) void k_small(SmallArgs a)
     __shared__ int P[TSITES];
     __shared__ uint8_t S[TSITES];   // states 0..q-1
     __shared__ uint8_t NS[TSITES];  // new state, at root slots
-    __shared__ unsigned long long red[NWAVE][11];
+    __shared__ unsigned long long red[NWAVE][3];
+    static_assert(2 * TSITES < (1 << 16), "per-workgroup counters fit 16-bit fields");
     const int W = a.W, H = a.H, N = W * H;
     const float inv_w = 1.0f / static_cast<float>(W);
     const int lane = threadIdx.x & 63, wave = wave_id();
@@ -1246,6 +1247,39 @@ __global__ __launch_bounds__(SMALL_NT) void k_small(SmallArgs a)
         S[i] = static_cast<uint8_t>(a.ising ? (b == 1u ? 1u : 0u) : b);
     }
     __syncthreads();
+    // Counters of a sweep's new spins (satisfied bonds, state counts) are
+    // taken during the next sweep's bond pass, which compares every
+    // neighbour pair anyway; those of the last sweep by one pass at the end.
+    // They are reduced as 16-bit fields, four to a word: no total of a
+    // workgroup exceeds 2 x 8192 (the bonds of a full tile).
+    auto reduce_record = [&](unsigned long long act, unsigned long long ncl, unsigned long long nsat,
+                             const unsigned long long (&cnt)[8]) {
+        unsigned long long pk[3] = {act | (ncl << 16) | (nsat << 32) | (cnt[0] << 48),
+                                    cnt[1] | (cnt[2] << 16) | (cnt[3] << 32) | (cnt[4] << 48),
+                                    cnt[5] | (cnt[6] << 16) | (cnt[7] << 32)};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const unsigned long long w = wave_sum(pk[k]);
+            if (lane == 0) red[wave][k] = w;
+        }
+    };
+    // after a barrier: thread k < 11 writes field k of the record of `sweep`
+    auto write_record = [&](int sweep, bool last) {
+        if (threadIdx.x >= 11) return;
+        const int k = threadIdx.x;
+        unsigned long long sum = 0;
+        for (int w = 0; w < NWAVE; ++w) sum += red[w][k >> 2];
+        const unsigned long long tot = (sum >> (16 * (k & 3))) & 0xFFFFull;
+        if (a.hist) {
+            int64_t *row = a.hist + static_cast<int64_t>(sweep) * HIST_LEN;
+            const int col = k == 0 ? HIST_ACTIVE : k == 1 ? HIST_NCLUST : k == 2 ? HIST_NSAT : HIST_COUNTS + k - 3;
+            row[col] = static_cast<int64_t>(tot);
+            if (k == 0) row[HIST_MAXCL] = -1;
+        }
+        if (last && k == 0) a.tile_act[0] = static_cast<int32_t>(tot);
+        if (last && k == 1) a.tile_ncl[0] = static_cast<int32_t>(tot);
+    };
+    unsigned long long prev_act = 0, prev_ncl = 0;
     for (int sweep = 0; sweep < a.n; ++sweep) {
         const uint32_t t = a.t0 + static_cast<uint32_t>(sweep);
         const bool last = sweep + 1 == a.n;
@@ -1253,6 +1287,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_small(SmallArgs a)
         // bonds of the thread's site pairs (one Philox block per pair): bit
         // 4m + 2j + k of `bonds` is bond k (0 right, 1 down) of site 2p + j
         uint32_t bonds = 0;
+        unsigned long long nsat = 0, cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int m = 0; m < PAIRS_PER_THREAD; ++m) {
             const int p = threadIdx.x + NT * m;
@@ -1263,15 +1298,24 @@ __global__ __launch_bounds__(SMALL_NT) void k_small(SmallArgs a)
                 const int i = 2 * p + j;
                 if (i >= N) break;
                 const uint32_t wr = j ? blk.v2 : blk.v0, wd = j ? blk.v3 : blk.v1;
-                const bool br = a.tany && S[i] == S[right_of(i)] && wr <= a.tm1;
-                const bool bd = a.tany && S[i] == S[down_of(i)] && wd <= a.tm1;
+                const uint32_t si = S[i];
+                const bool er = si == S[right_of(i)], ed = si == S[down_of(i)];
+                if (a.hist) {
+                    nsat += static_cast<unsigned>(er) + static_cast<unsigned>(ed);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) cnt[k] += si == static_cast<uint32_t>(k) ? 1u : 0u;
+                }
+                const bool br = a.tany && er && wr <= a.tm1;
+                const bool bd = a.tany && ed && wd <= a.tm1;
                 bonds |= (br ? 1u : 0u) << (4 * m + 2 * j);
                 bonds |= (bd ? 1u : 0u) << (4 * m + 2 * j + 1);
                 if (last && a.bonds_out) a.bonds_out[i] = static_cast<uint8_t>((br ? 1 : 0) | (bd ? 2 : 0));
             }
         }
         const unsigned long long act = static_cast<unsigned>(__popc(bonds));
+        if (sweep > 0 && a.hist) reduce_record(prev_act, prev_ncl, nsat, cnt);  // the previous sweep's record
         __syncthreads();
+        if (sweep > 0 && a.hist) write_record(sweep - 1, false);
         // unions of the thread's active bonds, one flat loop: a finished union
         // takes the next bond at once
         {
@@ -1316,37 +1360,21 @@ __global__ __launch_bounds__(SMALL_NT) void k_small(SmallArgs a)
             if (last && a.labels) a.labels[i] = P[i];
         }
         __syncthreads();
-        if (a.hist || last) {
-            // counters of the new spins
-            unsigned long long v[11];
-            v[0] = act;
-            v[1] = ncl;
-            for (int k = 2; k < 11; ++k) v[k] = 0;
-            for (int i = threadIdx.x; i < N; i += NT) {
-                const uint32_t si = S[i];
-                v[2] += static_cast<unsigned>(si == S[right_of(i)]) + static_cast<unsigned>(si == S[down_of(i)]);
-                if (si < 8) v[3 + si] += 1;
-            }
-            for (int k = 0; k < 11; ++k) {
-                const unsigned long long w = wave_sum(v[k]);
-                if (lane == 0) red[wave][k] = w;
-            }
-            __syncthreads();
-            if (threadIdx.x < 11) {
-                unsigned long long tot = 0;
-                for (int w = 0; w < NWAVE; ++w) tot += red[w][threadIdx.x];
-                const int k = threadIdx.x;
-                if (a.hist) {
-                    int64_t *row = a.hist + static_cast<int64_t>(sweep) * HIST_LEN;
-                    const int col = k == 0 ? HIST_ACTIVE : k == 1 ? HIST_NCLUST : k == 2 ? HIST_NSAT : HIST_COUNTS + k - 3;
-                    row[col] = static_cast<int64_t>(tot);
-                    if (k == 0) row[HIST_MAXCL] = -1;
-                }
-                if (last && k == 0) a.tile_act[0] = static_cast<int32_t>(tot);
-                if (last && k == 1) a.tile_ncl[0] = static_cast<int32_t>(tot);
-            }
-            __syncthreads();
+        prev_act = act;
+        prev_ncl = ncl;
+    }
+    {
+        // the last sweep's record, from the final spins
+        unsigned long long nsat = 0, cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int i = threadIdx.x; i < N; i += NT) {
+            const uint32_t si = S[i];
+            nsat += static_cast<unsigned>(si == S[right_of(i)]) + static_cast<unsigned>(si == S[down_of(i)]);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cnt[k] += si == static_cast<uint32_t>(k) ? 1u : 0u;
         }
+        reduce_record(prev_act, prev_ncl, nsat, cnt);
+        __syncthreads();
+        write_record(a.n - 1, true);
     }
     for (int i = threadIdx.x; i < N; i += NT) {
         const uint32_t st = S[i];
