@@ -1194,8 +1194,8 @@ __global__ __launch_bounds__(NT) void k_emit(EmitArgs a)
 // ------------------------------------------------------- small lattices ---
 //
 // A lattice of one tile (W <= TW, H <= TH) is swept entirely inside one
-// workgroup: spins, union-find parents and the new state of every root stay in
-// LDS for all n sweeps of one launch, so a sweep costs neither launches nor an
+// workgroup: spins and union-find parents stay in LDS for all n sweeps of one
+// launch, so a sweep costs neither launches nor an
 // HBM round trip (a 64 x 64 lattice is launch-latency bound otherwise).  The
 // bonds, canonical labels and new states are those of the tiled path; every
 // bond, wrap bonds included, is a union inside the workgroup.
@@ -1228,7 +1228,6 @@ __global__ __launch_bounds__(SMALL_NT) void k_small(SmallArgs a)
     constexpr int PAIRS_PER_THREAD = TSITES / 2 / NT;  // site pairs 2p, 2p+1 with p = tid + NT m
     __shared__ int P[TSITES];
     __shared__ uint8_t S[TSITES];   // states 0..q-1
-    __shared__ uint8_t NS[TSITES];  // new state, at root slots
     __shared__ unsigned long long red[NWAVE][3];
     static_assert(2 * TSITES < (1 << 16), "per-workgroup counters fit 16-bit fields");
     const int W = a.W, H = a.H, N = W * H;
@@ -1336,7 +1335,12 @@ __global__ __launch_bounds__(SMALL_NT) void k_small(SmallArgs a)
             }
         }
         __syncthreads();
-        // every site straight to its root (replacing a parent by an ancestor)
+        // Every site to its root (replacing parents by ancestors on the way),
+        // then the new state of its cluster: the draw at the canonical root
+        // (one uniform per cluster), which each site evaluates itself; with
+        // roots spread over the lanes a wave would pay for every draw anyway,
+        // and no table of new states (nor its barrier) is needed.
+        unsigned long long ncl = 0;
         for (int i = threadIdx.x; i < N; i += NT) {
             int x = i, px = lds_ld(&P[x]);
             while (px != x) {
@@ -1344,20 +1348,10 @@ __global__ __launch_bounds__(SMALL_NT) void k_small(SmallArgs a)
                 px = lds_ld(&P[x]);
             }
             if (x != i) lds_st(&P[i], x);
-        }
-        __syncthreads();
-        // one draw per cluster at its canonical (minimum) root
-        unsigned long long ncl = 0;
-        for (int i = threadIdx.x; i < N; i += NT) {
-            if (P[i] != i) continue;
-            const U4 b = philox4x32_10(static_cast<uint32_t>(i) >> 2, t, TAG_FLIP, a.sid, a.k0, a.k1);
-            NS[i] = static_cast<uint8_t>(draw_state(pick(b, static_cast<uint32_t>(i) & 3u), a.q));
-            ++ncl;
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < N; i += NT) {
-            S[i] = NS[P[i]];
-            if (last && a.labels) a.labels[i] = P[i];
+            ncl += x == i ? 1u : 0u;
+            const U4 b = philox4x32_10(static_cast<uint32_t>(x) >> 2, t, TAG_FLIP, a.sid, a.k0, a.k1);
+            S[i] = static_cast<uint8_t>(draw_state(pick(b, static_cast<uint32_t>(x) & 3u), a.q));
+            if (last && a.labels) a.labels[i] = x;
         }
         __syncthreads();
         prev_act = act;
