@@ -81,9 +81,15 @@ enum { SW_SPIN_ISING_I8 = 0, SW_SPIN_POTTS_U8 = 1 };
 enum {
     SW_F_KEEP_SPINS = 1u << 0, /* sw_init: do not draw initial spins; use the
                                   caller's (restart from a saved state)       */
-    SW_F_SIZES = 1u << 1       /* every sweep also lists its clusters: roots
+    SW_F_SIZES = 1u << 1,      /* every sweep also lists its clusters: roots
                                   (ascending) and sizes into sw_buffers.roots /
                                   .sizes, and the largest size (sw_obs)       */
+    SW_F_REVERSE_TILES = 1u << 2 /* a schedule check: the workgroups of the
+                                  tile, merge and flip launches visit the
+                                  tiles in the reverse order.  Every output is
+                                  canonical (minimum-index labels, draws keyed
+                                  on the index), so it is identical either
+                                  way; batches reject this flag. */
 };
 
 /* Input kinds of ccl_label. */

@@ -103,12 +103,14 @@ class SWLattice:
     With ``keep_labels`` / ``keep_bonds`` the canonical labels / packed bonds of
     the last sweep are kept in ``labels`` / ``bonds``; with ``sizes`` every sweep
     also lists its clusters (``cluster_sizes()``) and their largest size.
+    ``reverse_tiles`` runs the tiles in the reverse order (a schedule check:
+    every output is the same).
     """
 
     def __init__(self, W: int, H: int, q: int = 2, K: float | None = None, seed: int = 0,
                  stream_id: int = 0, ising: bool | None = None, keep_labels: bool = False,
                  keep_bonds: bool = False, sizes: bool = False, spins=None, t: int = 0,
-                 device: str = "cuda"):
+                 device: str = "cuda", reverse_tiles: bool = False):
         torch = _torch()
         L = _lib.lib()
         if ising is None:
@@ -120,7 +122,7 @@ class SWLattice:
         self.device = torch.device(device)
         p = _lib.SwParams(self.W, self.H, self.q, _lib.SW_SPIN_ISING_I8 if ising else _lib.SW_SPIN_POTTS_U8,
                           self.K, self.seed & (2**64 - 1), self.stream_id,
-                          _lib.SW_F_SIZES if sizes else 0)
+                          (_lib.SW_F_SIZES if sizes else 0) | (_lib.SW_F_REVERSE_TILES if reverse_tiles else 0))
         ws = L.sw_workspace_bytes(ctypes.byref(p))
         if ws == 0:
             _lib.check(_lib.SW_ERR_ARG if self.W >= 2 and self.H >= 2 else _lib.SW_ERR_SIZE, "sw_workspace_bytes")

@@ -12,7 +12,7 @@ ABI_VERSION = 2  # the SWCCL_ABI_VERSION these declarations follow
 # status codes
 SW_OK, SW_ERR_ARG, SW_ERR_SIZE, SW_ERR_WORKSPACE, SW_ERR_DEVICE, SW_ERR_STATE, SW_ERR_UNSUPPORTED = range(7)
 SW_SPIN_ISING_I8, SW_SPIN_POTTS_U8 = 0, 1
-SW_F_KEEP_SPINS, SW_F_SIZES = 1, 2
+SW_F_KEEP_SPINS, SW_F_SIZES, SW_F_REVERSE_TILES = 1, 2, 4
 CCL_BONDS_PERIODIC, CCL_BONDS_OPEN, CCL_SITES_OPEN = 0, 1, 2
 SW_PHASE_TILE, SW_PHASE_MERGE, SW_PHASE_FLIP = 0, 1, 2
 SW_HIST_ACTIVE, SW_HIST_NCLUST, SW_HIST_MAXCL, SW_HIST_NSAT, SW_HIST_COUNTS, SW_HIST_LEN = 0, 1, 2, 3, 4, 12

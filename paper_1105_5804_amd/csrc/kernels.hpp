@@ -60,6 +60,7 @@ enum { ST_ACTIVE = 0, ST_NCLUST = 1, ST_NSAT = 2, ST_MAGNET = 3, ST_COUNTS = 4, 
 
 struct Grid {
     int W, H, ntx, nty, ntiles;
+    int rev;  // visit the tiles in reverse order (single lattices only; a schedule check)
 };
 
 // One lattice of a batched launch (many independent lattices swept by one
@@ -437,6 +438,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         lt = tile - L.tile0;
     } else {
         tile = lt = xcd_remap(blockIdx.x, a.g.ntiles);
+        if (a.g.rev) tile = lt = a.g.ntiles - 1 - tile;
     }
     const int W = a.g.W, H = a.g.H;
     const int tx = lt % a.g.ntx, ty = lt / a.g.ntx;
@@ -806,6 +808,7 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a)
         tile0 = L.tile0;
     } else {
         if (tile >= a.g.ntiles) return;
+        if (a.g.rev) tile = a.g.ntiles - 1 - tile;
     }
     const int lt = tile - tile0;
     const int tx = lt % a.g.ntx, ty = lt / a.g.ntx;
@@ -902,6 +905,7 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
         lt = tile - L.tile0;
     } else {
         tile = lt = xcd_remap(blockIdx.x, a.g.ntiles);
+        if (a.g.rev) tile = lt = a.g.ntiles - 1 - tile;
     }
     const int W = a.g.W;
     const int tx = lt % a.g.ntx, ty = lt / a.g.ntx;

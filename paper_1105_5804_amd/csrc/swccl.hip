@@ -284,7 +284,7 @@ static sw_status check_params(const sw_params *p)
     if (p->spin_kind != SW_SPIN_ISING_I8 && p->spin_kind != SW_SPIN_POTTS_U8) return SW_ERR_ARG;
     if (p->spin_kind == SW_SPIN_ISING_I8 && p->q != 2) return SW_ERR_ARG;
     if (std::isnan(p->K)) return SW_ERR_ARG;
-    if (p->flags & ~static_cast<uint32_t>(SW_F_KEEP_SPINS | SW_F_SIZES)) return SW_ERR_ARG;
+    if (p->flags & ~static_cast<uint32_t>(SW_F_KEEP_SPINS | SW_F_SIZES | SW_F_REVERSE_TILES)) return SW_ERR_ARG;
     return SW_OK;
 }
 
@@ -310,6 +310,7 @@ sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, voi
     h->p = *p;
     h->b = *b;
     h->L = L;
+    h->L.g.rev = (p->flags & SW_F_REVERSE_TILES) ? 1 : 0;
     h->T = threshold_of(p->K);
     h->t = 0;
     h->swept = false;
@@ -654,7 +655,7 @@ static sw_status check_batch(const sw_params *p, const sw_buffers *b, int32_t n,
     for (int32_t j = 0; j < n; ++j) {
         const sw_status st = check_params(&p[j]);
         if (st != SW_OK) return st;
-        if (p[j].flags & SW_F_SIZES) return SW_ERR_UNSUPPORTED;
+        if (p[j].flags & (SW_F_SIZES | SW_F_REVERSE_TILES)) return SW_ERR_UNSUPPORTED;
         if (!b[j].spins || b[j].roots || b[j].sizes) return SW_ERR_ARG;
         nt += cdiv(p[j].W, TW) * cdiv(p[j].H, TH);
     }

@@ -165,6 +165,10 @@ def test_batch_argument_errors():
     PS = (_lib.SwParams * 1)(_params(flags=_lib.SW_F_SIZES))
     assert L.swb_workspace_bytes(PS, 1) == 0
     assert L.swb_init(ctypes.byref(h), PS, B, 1, ws, need, None) == _lib.SW_ERR_UNSUPPORTED
+    PR = (_lib.SwParams * 1)(_params(flags=_lib.SW_F_REVERSE_TILES))  # single lattices only
+    assert L.swb_workspace_bytes(PR, 1) == 0
+    assert L.swb_init(ctypes.byref(h), PR, B, 1, ws, need, None) == _lib.SW_ERR_UNSUPPORTED
+    assert L.sw_workspace_bytes(ctypes.byref(PR[0])) > 0
     assert L.swb_sweep(None, 1, None) == _lib.SW_ERR_ARG
     assert L.swb_sweep_graph(None, 1, None) == _lib.SW_ERR_ARG
     assert L.swb_observables(None, 0, None, None) == _lib.SW_ERR_ARG

@@ -332,3 +332,34 @@ def test_small_path_matches_tiled_path():
         assert torch.equal(a.spins, b.spins), (W, H)
         assert torch.equal(a.labels, b.labels) and torch.equal(a.bonds, b.bonds), (W, H)
         assert a.observables() == b.observables()
+
+
+@pytest.mark.parametrize("W,H,q,ising,sizes", [(1000, 300, 3, False, False), (517, 260, 2, True, True)])
+def test_schedule_independence(W, H, q, ising, sizes):
+    """Tiles visited in the reverse order (another workgroup -> tile schedule,
+    hence other orders of atomics, claims and merges): bonds, labels, spins,
+    sizes and counters are identical after every sweep, and equal the oracle."""
+    print(f"case W={W} H={H} q={q} ising={ising} sizes={sizes}", flush=True)
+    seed, sid = wl.SEED_BASE | 0x4E, 2
+    K = wl.K_ISING_C if ising else wl.K_POTTS3_C
+    kw = dict(q=q, K=K, seed=seed, stream_id=sid, ising=ising, keep_labels=True, keep_bonds=True, sizes=sizes)
+    fwd, rev = sw.SWLattice(W, H, **kw), sw.SWLattice(W, H, reverse_tiles=True, **kw)
+    T = oracle.threshold(K)
+    st = oracle.init_states(W, H, q, seed, sid)
+    for t in range(3):
+        fwd.sweep(1)
+        rev.sweep(1)
+        new, bonds, labels, rec = oracle.sw_sweep(W, H, q, T, seed, sid, t, st)
+        torch.cuda.synchronize()
+        for lat in (fwd, rev):
+            assert np.array_equal(lat.bonds.cpu().numpy().reshape(-1), bonds), t
+            assert np.array_equal(lat.labels.cpu().numpy().reshape(-1), labels), t
+            assert np.array_equal(_state(lat), new), t
+        if sizes:
+            rf, sf = fwd.cluster_sizes()
+            rr, sr = rev.cluster_sizes()
+            assert torch.equal(rf, rr) and torch.equal(sf, sr), t
+        of, orv = fwd.observables(), rev.observables()
+        for key in ("n_sat", "n_clusters", "n_active_bonds", "max_cluster", "digest_labels"):
+            assert of[key] == orv[key], (t, key)
+        st = new
