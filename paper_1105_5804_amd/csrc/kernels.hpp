@@ -926,6 +926,9 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
     }
 
     if constexpr (SIZES) {
+        // the scan's closing slot and the largest-size slot after the
+        // per-(row, tile column) counts start at zero (no other block writes them)
+        if (blockIdx.x == 0 && threadIdx.x < 2) a.row_count[static_cast<int64_t>(a.g.H) * a.g.ntx + threadIdx.x] = 0;
         for (int k = threadIdx.x; k < TSITES; k += NT) Ci[k] = 0;
         for (int k = threadIdx.x; k < CAP; k += NT) Cb[k] = 0;
     }
@@ -1155,6 +1158,7 @@ struct EmitArgs {
     int32_t *roots;
     int32_t *sizes;
     int32_t *max_size;        // largest size (atomic max), or nullptr
+    int32_t *n_clusters;      // the number of clusters (the offsets' total), or nullptr
 };
 
 // Write each tile's roots (ascending site index within a row) at their global
@@ -1193,6 +1197,8 @@ __global__ __launch_bounds__(NT) void k_emit(EmitArgs a)
         mx = wave_max(mx);
         if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(a.max_size, mx);
     }
+    if (a.n_clusters && blockIdx.x == 0 && threadIdx.x == 0)
+        *a.n_clusters = a.row_off[static_cast<int64_t>(a.g.H) * a.g.ntx];
 }
 
 // ------------------------------------------------------- small lattices ---

@@ -216,7 +216,7 @@ FlatArgs flat_args(const Layout &L, void *ws)
 // Roots in ascending order and their sizes from a flatten pass with sizes:
 // scan the per-(row, tile column) root counts, then place each tile's roots.
 void emit_sizes(const Layout &L, void *ws, const FlatArgs &fa, int32_t *roots, int32_t *sizes, int32_t *max_size,
-                hipStream_t s)
+                int32_t *n_clusters, hipStream_t s)
 {
     int32_t *row_off = at<int32_t>(ws, L.row_off);
     scan_i32(fa.row_count, row_off, L.nrow + 1, at<char>(ws, L.scan_tmp), s);
@@ -229,6 +229,7 @@ void emit_sizes(const Layout &L, void *ws, const FlatArgs &fa, int32_t *roots, i
     ea.roots = roots;
     ea.sizes = sizes;
     ea.max_size = max_size;
+    ea.n_clusters = n_clusters;
     hipLaunchKernelGGL(k_emit, dim3(static_cast<unsigned>(L.g.ntiles)), dim3(NT), 0, s, ea);
 }
 
@@ -370,9 +371,8 @@ static sw_status launch_phase(sw_lattice *h, int32_t phase, hipStream_t s)
         hipLaunchKernelGGL((k_flatten<M_SW, false>), grid, block, 0, s, fa);
         return launch_status("k_flatten");
     }
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, fa.row_count + L.nrow, 2);
     hipLaunchKernelGGL((k_flatten<M_SW, true>), grid, block, 0, s, fa);
-    emit_sizes(L, ws, fa, h->b.roots, h->b.sizes, fa.row_count + L.nrow + 1, s);
+    emit_sizes(L, ws, fa, h->b.roots, h->b.sizes, fa.row_count + L.nrow + 1, nullptr, s);
     return launch_status("k_flatten");
 }
 
@@ -611,14 +611,14 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
     FlatArgs fa = flat_args(L, workspace);
     fa.labels = labels;
     if (want_sizes) {
-        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, fa.row_count + L.nrow, 1);
-        // the flatten mode only matters for M_SW; all labeling inputs share one path
+        // the flatten mode only matters for M_SW; all labeling inputs share one
+        // path; the emit also writes the cluster count (the offsets' total)
         hipLaunchKernelGGL((k_flatten<M_BONDS_PERIODIC, true>), grid, block, 0, s, fa);
-        emit_sizes(L, workspace, fa, roots, sizes, nullptr, s);
+        emit_sizes(L, workspace, fa, roots, sizes, nullptr, n_clusters, s);
     } else {
         hipLaunchKernelGGL((k_flatten<M_BONDS_PERIODIC, false>), grid, block, 0, s, fa);
     }
-    if (n_clusters) {
+    if (n_clusters && !want_sizes) {
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, n_clusters, 1);
         const unsigned rb = static_cast<unsigned>(std::min<int64_t>(cdiv(L.g.ntiles, NT), 64));
         hipLaunchKernelGGL(k_reduce_tiles, dim3(rb), dim3(NT), 0, s, fa.tile_ncl, L.g.ntiles,
