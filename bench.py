@@ -197,8 +197,9 @@ def main() -> int:
     args = _args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(a lattice would shard by row strips; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(a lattice would shard into row strips, one per GPU, exchanging one halo row and one gather of "
+              "strip-crossing cluster pairs per sweep)", file=sys.stderr)
         return 2
 
     if args.study:
