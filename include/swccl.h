@@ -71,7 +71,7 @@ enum {
     SW_ERR_WORKSPACE = 3,   /* workspace missing or smaller than required   */
     SW_ERR_DEVICE = 4,      /* a HIP call failed (see sw_last_error)         */
     SW_ERR_STATE = 5,       /* sweep counter would overflow 32 bits          */
-    SW_ERR_UNSUPPORTED = 6  /* combination not supported by this build       */
+    SW_ERR_UNSUPPORTED = 6  /* combination not supported by the library      */
 };
 
 /* Spin storage. */

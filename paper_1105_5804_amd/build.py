@@ -27,7 +27,7 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    """Always recompile (the build check must exercise the compiler)."""
+    """Always recompile, so a stale library never stands in for the sources."""
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIPFLAGS, "-o", tmp, *SRCS]
     if verbose:
