@@ -746,7 +746,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         return p < 0 ? static_cast<uint32_t>(-p - 2) : static_cast<uint32_t>(CAP + (y >> 2));
     };
     uint32_t *codes32 = reinterpret_cast<uint32_t *>(a.codes + static_cast<int64_t>(tile) * TSITES);
-    for (int r = 0; r < nr; ++r) {
+    // unrolled: the rows' lookup chains are independent, so their LDS loads overlap
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        if (r >= nr) break;
         const int ly = ly0 + r;
         const EO O = MODE == M_SITES ? Om[ly] : valid;
         const int base = ly * TW;
