@@ -702,7 +702,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         wave_lds_fence();
     };
     int nrs = 0;
-    for (int r = 0; r < nr; ++r) {
+    // The parents of the wave's sites are read up front (the loads overlap).
+    // A flush only rewrites entries that are not their own (linked stays
+    // linked); a root claimed meanwhile reads as unlinked here and is rightly
+    // left out.
+    int2 ppr[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+        ppr[r] = r < nr ? *reinterpret_cast<const int2 *>(&P[(ly0 + r) * TW + lx0]) : make_int2(0, 0);
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        if (r >= nr) break;
         const int ly = ly0 + r;
         const int base = ly * TW;
         if (nrs > TL - TW) {
@@ -711,7 +721,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         }
         const EO R = uniform_eo(Rm[ly]);
         const EO O = MODE == M_SITES ? uniform_eo(Om[ly]) : valid;
-        const int2 pp = *reinterpret_cast<const int2 *>(&P[base + lx0]);
+        const int2 pp = ppr[r];
         const EO linked = EO{lanes_ne(static_cast<uint32_t>(pp.x), static_cast<uint32_t>(4 * (base + lx0))),
                              lanes_ne(static_cast<uint32_t>(pp.y), static_cast<uint32_t>(4 * (base + lx0 + 1)))};
         eo_append<2>(mylist, nrs, eo_and(eo_andnot(O, eo_shift1(R)), linked), lane, base);
