@@ -7,9 +7,10 @@
 //   k_tile    one workgroup per 128x64 tile.  Bond activation (Sec. II.A) fused
 //             with tile labeling (Sec. II.B): each lane of a 64-lane wave owns
 //             two sites of a tile row; the row's bonds become 128-bit masks by
-//             wave ballots, right bonds turn into row runs by a bit scan, and
-//             down bonds join runs by a lock-free union-find over run starts in
-//             LDS, fed from compacted per-wave lists of vertical contacts.
+//             wave ballots, right bonds turn into row runs (each site's run
+//             start from a DPP max-scan over the lanes), and down bonds join
+//             runs by a lock-free union-find over run starts in LDS, fed from
+//             compacted per-wave lists of vertical contacts.
 //             Clusters that touch the tile border are claimed by their border
 //             sites and get a compact boundary id; every site's result is a
 //             16-bit code (boundary id, or CAP + the slot of its interior root).
