@@ -108,3 +108,29 @@ def test_max_size_one_cluster():
     assert bool(torch.all(lat.spins == want))
     del lat, spins
     _free()
+
+
+def test_max_size_labeling_extremes():
+    """Labeling at the largest size: a full image is one cluster (label 0, size
+    N); an empty one has none (labels -1); a checkerboard is N/2 singletons
+    labelled by their own index."""
+    img = torch.ones((L, L), dtype=torch.uint8, device="cuda")
+    lab, roots, sizes, n = sw.ccl_label(img, "sites_open", sizes=True)
+    assert n == 1 and int(roots[0]) == 0 and int(sizes[0]) == N
+    assert int(torch.count_nonzero(lab)) == 0
+    img.zero_()
+    lab, roots, sizes, n = sw.ccl_label(img, "sites_open", sizes=True)
+    assert n == 0 and bool(torch.all(lab == -1))
+    del roots, sizes
+    # checkerboard: occupied iff x + y is even (L is even, so no wrap neighbours matter)
+    y = torch.arange(L, device="cuda", dtype=torch.int32).view(L, 1)
+    x = torch.arange(L, device="cuda", dtype=torch.int32).view(1, L)
+    img = ((x + y) % 2 == 0).to(torch.uint8)
+    del x, y
+    lab = sw.ccl_label(img, "sites_open")
+    own = torch.arange(N, device="cuda", dtype=torch.int32).view(L, L)  # N < 2^31
+    want = torch.where(img.bool(), own, torch.full_like(own, -1))
+    del own
+    assert bool(torch.all(lab == want))
+    del img, lab, want
+    _free()
