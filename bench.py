@@ -399,6 +399,31 @@ def main() -> int:
                         "us_per_sweep": round(res["fused"], 3),
                         "us_per_sweep_tiled_launches": round(res["tiled"], 3)}
 
+    # ---- Ising L=4096, packed bonds kept: 200 + 1000 sweeps, without and with per-sweep records ----
+    if not args.no_batch:
+        c = wl.CONFIGS["ising4096"]
+        lat = sw.SWLattice(c.W, c.H, q=2, K=c.K, seed=c.seed, keep_bonds=c.keep_bonds)
+        lat.sweep(c.warmup)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        lat.sweep(c.sweeps)
+        ev[1].record(stream)
+        hist = lat.sweep_history(c.sweeps)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        ms_plain = ev[0].elapsed_time(ev[1]) / c.sweeps
+        ms_rec = ev[1].elapsed_time(ev[2]) / c.sweeps
+        e = -(2.0 * hist[:, 3].double() - 2.0 * c.W * c.H) / (c.W * c.H)
+        out["ising4096"] = {"workload": f"Ising {c.W}x{c.H} at beta_c, packed bonds kept, "
+                                        f"{c.warmup} + {c.sweeps} sweeps",
+                            "ms_per_sweep": round(ms_plain, 4),
+                            "ns_per_spin": round(ms_plain * 1e6 / (c.W * c.H), 6),
+                            "ms_per_sweep_with_records": round(ms_rec, 4),
+                            "mean_energy_per_site": round(float(e.mean()), 6)}
+        del lat, hist
+        torch.cuda.empty_cache()
+
     # ---- served labeling ----
     if not args.no_serve:
         out["served"] = _served(args, torch, sw, wl)
