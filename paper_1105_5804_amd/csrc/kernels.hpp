@@ -145,7 +145,9 @@ __device__ __forceinline__ void unite_step(int *P, int &a, int &b, int &done)
     const int hi = max(a, b), lo = min(a, b);
     const int old = __hip_atomic_fetch_min(lds_entry<BYTES>(P, link ? hi : a), link ? lo : pa, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
-    done = roots && (!link || old == hi);
+    // a common parent already makes one tree: the union ends a step before
+    // both nodes reach the root (whose entry every finished lane would hit)
+    done = pa == pb || (roots && (!link || old == hi));
     a = link ? old : pa;
     b = link ? lo : pb;
 }
