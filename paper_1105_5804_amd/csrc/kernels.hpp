@@ -136,7 +136,7 @@ __device__ __forceinline__ int *lds_entry(int *P, int v)
     return BYTES ? reinterpret_cast<int *>(reinterpret_cast<char *>(P) + v) : &P[v];
 }
 
-template <bool BYTES = false>
+template <bool BYTES = false, bool SAME_PARENT = false>
 __device__ __forceinline__ void unite_step(int *P, int &a, int &b, int &done)
 {
     const int pa = lds_ld(lds_entry<BYTES>(P, a)), pb = lds_ld(lds_entry<BYTES>(P, b));
@@ -145,9 +145,11 @@ __device__ __forceinline__ void unite_step(int *P, int &a, int &b, int &done)
     const int hi = max(a, b), lo = min(a, b);
     const int old = __hip_atomic_fetch_min(lds_entry<BYTES>(P, link ? hi : a), link ? lo : pa, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
-    // a common parent already makes one tree: the union ends a step before
-    // both nodes reach the root (whose entry every finished lane would hit)
-    done = pa == pb || (roots && (!link || old == hi));
+    // with SAME_PARENT a common parent already makes one tree: the union ends
+    // a step before both nodes reach the root (whose entry every finished
+    // lane would hit; the run-start unions of the tile kernel gain from it,
+    // the site unions of the small-lattice kernel do not)
+    done = (SAME_PARENT && pa == pb) || (roots && (!link || old == hi));
     a = link ? old : pa;
     b = link ? lo : pb;
 }
@@ -470,7 +472,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         }
         while (i < n) {
             int done;
-            unite_step<true>(P, a, b, done);
+            unite_step<true, true>(P, a, b, done);
             if (done) {
                 i += 64;
                 if (i < n) {
