@@ -149,7 +149,8 @@ __device__ __forceinline__ void unite_step(int *P, int &a, int &b, int &done)
     // a step before both nodes reach the root (whose entry every finished
     // lane would hit; the run-start unions of the tile kernel gain from it,
     // the site unions of the small-lattice kernel do not)
-    done = (SAME_PARENT && pa == pb) || (roots && (!link || old == hi));
+    // bitwise, not short-circuit: the flags stay lane masks (no selects)
+    done = static_cast<int>((SAME_PARENT && pa == pb) | (roots & (!link | (old == hi))));
     a = link ? old : pa;
     b = link ? lo : pb;
 }
