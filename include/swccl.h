@@ -41,11 +41,14 @@
  * Memory and ownership: every device buffer is allocated and owned by the
  * caller; the library allocates no device memory.  Scratch space is the caller's
  * workspace of at least *_workspace_bytes() bytes.  A lattice handle is a small
- * host object created by sw_init and freed by sw_destroy.
+ * host object created by sw_init and freed by sw_destroy (a batch that ran
+ * swb_sweep_graph also holds a capture stream and an executable graph until
+ * swb_destroy).
  *
  * Streams: every call enqueues on the given stream (a hipStream_t passed as
  * void*; NULL is the null stream) and returns without waiting, except
- * sw_observables, which waits for the stream.
+ * sw_observables and swb_observables, which wait for the stream, and the
+ * server's release and destroy, which wait for their requests.
  *
  * Errors: every entry point returns an sw_status; arguments are checked before
  * anything is enqueued and nothing throws across the ABI.  SW_ERR_DEVICE means
