@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define SWCCL_ABI_VERSION 2
+#define SWCCL_ABI_VERSION 3
 
 typedef int32_t sw_status;
 enum {
@@ -73,8 +73,10 @@ enum {
     SW_ERR_SIZE = 2,        /* W or H < 1 (< 2 for SW), or W*H >= 2^31      */
     SW_ERR_WORKSPACE = 3,   /* workspace missing or smaller than required   */
     SW_ERR_DEVICE = 4,      /* a HIP call failed (see sw_last_error)         */
-    SW_ERR_STATE = 5,       /* sweep counter would overflow 32 bits          */
-    SW_ERR_UNSUPPORTED = 6  /* combination not supported by the library      */
+    SW_ERR_STATE = 5,       /* call out of order, sweep counter would pass
+                               32 bits, or no server block or slot free now */
+    SW_ERR_UNSUPPORTED = 6, /* combination not supported by the library      */
+    SW_ERR_HOST_MEMORY = 7  /* a host-side allocation of the library failed  */
 };
 
 /* Spin storage. */
@@ -312,7 +314,8 @@ sw_status ccl_server_submit(ccl_server *s, const uint8_t *image, int32_t W, int3
                             int32_t *slot);
 
 /* Completed requests not reported before (non-blocking): up to max pairs
- * (slot, tag) and their number *n. */
+ * (slot, tag) and their number *n.  On SW_ERR_DEVICE *n still counts the
+ * pairs written before the request whose event query failed. */
 sw_status ccl_server_poll(ccl_server *s, int32_t *slots, uint64_t *tags, int32_t max, int32_t *n);
 
 /* Device pointers of a request's outputs (as ccl_label writes them): labels

@@ -7,10 +7,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libswccl.so")
 
-ABI_VERSION = 2  # the SWCCL_ABI_VERSION these declarations follow
+ABI_VERSION = 3  # the SWCCL_ABI_VERSION these declarations follow
 
 # status codes
-SW_OK, SW_ERR_ARG, SW_ERR_SIZE, SW_ERR_WORKSPACE, SW_ERR_DEVICE, SW_ERR_STATE, SW_ERR_UNSUPPORTED = range(7)
+SW_OK, SW_ERR_ARG, SW_ERR_SIZE, SW_ERR_WORKSPACE, SW_ERR_DEVICE, SW_ERR_STATE, SW_ERR_UNSUPPORTED, SW_ERR_HOST_MEMORY = range(8)
 SW_SPIN_ISING_I8, SW_SPIN_POTTS_U8 = 0, 1
 SW_F_KEEP_SPINS, SW_F_SIZES, SW_F_REVERSE_TILES = 1, 2, 4
 CCL_BONDS_PERIODIC, CCL_BONDS_OPEN, CCL_SITES_OPEN = 0, 1, 2

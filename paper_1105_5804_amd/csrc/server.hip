@@ -80,21 +80,24 @@ struct ccl_server {
 
 namespace {
 
-// First fit; returns false when no free block is large enough.
+// First fit; returns false when no free block is large enough.  Throws
+// std::bad_alloc (with the free list unchanged) if the remainder's node cannot
+// be allocated.
 bool arena_take(ccl_server *s, size_t bytes, size_t *off)
 {
     for (auto it = s->free_blocks.begin(); it != s->free_blocks.end(); ++it) {
         if (it->second < bytes) continue;
-        *off = it->first;
-        const size_t rest = it->second - bytes;
-        const size_t at = it->first + bytes;
+        const size_t at = it->first, rest = it->second - bytes;
+        if (rest) s->free_blocks.emplace(at + bytes, rest);  // the only step that can throw
         s->free_blocks.erase(it);
-        if (rest) s->free_blocks[at] = rest;
+        *off = at;
         return true;
     }
     return false;
 }
 
+// Returns a block to the free list, merging it with its neighbours.  Throws
+// std::bad_alloc (with the free list unchanged) if its node cannot be allocated.
 void arena_give(ccl_server *s, size_t off, size_t bytes)
 {
     auto it = s->free_blocks.emplace(off, bytes).first;
@@ -134,14 +137,19 @@ sw_status ccl_server_create(ccl_server **out, const ccl_server_params *p, void *
     if (!out || !valid_params(p) || !streams) return SW_ERR_ARG;
     if (!arena || arena_bytes < ALIGN || reinterpret_cast<uintptr_t>(arena) % ALIGN) return SW_ERR_WORKSPACE;
     ccl_server *s = new (std::nothrow) ccl_server();
-    if (!s) return SW_ERR_ARG;
+    if (!s) return SW_ERR_HOST_MEMORY;
     s->p = *p;
     s->arena = static_cast<char *>(arena);
     s->arena_bytes = arena_bytes / ALIGN * ALIGN;
-    s->free_blocks[0] = s->arena_bytes;
-    for (int32_t i = 0; i < p->n_streams; ++i) s->streams.push_back(static_cast<hipStream_t>(streams[i]));
     s->next_stream = 0;
-    s->req.resize(static_cast<size_t>(p->max_inflight));
+    try {
+        s->free_blocks[0] = s->arena_bytes;
+        for (int32_t i = 0; i < p->n_streams; ++i) s->streams.push_back(static_cast<hipStream_t>(streams[i]));
+        s->req.resize(static_cast<size_t>(p->max_inflight));
+    } catch (const std::bad_alloc &) {
+        delete s;
+        return SW_ERR_HOST_MEMORY;
+    }
     for (auto &r : s->req) {
         if (hipEventCreateWithFlags(&r.done, hipEventDisableTiming) != hipSuccess) {
             for (auto &q : s->req)
@@ -168,7 +176,11 @@ sw_status ccl_server_submit(ccl_server *s, const uint8_t *image, int32_t W, int3
             break;
         }
     size_t off = 0;
-    if (k < 0 || !arena_take(s, L.total, &off)) return SW_ERR_STATE;  // wait for a release
+    try {
+        if (k < 0 || !arena_take(s, L.total, &off)) return SW_ERR_STATE;  // wait for a release
+    } catch (const std::bad_alloc &) {
+        return SW_ERR_HOST_MEMORY;
+    }
     Request &r = s->req[static_cast<size_t>(k)];
     hipStream_t st = s->streams[static_cast<size_t>(s->next_stream)];
     s->next_stream = (s->next_stream + 1) % s->p.n_streams;
@@ -192,7 +204,11 @@ sw_status ccl_server_submit(ccl_server *s, const uint8_t *image, int32_t W, int3
     if (status != SW_OK) {
         // nothing of this request may still run when its block is reused
         (void)hipStreamSynchronize(st);
-        arena_give(s, off, L.total);
+        try {
+            arena_give(s, off, L.total);
+        } catch (const std::bad_alloc &) {
+            // the block stays out of the free list: lost capacity, not a leak of device memory
+        }
         return status;
     }
     r.busy = true;
@@ -215,7 +231,10 @@ sw_status ccl_server_poll(ccl_server *s, int32_t *slots, uint64_t *tags, int32_t
         if (!r.busy || r.reported) continue;
         const hipError_t e = hipEventQuery(r.done);
         if (e == hipErrorNotReady) continue;
-        if (e != hipSuccess) return SW_ERR_DEVICE;
+        if (e != hipSuccess) {
+            *n = m;  // the pairs already written are still returned
+            return SW_ERR_DEVICE;
+        }
         r.reported = true;
         slots[m] = static_cast<int32_t>(i);
         tags[m] = r.tag;
@@ -246,7 +265,11 @@ sw_status ccl_server_release(ccl_server *s, int32_t slot)
     if (!r.busy) return SW_ERR_STATE;
     // a block is reused only after its request has finished on the device
     if (hipEventSynchronize(r.done) != hipSuccess) return SW_ERR_DEVICE;
-    arena_give(s, r.off, r.L.total);
+    try {
+        arena_give(s, r.off, r.L.total);
+    } catch (const std::bad_alloc &) {
+        return SW_ERR_HOST_MEMORY;  // still admitted: the release can be retried
+    }
     r.busy = false;
     r.reported = false;
     return SW_OK;

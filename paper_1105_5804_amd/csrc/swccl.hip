@@ -269,6 +269,7 @@ const char *sw_status_string(sw_status s)
     case SW_ERR_DEVICE: return "device error";
     case SW_ERR_STATE: return "invalid state";
     case SW_ERR_UNSUPPORTED: return "unsupported";
+    case SW_ERR_HOST_MEMORY: return "host memory allocation failed";
     default: return "unknown status";
     }
 }
@@ -307,7 +308,7 @@ sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, voi
     if (!b->workspace || b->workspace_bytes < L.total) return SW_ERR_WORKSPACE;
     if (reinterpret_cast<uintptr_t>(b->workspace) % ALIGN) return SW_ERR_WORKSPACE;
     sw_lattice *h = new (std::nothrow) sw_lattice();
-    if (!h) return SW_ERR_ARG;
+    if (!h) return SW_ERR_HOST_MEMORY;
     h->p = *p;
     h->b = *b;
     h->L = L;
@@ -668,9 +669,13 @@ static sw_status check_batch(const sw_params *p, const sw_buffers *b, int32_t n,
 size_t swb_workspace_bytes(const sw_params *p, int32_t n)
 {
     int64_t nt = 0;
-    std::vector<sw_buffers> dummy(n > 0 ? static_cast<size_t>(n) : 0);
-    for (auto &d : dummy) d.spins = reinterpret_cast<void *>(1);
-    if (n < 1 || check_batch(p, dummy.data(), n, &nt) != SW_OK) return 0;
+    try {
+        std::vector<sw_buffers> dummy(n > 0 ? static_cast<size_t>(n) : 0);
+        for (auto &d : dummy) d.spins = reinterpret_cast<void *>(1);
+        if (n < 1 || check_batch(p, dummy.data(), n, &nt) != SW_OK) return 0;
+    } catch (const std::bad_alloc &) {
+        return 0;
+    }
     return make_batch_layout(nt, n).total;
 }
 
@@ -685,16 +690,22 @@ sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int
     if (!workspace || workspace_bytes < L.total) return SW_ERR_WORKSPACE;
     if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return SW_ERR_WORKSPACE;
     swb_batch *h = new (std::nothrow) swb_batch();
-    if (!h) return SW_ERR_ARG;
+    if (!h) return SW_ERR_HOST_MEMORY;
     h->n = n;
-    h->p.assign(p, p + n);
-    h->b.assign(b, b + n);
     h->L = L;
     h->ws = workspace;
     h->t = 0;
     h->swept = false;
-    h->desc.resize(static_cast<size_t>(n));
-    h->lat_of_tile.resize(static_cast<size_t>(nt));
+    try {
+        h->p.assign(p, p + n);
+        h->b.assign(b, b + n);
+        h->T.resize(static_cast<size_t>(n));
+        h->desc.resize(static_cast<size_t>(n));
+        h->lat_of_tile.resize(static_cast<size_t>(nt));
+    } catch (const std::bad_alloc &) {
+        delete h;
+        return SW_ERR_HOST_MEMORY;
+    }
     // even widths first (one tile-kernel launch per width parity)
     int32_t tile = 0;
     for (int parity = 0; parity < 2; ++parity) {
@@ -723,7 +734,7 @@ sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int
         }
         if (parity == 0) h->tiles_even = tile;
     }
-    for (int32_t j = 0; j < n; ++j) h->T.push_back(threshold_of(p[j].K));
+    for (int32_t j = 0; j < n; ++j) h->T[static_cast<size_t>(j)] = threshold_of(p[j].K);
     hipStream_t s = static_cast<hipStream_t>(stream);
     sw_status st = device_status(hipMemcpyAsync(at<LatticeDesc>(workspace, L.lat_desc), h->desc.data(),
                                                 h->desc.size() * sizeof(LatticeDesc), hipMemcpyHostToDevice, s),
