@@ -104,7 +104,9 @@ class SWLattice:
     the last sweep are kept in ``labels`` / ``bonds``; with ``sizes`` every sweep
     also lists its clusters (``cluster_sizes()``) and their largest size.
     ``reverse_tiles`` runs the tiles in the reverse order (a schedule check:
-    every output is the same).
+    every output is the same).  The constructor enqueues on the current
+    stream; methods given another ``stream`` are ordered only with that
+    stream's work (synchronise the two as with any torch side stream).
     """
 
     def __init__(self, W: int, H: int, q: int = 2, K: float | None = None, seed: int = 0,
@@ -316,7 +318,9 @@ def ccl_label(inp, mode: str | int = "bonds_periodic", sizes: bool = False, work
     mode: "bonds_periodic" / "bonds_open" (packed bonds, bit0 right, bit1 down)
     or "sites_open" (binary image, 4-connected, background label -1).
     Returns labels, or (labels, roots, sizes, n_clusters) when sizes=True;
-    roots ascend and sizes[k] belongs to roots[k].
+    roots ascend and sizes[k] belongs to roots[k].  With a ``stream`` other
+    than the current one, that stream first waits for the current stream's
+    work; with sizes the call waits for ``stream`` (to read the count).
     """
     torch = _torch()
     L = _lib.lib()
@@ -328,9 +332,13 @@ def ccl_label(inp, mode: str | int = "bonds_periodic", sizes: bool = False, work
     ws = L.ccl_workspace_bytes(W, H, m)
     if ws == 0:
         _lib.check(_lib.SW_ERR_SIZE, "ccl_workspace_bytes")
+    made = []  # tensors allocated here, on the current stream
     if workspace is None:
         wbuf, wptr = _workspace(torch, ws, inp.device)
+        made.append(wbuf)
     else:
+        if workspace.device != inp.device or not workspace.is_contiguous():
+            raise ValueError(f"workspace must be a contiguous tensor on {inp.device}")
         wbuf = workspace
         p = workspace.data_ptr()
         wptr = p + ((-p) % 256)
@@ -338,18 +346,37 @@ def ccl_label(inp, mode: str | int = "bonds_periodic", sizes: bool = False, work
             raise ValueError("workspace too small")
     if labels is None:
         labels = torch.empty((H, W), dtype=torch.int32, device=inp.device)
-    ncl = torch.zeros(1, dtype=torch.int32, device=inp.device)
+        made.append(labels)
+    elif (labels.shape != (H, W) or labels.dtype != torch.int32 or labels.device != inp.device
+          or not labels.is_contiguous()):
+        raise ValueError(f"labels must be a contiguous ({H}, {W}) int32 tensor on {inp.device}")
+    ncl = torch.empty(1, dtype=torch.int32, device=inp.device)  # written by the library
+    made.append(ncl)
     roots = szs = None
     if sizes:
         roots = torch.empty(H * W, dtype=torch.int32, device=inp.device)
         szs = torch.empty(H * W, dtype=torch.int32, device=inp.device)
+        made += [roots, szs]
+    cur = torch.cuda.current_stream(inp.device)
+    side = stream is not None and stream != cur
+    if side:
+        # the input's copy (if .contiguous() made one) was enqueued on the current stream
+        stream.wait_stream(cur)
+        made.append(inp)
     st = L.ccl_label(inp.data_ptr(), W, H, m, labels.data_ptr(),
                      roots.data_ptr() if sizes else None, szs.data_ptr() if sizes else None,
                      ncl.data_ptr(), wptr, ws, _stream(torch, stream))
     _lib.check(st, "ccl_label")
+    if side:
+        # memory allocated on the current stream and used on another: the
+        # allocator must not hand it out again before that stream's work is done
+        for t in made:
+            t.record_stream(stream)
     del wbuf
     if not sizes:
         return labels
+    if side:
+        stream.synchronize()
     n = int(ncl.item())
     return labels, roots[:n], szs[:n], n
 

@@ -103,3 +103,33 @@ def test_percolation_16384_repeated():
         lab = sw.ccl_label(g, "bonds_periodic", workspace=ws)
         bad = int((lab != want).sum().item())
         assert bad == 0, (rep, bad)
+
+
+def test_side_stream_and_output_checks():
+    """ccl_label on a stream other than the current one: a non-contiguous
+    input (copied on the current stream first), sizes read back after the side
+    stream; results equal the oracle's.  Wrong caller-supplied outputs raise
+    before anything is enqueued."""
+    W, H = 515, 260
+    img = wl.site_image(W, H, 0.5927, seed=2901)
+    print(f"ccl side stream W={W} H={H}", flush=True)
+    g = torch.from_numpy(np.ascontiguousarray(img.T)).cuda().t()  # (H, W) view, not contiguous
+    assert not g.is_contiguous()
+    side = torch.cuda.Stream()
+    lab, roots, sizes, n = sw.ccl_label(g, "sites_open", sizes=True, stream=side)
+    side.synchronize()
+    want, nref = _oracle(img, "sites_open")
+    assert n == nref
+    assert np.array_equal(lab.cpu().numpy().reshape(-1), want)
+    r_ref, s_ref, _ = oracle.cluster_sizes(want)
+    assert np.array_equal(roots.cpu().numpy(), r_ref)
+    assert np.array_equal(sizes.cpu().numpy(), s_ref)
+    gc = g.contiguous()
+    for bad in (torch.empty((H, W + 1), dtype=torch.int32, device="cuda"),
+                torch.empty((H, W), dtype=torch.int64, device="cuda"),
+                torch.empty((W, H), dtype=torch.int32, device="cuda").t(),
+                torch.empty((H, W), dtype=torch.int32)):
+        with pytest.raises(ValueError):
+            sw.ccl_label(gc, "sites_open", labels=bad)
+    with pytest.raises(ValueError):
+        sw.ccl_label(gc, "sites_open", workspace=torch.empty(1 << 24, dtype=torch.uint8))
