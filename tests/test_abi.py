@@ -201,3 +201,15 @@ def test_server_argument_errors():
     assert L.ccl_server_result(None, 0, None, None, None, None) == _lib.SW_ERR_ARG
     assert L.ccl_server_release(None, 0) == _lib.SW_ERR_ARG
     assert L.ccl_server_destroy(None) == _lib.SW_ERR_ARG
+
+
+def test_missing_library_raises(monkeypatch, tmp_path):
+    """Without the built library every call raises: there is no fallback path."""
+    import paper_1105_5804_amd as sw
+
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libswccl.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.lib()
+    with pytest.raises(RuntimeError, match="missing"):
+        sw.threshold(1.0)
