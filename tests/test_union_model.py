@@ -1,0 +1,147 @@
+"""Interleaving model of the tile kernel's lock-free union step (Sec. II.B.2,
+union-and-find with the smaller index as the root).
+
+The step, as each lane runs it on nodes a, b of a parent array P with
+P[x] <= x:
+
+    pa = P[a]; pb = P[b]                       (two plain loads)
+    roots = pa == a and pb == b; link = roots and a != b
+    old = atomic_min(P[hi if link else a], lo if link else pa)
+    done = (same_parent and pa == pb) or (roots and (not link or old == hi))
+    a, b = (old, lo) if link else (pa, pb)
+
+with hi = max(a, b), lo = min(a, b); a union starts from the parents of its
+two sites.  Here every lane's loads and its atomic are separate events, and a
+seeded random scheduler interleaves the events of all lanes freely: a
+superset of the schedules a wave in lockstep and its neighbouring waves can
+produce.  Every run must keep P[x] <= x after every event and end with the
+exact partition of (initial forest + requested unions), each root being its
+component's minimum index.  Planted mistakes (a non-atomic min, a link that
+ignores the atomic's old value, a link of the smaller root under the larger)
+must be caught by the same exploration.
+"""
+import random
+
+import pytest
+
+
+def _components(P0, pairs):
+    """Minimum index of every node's component (sequential union-find)."""
+    n = len(P0)
+    f = list(range(n))
+
+    def find(x):
+        while f[x] != x:
+            f[x] = f[f[x]]
+            x = f[x]
+        return x
+
+    def join(x, y):
+        x, y = find(x), find(y)
+        if x != y:
+            f[max(x, y)] = min(x, y)
+
+    for x in range(n):
+        join(x, P0[x])
+    for u, v in pairs:
+        join(u, v)
+    return [find(x) for x in range(n)]
+
+
+def _run(P0, pairs, rng, same_parent=True, mistake=None, max_events=200000):
+    """Interleave all lanes' events; return the final P (or raise AssertionError
+    on a broken invariant)."""
+    P = list(P0)
+    lanes = [dict(u=u, v=v, pc="init_a") for u, v in pairs]
+    active = list(range(len(lanes)))
+    events = 0
+    while active:
+        events += 1
+        assert events < max_events, "no progress"
+        k = rng.randrange(len(active))
+        L = lanes[active[k]]
+        pc = L["pc"]
+        if pc == "init_a":
+            L["a"], L["pc"] = P[L["u"]], "init_b"
+        elif pc == "init_b":
+            L["b"], L["pc"] = P[L["v"]], "ld_a"
+        elif pc == "ld_a":
+            L["pa"], L["pc"] = P[L["a"]], "ld_b"
+        elif pc == "ld_b":
+            L["pb"], L["pc"] = P[L["b"]], "min"
+        elif pc in ("min", "min_store"):
+            a, b, pa, pb = L["a"], L["b"], L["pa"], L["pb"]
+            roots = pa == a and pb == b
+            link = roots and a != b
+            hi, lo = max(a, b), min(a, b)
+            if mistake == "link_up" and link:
+                hi, lo = lo, hi  # the larger index becomes the parent
+            addr, val = (hi, lo) if link else (a, pa)
+            if mistake == "non_atomic" and pc == "min":
+                # read now, write back later: other lanes may store in between
+                L["old"], L["pc"] = P[addr], "min_store"
+                continue
+            old = L.pop("old") if pc == "min_store" else P[addr]
+            P[addr] = min(old, val)
+            assert P[addr] <= addr or mistake == "link_up", "parent above its child"
+            if mistake == "ignore_old":
+                done = (same_parent and pa == pb) or roots
+            else:
+                done = (same_parent and pa == pb) or (roots and (not link or old == hi))
+            L["a"], L["b"] = (old, lo) if link else (pa, pb)
+            if done:
+                active[k] = active[-1]
+                active.pop()
+            else:
+                L["pc"] = "ld_a"
+    return P
+
+
+def _check(P, want):
+    for x in range(len(P)):
+        r, steps = x, 0
+        while P[r] != r:
+            r = P[r]
+            steps += 1
+            assert steps <= len(P), "cycle"
+        assert r == want[x], f"node {x}: root {r}, component minimum {want[x]}"
+
+
+def _case(rng, n, n_pairs):
+    # a forest with parents at smaller indices (row runs: a site points at its
+    # run start) and unions between arbitrary nodes, repeats and same-tree
+    # pairs included
+    P0 = [x if x == 0 or rng.random() < 0.4 else rng.randrange(x) for x in range(n)]
+    pairs = [(rng.randrange(n), rng.randrange(n)) for _ in range(n_pairs)]
+    return P0, pairs
+
+
+@pytest.mark.parametrize("same_parent", [False, True])
+@pytest.mark.parametrize("n,n_pairs", [(4, 6), (12, 12), (40, 30), (120, 100)])
+def test_union_step_any_interleaving(n, n_pairs, same_parent):
+    rng = random.Random(1000 * n + n_pairs + same_parent)
+    for _ in range(300 if n <= 40 else 60):
+        P0, pairs = _case(rng, n, n_pairs)
+        _check(_run(P0, pairs, rng, same_parent=same_parent), _components(P0, pairs))
+
+
+def test_union_step_contention_on_one_root():
+    """Every union ends at node 0 (the ordered phase's spanning cluster)."""
+    rng = random.Random(7)
+    for _ in range(200):
+        n = 24
+        P0 = [0] * n
+        pairs = [(rng.randrange(n), rng.randrange(n)) for _ in range(32)]
+        _check(_run(P0, pairs, rng), _components(P0, pairs))
+
+
+@pytest.mark.parametrize("mistake", ["non_atomic", "ignore_old", "link_up"])
+def test_planted_mistakes_are_caught(mistake):
+    rng = random.Random(99)
+    for trial in range(3000):
+        P0, pairs = _case(rng, 10, 12)
+        try:
+            _check(_run(P0, pairs, rng, mistake=mistake), _components(P0, pairs))
+        except AssertionError:
+            return
+    pytest.fail(f"{mistake}: no interleaving in 3000 trials exposed it")
