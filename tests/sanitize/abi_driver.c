@@ -3,7 +3,8 @@
  * device: workspace and footprint sizes over many shapes (up to the largest
  * accepted lattice and just past it), status strings, thresholds, and every
  * argument error of the lattice, batch, labeling and server calls.  Built with
- * AddressSanitizer on the host side of the library; prints "ok" at the end.
+ * AddressSanitizer and UBSan on the host side of the library; prints "ok" at
+ * the end.
  * Returns a non-zero code naming the first unexpected answer.
  */
 #include <math.h>
