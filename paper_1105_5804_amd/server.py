@@ -4,12 +4,15 @@ C ABI (argument marshalling only).
 Requests are host images labeled as they arrive.  The library admits a request
 when its footprint fits in the device arena (``SW_ERR_STATE`` otherwise: the
 request waits here, in submission order), spreads requests over the given
-streams, and reports completions through ``poll``.
+streams, and reports completions through ``poll``.  A request still waiting
+for admission can be withdrawn (``cancel``) or dropped after a deadline
+(``expire``); an admitted one runs to completion.
 """
 from __future__ import annotations
 
 import collections
 import ctypes
+import time
 
 from . import _lib
 from . import _MODES, _torch
@@ -42,7 +45,7 @@ class CCLServer:
         self._h = ctypes.c_void_p()
         _lib.check(L.ccl_server_create(ctypes.byref(self._h), ctypes.byref(self.params), self._arena_ptr,
                                        int(arena_bytes), arr), "ccl_server_create")
-        self._queue = collections.deque()   # (tag, image) waiting for admission
+        self._queue = collections.deque()   # (tag, image, submit time) waiting for admission
         self._inflight = {}                 # slot -> (tag, image, W, H)
         cap = int(max_inflight)
         self._pslots = (ctypes.c_int32 * cap)()
@@ -66,12 +69,32 @@ class CCLServer:
         if img.dim() != 2 or img.dtype.itemsize != 1 or img.device.type != "cpu" or img.stride(1) != 1:
             raise ValueError("a request is a 2D uint8 CPU tensor with unit column stride")
         if self._queue or not self._try_submit(tag, img):
-            self._queue.append((tag, img))
+            self._queue.append((tag, img, time.monotonic()))
 
     def pump(self) -> None:
         """Admit queued requests, in order, while they fit."""
-        while self._queue and self._try_submit(*self._queue[0]):
+        while self._queue and self._try_submit(self._queue[0][0], self._queue[0][1]):
             self._queue.popleft()
+
+    def cancel(self, tag: int) -> bool:
+        """Withdraw the oldest queued request with this tag (True if there was
+        one).  An admitted request cannot be withdrawn from the device: poll and
+        release it."""
+        for k, item in enumerate(self._queue):
+            if item[0] == tag:
+                del self._queue[k]
+                return True
+        return False
+
+    def expire(self, max_wait: float, now: float | None = None) -> list:
+        """Withdraw the queued requests that have waited more than max_wait
+        seconds since their submit (``now`` defaults to time.monotonic());
+        returns their tags in queue order."""
+        now = time.monotonic() if now is None else now
+        gone = [item[0] for item in self._queue if now - item[2] > max_wait]
+        if gone:
+            self._queue = collections.deque(item for item in self._queue if now - item[2] <= max_wait)
+        return gone
 
     def poll(self) -> list:
         """[(slot, tag)] of requests completed since the last poll (non-blocking)."""

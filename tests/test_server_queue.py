@@ -1,0 +1,92 @@
+"""Host logic of the labeling server's admission queue (no device): requests
+that do not fit wait in submission order, are admitted by ``pump`` as room
+appears, and can be withdrawn (``cancel``) or dropped after a deadline
+(``expire``) while they wait.  The device-side admission is replaced by a stub
+that admits while a capacity lasts."""
+import collections
+
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1105_5804_amd.server import CCLServer  # noqa: E402
+
+
+def _server(capacity):
+    srv = object.__new__(CCLServer)  # no device: the queue logic only
+    srv._queue = collections.deque()
+    srv._inflight = {}
+    srv.admitted = []
+    srv.room = capacity
+
+    def try_submit(tag, img):
+        if srv.room == 0:
+            return False
+        srv.room -= 1
+        slot = len(srv.admitted)
+        srv.admitted.append(tag)
+        srv._inflight[slot] = (tag, img, img.shape[1], img.shape[0])
+        return True
+
+    srv._try_submit = try_submit
+    return srv
+
+
+def _img(n=4):
+    return torch.zeros((n, n), dtype=torch.uint8)
+
+
+def test_fifo_admission():
+    srv = _server(2)
+    for t in range(5):
+        srv.submit(t, _img())
+    assert srv.admitted == [0, 1] and [q[0] for q in srv._queue] == [2, 3, 4]
+    assert srv.pending == 5
+    srv.room = 1
+    srv.pump()
+    assert srv.admitted == [0, 1, 2]
+    srv.submit(5, _img())  # the queue is not empty: a new request waits behind it
+    assert srv.admitted == [0, 1, 2] and [q[0] for q in srv._queue] == [3, 4, 5]
+    srv.room = 10
+    srv.pump()
+    assert srv.admitted == [0, 1, 2, 3, 4, 5] and not srv._queue
+
+
+def test_cancel_queued_only():
+    srv = _server(1)
+    for t in (10, 11, 12, 11):
+        srv.submit(t, _img())
+    assert srv.cancel(10) is False  # admitted: runs to completion
+    assert srv.cancel(11) is True
+    assert [q[0] for q in srv._queue] == [12, 11]  # the oldest 11 went first
+    assert srv.cancel(11) is True and srv.cancel(11) is False
+    assert srv.cancel(99) is False
+    srv.room = 5
+    srv.pump()
+    assert srv.admitted == [10, 12]
+
+
+def test_expire_by_wait():
+    srv = _server(0)
+    for t in range(4):
+        srv.submit(t, _img())
+    t0 = srv._queue[0][2]
+    stamps = [t0 - 5.0, t0 - 1.0, t0 - 3.0, t0]  # submit times, as if spread out
+    srv._queue = collections.deque((q[0], q[1], s) for q, s in zip(srv._queue, stamps))
+    assert srv.expire(10.0, now=t0) == []
+    assert srv.expire(2.0, now=t0) == [0, 2]
+    assert [q[0] for q in srv._queue] == [1, 3]
+    assert srv.expire(0.5, now=t0 + 0.25) == [1]
+    assert srv.pending == 1
+    srv.room = 1
+    srv.pump()
+    assert srv.admitted == [3] and srv.pending == 1  # admitted requests stay pending until released
+
+
+def test_submit_rejects_bad_images():
+    srv = _server(1)
+    for bad in (torch.zeros(4, dtype=torch.uint8), torch.zeros((4, 4), dtype=torch.int32),
+                torch.zeros((4, 4), dtype=torch.uint8).t()[:, ::2]):
+        with pytest.raises(ValueError):
+            srv.submit(0, bad)
+    assert srv.admitted == [] and not srv._queue
