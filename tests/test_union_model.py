@@ -18,7 +18,8 @@ produce.  Every run must keep P[x] <= x after every event and end with the
 exact partition of (initial forest + requested unions), each root being its
 component's minimum index.  Planted mistakes (a non-atomic min, a link that
 ignores the atomic's old value, a link of the smaller root under the larger)
-must be caught by the same exploration.
+must be caught by the same exploration.  A candidate form in which a lane
+with nothing to link aims its no-op at max(a, b) instead of a is checked too.
 """
 import random
 
@@ -48,7 +49,7 @@ def _components(P0, pairs):
     return [find(x) for x in range(n)]
 
 
-def _run(P0, pairs, rng, same_parent=True, mistake=None, max_events=200000):
+def _run(P0, pairs, rng, same_parent=True, mistake=None, noop_at_hi=False, max_events=200000):
     """Interleave all lanes' events; return the final P (or raise AssertionError
     on a broken invariant)."""
     P = list(P0)
@@ -76,7 +77,12 @@ def _run(P0, pairs, rng, same_parent=True, mistake=None, max_events=200000):
             hi, lo = max(a, b), min(a, b)
             if mistake == "link_up" and link:
                 hi, lo = lo, hi  # the larger index becomes the parent
-            addr, val = (hi, lo) if link else (a, pa)
+            if noop_at_hi:
+                # candidate form: a lane with nothing to link applies min(P[hi], hi),
+                # a no-op because P[x] <= x, so the address needs no select
+                addr, val = (hi, lo) if link else (hi, hi)
+            else:
+                addr, val = (hi, lo) if link else (a, pa)
             if mistake == "non_atomic" and pc == "min":
                 # read now, write back later: other lanes may store in between
                 L["old"], L["pc"] = P[addr], "min_store"
@@ -116,13 +122,14 @@ def _case(rng, n, n_pairs):
     return P0, pairs
 
 
+@pytest.mark.parametrize("noop_at_hi", [False, True])
 @pytest.mark.parametrize("same_parent", [False, True])
 @pytest.mark.parametrize("n,n_pairs", [(4, 6), (12, 12), (40, 30), (120, 100)])
-def test_union_step_any_interleaving(n, n_pairs, same_parent):
-    rng = random.Random(1000 * n + n_pairs + same_parent)
+def test_union_step_any_interleaving(n, n_pairs, same_parent, noop_at_hi):
+    rng = random.Random(1000 * n + n_pairs + same_parent + 7 * noop_at_hi)
     for _ in range(300 if n <= 40 else 60):
         P0, pairs = _case(rng, n, n_pairs)
-        _check(_run(P0, pairs, rng, same_parent=same_parent), _components(P0, pairs))
+        _check(_run(P0, pairs, rng, same_parent=same_parent, noop_at_hi=noop_at_hi), _components(P0, pairs))
 
 
 def test_union_step_contention_on_one_root():
