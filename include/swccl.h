@@ -174,7 +174,7 @@ size_t sw_workspace_bytes(const sw_params *p);
  * SW_F_SIZES needs b->roots and b->sizes (else SW_ERR_ARG).
  * The handle keeps copies of p and b; the buffers must outlive it.
  * Returns SW_ERR_ARG / SW_ERR_SIZE / SW_ERR_WORKSPACE before enqueuing
- * anything. */
+ * anything, SW_ERR_HOST_MEMORY if the handle cannot be allocated. */
 sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, void *stream);
 
 /* Enqueue n_sweeps SW sweeps t, t+1, ... (Sec. II, steps 1-3).  After the call
