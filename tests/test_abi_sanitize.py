@@ -1,6 +1,6 @@
 """The library's host code under AddressSanitizer and UBSan: the C ABI built
 with the sanitizers on its host side only (the device part is compiled but never run),
-and a C driver that calls every entry point answering before the device is
+and a C program that calls every entry point answering before the device is
 touched (sizes, status strings, thresholds, every argument error of the
 lattice, batch, labeling and server calls)."""
 import os
@@ -27,10 +27,10 @@ def test_abi_host_code_clean_under_sanitizers(tmp_path):
                     "-Xarch_host", "-fno-omit-frame-pointer",
                     "-I", inc, "-o", lib, os.path.join(csrc, "swccl.hip"), os.path.join(csrc, "server.hip")],
                    check=True, capture_output=True, timeout=600)
-    exe = str(tmp_path / "abi_driver")
+    exe = str(tmp_path / "abi_exercise")
     subprocess.run([CLANG, "-std=c11", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
                     "-fno-omit-frame-pointer", "-I", inc,
-                    os.path.join(ROOT, "tests", "sanitize", "abi_driver.c"), lib,
+                    os.path.join(ROOT, "tests", "sanitize", "abi_exercise.c"), lib,
                     "-Wl,-rpath," + str(tmp_path), "-lm", "-o", exe],
                    check=True, capture_output=True, timeout=120)
     # leaks of the HIP runtime's own start-up are not this library's

@@ -1,5 +1,5 @@
 """The C oracle under AddressSanitizer and UndefinedBehaviorSanitizer (gcc,
-host code only): a driver calls every oracle function on small, ragged and
+host code only): a C program calls every oracle function on small, ragged and
 degenerate shapes with exactly sized heap buffers; any report aborts it."""
 import os
 import shutil
@@ -14,11 +14,11 @@ def test_oracle_clean_under_sanitizers(tmp_path):
     gcc = shutil.which("gcc")
     if gcc is None:
         pytest.skip("gcc not found")
-    exe = str(tmp_path / "oracle_driver")
+    exe = str(tmp_path / "oracle_exercise")
     flags = ["-std=c11", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
              "-fno-sanitize-recover=all"]
     subprocess.run([gcc, *flags, "-I", os.path.join(ROOT, "oracle"),
-                    os.path.join(ROOT, "tests", "sanitize", "oracle_driver.c"),
+                    os.path.join(ROOT, "tests", "sanitize", "oracle_exercise.c"),
                     os.path.join(ROOT, "oracle", "swccl_oracle.c"), "-lm", "-o", exe],
                    check=True, capture_output=True, timeout=120)
     # verify_asan_link_order=0: run even if the environment preloads a library ahead of the sanitizer runtime
