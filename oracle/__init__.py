@@ -18,6 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "swccl_oracle.c")
+_HDR = os.path.join(_HERE, "swccl_oracle.h")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 TAG_INIT, TAG_BOND, TAG_FLIP = 0, 1, 2
@@ -26,9 +27,11 @@ REC_ACTIVE, REC_NCLUST, REC_MAXCL, REC_NSAT, REC_COUNTS, REC_LEN = 0, 1, 2, 3, 4
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle into ``liboracle.so`` with gcc (plain -O2 C11)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+    """Compile the oracle into ``liboracle.so`` with gcc (plain -O2 C11) when
+    forced, missing, or older than its source or header."""
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_HDR))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
+        tmp = f"{_LIB}.tmp{os.getpid()}"  # one per process: parallel test workers may build at once
         subprocess.check_call(
             ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
         )
