@@ -28,7 +28,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     """Always recompile, so a stale library never stands in for the sources."""
-    tmp = LIB + ".tmp"
+    tmp = f"{LIB}.tmp{os.getpid()}"  # one per process: concurrent builds never share a partial file
     cmd = [hipcc(), *HIPFLAGS, "-o", tmp, *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
