@@ -28,7 +28,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     """Always recompile, so a stale library never stands in for the sources."""
-    tmp = f"{LIB}.tmp{os.getpid()}"  # one per process: concurrent builds never share a partial file
+    tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIPFLAGS, "-o", tmp, *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
