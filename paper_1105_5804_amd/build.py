@@ -28,6 +28,8 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     """Always recompile, so a stale library never stands in for the sources."""
+    # a fixed temporary name: the compiler records the output path in the
+    # library, so a per-process name would make identical sources build differently
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIPFLAGS, "-o", tmp, *SRCS]
     if verbose:
