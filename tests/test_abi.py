@@ -213,3 +213,20 @@ def test_missing_library_raises(monkeypatch, tmp_path):
         _lib.lib()
     with pytest.raises(RuntimeError, match="missing"):
         sw.threshold(1.0)
+
+
+@pytest.mark.parametrize("compiler,std,ext", [("gcc", "c99", "c"), ("gcc", "c11", "c"), ("g++", "c++11", "cpp")])
+def test_header_compiles_strictly(compiler, std, ext, tmp_path):
+    """include/swccl.h is plain C (and C++): no warnings under -Wall -Wextra -Wpedantic."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which(compiler)
+    if cc is None:
+        pytest.skip(f"{compiler} not found")
+    src = tmp_path / f"use.{ext}"
+    src.write_text('#include "swccl.h"\nint main(void) { return (int)sizeof(sw_params) + (int)sizeof(sw_obs); }\n')
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    r = subprocess.run([cc, f"-std={std}", "-Wall", "-Wextra", "-Wpedantic", "-Werror", "-I", inc, "-c", str(src),
+                        "-o", str(tmp_path / "use.o")], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
