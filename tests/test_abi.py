@@ -230,3 +230,51 @@ def test_header_compiles_strictly(compiler, std, ext, tmp_path):
     r = subprocess.run([cc, f"-std={std}", "-Wall", "-Wextra", "-Wpedantic", "-Werror", "-I", inc, "-c", str(src),
                         "-o", str(tmp_path / "use.o")], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, r.stderr
+
+
+def test_ctypes_layout_matches_header(tmp_path):
+    """The binding's structures and constants equal the header's: sizes, field
+    offsets and field sizes from a C program built against include/swccl.h."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("gcc not found")
+    structs = {"sw_params": _lib.SwParams, "sw_buffers": _lib.SwBuffers, "sw_obs": _lib.SwObs,
+               "ccl_server_params": _lib.CclServerParams}
+    consts = ["SWCCL_ABI_VERSION", "SW_OK", "SW_ERR_ARG", "SW_ERR_SIZE", "SW_ERR_WORKSPACE", "SW_ERR_DEVICE",
+              "SW_ERR_STATE", "SW_ERR_UNSUPPORTED", "SW_ERR_HOST_MEMORY", "SW_SPIN_ISING_I8", "SW_SPIN_POTTS_U8",
+              "SW_F_KEEP_SPINS", "SW_F_SIZES", "SW_F_REVERSE_TILES", "CCL_BONDS_PERIODIC", "CCL_BONDS_OPEN",
+              "CCL_SITES_OPEN", "SW_PHASE_TILE", "SW_PHASE_MERGE", "SW_PHASE_FLIP", "SW_HIST_ACTIVE",
+              "SW_HIST_NCLUST", "SW_HIST_MAXCL", "SW_HIST_NSAT", "SW_HIST_COUNTS", "SW_HIST_LEN"]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "swccl.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("size {cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("field {cname} {f} %zu %zu\\n", offsetof({cname}, {f}), '
+                         f"sizeof((({cname} *)0)->{f}));")
+    for c in consts:
+        lines.append(f'printf("const {c} %lld\\n", (long long)({c}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    exe = str(tmp_path / "layout")
+    subprocess.run([cc, "-std=c11", "-I", inc, str(src), "-o", exe], check=True, capture_output=True, timeout=60)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True, timeout=60).stdout.split("\n")
+    seen = 0
+    for line in out:
+        w = line.split()
+        if not w:
+            continue
+        if w[0] == "size":
+            assert ctypes.sizeof(structs[w[1]]) == int(w[2]), line
+        elif w[0] == "field":
+            fd = getattr(structs[w[1]], w[2])
+            assert (fd.offset, fd.size) == (int(w[3]), int(w[4])), line
+        else:
+            want = _lib.ABI_VERSION if w[1] == "SWCCL_ABI_VERSION" else getattr(_lib, w[1])
+            assert want == int(w[2]), line
+        seen += 1
+    assert seen == len(structs) + sum(len(p._fields_) for p in structs.values()) + len(consts)
