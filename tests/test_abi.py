@@ -278,3 +278,45 @@ def test_ctypes_layout_matches_header(tmp_path):
             assert want == int(w[2]), line
         seen += 1
     assert seen == len(structs) + sum(len(p._fields_) for p in structs.values()) + len(consts)
+
+
+def test_ctypes_signatures_match_prototypes():
+    """Every SIGNATURES entry has the header prototype's return type, parameter
+    count and parameter types (scalars exactly; struct pointers to the matching
+    structure; other pointers as pointers)."""
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                            "swccl.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", " ", hdr, flags=re.S)
+    scalars = {"int32_t": ctypes.c_int32, "sw_status": ctypes.c_int32, "uint32_t": ctypes.c_uint32,
+               "uint64_t": ctypes.c_uint64, "size_t": ctypes.c_size_t, "double": ctypes.c_double}
+    structs = {"sw_params": _lib.SwParams, "sw_buffers": _lib.SwBuffers, "sw_obs": _lib.SwObs,
+               "ccl_server_params": _lib.CclServerParams}
+
+    def agrees(ctype: str, py) -> bool:
+        ctype = " ".join(ctype.replace("const", " ").split())
+        if "*" not in ctype:
+            return py is scalars[ctype]
+        base, stars = ctype.replace("*", " ").strip(), ctype.count("*")
+        if stars == 1 and base in structs:
+            return py is ctypes.POINTER(structs[base])
+        if stars == 1 and base in scalars:
+            return py in (ctypes.POINTER(scalars[base]), ctypes.c_void_p)
+        if stars == 1 and base == "char":
+            return py is ctypes.c_char_p
+        if stars == 1:  # void * or an opaque handle
+            return py is ctypes.c_void_p
+        return py is ctypes.POINTER(ctypes.c_void_p)  # an out-pointer to a handle or pointer
+
+    checked = 0
+    for name, (res, args) in _lib.SIGNATURES.items():
+        m = re.search(r"([\w\s\*]+?)\b" + name + r"\s*\(([^)]*)\)\s*;", hdr)
+        assert m, name
+        ret = m.group(1).split("\n")[-1]
+        assert agrees(ret.replace(name, ""), res), (name, ret)
+        params = [p.strip() for p in m.group(2).split(",") if p.strip() and p.strip() != "void"]
+        assert len(params) == len(args), (name, params)
+        for p, py in zip(params, args):
+            ctype = re.sub(r"\b\w+$", "", p.replace("*const*", "**")).strip()  # drop the parameter name
+            assert agrees(ctype, py), (name, p, py)
+        checked += 1
+    assert checked == len(_lib.SIGNATURES)
