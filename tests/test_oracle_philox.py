@@ -94,3 +94,29 @@ def test_threshold_closed_forms():
     Ks = np.linspace(0.01, 5, 200)
     Ts = [oracle.threshold(k) for k in Ks]
     assert all(a <= b for a, b in zip(Ts, Ts[1:]))
+
+
+def test_oracle_ctypes_match_header():
+    """The oracle wrapper's ctypes declarations equal the C prototypes of
+    swccl_oracle.h (return type, arity, parameter types; arrays are pointers)."""
+    import ctypes
+    import os
+    import re
+
+    hdr = open(os.path.join(os.path.dirname(oracle.__file__), "swccl_oracle.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", " ", hdr, flags=re.S)
+    scalars = {"int32_t": ctypes.c_int32, "uint32_t": ctypes.c_uint32, "int64_t": ctypes.c_int64,
+               "uint64_t": ctypes.c_uint64, "uint8_t": ctypes.c_uint8, "double": ctypes.c_double}
+    lib = oracle._load()
+    protos = re.findall(r"(\w+)\s+(orc_\w+)\s*\(([^)]*)\)\s*;", hdr)
+    assert {p[1] for p in protos} == set(re.findall(r"\b(orc_\w+)\s*\(", hdr))  # every prototype parsed
+    for ret, name, params in protos:
+        fn = getattr(lib, name)
+        assert (fn.restype is None) if ret == "void" else (fn.restype is scalars[ret]), name
+        plist = [p.strip() for p in params.split(",") if p.strip() and p.strip() != "void"]
+        assert len(plist) == len(fn.argtypes), name
+        for p, py in zip(plist, fn.argtypes):
+            p = re.sub(r"(\w+)\s*\[\d*\]$", r"* \1", p)  # an array parameter is a pointer
+            base = " ".join(re.sub(r"\b\w+$", "", p).replace("const", " ").replace("*", " ").split())
+            want = ctypes.POINTER(scalars[base]) if "*" in p else scalars[base]
+            assert py is want, (name, p, py)
