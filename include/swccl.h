@@ -70,7 +70,9 @@ typedef int32_t sw_status;
 enum {
     SW_OK = 0,
     SW_ERR_ARG = 1,         /* null pointer, bad enum, q out of range, n < 0 */
-    SW_ERR_SIZE = 2,        /* W or H < 1 (< 2 for SW), or W*H >= 2^31      */
+    SW_ERR_SIZE = 2,        /* W or H < 1 (< 2 for SW), W*H >= 2^31, or a
+                               lattice so thin that its tiles' boundary ids
+                               (384 per 128 x 64 tile) reach 2^31          */
     SW_ERR_WORKSPACE = 3,   /* workspace missing or smaller than required   */
     SW_ERR_DEVICE = 4,      /* a HIP call failed (see sw_last_error)         */
     SW_ERR_STATE = 5,       /* call out of order, sweep counter would pass
@@ -170,7 +172,9 @@ uint64_t sw_threshold(double K);
 size_t sw_workspace_bytes(const sw_params *p);
 
 /* Create a lattice handle over caller-owned buffers and, unless
- * SW_F_KEEP_SPINS is set, draw the initial spins (t = 0, Philox tag 0).
+ * SW_F_KEEP_SPINS is set, draw the initial spins (t = 0, Philox tag 0): each
+ * site independently uniform over the q states, the same law as the state a
+ * cluster draws in SW step 3 (Sec. II, enumerated steps).
  * SW_F_SIZES needs b->roots and b->sizes (else SW_ERR_ARG).
  * The handle keeps copies of p and b; the buffers must outlive it.
  * Returns SW_ERR_ARG / SW_ERR_SIZE / SW_ERR_WORKSPACE before enqueuing
@@ -209,7 +213,10 @@ sw_status sw_sweep_phase(sw_lattice *h, int32_t phase, void *stream);
 
 /* Measure the current spins (satisfied bonds, state counts, digests) and the
  * last sweep's counters (active bonds, clusters, largest cluster); waits for
- * the stream. */
+ * the stream.  The number of satisfied bonds is -H/J of the Potts Hamiltonian
+ * (Sec. II, Eq. potts_hamiltonian); the Ising energy per site follows as
+ * -(2 n_sat - 2N)/N and the magnetisation from the state counts.  Active bonds
+ * and clusters are those of the last sweep's steps 1 and 2 (Sec. II). */
 sw_status sw_observables(sw_lattice *h, sw_obs *out, void *stream);
 
 /* Checkpointing: the full state of a lattice is (spins, t); a restart is
@@ -280,7 +287,10 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
                     size_t workspace_bytes, void *stream);
 
 /* ---- Served labeling: requests labeled as they arrive (ccl_label on each),
- * over one caller-owned device arena.  An admitted request takes one arena
+ * over one caller-owned device arena.  The workload is the image-segmentation
+ * use of connected-component labeling that motivates the paper (Sec. I): each
+ * request is a binary image (or bond array) whose clusters are identified as
+ * in SW step 2 (Sec. II.B-II.C).  An admitted request takes one arena
  * block of ccl_server_footprint() bytes (its input, labels, optional roots
  * and sizes, and labeling workspace), so the number in flight is bounded by
  * memory, not by a fixed slot size; a request that does not fit is refused

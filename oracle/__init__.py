@@ -10,9 +10,11 @@ Ising conversion (s = 2*state - 1) is done by the caller.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
+import tempfile
 
 import numpy as np
 
@@ -39,49 +41,95 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
-_lib = None
+NATIVE_FLAGS = ["-O3", "-march=native", "-std=c11"]
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB)
-        u8p = ctypes.POINTER(ctypes.c_uint8)
-        i32p = ctypes.POINTER(ctypes.c_int32)
-        i64p = ctypes.POINTER(ctypes.c_int64)
-        u32p = ctypes.POINTER(ctypes.c_uint32)
-        c_i32, c_u32, c_u64, c_i64 = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64
-        lib.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
-        lib.orc_philox4x32_10.restype = None
-        lib.orc_threshold.argtypes = [ctypes.c_double]
-        lib.orc_threshold.restype = c_u64
-        lib.orc_init_states.argtypes = [c_i32, c_i32, c_i32, c_u64, c_u32, u8p]
-        lib.orc_init_states.restype = None
-        lib.orc_activate_bonds.argtypes = [c_i32, c_i32, u8p, c_u64, c_u64, c_u32, c_u32, u8p]
-        lib.orc_activate_bonds.restype = None
-        lib.orc_label_bonds.argtypes = [c_i32, c_i32, u8p, c_i32, i32p]
-        lib.orc_label_bonds.restype = c_i64
-        lib.orc_label_sites.argtypes = [c_i32, c_i32, u8p, i32p]
-        lib.orc_label_sites.restype = c_i64
-        lib.orc_cluster_sizes.argtypes = [c_i64, i32p, i32p, i32p, i64p]
-        lib.orc_cluster_sizes.restype = c_i64
-        lib.orc_flip.argtypes = [c_i32, c_i32, c_i32, i32p, c_u64, c_u32, c_u32, u8p]
-        lib.orc_flip.restype = None
-        lib.orc_satisfied.argtypes = [c_i32, c_i32, c_i32, u8p, i64p]
-        lib.orc_satisfied.restype = c_i64
-        lib.orc_sw_sweep.argtypes = [c_i32, c_i32, c_i32, c_u64, c_u64, c_u32, c_u32,
-                                     u8p, u8p, i32p, i64p]
-        lib.orc_sw_sweep.restype = None
-        lib.orc_sw_run.argtypes = [c_i32, c_i32, c_i32, c_u64, c_u64, c_u32, c_u32, c_i32,
-                                   u8p, i64p]
-        lib.orc_sw_run.restype = None
-        lib.orc_digest_u8.argtypes = [c_i64, u8p]
-        lib.orc_digest_u8.restype = c_u64
-        lib.orc_digest_i32.argtypes = [c_i64, i32p]
-        lib.orc_digest_i32.restype = c_u64
-        _lib = lib
-    return _lib
+def build_native() -> str:
+    """Compile the same source with -O3 -march=native for the host that runs
+    this process (the CPU-baseline timing and long fixture runs).  Built into a
+    fresh temporary directory every time: a library tuned for one host's CPU
+    must never be loaded on another."""
+    d = tempfile.mkdtemp(prefix="swccl_oracle_native_")
+    out = os.path.join(d, "liboracle_native.so")
+    subprocess.check_call(["gcc", *NATIVE_FLAGS, "-fPIC", "-shared", "-o", out, _SRC, "-lm"])
+    return out
+
+
+_libs: dict = {}
+_flavor = "O2"
+
+
+def use_flavor(flavor: str) -> None:
+    """Select the build the functions below call: "O2" (the default, built
+    in-tree) or "native" (-O3 -march=native, built for this host on first
+    use).  Both compile the same source; a CPU test checks that they agree."""
+    global _flavor
+    if flavor not in ("O2", "native"):
+        raise ValueError(f"unknown oracle build flavor {flavor!r}")
+    _flavor = flavor
+
+
+def flavor() -> str:
+    return _flavor
+
+
+def _load(which: str | None = None):
+    which = which or _flavor
+    if which not in _libs:
+        _libs[which] = _declare(ctypes.CDLL(build() if which == "O2" else build_native()))
+    return _libs[which]
+
+
+@contextlib.contextmanager
+def using_library(path: str):
+    """Route every call below to another build of the oracle (tests that plant
+    a mistake in a copy of the source check that the pins catch it)."""
+    global _flavor
+    key = f"path:{path}"
+    _libs[key] = _declare(ctypes.CDLL(path))
+    prev, _flavor = _flavor, key
+    try:
+        yield
+    finally:
+        _flavor = prev
+        _libs.pop(key, None)
+
+
+def _declare(lib):
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    c_i32, c_u32, c_u64, c_i64 = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64
+    lib.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    lib.orc_philox4x32_10.restype = None
+    lib.orc_threshold.argtypes = [ctypes.c_double]
+    lib.orc_threshold.restype = c_u64
+    lib.orc_init_states.argtypes = [c_i32, c_i32, c_i32, c_u64, c_u32, u8p]
+    lib.orc_init_states.restype = None
+    lib.orc_activate_bonds.argtypes = [c_i32, c_i32, u8p, c_u64, c_u64, c_u32, c_u32, u8p]
+    lib.orc_activate_bonds.restype = None
+    lib.orc_label_bonds.argtypes = [c_i32, c_i32, u8p, c_i32, i32p]
+    lib.orc_label_bonds.restype = c_i64
+    lib.orc_label_sites.argtypes = [c_i32, c_i32, u8p, i32p]
+    lib.orc_label_sites.restype = c_i64
+    lib.orc_cluster_sizes.argtypes = [c_i64, i32p, i32p, i32p, i64p]
+    lib.orc_cluster_sizes.restype = c_i64
+    lib.orc_flip.argtypes = [c_i32, c_i32, c_i32, i32p, c_u64, c_u32, c_u32, u8p]
+    lib.orc_flip.restype = None
+    lib.orc_satisfied.argtypes = [c_i32, c_i32, c_i32, u8p, i64p]
+    lib.orc_satisfied.restype = c_i64
+    lib.orc_sw_sweep.argtypes = [c_i32, c_i32, c_i32, c_u64, c_u64, c_u32, c_u32,
+                                 u8p, u8p, i32p, i64p]
+    lib.orc_sw_sweep.restype = None
+    lib.orc_sw_run.argtypes = [c_i32, c_i32, c_i32, c_u64, c_u64, c_u32, c_u32, c_i32,
+                               u8p, i64p]
+    lib.orc_sw_run.restype = None
+    lib.orc_digest_u8.argtypes = [c_i64, u8p]
+    lib.orc_digest_u8.restype = c_u64
+    lib.orc_digest_i32.argtypes = [c_i64, i32p]
+    lib.orc_digest_i32.restype = c_u64
+    return lib
 
 
 def _p(a: np.ndarray | None, ct):

@@ -69,7 +69,11 @@ class CclServerParams(ctypes.Structure):
 
 
 class SwccLError(RuntimeError):
-    """A non-zero sw_status from the library."""
+    """A non-zero sw_status from the library (``status``)."""
+
+    def __init__(self, message: str, status: int = 0):
+        super().__init__(message)
+        self.status = int(status)
 
 
 _lib = None
@@ -143,4 +147,4 @@ def check(status: int, what: str) -> None:
         L = lib()
         msg = L.sw_status_string(status).decode()
         extra = L.sw_last_error().decode() if status == SW_ERR_DEVICE else ""
-        raise SwccLError(f"{what}: {msg} ({status}) {extra}".strip())
+        raise SwccLError(f"{what}: {msg} ({status}) {extra}".strip(), status)

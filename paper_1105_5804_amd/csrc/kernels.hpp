@@ -1471,7 +1471,17 @@ __global__ __launch_bounds__(NT) void k_observe(const uint8_t *s, int W, int H, 
         const uint8_t *row = s + static_cast<int64_t>(y) * W;
         const uint8_t *dwn = s + static_cast<int64_t>(y + 1 == H ? 0 : y + 1) * W;
         uint64_t h03 = 0, h47 = 0;
+        int steps = 0;  // a 16-bit field takes at most 4 per step: flushed every 8192 steps
         for (int x = threadIdx.x * 4; x < W; x += NT * 4) {
+            if (++steps == 8192) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    cnt[k] += (h03 >> (16 * k)) & 0xFFFFull;
+                    cnt[k + 4] += (h47 >> (16 * k)) & 0xFFFFull;
+                }
+                h03 = h47 = 0;
+                steps = 0;
+            }
             uint32_t v[5], d[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {

@@ -49,10 +49,13 @@ size_t scan_tmp_bytes(int64_t n)
     return b + ALIGN;
 }
 
+// N = W H < 2^31, and the boundary ids of all tiles (ntiles x CAP) index int32
+// arrays: a very thin lattice has far more tiles than sites / TSITES.
 bool valid_shape(int32_t W, int32_t H, int32_t min_side)
 {
     if (W < min_side || H < min_side) return false;
-    return static_cast<int64_t>(W) * H < (static_cast<int64_t>(1) << 31);
+    if (static_cast<int64_t>(W) * H >= (static_cast<int64_t>(1) << 31)) return false;
+    return cdiv(W, TW) * cdiv(H, TH) * CAP < (static_cast<int64_t>(1) << 31);
 }
 
 // Per-tile arrays shared by single lattices and batches; returns the bytes used.

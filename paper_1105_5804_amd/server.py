@@ -6,7 +6,10 @@ when its footprint fits in the device arena (``SW_ERR_STATE`` otherwise: the
 request waits here, in submission order), spreads requests over the given
 streams, and reports completions through ``poll``.  A request still waiting
 for admission can be withdrawn (``cancel``) or dropped after a deadline
-(``expire``); an admitted one runs to completion.
+(``expire``); an admitted one runs to completion.  A request that can never
+be admitted (an invalid shape, or a footprint larger than the arena) is refused
+by ``submit``; one the library refuses later for another reason is dropped from
+the queue by ``pump`` and reported in ``rejected``.
 """
 from __future__ import annotations
 
@@ -45,9 +48,11 @@ class CCLServer:
         self._h = ctypes.c_void_p()
         _lib.check(L.ccl_server_create(ctypes.byref(self._h), ctypes.byref(self.params), self._arena_ptr,
                                        int(arena_bytes), arr), "ccl_server_create")
+        self.arena_bytes = int(arena_bytes)
         self._queue = collections.deque()   # (tag, image, submit time) waiting for admission
         self._inflight = {}                 # slot -> (tag, image, W, H)
         cap = int(max_inflight)
+        self.rejected = []                  # (tag, status) dropped from the queue by pump
         self._pslots = (ctypes.c_int32 * cap)()
         self._ptags = (ctypes.c_uint64 * cap)()
 
@@ -65,16 +70,34 @@ class CCLServer:
         return True
 
     def submit(self, tag: int, img) -> None:
-        """Queue a request; it is admitted at once if the arena has room."""
+        """Queue a request; it is admitted at once if the arena has room.
+        Raises for a request that could never be admitted (nothing is queued)."""
         if img.dim() != 2 or img.dtype.itemsize != 1 or img.device.type != "cpu" or img.stride(1) != 1:
             raise ValueError("a request is a 2D uint8 CPU tensor with unit column stride")
+        H, W = img.shape
+        fp = self.footprint(W, H)
+        if fp == 0 or fp > self.arena_bytes:
+            raise _lib.SwccLError(f"ccl_server_submit: a {W}x{H} request can never be admitted "
+                                  f"(footprint {fp} B, arena {self.arena_bytes} B)", _lib.SW_ERR_SIZE)
         if self._queue or not self._try_submit(tag, img):
             self._queue.append((tag, img, time.monotonic()))
 
-    def pump(self) -> None:
-        """Admit queued requests, in order, while they fit."""
-        while self._queue and self._try_submit(self._queue[0][0], self._queue[0][1]):
+    def pump(self) -> list:
+        """Admit queued requests, in order, while they fit.  A queued request the
+        library refuses for any reason other than lack of room is dropped (so it
+        cannot block the requests behind it); returns the tags dropped by this
+        call, which are also appended, with their status, to ``rejected``."""
+        dropped = []
+        while self._queue:
+            tag, img, _ = self._queue[0]
+            try:
+                if not self._try_submit(tag, img):
+                    break
+            except _lib.SwccLError as e:
+                self.rejected.append((tag, e.status))
+                dropped.append(tag)
             self._queue.popleft()
+        return dropped
 
     def cancel(self, tag: int) -> bool:
         """Withdraw the oldest queued request with this tag (True if there was
@@ -126,6 +149,14 @@ class CCLServer:
         return labels, view(ptrs[1].value, ncl), view(ptrs[2].value, ncl), ncl
 
     def release(self, slot: int) -> None:
+        """Return a request's arena block.  Work the caller has enqueued on the
+        current stream (e.g. a copy of the result views) finishes before any
+        later request can write the block: every server stream waits for it."""
+        torch = _torch()
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(self.device))
+        for s in self.streams:
+            s.wait_event(ev)
         _lib.check(_lib.lib().ccl_server_release(self._h, int(slot)), "ccl_server_release")
         del self._inflight[slot]
 

@@ -71,7 +71,8 @@ int main(void)
     EXPECT(ccl_workspace_bytes(16, 16, -1) == 0 && ccl_workspace_bytes(16, 16, 3) == 0);
     EXPECT(ccl_workspace_bytes(0, 16, CCL_SITES_OPEN) == 0 && ccl_workspace_bytes(16, -5, CCL_SITES_OPEN) == 0);
     EXPECT(ccl_workspace_bytes(65536, 32768, CCL_SITES_OPEN) == 0);  /* W*H = 2^31 */
-    EXPECT(ccl_workspace_bytes(2147483647, 1, CCL_SITES_OPEN) > 0);  /* one row, just below 2^31 */
+    EXPECT(ccl_workspace_bytes(2147483647, 1, CCL_SITES_OPEN) == 0); /* one row below 2^31: tile ids pass 2^31 */
+    EXPECT(ccl_workspace_bytes(1 << 22, 1, CCL_SITES_OPEN) > 0);      /* one row of 2^22 pixels */
 
     /* lattice parameters */
     sw_params bad[] = {params(1, 8, 2, SW_SPIN_ISING_I8, 0), params(8, 8, 1, SW_SPIN_POTTS_U8, 0),

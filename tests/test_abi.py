@@ -86,6 +86,19 @@ def test_good_params_sized():
     assert L.sw_workspace_bytes(ctypes.byref(big)) < 16384 * 16384 * 3
 
 
+def test_thin_lattices_bounded_by_tile_ids():
+    """N < 2^31 is not enough: every tile's boundary ids (ntiles x 384) index
+    int32 arrays, which bounds very thin lattices."""
+    L = _lib.lib()
+    for W, H in [(2**30 - 1, 2), (2, 2**30 - 1), (1_000_000_000, 2)]:
+        assert W * H < 2**31
+        assert L.sw_workspace_bytes(ctypes.byref(_params(W=W, H=H))) == 0, (W, H)
+        assert L.ccl_workspace_bytes(W, H, 0) == 0, (W, H)
+    for W, H in [(2**22, 2), (2, 2**20), (46340, 46340)]:
+        assert L.sw_workspace_bytes(ctypes.byref(_params(W=W, H=H))) > 0, (W, H)
+        assert L.ccl_workspace_bytes(W, H, 2) > 0, (W, H)
+
+
 def test_init_argument_errors():
     L = _lib.lib()
     p = _params()

@@ -13,6 +13,16 @@ partition of the requested unions, and leave each component's minimum key at
 its root (the key the flatten reports as the canonical label).  A non-atomic
 swap, a link in the wrong key order and a halving store that crosses the two
 chains must each be caught.
+
+The GPU runs the merge across eight chiplets whose L2 caches are not kept
+coherent with each other inside a launch: a plain load may return any value
+the location held earlier in the launch (a stale cache line), and a plain
+store may become visible to other work-groups late, after later events of
+its own thread.  Only the compare-and-swap acts on the location's current
+value.  The weak-memory runs give every plain load and store those
+semantics; the same checks must hold, and a mistake that only stale loads
+can expose (after a failed swap, continuing from a plain reload of the node
+and giving up when that reload still shows it as a root) must be caught.
 """
 import random
 
@@ -40,7 +50,53 @@ def _want(n, pairs, key):
     return comp, {c: best[c] for c in best}
 
 
-def _unite(G, key, a, b, mistake):
+class _Mem:
+    """Shared parents.  Sequentially consistent unless weak: then a plain load
+    may return any earlier value of the location, and a plain store may be
+    held back and applied later (in program order per thread)."""
+
+    def __init__(self, n, rng, weak):
+        self.hist = [[x] for x in range(n)]  # every value each location held, oldest first
+        self.rng, self.weak = rng, weak
+        self.pending = {}  # thread -> list of held-back stores
+
+    def cur(self, x):
+        return self.hist[x][-1]
+
+    def __getitem__(self, x):
+        h = self.hist[x]
+        if self.weak and len(h) > 1 and self.rng.random() < 0.5:
+            return h[self.rng.randrange(len(h))]
+        return h[-1]
+
+    def store(self, tid, x, v):
+        if self.weak and self.rng.random() < 0.5:
+            self.pending.setdefault(tid, []).append((x, v))
+        else:
+            self.flush_thread(tid)  # a thread's stores stay in program order
+            self.hist[x].append(v)
+
+    def flush_thread(self, tid):
+        for x, v in self.pending.pop(tid, []):
+            self.hist[x].append(v)
+
+    def flush_some(self):
+        if self.pending:
+            self.flush_thread(self.rng.choice(list(self.pending)))
+
+    def cas(self, x, expect, new):
+        if self.hist[x][-1] == expect:
+            self.hist[x].append(new)
+            return True, expect
+        return False, self.hist[x][-1]
+
+    def final(self):
+        for tid in list(self.pending):
+            self.flush_thread(tid)
+        return [h[-1] for h in self.hist]
+
+
+def _unite(G, key, a, b, mistake, tid=0):
     """Generator: one yield per shared-memory event of gunite(a, b)."""
 
     def find2():
@@ -55,10 +111,10 @@ def _unite(G, key, a, b, mistake):
             gb = G[pb]
             yield
             if ga != pa:
-                G[a] = gb if mistake == "crossed_halving" else ga
+                G.store(tid, a, gb if mistake == "crossed_halving" else ga)
                 yield
             if gb != pb:
-                G[b] = gb
+                G.store(tid, b, gb)
                 yield
             a, b = ga, gb
             pa = G[a]
@@ -76,25 +132,30 @@ def _unite(G, key, a, b, mistake):
             seen = G[a]
             yield
             if seen == a:
-                G[a] = b  # written later than read: another link may land in between
+                G.store(tid, a, b)  # written later than read: another link may land in between
                 yield
                 return
             a = seen
         else:
-            cur = G[a]
-            if cur == a:
-                G[a] = b
-                yield
-                return
+            ok, cur = G.cas(a, a, b)
             yield
+            if ok:
+                return
+            if mistake == "reload_after_failed_cas":
+                cur = G[a]  # a plain reload instead of the value the swap returned
+                yield
+                if cur == a:
+                    return  # "it is still a root, so another lane linked it to b": wrong
             a = cur
         yield from find2()
 
 
-def _run(n, pairs, key, rng, mistake=None):
-    G = list(range(n))
-    live = [_unite(G, key, a, b, mistake) for a, b in pairs]
+def _run(n, pairs, key, rng, mistake=None, weak=False):
+    G = _Mem(n, rng, weak)
+    live = [_unite(G, key, a, b, mistake, tid) for tid, (a, b) in enumerate(pairs)]
     while live:
+        if weak and rng.random() < 0.2:
+            G.flush_some()
         k = rng.randrange(len(live))
         try:
             next(live[k])
@@ -104,8 +165,9 @@ def _run(n, pairs, key, rng, mistake=None):
             continue
         if mistake is None:
             for x in range(n):
-                assert G[x] == x or key[G[x]] < key[x], "parent key above its child's"
-    return G
+                p = G.cur(x)
+                assert p == x or key[p] < key[x], "parent key above its child's"
+    return G.final()
 
 
 def _check(G, key, comp, best):
@@ -153,14 +215,47 @@ def test_merge_chain_of_tiles():
         _check(_run(n, pairs, key, rng), key, comp, best)
 
 
-@pytest.mark.parametrize("mistake", ["non_atomic", "wrong_order", "crossed_halving"])
-def test_planted_mistakes_are_caught(mistake):
+@pytest.mark.parametrize("n,n_pairs", [(4, 6), (10, 12), (30, 40), (80, 60)])
+def test_merge_weak_memory(n, n_pairs):
+    """Stale plain loads and late plain stores (no coherence across chiplets
+    inside a launch): the same partition, minimum-key roots and key order."""
+    rng = random.Random(1000 + 31 * n + n_pairs)
+    for _ in range(300 if n <= 30 else 60):
+        key, pairs = _case(rng, n, n_pairs)
+        comp, best = _want(n, pairs, key)
+        _check(_run(n, pairs, key, rng, weak=True), key, comp, best)
+
+
+def test_merge_chain_weak_memory():
+    rng = random.Random(5)
+    for _ in range(100):
+        n = 40
+        key = rng.sample(range(1000), n)
+        pairs = [(i, i + 1) for i in range(n - 1)]
+        rng.shuffle(pairs)
+        comp, best = _want(n, pairs, key)
+        _check(_run(n, pairs, key, rng, weak=True), key, comp, best)
+
+
+def _caught(mistake, weak, tries=3000):
     rng = random.Random(77)
-    for _ in range(3000):
+    for _ in range(tries):
         key, pairs = _case(rng, 8, 10)
         comp, best = _want(8, pairs, key)
         try:
-            _check(_run(8, pairs, key, rng, mistake=mistake), key, comp, best)
+            _check(_run(8, pairs, key, rng, mistake=mistake, weak=weak), key, comp, best)
         except AssertionError:
-            return
-    pytest.fail(f"{mistake}: no schedule in 3000 exposed it")
+            return True
+    return False
+
+
+@pytest.mark.parametrize("mistake", ["non_atomic", "wrong_order", "crossed_halving"])
+def test_planted_mistakes_are_caught(mistake):
+    assert _caught(mistake, weak=False), f"{mistake}: no schedule in 3000 exposed it"
+
+
+def test_stale_load_mistake_needs_weak_memory():
+    """Continuing from a plain reload after a failed swap is right when loads
+    are fresh and wrong when they may be stale: only the weak model sees it."""
+    assert not _caught("reload_after_failed_cas", weak=False, tries=1500)
+    assert _caught("reload_after_failed_cas", weak=True)

@@ -5,6 +5,7 @@ generator (its host-callable header, compiled here for the CPU), which shares
 nothing with the oracle.  The threshold is pinned against closed forms of the
 critical bond probabilities.
 """
+import atexit
 import math
 import os
 import shutil
@@ -36,20 +37,31 @@ int main() {
 """
 
 
-def _rocrand_blocks(rows):
-    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
-    hdr = "/opt/rocm/include/rocrand/rocrand_kernel.h"
-    if not (os.path.exists(hipcc) and os.path.exists(hdr)):
-        pytest.skip("hipcc or rocRAND headers not available")
-    with tempfile.TemporaryDirectory() as d:
+_HELPER = {}
+
+
+def _rocrand_exe():
+    """The helper program, compiled once per test session."""
+    if "exe" not in _HELPER:
+        hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+        hdr = "/opt/rocm/include/rocrand/rocrand_kernel.h"
+        if not (os.path.exists(hipcc) and os.path.exists(hdr)):
+            pytest.skip("hipcc or rocRAND headers not available")
+        d = tempfile.mkdtemp(prefix="swccl_rocrand_")
+        atexit.register(shutil.rmtree, d, True)
         src = os.path.join(d, "rr.cpp")
         exe = os.path.join(d, "rr")
         with open(src, "w") as f:
             f.write(_ROCRAND_HELPER)
         subprocess.check_call([hipcc, "-O1", "-o", exe, src],
                               stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
-        inp = "\n".join(" ".join("%08x" % v for v in r) for r in rows) + "\n"
-        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+        _HELPER["exe"] = exe
+    return _HELPER["exe"]
+
+
+def _rocrand_blocks(rows):
+    inp = "\n".join(" ".join("%08x" % v for v in r) for r in rows) + "\n"
+    out = subprocess.run([_rocrand_exe()], input=inp, capture_output=True, text=True, check=True).stdout
     return [[int(w, 16) for w in line.split()] for line in out.strip().splitlines()]
 
 
