@@ -286,6 +286,25 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
                     int32_t *roots, int32_t *sizes, int32_t *n_clusters, void *workspace,
                     size_t workspace_bytes, void *stream);
 
+/* ccl_label without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Its scratch is one
+ * static device array of CCL_NOALLOC_SCRATCH_BYTES per GPU, held by the loaded
+ * library until the process ends, at an address looked up once per device on
+ * that device's first call.  Arguments, outputs and results as ccl_label; the
+ * stream must belong to the current device.
+ * Limit: a shape whose ccl_workspace_bytes(W, H, mode) (with sizes when roots
+ * are requested) exceeds CCL_NOALLOC_SCRATCH_BYTES is refused with
+ * SW_ERR_WORKSPACE before anything is enqueued (sw_last_error() gives both
+ * sizes); 64 MiB holds an image of 2048 x 2048 with sizes.
+ * Every call on one GPU uses the same scratch: calls that overlap on one GPU
+ * (different streams, or host threads, without ordering) race and give wrong
+ * results; calls on one stream are ordered and safe.  No part of the scratch
+ * needs to start at zero.  SW_ERR_DEVICE if the address lookup fails. */
+#define CCL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sw_status ccl_label_noalloc(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32_t *labels,
+                            int32_t *roots, int32_t *sizes, int32_t *n_clusters, void *stream);
+
 /* ---- Served labeling: requests labeled as they arrive (ccl_label on each),
  * over one caller-owned device arena.  The workload is the image-segmentation
  * use of connected-component labeling that motivates the paper (Sec. I): each

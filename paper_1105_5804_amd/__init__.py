@@ -24,6 +24,7 @@ __all__ = [
     "SWLattice",
     "SWBatch",
     "ccl_label",
+    "ccl_label_noalloc",
     "ccl_workspace_bytes",
     "threshold",
     "ising_K",
@@ -379,6 +380,39 @@ def ccl_label(inp, mode: str | int = "bonds_periodic", sizes: bool = False, work
         stream.synchronize()
     n = int(ncl.item())
     return labels, roots[:n], szs[:n], n
+
+
+def ccl_label_noalloc(inp, labels, n_clusters=None, roots=None, sizes=None,
+                      mode: str | int = "bonds_periodic", stream=None) -> None:
+    """ccl_label into caller-made outputs with the library's static scratch:
+    nothing is allocated (for code under graph capture or loops that must not
+    allocate).  ``inp`` (H, W) uint8 and ``labels`` (H, W) int32, contiguous, on
+    the current device; ``n_clusters`` one int32 or None; ``roots`` and
+    ``sizes`` N int32 each or both None.  Enqueued on ``stream`` (default: the
+    current stream) without waiting.  Calls that overlap on one GPU share the
+    scratch and race; calls on one stream are safe."""
+    torch = _torch()
+    L = _lib.lib()
+    m = _MODES[mode] if isinstance(mode, str) else int(mode)
+    if inp.dim() != 2 or inp.dtype != torch.uint8 or inp.device.type != "cuda" or not inp.is_contiguous():
+        raise ValueError("input must be a contiguous 2D uint8 GPU tensor")
+    H, W = inp.shape
+    if (labels.shape != (H, W) or labels.dtype != torch.int32 or labels.device != inp.device
+            or not labels.is_contiguous()):
+        raise ValueError(f"labels must be a contiguous ({H}, {W}) int32 tensor on {inp.device}")
+    for name, t in (("n_clusters", n_clusters), ("roots", roots), ("sizes", sizes)):
+        if t is not None and (t.dtype != torch.int32 or t.device != inp.device or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous int32 tensor on {inp.device}")
+    if (roots is None) != (sizes is None):
+        raise ValueError("roots and sizes go together")
+    if roots is not None and (roots.numel() < H * W or sizes.numel() < H * W):
+        raise ValueError("roots and sizes need H * W entries each")
+    st = L.ccl_label_noalloc(inp.data_ptr(), W, H, m, labels.data_ptr(),
+                             roots.data_ptr() if roots is not None else None,
+                             sizes.data_ptr() if sizes is not None else None,
+                             n_clusters.data_ptr() if n_clusters is not None else None,
+                             _stream(torch, stream))
+    _lib.check(st, "ccl_label_noalloc")
 
 
 from .server import CCLServer  # noqa: E402  (needs the helpers above)

@@ -14,6 +14,7 @@ SW_OK, SW_ERR_ARG, SW_ERR_SIZE, SW_ERR_WORKSPACE, SW_ERR_DEVICE, SW_ERR_STATE, S
 SW_SPIN_ISING_I8, SW_SPIN_POTTS_U8 = 0, 1
 SW_F_KEEP_SPINS, SW_F_SIZES, SW_F_REVERSE_TILES = 1, 2, 4
 CCL_BONDS_PERIODIC, CCL_BONDS_OPEN, CCL_SITES_OPEN = 0, 1, 2
+CCL_NOALLOC_SCRATCH_BYTES = 64 << 20
 SW_PHASE_TILE, SW_PHASE_MERGE, SW_PHASE_FLIP = 0, 1, 2
 SW_HIST_ACTIVE, SW_HIST_NCLUST, SW_HIST_MAXCL, SW_HIST_NSAT, SW_HIST_COUNTS, SW_HIST_LEN = 0, 1, 2, 3, 4, 12
 
@@ -120,6 +121,9 @@ SIGNATURES = {
     "ccl_label": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "ccl_label_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
 }
 
 

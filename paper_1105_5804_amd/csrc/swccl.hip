@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -588,8 +589,13 @@ size_t ccl_workspace_bytes(int32_t W, int32_t H, int32_t mode)
     return make_layout(W, H, true).total;
 }
 
-sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32_t *labels, int32_t *roots,
-                    int32_t *sizes, int32_t *n_clusters, void *workspace, size_t workspace_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Argument checks of ccl_label (before anything is enqueued).
+sw_status ccl_check(const uint8_t *in, int32_t W, int32_t H, int32_t mode, const int32_t *labels,
+                    const int32_t *roots, const int32_t *sizes)
 {
     if (!in || !labels) return SW_ERR_ARG;
     if (mode < CCL_BONDS_PERIODIC || mode > CCL_SITES_OPEN) return SW_ERR_ARG;
@@ -598,13 +604,16 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
     const int64_t N = static_cast<int64_t>(W) * H;
     const uintptr_t ib = reinterpret_cast<uintptr_t>(in), lb = reinterpret_cast<uintptr_t>(labels);
     if (ib < lb + static_cast<uintptr_t>(N) * 4 && lb < ib + static_cast<uintptr_t>(N)) return SW_ERR_ARG;
-    const bool want_sizes = roots != nullptr;
-    const Layout L = make_layout(W, H, want_sizes);
-    if (!workspace || workspace_bytes < L.total) return SW_ERR_WORKSPACE;
-    if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return SW_ERR_WORKSPACE;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const dim3 grid(static_cast<unsigned>(L.g.ntiles)), block(NT);
+    return SW_OK;
+}
 
+// The labeling launches over a workspace laid out by L (no entry of it needs
+// to start at zero: every word is written before it is read).
+sw_status ccl_enqueue(const Layout &L, const uint8_t *in, int32_t mode, int32_t *labels, int32_t *roots,
+                      int32_t *sizes, int32_t *n_clusters, void *workspace, hipStream_t s)
+{
+    const bool want_sizes = roots != nullptr;
+    const dim3 grid(static_cast<unsigned>(L.g.ntiles)), block(NT);
     const TileArgs ta = tile_args(L, workspace, in);
     switch (mode) {
     case CCL_BONDS_PERIODIC: launch_tile<M_BONDS_PERIODIC>(L, ta, s); break;
@@ -628,9 +637,74 @@ sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32
         hipLaunchKernelGGL(k_reduce_tiles, dim3(rb), dim3(NT), 0, s, fa.tile_ncl, L.g.ntiles,
                            static_cast<unsigned long long *>(nullptr), n_clusters);
     }
+    return SW_OK;
+}
+
+// Scratch of ccl_label_noalloc: one copy per GPU, held from module load until
+// the process ends.  Host code never uses the symbol's name as an address (on
+// the host it is a stand-in); it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) char scratch[CCL_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current device's scratch.
+sw_status scratch_of_current_device(void **out)
+{
+    int dev = -1;
+    if (const sw_status st = device_status(hipGetDevice(&dev), "hipGetDevice")) return st;
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        g_last_error = "device ordinal beyond the library's table";
+        return SW_ERR_DEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (const sw_status st = device_status(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress"))
+            return st;
+        if (!ptr || reinterpret_cast<uintptr_t>(ptr) % ALIGN) {
+            g_last_error = "static scratch has no usable device address";
+            return SW_ERR_DEVICE;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32_t *labels, int32_t *roots,
+                    int32_t *sizes, int32_t *n_clusters, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (const sw_status st = ccl_check(in, W, H, mode, labels, roots, sizes)) return st;
+    const Layout L = make_layout(W, H, roots != nullptr);
+    if (!workspace || workspace_bytes < L.total) return SW_ERR_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return SW_ERR_WORKSPACE;
+    ccl_enqueue(L, in, mode, labels, roots, sizes, n_clusters, workspace, static_cast<hipStream_t>(stream));
     return launch_status("ccl_label");
 }
 
+sw_status ccl_label_noalloc(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32_t *labels, int32_t *roots,
+                            int32_t *sizes, int32_t *n_clusters, void *stream)
+{
+    if (const sw_status st = ccl_check(in, W, H, mode, labels, roots, sizes)) return st;
+    const Layout L = make_layout(W, H, roots != nullptr);
+    if (L.total > CCL_NOALLOC_SCRATCH_BYTES) {
+        g_last_error = "ccl_label_noalloc: this shape needs " + std::to_string(L.total) +
+                       " bytes of scratch, the static scratch holds " +
+                       std::to_string(static_cast<size_t>(CCL_NOALLOC_SCRATCH_BYTES));
+        return SW_ERR_WORKSPACE;
+    }
+    void *ws = nullptr;
+    if (const sw_status st = scratch_of_current_device(&ws)) return st;
+    ccl_enqueue(L, in, mode, labels, roots, sizes, n_clusters, ws, static_cast<hipStream_t>(stream));
+    return launch_status("ccl_label_noalloc");
+}
 
 // ------------------------------------------------------------------ batches --
 

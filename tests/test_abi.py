@@ -153,6 +153,28 @@ def test_ccl_argument_errors():
     assert call(inp, W, H, 0, lab, None, None, None, ws + 4, need, None) == _lib.SW_ERR_WORKSPACE
 
 
+def test_ccl_noalloc_argument_errors():
+    """The allocation-free labeling call refuses bad arguments and shapes whose
+    workspace exceeds its static scratch before it touches a device."""
+    L = _lib.lib()
+    inp, lab = 0x10000000, 0x20000000
+    call = L.ccl_label_noalloc
+    assert call(None, 64, 64, 0, lab, None, None, None, None) == _lib.SW_ERR_ARG
+    assert call(inp, 64, 64, 0, None, None, None, None, None) == _lib.SW_ERR_ARG
+    assert call(inp, 64, 64, 3, lab, None, None, None, None) == _lib.SW_ERR_ARG
+    assert call(inp, 64, 64, 0, lab, 0x50000000, None, None, None) == _lib.SW_ERR_ARG
+    assert call(inp, 0, 64, 0, lab, None, None, None, None) == _lib.SW_ERR_SIZE
+    assert call(inp, 64, 64, 0, inp + 8, None, None, None, None) == _lib.SW_ERR_ARG
+    # the largest square image with sizes that fits, and the next sizes that do not
+    lim = _lib.CCL_NOALLOC_SCRATCH_BYTES
+    assert L.ccl_workspace_bytes(2048, 2048, 2) <= lim < L.ccl_workspace_bytes(2560, 2560, 2)
+    assert call(inp, 2560, 2560, 2, lab, 0x50000000, 0x60000000, None, None) == _lib.SW_ERR_WORKSPACE
+    msg = L.sw_last_error().decode()
+    assert str(lim) in msg and str(L.ccl_workspace_bytes(2560, 2560, 2)) in msg
+    assert L.ccl_workspace_bytes(8192, 8192, 0) > lim
+    assert call(inp, 8192, 8192, 0, lab, None, None, None, None) == _lib.SW_ERR_WORKSPACE
+
+
 def test_batch_argument_errors():
     L = _lib.lib()
     P = (_lib.SwParams * 3)(_params(), _params(W=100, H=37, q=3, kind=1), _params(W=2, H=2))
