@@ -49,6 +49,8 @@ def _args():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--study", action="store_true",
                     help="instead of the bench line: sweep time and phases over couplings and q at L=16384")
+    ap.add_argument("--tile-scan", action="store_true",
+                    help="instead of the bench line: sweep time and phases over tile shapes and merge schedules")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -193,6 +195,63 @@ def _study(args) -> int:
     return 0
 
 
+def _phase_times(torch, lat, steps, stream):
+    """Mean per-phase device time (tile, merge, flatten + flip) over `steps` sweeps."""
+    import numpy as np
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for k in range(steps):
+        evs[k][0].record(stream)
+        for ph in range(3):
+            lat.sweep_phase(ph)
+            evs[k][ph + 1].record(stream)
+    torch.cuda.synchronize()
+    return [float(np.mean([evs[k][p].elapsed_time(evs[k][p + 1]) for k in range(steps)])) for p in range(3)]
+
+
+def _tile_scan(args) -> int:
+    """Sweep time and per-phase split against the tile shape (128 x tile_h) and
+    the merge schedule (tiles per merge workgroup), on the benchmark lattice
+    (q = 3 Potts, L = 16384, critical coupling) and on bond-percolation
+    labeling of the same size: the local/global trade-off of the tile size."""
+    import torch
+
+    import paper_1105_5804_amd as sw
+    from paper_1105_5804_amd import workloads as wl
+
+    cfg = wl.CONFIGS["potts16384"]
+    N = cfg.W * cfg.H
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    inp = torch.from_numpy(wl.percolation_bonds(cfg.W, cfg.H, seed=wl.SEED_BASE | 3)).cuda()
+    labels = torch.empty((cfg.H, cfg.W), dtype=torch.int32, device="cuda")
+    for th in (16, 32, 64, 128):
+        for mw in (4, 8, 16):
+            lat = sw.SWLattice(cfg.W, cfg.H, q=cfg.q, K=cfg.K, seed=cfg.seed, ising=False, tile_h=th, merge_waves=mw)
+            lat.sweep(max(args.warmup, 5))
+            torch.cuda.synchronize()
+            ph = _phase_times(torch, lat, args.steps, stream)
+            del lat
+            torch.cuda.empty_cache()
+            ws = torch.empty(sw.ccl_workspace_bytes(cfg.W, cfg.H, tile_h=th) + 256, dtype=torch.uint8, device="cuda")
+            for _ in range(2):
+                sw.ccl_label(inp, "bonds_periodic", workspace=ws, labels=labels, tile_h=th, merge_waves=mw)
+            c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            c0.record(stream)
+            for _ in range(args.steps):
+                sw.ccl_label(inp, "bonds_periodic", workspace=ws, labels=labels, tile_h=th, merge_waves=mw)
+            c1.record(stream)
+            torch.cuda.synchronize()
+            ccl_ms = c0.elapsed_time(c1) / args.steps
+            del ws
+            torch.cuda.empty_cache()
+            row = {"tile": f"128x{th}", "merge_waves": mw, "ms_per_sweep": round(sum(ph), 4),
+                   "ns_per_spin": round(sum(ph) * 1e6 / N, 6), "tile_ms": round(ph[0], 4),
+                   "merge_ms": round(ph[1], 4), "flip_ms": round(ph[2], 4), "ccl_ms": round(ccl_ms, 4)}
+            print(json.dumps(row), flush=True)
+    return 0
+
+
 def main() -> int:
     args = _args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -204,6 +263,8 @@ def main() -> int:
 
     if args.study:
         return _study(args)
+    if args.tile_scan:
+        return _tile_scan(args)
 
     import numpy as np
     import torch

@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define SWCCL_ABI_VERSION 3
+#define SWCCL_ABI_VERSION 4
 
 typedef int32_t sw_status;
 enum {
@@ -116,6 +116,14 @@ typedef struct sw_params {
     uint64_t seed;      /* Philox key                                       */
     uint32_t stream_id; /* fourth counter word: independent replicas        */
     uint32_t flags;     /* SW_F_*                                           */
+    int32_t tile_h;     /* tile height of the labeling (tiles are 128 wide):
+                           16, 32, 64 or 128, or 0 for the default 64.  The
+                           tile size is a free parameter of the paper's
+                           local/global split (Sec. II.E, Eqs. optimaltile1-2);
+                           results do not depend on it                      */
+    int32_t merge_waves; /* merge schedule: tiles per merge workgroup (one
+                           wave each), 4, 8 or 16, or 0 for the default 8;
+                           results do not depend on it                      */
 } sw_params;
 
 /* Device buffers of one lattice.  All are row-major (i = y*W + x). */
@@ -273,6 +281,10 @@ sw_status swb_destroy(swb_batch *h);
 /* Workspace bytes needed by ccl_label for this shape (0 if invalid). */
 size_t ccl_workspace_bytes(int32_t W, int32_t H, int32_t mode);
 
+/* As ccl_workspace_bytes, for ccl_label_tiled with tile height tile_h (16,
+ * 32, 64, 128, or 0 for the default 64; 0 bytes if invalid). */
+size_t ccl_workspace_bytes_tiled(int32_t W, int32_t H, int32_t mode, int32_t tile_h);
+
 /* Connected-component labeling of a bond or site input (steps 2 of the SW
  * update on a given graph; Sec. II.B-II.C solve the same problem).
  *   in          device, N bytes (packed bonds or image, see CCL_*)
@@ -285,6 +297,17 @@ size_t ccl_workspace_bytes(int32_t W, int32_t H, int32_t mode);
 sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32_t *labels,
                     int32_t *roots, int32_t *sizes, int32_t *n_clusters, void *workspace,
                     size_t workspace_bytes, void *stream);
+
+/* ccl_label with the tile shape and merge schedule chosen by the caller (an
+ * autotuner): tile_h and merge_waves as in sw_params (0: defaults).  The
+ * local/global split's tile size trades local work against consolidation
+ * work (Sec. II.E, Eqs. optimaltile1-2); the labels do not depend on it.
+ * The workspace must hold ccl_workspace_bytes_tiled(W, H, mode, tile_h)
+ * bytes.  SW_ERR_ARG for an invalid tile_h or merge_waves, otherwise as
+ * ccl_label. */
+sw_status ccl_label_tiled(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32_t tile_h,
+                          int32_t merge_waves, int32_t *labels, int32_t *roots, int32_t *sizes,
+                          int32_t *n_clusters, void *workspace, size_t workspace_bytes, void *stream);
 
 /* ccl_label without a workspace argument and without any allocation, for
  * callers that cannot allocate device memory (code under HIP graph capture,

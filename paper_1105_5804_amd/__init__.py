@@ -105,7 +105,9 @@ class SWLattice:
     the last sweep are kept in ``labels`` / ``bonds``; with ``sizes`` every sweep
     also lists its clusters (``cluster_sizes()``) and their largest size.
     ``reverse_tiles`` runs the tiles in the reverse order (a schedule check:
-    every output is the same).  The constructor enqueues on the current
+    every output is the same).  ``tile_h`` (16, 32, 64, 128; 0 = 64) and
+    ``merge_waves`` (4, 8, 16; 0 = 8) choose the tile shape and merge schedule
+    (outputs do not depend on them; ``paper_1105_5804_amd.tune`` picks them).  The constructor enqueues on the current
     stream; methods given another ``stream`` are ordered only with that
     stream's work (synchronise the two as with any torch side stream).
     """
@@ -113,7 +115,7 @@ class SWLattice:
     def __init__(self, W: int, H: int, q: int = 2, K: float | None = None, seed: int = 0,
                  stream_id: int = 0, ising: bool | None = None, keep_labels: bool = False,
                  keep_bonds: bool = False, sizes: bool = False, spins=None, t: int = 0,
-                 device: str = "cuda", reverse_tiles: bool = False):
+                 device: str = "cuda", reverse_tiles: bool = False, tile_h: int = 0, merge_waves: int = 0):
         torch = _torch()
         L = _lib.lib()
         if ising is None:
@@ -125,7 +127,9 @@ class SWLattice:
         self.device = torch.device(device)
         p = _lib.SwParams(self.W, self.H, self.q, _lib.SW_SPIN_ISING_I8 if ising else _lib.SW_SPIN_POTTS_U8,
                           self.K, self.seed & (2**64 - 1), self.stream_id,
-                          (_lib.SW_F_SIZES if sizes else 0) | (_lib.SW_F_REVERSE_TILES if reverse_tiles else 0))
+                          (_lib.SW_F_SIZES if sizes else 0) | (_lib.SW_F_REVERSE_TILES if reverse_tiles else 0),
+                          int(tile_h), int(merge_waves))
+        self.tile_h, self.merge_waves = int(tile_h) or 64, int(merge_waves) or 8
         ws = L.sw_workspace_bytes(ctypes.byref(p))
         if ws == 0:
             _lib.check(_lib.SW_ERR_ARG if self.W >= 2 and self.H >= 2 else _lib.SW_ERR_SIZE, "sw_workspace_bytes")
@@ -233,9 +237,11 @@ class SWBatch:
     stream_id, ising (defaults as in ``SWLattice``).  Lattice j evolves exactly
     as ``SWLattice(**specs[j])`` would.  ``spins[j]`` (and ``labels[j]`` /
     ``bonds[j]`` with ``keep_labels`` / ``keep_bonds``) are its tensors.
+    ``tile_h`` / ``merge_waves`` as in ``SWLattice``, one choice per batch.
     """
 
-    def __init__(self, specs, keep_labels: bool = False, keep_bonds: bool = False, device: str = "cuda"):
+    def __init__(self, specs, keep_labels: bool = False, keep_bonds: bool = False, device: str = "cuda",
+                 tile_h: int = 0, merge_waves: int = 0):
         torch = _torch()
         L = _lib.lib()
         self.device = torch.device(device)
@@ -255,7 +261,7 @@ class SWBatch:
             seed, sid = int(sp.get("seed", 0)), int(sp.get("stream_id", 0))
             self.specs.append(dict(W=W, H=H, q=q, K=float(K), seed=seed, stream_id=sid, ising=ising))
             P[j] = _lib.SwParams(W, H, q, _lib.SW_SPIN_ISING_I8 if ising else _lib.SW_SPIN_POTTS_U8, float(K),
-                                 seed & (2**64 - 1), sid, 0)
+                                 seed & (2**64 - 1), sid, 0, int(tile_h), int(merge_waves))
             dt = torch.int8 if ising else torch.uint8
             sp_t = torch.empty((H, W), dtype=dt, device=self.device)
             lab = torch.empty((H, W), dtype=torch.int32, device=self.device) if keep_labels else None
@@ -307,13 +313,13 @@ class SWBatch:
             pass
 
 
-def ccl_workspace_bytes(W: int, H: int, mode: str | int = "bonds_periodic") -> int:
+def ccl_workspace_bytes(W: int, H: int, mode: str | int = "bonds_periodic", tile_h: int = 0) -> int:
     m = _MODES[mode] if isinstance(mode, str) else int(mode)
-    return int(_lib.lib().ccl_workspace_bytes(int(W), int(H), m))
+    return int(_lib.lib().ccl_workspace_bytes_tiled(int(W), int(H), m, int(tile_h)))
 
 
 def ccl_label(inp, mode: str | int = "bonds_periodic", sizes: bool = False, workspace=None,
-              labels=None, stream=None):
+              labels=None, stream=None, tile_h: int = 0, merge_waves: int = 0):
     """Connected-component labels of an (H, W) uint8 GPU tensor.
 
     mode: "bonds_periodic" / "bonds_open" (packed bonds, bit0 right, bit1 down)
@@ -322,6 +328,8 @@ def ccl_label(inp, mode: str | int = "bonds_periodic", sizes: bool = False, work
     roots ascend and sizes[k] belongs to roots[k].  With a ``stream`` other
     than the current one, that stream first waits for the current stream's
     work; with sizes the call waits for ``stream`` (to read the count).
+    ``tile_h`` / ``merge_waves`` choose the tile shape and merge schedule as in
+    ``SWLattice`` (the labels do not depend on them).
     """
     torch = _torch()
     L = _lib.lib()
@@ -330,7 +338,7 @@ def ccl_label(inp, mode: str | int = "bonds_periodic", sizes: bool = False, work
         raise ValueError("input must be a 2D uint8 GPU tensor")
     inp = inp.contiguous()
     H, W = inp.shape
-    ws = L.ccl_workspace_bytes(W, H, m)
+    ws = L.ccl_workspace_bytes_tiled(W, H, m, int(tile_h))
     if ws == 0:
         _lib.check(_lib.SW_ERR_SIZE, "ccl_workspace_bytes")
     made = []  # tensors allocated here, on the current stream
@@ -364,9 +372,9 @@ def ccl_label(inp, mode: str | int = "bonds_periodic", sizes: bool = False, work
         # the input's copy (if .contiguous() made one) was enqueued on the current stream
         stream.wait_stream(cur)
         made.append(inp)
-    st = L.ccl_label(inp.data_ptr(), W, H, m, labels.data_ptr(),
-                     roots.data_ptr() if sizes else None, szs.data_ptr() if sizes else None,
-                     ncl.data_ptr(), wptr, ws, _stream(torch, stream))
+    st = L.ccl_label_tiled(inp.data_ptr(), W, H, m, int(tile_h), int(merge_waves), labels.data_ptr(),
+                           roots.data_ptr() if sizes else None, szs.data_ptr() if sizes else None,
+                           ncl.data_ptr(), wptr, ws, _stream(torch, stream))
     _lib.check(st, "ccl_label")
     if side:
         # memory allocated on the current stream and used on another: the

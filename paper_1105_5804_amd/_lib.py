@@ -7,7 +7,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libswccl.so")
 
-ABI_VERSION = 3  # the SWCCL_ABI_VERSION these declarations follow
+ABI_VERSION = 4  # the SWCCL_ABI_VERSION these declarations follow
 
 # status codes
 SW_OK, SW_ERR_ARG, SW_ERR_SIZE, SW_ERR_WORKSPACE, SW_ERR_DEVICE, SW_ERR_STATE, SW_ERR_UNSUPPORTED, SW_ERR_HOST_MEMORY = range(8)
@@ -15,6 +15,8 @@ SW_SPIN_ISING_I8, SW_SPIN_POTTS_U8 = 0, 1
 SW_F_KEEP_SPINS, SW_F_SIZES, SW_F_REVERSE_TILES = 1, 2, 4
 CCL_BONDS_PERIODIC, CCL_BONDS_OPEN, CCL_SITES_OPEN = 0, 1, 2
 CCL_NOALLOC_SCRATCH_BYTES = 64 << 20
+TILE_HEIGHTS = (16, 32, 64, 128)  # sw_params.tile_h (0: 64)
+MERGE_WAVES = (4, 8, 16)          # sw_params.merge_waves (0: 8)
 SW_PHASE_TILE, SW_PHASE_MERGE, SW_PHASE_FLIP = 0, 1, 2
 SW_HIST_ACTIVE, SW_HIST_NCLUST, SW_HIST_MAXCL, SW_HIST_NSAT, SW_HIST_COUNTS, SW_HIST_LEN = 0, 1, 2, 3, 4, 12
 
@@ -29,6 +31,8 @@ class SwParams(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("stream_id", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
+        ("tile_h", ctypes.c_int32),
+        ("merge_waves", ctypes.c_int32),
     ]
 
 
@@ -105,6 +109,12 @@ SIGNATURES = {
     "swb_get_t": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "swb_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "ccl_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "ccl_workspace_bytes_tiled": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                    ctypes.c_int32]),
+    "ccl_label_tiled": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                         ctypes.c_void_p]),
     "ccl_server_footprint": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(CclServerParams)]),
     "ccl_server_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(CclServerParams),
                                            ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]),

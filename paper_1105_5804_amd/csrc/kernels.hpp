@@ -36,22 +36,39 @@
 namespace swccl {
 
 constexpr int TW = 128;               // tile width: a wave covers a tile row, 2 sites per lane
-constexpr int TH = 64;                // tile height
-constexpr int TSITES = TW * TH;       // sites per tile
-constexpr int CAP = 2 * (TW + TH);    // boundary ids per tile (>= border sites)
-constexpr int EDGE = 2 * TW + 2 * TH; // edge id entries per tile: top, bottom, left, right
-constexpr int XW = 4;                 // crossing-bond words per tile: right rows, bottom cols (2)
-constexpr int NT = 512;               // threads per workgroup
-constexpr int NWAVE = NT / 64;
-constexpr int RPW = TH / NWAVE;       // tile rows per wave
+constexpr int RPW = 8;                // tile rows per wave
 constexpr int WLIST = RPW * TW;       // per-wave work list capacity (one entry per site at most)
 constexpr int TLIST = 3 * TW;         // k_tile's per-wave lists: a row adds at most TW entries, a
-                                      // fuller list is worked off first (keeps 4 workgroups per CU)
+                                      // fuller list is worked off first (keeps the LDS per wave small)
 constexpr uint16_t ID_NONE = 0xFFFF;
 constexpr uint16_t CODE_BG = 0xFFFF;
-static_assert(TH <= 64, "right-edge crossing bits are one 64-bit word");
-static_assert(CAP + TSITES < 0xFFFE, "codes are 16-bit");
-static_assert(TW == 128, "a tile row is one wave of 64 lanes x 2 sites");
+
+// Tile shapes: TW x TH sites, one wave per RPW rows, so a tile is worked by
+// TH / RPW waves.  Per tile there are CAP boundary ids (at least the border
+// sites), EDGE edge entries (top row, bottom row, left column, right column)
+// and XW words of crossing bits (the right edge's rows, XR words of 64, then
+// the bottom edge's even and odd columns).
+template <int TH_>
+struct Tile {
+    static constexpr int TH = TH_;
+    static constexpr int TSITES = TW * TH;
+    static constexpr int CAP = 2 * (TW + TH);
+    static constexpr int EDGE = 2 * TW + 2 * TH;
+    static constexpr int XR = (TH + 63) / 64;
+    static constexpr int XW = XR + 2;
+    static constexpr int NWAVE = TH / RPW;
+    static constexpr int NT = 64 * NWAVE;
+    static_assert(TH % RPW == 0 && TH >= 2 * RPW && TH <= 128, "tile heights 16, 32, 64, 128");
+    static_assert(CAP + TSITES < 0xFFFE, "codes are 16-bit");
+};
+constexpr int TH_DEFAULT = 64;        // the shape the library uses unless told otherwise
+
+// Kernels that do not depend on the tile shape run 512-thread workgroups.
+constexpr int NT = 512;
+constexpr int NWAVE = NT / 64;
+
+// The one-tile lattices that k_small sweeps whole in LDS: W <= 128, H <= 64.
+constexpr int SMALL_W = 128, SMALL_H = 64, SMALL_SITES = SMALL_W * SMALL_H;
 
 enum : uint32_t { TAG_INIT = 0, TAG_BOND = 1, TAG_FLIP = 2 };
 enum Mode : int { M_SW = 0, M_BONDS_PERIODIC = 1, M_BONDS_OPEN = 2, M_SITES = 3 };
@@ -357,6 +374,7 @@ __device__ __forceinline__ int lroot(int *P, int x)
 // Border position t of a tile in the layout of the edge arrays: top row,
 // bottom row, left column, right column.  Returns the slot, or -1 if the
 // position lies outside a ragged tile.
+template <int TH>
 __device__ __forceinline__ int border_slot(int t, int tw, int th)
 {
     if (t < TW) return t < tw ? t : -1;
@@ -408,22 +426,26 @@ __device__ __forceinline__ int wave_max_below(int v)
     return out;
 }
 
-// Four workgroups per CU (8 waves per SIMD): the LDS use stays under 40 KB
-// and the registers are held to what 8 waves allow (some scalar registers
-// spill to vector lanes; the extra latency hiding is worth more).
-template <int MODE, bool EVENW, bool BATCH = false>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_tile(TileArgs a)
+// 8 waves per SIMD (four 128 x 64 workgroups per CU): the LDS use stays
+// under 40 KB per 64 rows and the registers are held to what 8 waves allow
+// (some scalar registers spill to vector lanes; the extra latency hiding is
+// worth more).
+template <int MODE, bool EVENW, bool BATCH, int TH_>
+__global__ __launch_bounds__(Tile<TH_>::NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_tile(TileArgs a)
 {
+    using S = Tile<TH_>;
+    constexpr int TH = S::TH, TSITES = S::TSITES, CAP = S::CAP, EDGE = S::EDGE, XR = S::XR, XW = S::XW;
+    constexpr int NT = S::NT, NWAVE = S::NWAVE;
     constexpr bool NEED_DOWN = MODE == M_SW || MODE == M_SITES;  // bonds from two rows
     constexpr bool NEED_HALO = MODE == M_SW || MODE == M_SITES;  // column right of the tile
     __shared__ int P[TSITES];             // union-find parent per site slot, as 4 x slot
     __shared__ EO Rm[TH];                 // in-tile right bonds per row
     __shared__ EO Om[TH];                 // occupied sites per row
     // the image mode's extra occupancy masks are paid for by slightly shorter
-    // lists, so every mode stays under 40 KB of LDS (four workgroups per CU)
-    constexpr int TL = MODE == M_SITES ? TLIST - 8 : TLIST;
+    // lists, so every mode stays under 40 KB of LDS per 64 rows
+    constexpr int TL = MODE == M_SITES ? (TH < 64 ? TLIST - 16 : TLIST - 8) : TLIST;
     __shared__ uint16_t wl[NWAVE][TL];    // per-wave work list (contacts, then run starts)
-    __shared__ unsigned long long xr_w[NWAVE];  // right crossing bonds of each wave's rows
+    __shared__ unsigned long long xr_w[NWAVE];  // right crossing bonds of each wave's rows (bit ly % 64)
     __shared__ EO xd_s;                   // bottom crossing bonds
     __shared__ int nb_s;
     __shared__ int act_w[NWAVE];
@@ -614,7 +636,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 
         // Crossing bonds leave the tile: the last column's right bond and the
         // last row's down bonds.  They are merged by k_merge.
-        if ((mR0 & L0) | (mR1 & L1)) xr |= 1ull << ly;
+        if ((mR0 & L0) | (mR1 & L1)) xr |= 1ull << (ly & 63);
         const EO R = EO{mR0 & ~L0, mR1 & ~L1};
         // the last tile row's down bonds cross the tile; selected on a uniform
         // condition so the masks stay in scalar registers
@@ -734,7 +756,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     }
     compress_list(nrs);
     for (int t = threadIdx.x; t < EDGE; t += NT) {
-        const int slot = border_slot(t, tw, th);
+        const int slot = border_slot<TH>(t, tw, th);
         if (slot < 0 || !occupied(slot)) continue;
         const int root4 = lroot(P, 4 * slot), root = root4 >> 2;
         int expect = root4;
@@ -776,22 +798,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     }
     uint16_t *edg = a.edges + static_cast<int64_t>(tile) * EDGE;
     for (int t = threadIdx.x; t < EDGE; t += NT) {
-        const int slot = border_slot(t, tw, th);
+        const int slot = border_slot<TH>(t, tw, th);
         uint16_t eid = ID_NONE;
         if (slot >= 0 && occupied(slot)) eid = static_cast<uint16_t>(code_of(slot, P[slot]));
         edg[t] = eid;
     }
     if (threadIdx.x == 0) {
         uint64_t *xb = a.xbits + static_cast<int64_t>(tile) * XW;
-        unsigned long long xrt = 0;
         int act = 0;
-        for (int w = 0; w < NWAVE; ++w) {
-            xrt |= xr_w[w];
-            act += act_w[w];
+#pragma unroll
+        for (int j = 0; j < XR; ++j) {
+            unsigned long long xrt = 0;  // rows 64 j ... 64 j + 63: the waves (64 / RPW of them) holding them
+            for (int w = j * (64 / RPW); w < min(NWAVE, (j + 1) * (64 / RPW)); ++w) xrt |= xr_w[w];
+            xb[j] = xrt;
         }
-        xb[0] = xrt;
-        xb[1] = xd_s.e;  // bottom crossing bonds of even columns
-        xb[2] = xd_s.o;  // ... and of odd columns
+        for (int w = 0; w < NWAVE; ++w) act += act_w[w];
+        xb[XR] = xd_s.e;      // bottom crossing bonds of even columns
+        xb[XR + 1] = xd_s.o;  // ... and of odd columns
         a.nb[tile] = nb_s;
         if (MODE == M_SW && a.tile_act) a.tile_act[tile] = act;
     }
@@ -808,16 +831,18 @@ struct MergeArgs {
     Batch b;                  // batched launches only
 };
 
-constexpr int MERGE_TILES = NWAVE;  // tiles per workgroup: one wave each
-
 // A wave per tile: its lanes walk the bonds crossing the tile's right edge
-// (TH rows) and bottom edge (TW columns).  Consecutive crossing bonds that
-// join the same pair of boundary ids are skipped.
-template <bool BATCH = false>
-__global__ __launch_bounds__(NT) void k_merge(MergeArgs a)
+// (TH rows, 64 per pass) and bottom edge (TW columns, two passes).
+// Consecutive crossing bonds that join the same pair of boundary ids are
+// skipped.  The workgroup size (tiles per workgroup, one wave each) is the
+// merge schedule's free parameter; it is read from blockDim.
+template <bool BATCH, int TH_>
+__global__ __launch_bounds__(1024) void k_merge(MergeArgs a)
 {
+    using S = Tile<TH_>;
+    constexpr int TH = S::TH, CAP = S::CAP, EDGE = S::EDGE, XR = S::XR, XW = S::XW;
     const int lane = threadIdx.x & 63, wave = wave_id();
-    int tile = blockIdx.x * MERGE_TILES + wave;
+    int tile = blockIdx.x * static_cast<int>(blockDim.x >> 6) + wave;
     int tile0 = 0;  // first tile of the lattice in the arrays
     if constexpr (BATCH) {
         if (tile >= a.b.ntiles) return;
@@ -838,26 +863,41 @@ __global__ __launch_bounds__(NT) void k_merge(MergeArgs a)
     const int ntD = tile0 + (ty + 1 == a.g.nty ? 0 : ty + 1) * a.g.ntx + tx;
     const uint16_t *eR = a.edges + static_cast<int64_t>(ntR) * EDGE;
     const uint16_t *eD = a.edges + static_cast<int64_t>(ntD) * EDGE;
-    const uint64_t xr = xb[0];
-    const uint64_t xde = xb[1], xdo = xb[2];  // bottom crossing bonds, even / odd columns
+    uint64_t xr[XR];
+#pragma unroll
+    for (int j = 0; j < XR; ++j) xr[j] = xb[j];
+    const uint64_t xde = xb[XR], xdo = xb[XR + 1];  // bottom crossing bonds, even / odd columns
+    auto xr_bit = [&](int y) { return (xr[y >> 6] >> (y & 63)) & 1ull; };
     auto xd_bit = [&](int x) { return (((x & 1) ? xdo : xde) >> (x >> 1)) & 1ull; };
-    // Three 64-lane passes: the right edge (TH rows), then the bottom edge in
+    // Passes of 64 lanes: the right edge (TH rows), then the bottom edge in
     // two halves (TW columns).  Every edge entry a lane needs, and the one
     // before it (for skipping repeats), is loaded up front; all lie inside
     // the tiles' edge arrays.
-    static_assert(TH == 64 && TW == 128, "one pass per 64 edge positions");
-    const int lm = max(lane - 1, 0);
+    constexpr int RP = (TH + 63) / 64;  // passes over the right edge
     const uint16_t *er = e + 2 * TW + TH, *el = eR + 2 * TW, *eb = e + TW;
-    const uint16_t r_a = er[lane], r_b = el[lane], r_ap = er[lm], r_bp = el[lm];
+    uint16_t r_a[RP], r_b[RP], r_ap[RP], r_bp[RP];
+#pragma unroll
+    for (int j = 0; j < RP; ++j) {
+        const int y = min(64 * j + lane, TH - 1), ym = max(y - 1, 0);
+        r_a[j] = er[y];
+        r_b[j] = el[y];
+        r_ap[j] = er[ym];
+        r_bp[j] = el[ym];
+    }
+    const int lm = max(lane - 1, 0);
     const uint16_t b1_a = eb[lane], b1_b = eD[lane], b1_ap = eb[lm], b1_bp = eD[lm];
     const uint16_t b2_a = eb[64 + lane], b2_b = eD[64 + lane], b2_ap = eb[63 + lane], b2_bp = eD[63 + lane];
     // Both ends of a crossing bond are border sites, whose codes are boundary
     // ids (< CAP); the bound keeps any other entry from addressing memory
     // outside the tiles' tables.
     auto ids = [](uint16_t u, uint16_t v) { return u < CAP && v < CAP; };
-    if (lane < th && ((xr >> lane) & 1ull) &&
-        !(lane > 0 && ((xr >> (lane - 1)) & 1ull) && r_ap == r_a && r_bp == r_b) && ids(r_a, r_b))
-        gunite(a.gparent, a.gkey, tile * CAP + r_a, ntR * CAP + r_b);
+#pragma unroll
+    for (int j = 0; j < RP; ++j) {
+        const int y = 64 * j + lane;
+        if (y < th && xr_bit(y) && !(y > 0 && xr_bit(y - 1) && r_ap[j] == r_a[j] && r_bp[j] == r_b[j]) &&
+            ids(r_a[j], r_b[j]))
+            gunite(a.gparent, a.gkey, tile * CAP + r_a[j], ntR * CAP + r_b[j]);
+    }
     if (lane < tw && xd_bit(lane) && !(lane > 0 && xd_bit(lane - 1) && b1_ap == b1_a && b1_bp == b1_b) &&
         ids(b1_a, b1_b))
         gunite(a.gparent, a.gkey, tile * CAP + b1_a, ntD * CAP + b1_b);
@@ -895,9 +935,12 @@ __device__ __forceinline__ uint8_t flip_state(uint32_t R, const FlatArgs &a)
     return static_cast<uint8_t>(draw_state(pick(b, R & 3u), a.q));
 }
 
-template <int MODE, bool SIZES, bool BATCH = false>
-__global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
+template <int MODE, bool SIZES, bool BATCH, int TH_>
+__global__ __launch_bounds__(Tile<TH_>::NT) void k_flatten(FlatArgs a)
 {
+    using S = Tile<TH_>;
+    constexpr int TH = S::TH, TSITES = S::TSITES, CAP = S::CAP, NT = S::NT, NWAVE = S::NWAVE;
+    constexpr int BPT = (CAP + NT - 1) / NT;  // boundary ids per thread
     constexpr int NCODE = CAP + TSITES;
     __shared__ uint8_t ST[MODE == M_SW ? NCODE : 1];  // new state per code (boundary id or CAP + slot)
     __shared__ int32_t Rb[CAP];                        // canonical root (site index) per boundary id
@@ -935,13 +978,18 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
     const int ly0 = wave * RPW;
     const int nr = max(0, min(RPW, th - ly0));
     const int nbt = a.nb[tile];
-    static_assert(CAP <= NT, "one boundary id per thread");
-    // each boundary id's parent and key, issued with the count's loads (entries
-    // past nb are read, not used); a root's key is its cluster's canonical label
-    int broot = 0, bR = 0;
-    if (threadIdx.x < CAP) {
-        broot = a.gparent[tile * CAP + threadIdx.x];
-        bR = a.gkey[tile * CAP + threadIdx.x];
+    // each boundary id's parent and key (ids threadIdx.x + j NT), issued with
+    // the count's loads (entries past nb are read, not used); a root's key is
+    // its cluster's canonical label
+    int broot[BPT], bR[BPT];
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+        const int k = static_cast<int>(threadIdx.x) + j * NT;
+        broot[j] = bR[j] = 0;
+        if (k < CAP) {
+            broot[j] = a.gparent[tile * CAP + k];
+            bR[j] = a.gkey[tile * CAP + k];
+        }
     }
 
     if constexpr (SIZES) {
@@ -975,18 +1023,23 @@ __global__ __launch_bounds__(NT) void k_flatten(FlatArgs a)
         }
     }
     // boundary ids: the root and its key (the cluster's minimum site index),
-    // loaded at the start; one id per thread since nb <= CAP <= NT
+    // loaded at the start
     int nbr = 0;
-    if (threadIdx.x < nbt) {
-        const int k = threadIdx.x, id = tile * CAP + k;
-        if (broot != id) {  // below a root (the merge keeps trees shallow): walk up, take the root's key
-            broot = gfind(a.gparent, broot);
-            bR = a.gkey[broot];
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+        const int k = static_cast<int>(threadIdx.x) + j * NT;
+        if (k < nbt) {
+            const int id = tile * CAP + k;
+            int r = broot[j], key = bR[j];
+            if (r != id) {  // below a root (the merge keeps trees shallow): walk up, take the root's key
+                r = gfind(a.gparent, r);
+                key = a.gkey[r];
+            }
+            Rb[k] = key;
+            Gid[k] = r;
+            nbr += r == id;
+            if constexpr (MODE == M_SW) ST[k] = flip_state(static_cast<uint32_t>(key), a);
         }
-        Rb[k] = bR;
-        Gid[k] = broot;
-        nbr = broot == id;
-        if constexpr (MODE == M_SW) ST[k] = flip_state(static_cast<uint32_t>(bR), a);
     }
     {
         const unsigned long long s = wave_sum(static_cast<unsigned long long>(nbr));
@@ -1182,8 +1235,10 @@ struct EmitArgs {
 
 // Write each tile's roots (ascending site index within a row) at their global
 // positions; boundary clusters take their size from the global root id.
+template <int TH_>
 __global__ __launch_bounds__(NT) void k_emit(EmitArgs a)
 {
+    constexpr int TH = Tile<TH_>::TH, TSITES = Tile<TH_>::TSITES;
     __shared__ int32_t rstart[TH + 1];
     const int tile = xcd_remap(blockIdx.x, a.g.ntiles);
     const int tx = tile % a.g.ntx, ty = tile / a.g.ntx;
@@ -1222,7 +1277,7 @@ __global__ __launch_bounds__(NT) void k_emit(EmitArgs a)
 
 // ------------------------------------------------------- small lattices ---
 //
-// A lattice of one tile (W <= TW, H <= TH) is swept entirely inside one
+// A lattice of one tile (W <= SMALL_W, H <= SMALL_H) is swept entirely inside one
 // workgroup: spins and union-find parents stay in LDS for all n sweeps of one
 // launch, so a sweep costs neither launches nor an
 // HBM round trip (a 64 x 64 lattice is launch-latency bound otherwise).  The
@@ -1253,7 +1308,7 @@ constexpr int SMALL_NT = 1024;  // 16 waves: more LDS round trips in flight on t
 
 __global__ __launch_bounds__(SMALL_NT) void k_small(SmallArgs a)
 {
-    constexpr int NT = SMALL_NT, NWAVE = SMALL_NT / 64;
+    constexpr int NT = SMALL_NT, NWAVE = SMALL_NT / 64, TSITES = SMALL_SITES;
     constexpr int PAIRS_PER_THREAD = TSITES / 2 / NT;  // site pairs 2p, 2p+1 with p = tid + NT m
     __shared__ int P[TSITES];
     __shared__ uint8_t S[TSITES];   // states 0..q-1

@@ -26,8 +26,34 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Per-tile sizes of a tile shape (the Tile<TH> constants, on the host).
+struct TileDims {
+    int th, tsites, cap, edge, xw, nt;
+};
+TileDims dims_of(int th)
+{
+    return TileDims{th, TW * th, 2 * (TW + th), 2 * TW + 2 * th, (th + 63) / 64 + 2, 64 * (th / RPW)};
+}
+bool valid_tile_h(int32_t th) { return th == 16 || th == 32 || th == 64 || th == 128; }
+bool valid_merge_waves(int32_t mw) { return mw == 4 || mw == 8 || mw == 16; }
+constexpr int MERGE_WAVES_DEFAULT = 8;
+
+// Calls f with the tile height as a compile-time constant.
+template <typename F>
+void with_tile_h(int th, F &&f)
+{
+    switch (th) {
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    case 128: f(std::integral_constant<int, 128>{}); break;
+    default: f(std::integral_constant<int, 64>{}); break;
+    }
+}
+
 struct Layout {
     Grid g;
+    TileDims d;       // tile shape
+    int mw;           // merge workgroup: tiles (waves) per workgroup
     bool sizes;
     int64_t nrow;  // H * ntx: entries of the per-(row, tile column) root counts
     size_t codes, gkey, gparent, gsize, edges, xbits, nb, tile_act, tile_ncl, stats;
@@ -52,11 +78,11 @@ size_t scan_tmp_bytes(int64_t n)
 
 // N = W H < 2^31, and the boundary ids of all tiles (ntiles x CAP) index int32
 // arrays: a very thin lattice has far more tiles than sites / TSITES.
-bool valid_shape(int32_t W, int32_t H, int32_t min_side)
+bool valid_shape(int32_t W, int32_t H, int32_t min_side, int th = TH_DEFAULT)
 {
     if (W < min_side || H < min_side) return false;
     if (static_cast<int64_t>(W) * H >= (static_cast<int64_t>(1) << 31)) return false;
-    return cdiv(W, TW) * cdiv(H, TH) * CAP < (static_cast<int64_t>(1) << 31);
+    return cdiv(W, TW) * cdiv(H, th) * dims_of(th).cap < (static_cast<int64_t>(1) << 31);
 }
 
 // Per-tile arrays shared by single lattices and batches; returns the bytes used.
@@ -68,11 +94,12 @@ size_t carve_tiles(Layout &L, size_t nt)
         off += align_up(bytes);
         return at;
     };
-    L.codes = take(nt * TSITES * sizeof(uint16_t));
-    L.gkey = take(nt * CAP * sizeof(int32_t));
-    L.gparent = take(nt * CAP * sizeof(int32_t));
-    L.edges = take(nt * EDGE * sizeof(uint16_t));
-    L.xbits = take(nt * XW * sizeof(uint64_t));
+    const TileDims &d = L.d;
+    L.codes = take(nt * static_cast<size_t>(d.tsites) * sizeof(uint16_t));
+    L.gkey = take(nt * static_cast<size_t>(d.cap) * sizeof(int32_t));
+    L.gparent = take(nt * static_cast<size_t>(d.cap) * sizeof(int32_t));
+    L.edges = take(nt * static_cast<size_t>(d.edge) * sizeof(uint16_t));
+    L.xbits = take(nt * static_cast<size_t>(d.xw) * sizeof(uint64_t));
     L.nb = take(nt * sizeof(int32_t));
     L.tile_act = take(nt * sizeof(int32_t));
     L.tile_ncl = take(nt * sizeof(int32_t));
@@ -80,13 +107,15 @@ size_t carve_tiles(Layout &L, size_t nt)
     return off;
 }
 
-Layout make_layout(int32_t W, int32_t H, bool sizes)
+Layout make_layout(int32_t W, int32_t H, bool sizes, int th = TH_DEFAULT, int mw = MERGE_WAVES_DEFAULT)
 {
     Layout L{};
+    L.d = dims_of(th);
+    L.mw = mw;
     L.g.W = W;
     L.g.H = H;
     L.g.ntx = static_cast<int>(cdiv(W, TW));
-    L.g.nty = static_cast<int>(cdiv(H, TH));
+    L.g.nty = static_cast<int>(cdiv(H, th));
     L.g.ntiles = L.g.ntx * L.g.nty;
     L.sizes = sizes;
     L.nrow = static_cast<int64_t>(H) * L.g.ntx;
@@ -98,13 +127,13 @@ Layout make_layout(int32_t W, int32_t H, bool sizes)
         return at;
     };
     if (sizes) {
-        L.gsize = take(nt * CAP * sizeof(int32_t));
+        L.gsize = take(nt * static_cast<size_t>(L.d.cap) * sizeof(int32_t));
         // per-(row, tile column) root counts, their total, then the largest size
         L.row_count = take(static_cast<size_t>(L.nrow + 2) * sizeof(int32_t));
         L.row_off = take(static_cast<size_t>(L.nrow + 1) * sizeof(int32_t));
         L.scan_tmp = take(scan_tmp_bytes(L.nrow + 1));
-        L.rl_slot = take(nt * TSITES * sizeof(int32_t));
-        L.rl_size = take(nt * TSITES * sizeof(int32_t));
+        L.rl_slot = take(nt * static_cast<size_t>(L.d.tsites) * sizeof(int32_t));
+        L.rl_size = take(nt * static_cast<size_t>(L.d.tsites) * sizeof(int32_t));
     }
     L.total = off;
     return L;
@@ -112,9 +141,11 @@ Layout make_layout(int32_t W, int32_t H, bool sizes)
 
 // Workspace of a batch of lattices: the tile arrays over all their tiles,
 // then the lattice descriptors and the tile -> lattice table.
-Layout make_batch_layout(int64_t ntiles, int32_t nlat)
+Layout make_batch_layout(int64_t ntiles, int32_t nlat, int th, int mw)
 {
     Layout L{};
+    L.d = dims_of(th);
+    L.mw = mw;
     L.g.ntiles = static_cast<int>(ntiles);
     size_t off = carve_tiles(L, static_cast<size_t>(ntiles));
     L.lat_desc = off;
@@ -190,14 +221,36 @@ MergeArgs merge_args(const Layout &L, void *ws)
 template <int MODE>
 void launch_tile(const Layout &L, const TileArgs &ta, hipStream_t s)
 {
-    const dim3 grid(static_cast<unsigned>(L.g.ntiles)), block(NT);
-    if (L.g.W % 2 == 0)
-        hipLaunchKernelGGL((k_tile<MODE, true>), grid, block, 0, s, ta);
-    else
-        hipLaunchKernelGGL((k_tile<MODE, false>), grid, block, 0, s, ta);
+    with_tile_h(L.d.th, [&](auto c) {
+        constexpr int TH = decltype(c)::value;
+        const dim3 grid(static_cast<unsigned>(L.g.ntiles)), block(Tile<TH>::NT);
+        if (L.g.W % 2 == 0)
+            hipLaunchKernelGGL((k_tile<MODE, true, false, TH>), grid, block, 0, s, ta);
+        else
+            hipLaunchKernelGGL((k_tile<MODE, false, false, TH>), grid, block, 0, s, ta);
+    });
 }
 
-dim3 merge_grid(const Layout &L) { return dim3(static_cast<unsigned>(cdiv(L.g.ntiles, MERGE_TILES))); }
+// The merge: mw tiles per workgroup, one wave each, over ntiles tiles.
+template <bool BATCH>
+void launch_merge(const Layout &L, const MergeArgs &ma, int64_t ntiles, hipStream_t s)
+{
+    const dim3 grid(static_cast<unsigned>(cdiv(ntiles, L.mw))), block(static_cast<unsigned>(64 * L.mw));
+    with_tile_h(L.d.th, [&](auto c) {
+        constexpr int TH = decltype(c)::value;
+        hipLaunchKernelGGL((k_merge<BATCH, TH>), grid, block, 0, s, ma);
+    });
+}
+
+template <int MODE, bool SIZES, bool BATCH>
+void launch_flatten(const Layout &L, const FlatArgs &fa, int64_t ntiles, hipStream_t s)
+{
+    with_tile_h(L.d.th, [&](auto c) {
+        constexpr int TH = decltype(c)::value;
+        hipLaunchKernelGGL((k_flatten<MODE, SIZES, BATCH, TH>), dim3(static_cast<unsigned>(ntiles)),
+                           dim3(Tile<TH>::NT), 0, s, fa);
+    });
+}
 
 FlatArgs flat_args(const Layout &L, void *ws)
 {
@@ -234,7 +287,10 @@ void emit_sizes(const Layout &L, void *ws, const FlatArgs &fa, int32_t *roots, i
     ea.sizes = sizes;
     ea.max_size = max_size;
     ea.n_clusters = n_clusters;
-    hipLaunchKernelGGL(k_emit, dim3(static_cast<unsigned>(L.g.ntiles)), dim3(NT), 0, s, ea);
+    with_tile_h(L.d.th, [&](auto c) {
+        constexpr int TH = decltype(c)::value;
+        hipLaunchKernelGGL(k_emit<TH>, dim3(static_cast<unsigned>(L.g.ntiles)), dim3(NT), 0, s, ea);
+    });
 }
 
 uint64_t threshold_of(double K)
@@ -256,6 +312,7 @@ struct sw_lattice {
     uint64_t T;
     uint64_t t;
     bool swept;       // at least one sweep since init / set_t
+    bool small_last;  // the last sweep ran in k_small (its counters are in tile 0 alone)
     int32_t next_phase;  // SW_PHASE_* expected next
 };
 
@@ -282,22 +339,29 @@ const char *sw_last_error(void) { return g_last_error.c_str(); }
 
 uint64_t sw_threshold(double K) { return threshold_of(K); }
 
+static int tile_h_of(const sw_params *p) { return p->tile_h ? p->tile_h : TH_DEFAULT; }
+static int merge_waves_of(const sw_params *p) { return p->merge_waves ? p->merge_waves : MERGE_WAVES_DEFAULT; }
+
 static sw_status check_params(const sw_params *p)
 {
     if (!p) return SW_ERR_ARG;
-    if (!valid_shape(p->W, p->H, 2)) return SW_ERR_SIZE;
+    if (p->W < 2 || p->H < 2 || static_cast<int64_t>(p->W) * p->H >= (static_cast<int64_t>(1) << 31))
+        return SW_ERR_SIZE;
     if (p->q < 2 || p->q > 255) return SW_ERR_ARG;
     if (p->spin_kind != SW_SPIN_ISING_I8 && p->spin_kind != SW_SPIN_POTTS_U8) return SW_ERR_ARG;
     if (p->spin_kind == SW_SPIN_ISING_I8 && p->q != 2) return SW_ERR_ARG;
     if (std::isnan(p->K)) return SW_ERR_ARG;
     if (p->flags & ~static_cast<uint32_t>(SW_F_KEEP_SPINS | SW_F_SIZES | SW_F_REVERSE_TILES)) return SW_ERR_ARG;
+    if (p->tile_h != 0 && !valid_tile_h(p->tile_h)) return SW_ERR_ARG;
+    if (p->merge_waves != 0 && !valid_merge_waves(p->merge_waves)) return SW_ERR_ARG;
+    if (!valid_shape(p->W, p->H, 2, tile_h_of(p))) return SW_ERR_SIZE;
     return SW_OK;
 }
 
 size_t sw_workspace_bytes(const sw_params *p)
 {
     if (check_params(p) != SW_OK) return 0;
-    return make_layout(p->W, p->H, (p->flags & SW_F_SIZES) != 0).total;
+    return make_layout(p->W, p->H, (p->flags & SW_F_SIZES) != 0, tile_h_of(p), merge_waves_of(p)).total;
 }
 
 sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, void *stream)
@@ -308,7 +372,7 @@ sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, voi
     if (!b->spins) return SW_ERR_ARG;
     const bool sizes = (p->flags & SW_F_SIZES) != 0;
     if (sizes && (!b->roots || !b->sizes)) return SW_ERR_ARG;
-    const Layout L = make_layout(p->W, p->H, sizes);
+    const Layout L = make_layout(p->W, p->H, sizes, tile_h_of(p), merge_waves_of(p));
     if (!b->workspace || b->workspace_bytes < L.total) return SW_ERR_WORKSPACE;
     if (reinterpret_cast<uintptr_t>(b->workspace) % ALIGN) return SW_ERR_WORKSPACE;
     sw_lattice *h = new (std::nothrow) sw_lattice();
@@ -346,7 +410,6 @@ static sw_status launch_phase(sw_lattice *h, int32_t phase, hipStream_t s)
     void *ws = h->b.workspace;
     const uint32_t k0 = static_cast<uint32_t>(h->p.seed), k1 = static_cast<uint32_t>(h->p.seed >> 32);
     const uint32_t t = static_cast<uint32_t>(h->t);
-    const dim3 grid(static_cast<unsigned>(L.g.ntiles)), block(NT);
     if (phase == SW_PHASE_TILE) {
         TileArgs ta = tile_args(L, ws, static_cast<const uint8_t *>(h->b.spins));
         ta.bonds_out = h->b.bonds;
@@ -360,7 +423,7 @@ static sw_status launch_phase(sw_lattice *h, int32_t phase, hipStream_t s)
         return launch_status("k_tile");
     }
     if (phase == SW_PHASE_MERGE) {
-        hipLaunchKernelGGL(k_merge<false>, merge_grid(L), block, 0, s, merge_args(L, ws));
+        launch_merge<false>(L, merge_args(L, ws), L.g.ntiles, s);
         return launch_status("k_merge");
     }
     FlatArgs fa = flat_args(L, ws);
@@ -373,10 +436,10 @@ static sw_status launch_phase(sw_lattice *h, int32_t phase, hipStream_t s)
     fa.sid = h->p.stream_id;
     fa.ising = h->p.spin_kind == SW_SPIN_ISING_I8 ? 1 : 0;
     if (!L.sizes) {
-        hipLaunchKernelGGL((k_flatten<M_SW, false>), grid, block, 0, s, fa);
+        launch_flatten<M_SW, false, false>(L, fa, L.g.ntiles, s);
         return launch_status("k_flatten");
     }
-    hipLaunchKernelGGL((k_flatten<M_SW, true>), grid, block, 0, s, fa);
+    launch_flatten<M_SW, true, false>(L, fa, L.g.ntiles, s);
     emit_sizes(L, ws, fa, h->b.roots, h->b.sizes, fa.row_count + L.nrow + 1, nullptr, s);
     return launch_status("k_flatten");
 }
@@ -392,6 +455,7 @@ sw_status sw_sweep_phase(sw_lattice *h, int32_t phase, void *stream)
         h->next_phase = SW_PHASE_TILE;
         h->t += 1;
         h->swept = true;
+        h->small_last = false;
     } else {
         h->next_phase = phase + 1;
     }
@@ -400,7 +464,10 @@ sw_status sw_sweep_phase(sw_lattice *h, int32_t phase, void *stream)
 
 // A lattice of one tile is swept by k_small, all sweeps in one launch (the
 // per-phase entry point keeps the tiled path; both give the same results).
-static bool small_path(const sw_lattice *h) { return h->L.g.ntiles == 1 && !h->L.sizes; }
+static bool small_path(const sw_lattice *h)
+{
+    return h->p.W <= SMALL_W && h->p.H <= SMALL_H && !h->L.sizes;
+}
 
 static sw_status launch_small(sw_lattice *h, int32_t n, int64_t *hist, hipStream_t s)
 {
@@ -439,6 +506,7 @@ sw_status sw_sweep(sw_lattice *h, int32_t n_sweeps, void *stream)
         if (st != SW_OK) return st;
         h->t += static_cast<uint64_t>(n_sweeps);
         h->swept = true;
+        h->small_last = true;
         return SW_OK;
     }
     for (int32_t n = 0; n < n_sweeps; ++n) {
@@ -448,6 +516,7 @@ sw_status sw_sweep(sw_lattice *h, int32_t n_sweeps, void *stream)
         }
         h->t += 1;
         h->swept = true;
+        h->small_last = false;
     }
     return SW_OK;
 }
@@ -514,7 +583,8 @@ sw_status sw_observables(sw_lattice *h, sw_obs *out, void *stream)
     const Layout &L = h->L;
     void *ws = h->b.workspace;
     const int32_t *max_dev = L.sizes ? at<int32_t>(ws, L.row_count) + L.nrow + 1 : nullptr;
-    return measure(h->p, h->b, h->swept, at<int32_t>(ws, L.tile_act), at<int32_t>(ws, L.tile_ncl), L.g.ntiles,
+    return measure(h->p, h->b, h->swept, at<int32_t>(ws, L.tile_act), at<int32_t>(ws, L.tile_ncl),
+                   h->small_last ? 1 : L.g.ntiles,
                    at<unsigned long long>(ws, L.stats), max_dev, h->T, h->t, out, static_cast<hipStream_t>(stream));
 }
 
@@ -530,6 +600,7 @@ sw_status sw_sweep_history(sw_lattice *h, int32_t n_sweeps, int64_t *history, vo
         if (st != SW_OK) return st;
         h->t += static_cast<uint64_t>(n_sweeps);
         h->swept = true;
+        h->small_last = true;
         return SW_OK;
     }
     const Layout &L = h->L;
@@ -545,6 +616,7 @@ sw_status sw_sweep_history(sw_lattice *h, int32_t n_sweeps, int64_t *history, vo
         }
         h->t += 1;
         h->swept = true;
+        h->small_last = false;
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, obs, ST_LEN);
         hipLaunchKernelGGL(k_observe, dim3(blocks), dim3(NT), 0, s, static_cast<const uint8_t *>(h->b.spins), h->p.W,
                            h->p.H, static_cast<uint32_t>(h->p.q), h->p.spin_kind == SW_SPIN_ISING_I8 ? 1 : 0, obs);
@@ -584,9 +656,16 @@ sw_status sw_destroy(sw_lattice *h)
 
 size_t ccl_workspace_bytes(int32_t W, int32_t H, int32_t mode)
 {
+    return ccl_workspace_bytes_tiled(W, H, mode, 0);
+}
+
+size_t ccl_workspace_bytes_tiled(int32_t W, int32_t H, int32_t mode, int32_t tile_h)
+{
     if (mode < CCL_BONDS_PERIODIC || mode > CCL_SITES_OPEN) return 0;
-    if (!valid_shape(W, H, 1)) return 0;
-    return make_layout(W, H, true).total;
+    if (tile_h != 0 && !valid_tile_h(tile_h)) return 0;
+    const int th = tile_h ? tile_h : TH_DEFAULT;
+    if (!valid_shape(W, H, 1, th)) return 0;
+    return make_layout(W, H, true, th).total;
 }
 
 }  // extern "C"
@@ -595,12 +674,12 @@ namespace {
 
 // Argument checks of ccl_label (before anything is enqueued).
 sw_status ccl_check(const uint8_t *in, int32_t W, int32_t H, int32_t mode, const int32_t *labels,
-                    const int32_t *roots, const int32_t *sizes)
+                    const int32_t *roots, const int32_t *sizes, int th = TH_DEFAULT)
 {
     if (!in || !labels) return SW_ERR_ARG;
     if (mode < CCL_BONDS_PERIODIC || mode > CCL_SITES_OPEN) return SW_ERR_ARG;
     if ((roots == nullptr) != (sizes == nullptr)) return SW_ERR_ARG;
-    if (!valid_shape(W, H, 1)) return SW_ERR_SIZE;
+    if (!valid_shape(W, H, 1, th)) return SW_ERR_SIZE;
     const int64_t N = static_cast<int64_t>(W) * H;
     const uintptr_t ib = reinterpret_cast<uintptr_t>(in), lb = reinterpret_cast<uintptr_t>(labels);
     if (ib < lb + static_cast<uintptr_t>(N) * 4 && lb < ib + static_cast<uintptr_t>(N)) return SW_ERR_ARG;
@@ -613,23 +692,22 @@ sw_status ccl_enqueue(const Layout &L, const uint8_t *in, int32_t mode, int32_t 
                       int32_t *sizes, int32_t *n_clusters, void *workspace, hipStream_t s)
 {
     const bool want_sizes = roots != nullptr;
-    const dim3 grid(static_cast<unsigned>(L.g.ntiles)), block(NT);
     const TileArgs ta = tile_args(L, workspace, in);
     switch (mode) {
     case CCL_BONDS_PERIODIC: launch_tile<M_BONDS_PERIODIC>(L, ta, s); break;
     case CCL_BONDS_OPEN: launch_tile<M_BONDS_OPEN>(L, ta, s); break;
     default: launch_tile<M_SITES>(L, ta, s); break;
     }
-    hipLaunchKernelGGL(k_merge<false>, merge_grid(L), block, 0, s, merge_args(L, workspace));
+    launch_merge<false>(L, merge_args(L, workspace), L.g.ntiles, s);
     FlatArgs fa = flat_args(L, workspace);
     fa.labels = labels;
     if (want_sizes) {
         // the flatten mode only matters for M_SW; all labeling inputs share one
         // path; the emit also writes the cluster count (the offsets' total)
-        hipLaunchKernelGGL((k_flatten<M_BONDS_PERIODIC, true>), grid, block, 0, s, fa);
+        launch_flatten<M_BONDS_PERIODIC, true, false>(L, fa, L.g.ntiles, s);
         emit_sizes(L, workspace, fa, roots, sizes, nullptr, n_clusters, s);
     } else {
-        hipLaunchKernelGGL((k_flatten<M_BONDS_PERIODIC, false>), grid, block, 0, s, fa);
+        launch_flatten<M_BONDS_PERIODIC, false, false>(L, fa, L.g.ntiles, s);
     }
     if (n_clusters && !want_sizes) {
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, n_clusters, 1);
@@ -650,7 +728,7 @@ constexpr int MAX_DEVICES = 64;
 std::mutex g_scratch_mu;
 void *g_scratch_ptr[MAX_DEVICES] = {};
 
-// Device address of the current device's scratch.
+// Device address of the current device's scratch (nullptr on failure).
 sw_status scratch_of_current_device(void **out)
 {
     int dev = -1;
@@ -681,8 +759,19 @@ extern "C" {
 sw_status ccl_label(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32_t *labels, int32_t *roots,
                     int32_t *sizes, int32_t *n_clusters, void *workspace, size_t workspace_bytes, void *stream)
 {
-    if (const sw_status st = ccl_check(in, W, H, mode, labels, roots, sizes)) return st;
-    const Layout L = make_layout(W, H, roots != nullptr);
+    return ccl_label_tiled(in, W, H, mode, 0, 0, labels, roots, sizes, n_clusters, workspace, workspace_bytes,
+                           stream);
+}
+
+sw_status ccl_label_tiled(const uint8_t *in, int32_t W, int32_t H, int32_t mode, int32_t tile_h,
+                          int32_t merge_waves, int32_t *labels, int32_t *roots, int32_t *sizes,
+                          int32_t *n_clusters, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (tile_h != 0 && !valid_tile_h(tile_h)) return SW_ERR_ARG;
+    if (merge_waves != 0 && !valid_merge_waves(merge_waves)) return SW_ERR_ARG;
+    const int th = tile_h ? tile_h : TH_DEFAULT, mw = merge_waves ? merge_waves : MERGE_WAVES_DEFAULT;
+    if (const sw_status st = ccl_check(in, W, H, mode, labels, roots, sizes, th)) return st;
+    const Layout L = make_layout(W, H, roots != nullptr, th, mw);
     if (!workspace || workspace_bytes < L.total) return SW_ERR_WORKSPACE;
     if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return SW_ERR_WORKSPACE;
     ccl_enqueue(L, in, mode, labels, roots, sizes, n_clusters, workspace, static_cast<hipStream_t>(stream));
@@ -730,15 +819,18 @@ static sw_status check_batch(const sw_params *p, const sw_buffers *b, int32_t n,
 {
     if (!p || !b || n < 1) return SW_ERR_ARG;
     int64_t nt = 0;
+    const int th = tile_h_of(&p[0]);
     for (int32_t j = 0; j < n; ++j) {
         const sw_status st = check_params(&p[j]);
         if (st != SW_OK) return st;
         if (p[j].flags & (SW_F_SIZES | SW_F_REVERSE_TILES)) return SW_ERR_UNSUPPORTED;
+        // one tile shape and merge schedule per batch
+        if (tile_h_of(&p[j]) != th || merge_waves_of(&p[j]) != merge_waves_of(&p[0])) return SW_ERR_ARG;
         if (!b[j].spins || b[j].roots || b[j].sizes) return SW_ERR_ARG;
-        nt += cdiv(p[j].W, TW) * cdiv(p[j].H, TH);
+        nt += cdiv(p[j].W, TW) * cdiv(p[j].H, th);
     }
     // tile ids times CAP must stay in int32
-    if (nt * CAP >= (static_cast<int64_t>(1) << 31)) return SW_ERR_SIZE;
+    if (nt * dims_of(th).cap >= (static_cast<int64_t>(1) << 31)) return SW_ERR_SIZE;
     *ntiles = nt;
     return SW_OK;
 }
@@ -753,7 +845,7 @@ size_t swb_workspace_bytes(const sw_params *p, int32_t n)
     } catch (const std::bad_alloc &) {
         return 0;
     }
-    return make_batch_layout(nt, n).total;
+    return make_batch_layout(nt, n, tile_h_of(&p[0]), merge_waves_of(&p[0])).total;
 }
 
 sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int32_t n, void *workspace,
@@ -763,7 +855,7 @@ sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int
     int64_t nt = 0;
     const sw_status cs = check_batch(p, b, n, &nt);
     if (cs != SW_OK) return cs;
-    const Layout L = make_batch_layout(nt, n);
+    const Layout L = make_batch_layout(nt, n, tile_h_of(&p[0]), merge_waves_of(&p[0]));
     if (!workspace || workspace_bytes < L.total) return SW_ERR_WORKSPACE;
     if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return SW_ERR_WORKSPACE;
     swb_batch *h = new (std::nothrow) swb_batch();
@@ -792,7 +884,7 @@ sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int
             d.g.W = p[j].W;
             d.g.H = p[j].H;
             d.g.ntx = static_cast<int>(cdiv(p[j].W, TW));
-            d.g.nty = static_cast<int>(cdiv(p[j].H, TH));
+            d.g.nty = static_cast<int>(cdiv(p[j].H, L.d.th));
             d.g.ntiles = d.g.ntx * d.g.nty;
             d.tile0 = tile;
             d.spins = static_cast<uint8_t *>(b[j].spins);
@@ -860,27 +952,31 @@ void enqueue_batch_sweep(const swb_batch *h, hipStream_t s)
     const int32_t total = L.g.ntiles, even = h->tiles_even;
     TileArgs ta = tile_args(L, ws, nullptr);
     ta.b = bt;
-    if (even > 0) {
-        ta.b.tile_base = 0;
-        ta.b.ntiles = even;
-        hipLaunchKernelGGL((k_tile<M_SW, true, true>), dim3(static_cast<unsigned>(even)), dim3(NT), 0, s, ta);
-    }
-    if (total > even) {
-        ta.b.tile_base = even;
-        ta.b.ntiles = total - even;
-        hipLaunchKernelGGL((k_tile<M_SW, false, true>), dim3(static_cast<unsigned>(total - even)), dim3(NT), 0, s,
-                           ta);
-    }
+    with_tile_h(L.d.th, [&](auto c) {
+        constexpr int TH = decltype(c)::value;
+        if (even > 0) {
+            ta.b.tile_base = 0;
+            ta.b.ntiles = even;
+            hipLaunchKernelGGL((k_tile<M_SW, true, true, TH>), dim3(static_cast<unsigned>(even)), dim3(Tile<TH>::NT),
+                               0, s, ta);
+        }
+        if (total > even) {
+            ta.b.tile_base = even;
+            ta.b.ntiles = total - even;
+            hipLaunchKernelGGL((k_tile<M_SW, false, true, TH>), dim3(static_cast<unsigned>(total - even)),
+                               dim3(Tile<TH>::NT), 0, s, ta);
+        }
+    });
     MergeArgs ma = merge_args(L, ws);
     ma.b = bt;
     ma.b.tile_base = 0;
     ma.b.ntiles = total;
-    hipLaunchKernelGGL(k_merge<true>, dim3(static_cast<unsigned>(cdiv(total, MERGE_TILES))), dim3(NT), 0, s, ma);
+    launch_merge<true>(L, ma, total, s);
     FlatArgs fa = flat_args(L, ws);
     fa.b = bt;
     fa.b.tile_base = 0;
     fa.b.ntiles = total;
-    hipLaunchKernelGGL((k_flatten<M_SW, false, true>), dim3(static_cast<unsigned>(total)), dim3(NT), 0, s, fa);
+    launch_flatten<M_SW, false, true>(L, fa, total, s);
     hipLaunchKernelGGL(k_bump_u32, dim3(1), dim3(64), 0, s, at<uint32_t>(ws, L.t_dev));
 }
 

@@ -54,8 +54,8 @@ def test_threshold_matches_oracle():
         assert L.sw_threshold(K) == oracle.threshold(K), K
 
 
-def _params(W=64, H=64, q=2, kind=0, K=0.88, flags=0):
-    return _lib.SwParams(W, H, q, kind, K, 1, 0, flags)
+def _params(W=64, H=64, q=2, kind=0, K=0.88, flags=0, tile_h=0, merge_waves=0):
+    return _lib.SwParams(W, H, q, kind, K, 1, 0, flags, tile_h, merge_waves)
 
 
 def _bufs(spins, ws, nbytes, roots=None, sizes=None):
@@ -65,6 +65,8 @@ def _bufs(spins, ws, nbytes, roots=None, sizes=None):
 @pytest.mark.parametrize("kw", [
     dict(W=1), dict(H=1), dict(W=0), dict(W=-5), dict(W=65536, H=32768),
     dict(q=1), dict(q=256), dict(kind=0, q=3), dict(kind=7), dict(K=float("nan")), dict(flags=8),
+    dict(tile_h=8), dict(tile_h=48), dict(tile_h=256), dict(tile_h=-64), dict(merge_waves=2),
+    dict(merge_waves=32), dict(merge_waves=-8),
 ])
 def test_bad_params_rejected(kw):
     L = _lib.lib()
@@ -151,6 +153,28 @@ def test_ccl_argument_errors():
     assert call(inp, W, H, 0, lab, 0x50000000, 0x60000000, None, ws, need - 1, None) == _lib.SW_ERR_WORKSPACE
     assert call(inp, W, H, 0, lab, None, None, None, None, need, None) == _lib.SW_ERR_WORKSPACE
     assert call(inp, W, H, 0, lab, None, None, None, ws + 4, need, None) == _lib.SW_ERR_WORKSPACE
+
+
+def test_tile_shapes_sized():
+    """Every tile height sizes a workspace; smaller tiles need more boundary ids."""
+    L = _lib.lib()
+    sizes = {}
+    for th in _lib.TILE_HEIGHTS:
+        for mw in (0,) + _lib.MERGE_WAVES:
+            p = _params(W=1024, H=1024, tile_h=th, merge_waves=mw)
+            sizes[th] = L.sw_workspace_bytes(ctypes.byref(p))
+            assert sizes[th] > 0
+        assert L.ccl_workspace_bytes_tiled(1000, 700, 2, th) > 0
+    assert sizes[16] > sizes[32] > sizes[64] > sizes[128]
+    assert L.sw_workspace_bytes(ctypes.byref(_params(W=1024, H=1024))) == sizes[64]
+    assert L.ccl_workspace_bytes_tiled(1000, 700, 2, 0) == L.ccl_workspace_bytes(1000, 700, 2)
+    assert L.ccl_workspace_bytes_tiled(1000, 700, 2, 24) == 0
+    inp, lab, ws = 0x10000000, 0x20000000, 0x40000000
+    need = L.ccl_workspace_bytes_tiled(100, 100, 0, 32)
+    assert L.ccl_label_tiled(inp, 100, 100, 0, 24, 0, lab, None, None, None, ws, need, None) == _lib.SW_ERR_ARG
+    assert L.ccl_label_tiled(inp, 100, 100, 0, 32, 3, lab, None, None, None, ws, need, None) == _lib.SW_ERR_ARG
+    assert L.ccl_label_tiled(inp, 100, 100, 0, 32, 4, lab, 0x50000000, 0x60000000, None, ws, need - 1,
+                             None) == _lib.SW_ERR_WORKSPACE
 
 
 def test_ccl_noalloc_argument_errors():

@@ -33,9 +33,11 @@ MIX = [
 ]
 
 
-def test_batch_mixed_parity():
+@pytest.mark.parametrize("tile", [{}, dict(tile_h=16, merge_waves=4), dict(tile_h=128, merge_waves=16)],
+                         ids=["default", "h16m4", "h128m16"])
+def test_batch_mixed_parity(tile):
     specs = [dict(sp, stream_id=j) for j, sp in enumerate(MIX)]
-    b = sw.SWBatch(specs, keep_labels=True, keep_bonds=True)
+    b = sw.SWBatch(specs, keep_labels=True, keep_bonds=True, **tile)
     st = []
     for sp in b.specs:
         st.append(oracle.init_states(sp["W"], sp["H"], sp["q"], sp["seed"], sp["stream_id"]))

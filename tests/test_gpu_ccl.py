@@ -26,11 +26,11 @@ def _oracle(inp, mode):
     return oracle.label_bonds(W, H, inp.reshape(-1), MODES[mode])
 
 
-def _check(inp, mode):
+def _check(inp, mode, **tile):
     H, W = inp.shape
-    print(f"ccl W={W} H={H} mode={mode}", flush=True)
+    print(f"ccl W={W} H={H} mode={mode} {tile}", flush=True)
     g = torch.from_numpy(inp).cuda()
-    lab, roots, sizes, n = sw.ccl_label(g, mode, sizes=True)
+    lab, roots, sizes, n = sw.ccl_label(g, mode, sizes=True, **tile)
     want, nref = _oracle(inp, mode)
     got = lab.cpu().numpy().reshape(-1)
     assert np.array_equal(got, want)
@@ -38,7 +38,7 @@ def _check(inp, mode):
     r_ref, s_ref, _ = oracle.cluster_sizes(want)
     assert np.array_equal(roots.cpu().numpy(), r_ref)
     assert np.array_equal(sizes.cpu().numpy(), s_ref)
-    lab2 = sw.ccl_label(g, mode)
+    lab2 = sw.ccl_label(g, mode, **tile)
     assert torch.equal(lab, lab2)
 
 
@@ -57,6 +57,19 @@ def test_bonds(W, H, mode):
 def test_sites(W, H):
     for k, p in enumerate((0.0, 0.4, 0.5927, 0.7, 1.0)):
         _check(wl.site_image(W, H, p, seed=2000 + 7 * W + H + k), "sites_open")
+
+
+@pytest.mark.parametrize("tile_h,merge_waves", [(16, 4), (32, 16), (128, 8), (128, 4)])
+@pytest.mark.parametrize("W,H", [(1, 300), (300, 1), (129, 33), (515, 260), (1000, 257)])
+def test_tile_shapes(W, H, tile_h, merge_waves):
+    """Every tile shape and merge schedule labels bonds and images as the oracle does."""
+    for k, p in enumerate((0.35, 0.5, 0.65)):
+        seed = 5000 + 7 * W + H + k + tile_h
+        _check(wl.random_bonds(W, H, p, seed=seed), "bonds_periodic", tile_h=tile_h, merge_waves=merge_waves)
+        _check(wl.random_bonds(W, H, p, seed=seed + 1), "bonds_open", tile_h=tile_h, merge_waves=merge_waves)
+    for k, p in enumerate((0.4, 0.5927, 0.7)):
+        _check(wl.site_image(W, H, p, seed=6000 + 7 * W + H + k), "sites_open", tile_h=tile_h,
+               merge_waves=merge_waves)
 
 
 def test_structured_inputs():

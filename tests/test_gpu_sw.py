@@ -59,10 +59,11 @@ CASES = [
 
 
 @pytest.mark.parametrize("W,H,q,ising,K", CASES)
-def test_sweep_parity(W, H, q, ising, K):
-    print(f"case W={W} H={H} q={q} ising={ising} K={K}", flush=True)
+def test_sweep_parity(W, H, q, ising, K, tile=None):
+    print(f"case W={W} H={H} q={q} ising={ising} K={K} tile={tile}", flush=True)
     seed, sid = wl.SEED_BASE | 0x77, 3
-    lat = sw.SWLattice(W, H, q=q, K=K, seed=seed, stream_id=sid, ising=ising, keep_labels=True, keep_bonds=True)
+    lat = sw.SWLattice(W, H, q=q, K=K, seed=seed, stream_id=sid, ising=ising, keep_labels=True, keep_bonds=True,
+                       **(tile or {}))
     T = oracle.threshold(K)
     assert lat.threshold == T
     st = oracle.init_states(W, H, q, seed, sid)
@@ -319,11 +320,14 @@ def test_sweep_history(W, H, q, ising, n):
     assert o["t"] == n and o["n_clusters"] == rec[-1, oracle.REC_NCLUST]
 
 
-def test_small_path_matches_tiled_path():
-    """One-tile lattices: the fused launch and the per-phase (tiled) path agree."""
+@pytest.mark.parametrize("tile_h", [64, 16])
+def test_small_path_matches_tiled_path(tile_h):
+    """Lattices of at most 128 x 64: the fused one-workgroup launch and the
+    per-phase (tiled) path agree, also where the tiled path has several tiles."""
     for (W, H, q) in [(64, 64, 2), (128, 64, 3), (33, 17, 4), (2, 64, 2)]:
-        a = sw.SWLattice(W, H, q=q, seed=5, ising=(q == 2), keep_labels=True, keep_bonds=True)
-        b = sw.SWLattice(W, H, q=q, seed=5, ising=(q == 2), keep_labels=True, keep_bonds=True)
+        kw = dict(q=q, seed=5, ising=(q == 2), keep_labels=True, keep_bonds=True, tile_h=tile_h)
+        a = sw.SWLattice(W, H, **kw)
+        b = sw.SWLattice(W, H, **kw)
         for _ in range(4):
             a.sweep(1)
             for ph in range(3):
@@ -334,15 +338,29 @@ def test_small_path_matches_tiled_path():
         assert a.observables() == b.observables()
 
 
+TILE_CONFIGS = [dict(tile_h=16, merge_waves=4), dict(tile_h=32, merge_waves=16), dict(tile_h=128, merge_waves=8),
+                dict(tile_h=64, merge_waves=4)]
+
+
+@pytest.mark.parametrize("tile", TILE_CONFIGS, ids=lambda d: f"h{d['tile_h']}m{d['merge_waves']}")
+@pytest.mark.parametrize("W,H,q,ising,K", [CASES[i] for i in (2, 3, 5, 6, 8, 9, 13)])
+def test_sweep_parity_tile_shapes(W, H, q, ising, K, tile):
+    """Every tile shape and merge schedule gives the oracle's trajectory."""
+    test_sweep_parity(W, H, q, ising, K, tile)
+
+
+@pytest.mark.parametrize("tile_h", [16, 32, 64, 128])
 @pytest.mark.parametrize("W,H,q,ising,sizes", [(1000, 300, 3, False, False), (517, 260, 2, True, True)])
-def test_schedule_independence(W, H, q, ising, sizes):
+def test_schedule_independence(W, H, q, ising, sizes, tile_h):
     """Tiles visited in the reverse order (another workgroup -> tile schedule,
-    hence other orders of atomics, claims and merges): bonds, labels, spins,
-    sizes and counters are identical after every sweep, and equal the oracle."""
-    print(f"case W={W} H={H} q={q} ising={ising} sizes={sizes}", flush=True)
+    hence other orders of atomics, claims and merges), for every tile shape:
+    bonds, labels, spins, sizes and counters are identical after every sweep,
+    and equal the oracle."""
+    print(f"case W={W} H={H} q={q} ising={ising} sizes={sizes} tile_h={tile_h}", flush=True)
     seed, sid = wl.SEED_BASE | 0x4E, 2
     K = wl.K_ISING_C if ising else wl.K_POTTS3_C
-    kw = dict(q=q, K=K, seed=seed, stream_id=sid, ising=ising, keep_labels=True, keep_bonds=True, sizes=sizes)
+    kw = dict(q=q, K=K, seed=seed, stream_id=sid, ising=ising, keep_labels=True, keep_bonds=True, sizes=sizes,
+              tile_h=tile_h)
     fwd, rev = sw.SWLattice(W, H, **kw), sw.SWLattice(W, H, reverse_tiles=True, **kw)
     T = oracle.threshold(K)
     st = oracle.init_states(W, H, q, seed, sid)
