@@ -91,12 +91,16 @@ enum {
     SW_F_SIZES = 1u << 1,      /* every sweep also lists its clusters: roots
                                   (ascending) and sizes into sw_buffers.roots /
                                   .sizes, and the largest size (sw_obs)       */
-    SW_F_REVERSE_TILES = 1u << 2 /* a schedule check: the workgroups of the
+    SW_F_REVERSE_TILES = 1u << 2, /* a schedule check: the workgroups of the
                                   tile, merge and flip launches visit the
                                   tiles in the reverse order.  Every output is
                                   canonical (minimum-index labels, draws keyed
                                   on the index), so it is identical either
                                   way; batches reject this flag. */
+    SW_F_BATCH_FUSED = 1u << 3   /* batches only (on p[0]): sweep with the
+                                  fused persistent launch instead of one
+                                  launch per phase; the same results.  Single
+                                  lattices reject it. */
 };
 
 /* Input kinds of ccl_label. */
@@ -235,12 +239,25 @@ sw_status sw_set_t(sw_lattice *h, uint64_t t);
 /* Free the host handle (device buffers stay with the caller). */
 sw_status sw_destroy(sw_lattice *h);
 
-/* ---- Batches: many independent lattices advanced together, one launch per
- * phase for the whole batch (the SW update of Sec. II, steps 1-3, on each
- * lattice).  Lattice j evolves exactly as a single lattice created with p[j]
- * and swept as often would: same spins, bonds, labels and counters.  The
- * lattices share one sweep counter t, starting at 0.  Small lattices occupy
- * one tile each; large ones are tiled as single lattices are. */
+/* ---- Batches: many independent lattices advanced together (the SW update
+ * of Sec. II, steps 1-3, on each lattice).  Lattice j evolves exactly as a
+ * single lattice created with p[j] and swept as often would: same spins,
+ * bonds, labels and counters.  The lattices share one sweep counter t,
+ * starting at 0.  Two engines give the same results:
+ *   - by default a sweep is one launch per phase (tile, merge, flatten) over
+ *     the tiles of every lattice, a lattice smaller than a tile being one
+ *     partial tile;
+ *   - with SW_F_BATCH_FUSED on p[0] a sweep is one launch of a persistent
+ *     kernel over a work queue: lattices of at most 128 x 64 sites (and at
+ *     most 15 x the workgroup's threads, 7680 at the default tile) are swept
+ *     whole in one workgroup's LDS; the others are tiled, with their merge
+ *     waiting for their own tiles and their flatten for their own merge
+ *     (per-lattice counters, no grid-wide barrier), so lattices pipeline
+ *     inside the launch.  Each of those waits costs an agent-scope release
+ *     and acquire, which on a chip of several XCDs write back and invalidate
+ *     L2; the per-phase engine, whose phases meet at kernel boundaries, is
+ *     the faster one on MI355X.
+ * Every lattice of a batch uses p[0]'s tile_h and merge_waves. */
 typedef struct swb_batch swb_batch;
 
 /* Workspace bytes of a batch of n >= 1 lattices (0 if a parameter set is
@@ -271,7 +288,9 @@ sw_status swb_sweep(swb_batch *h, int32_t n_sweeps, void *stream);
 sw_status swb_sweep_graph(swb_batch *h, int32_t n_sweeps, void *stream);
 
 /* Observables of lattice j, 0 <= j < n, as sw_observables (max_cluster is
- * always -1); waits for the stream. */
+ * always -1); waits for the stream.  SW_ERR_DEVICE if a fused sweep gave up
+ * waiting for a lattice's tiles or merge (a broken invariant: the batch's
+ * results are then invalid; this bound keeps the launch from hanging). */
 sw_status swb_observables(swb_batch *h, int32_t j, sw_obs *out, void *stream);
 
 /* Sweeps done so far; free the host handle. */

@@ -238,10 +238,13 @@ class SWBatch:
     as ``SWLattice(**specs[j])`` would.  ``spins[j]`` (and ``labels[j]`` /
     ``bonds[j]`` with ``keep_labels`` / ``keep_bonds``) are its tensors.
     ``tile_h`` / ``merge_waves`` as in ``SWLattice``, one choice per batch.
+    A sweep is one launch per phase over all lattices; ``fused=True`` uses one
+    launch of the fused persistent kernel instead (lattices of at most 128 x 64
+    swept whole in LDS, the others tiled, phases ordered per lattice).
     """
 
     def __init__(self, specs, keep_labels: bool = False, keep_bonds: bool = False, device: str = "cuda",
-                 tile_h: int = 0, merge_waves: int = 0):
+                 tile_h: int = 0, merge_waves: int = 0, fused: bool = False):
         torch = _torch()
         L = _lib.lib()
         self.device = torch.device(device)
@@ -261,7 +264,8 @@ class SWBatch:
             seed, sid = int(sp.get("seed", 0)), int(sp.get("stream_id", 0))
             self.specs.append(dict(W=W, H=H, q=q, K=float(K), seed=seed, stream_id=sid, ising=ising))
             P[j] = _lib.SwParams(W, H, q, _lib.SW_SPIN_ISING_I8 if ising else _lib.SW_SPIN_POTTS_U8, float(K),
-                                 seed & (2**64 - 1), sid, 0, int(tile_h), int(merge_waves))
+                                 seed & (2**64 - 1), sid, _lib.SW_F_BATCH_FUSED if fused else 0,
+                                 int(tile_h), int(merge_waves))
             dt = torch.int8 if ising else torch.uint8
             sp_t = torch.empty((H, W), dtype=dt, device=self.device)
             lab = torch.empty((H, W), dtype=torch.int32, device=self.device) if keep_labels else None

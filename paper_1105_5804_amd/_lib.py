@@ -12,7 +12,7 @@ ABI_VERSION = 4  # the SWCCL_ABI_VERSION these declarations follow
 # status codes
 SW_OK, SW_ERR_ARG, SW_ERR_SIZE, SW_ERR_WORKSPACE, SW_ERR_DEVICE, SW_ERR_STATE, SW_ERR_UNSUPPORTED, SW_ERR_HOST_MEMORY = range(8)
 SW_SPIN_ISING_I8, SW_SPIN_POTTS_U8 = 0, 1
-SW_F_KEEP_SPINS, SW_F_SIZES, SW_F_REVERSE_TILES = 1, 2, 4
+SW_F_KEEP_SPINS, SW_F_SIZES, SW_F_REVERSE_TILES, SW_F_BATCH_FUSED = 1, 2, 4, 8
 CCL_BONDS_PERIODIC, CCL_BONDS_OPEN, CCL_SITES_OPEN = 0, 1, 2
 CCL_NOALLOC_SCRATCH_BYTES = 64 << 20
 TILE_HEIGHTS = (16, 32, 64, 128)  # sw_params.tile_h (0: 64)

@@ -92,6 +92,7 @@ struct LatticeDesc {
     int32_t *labels;   // canonical labels, or nullptr
     uint32_t tm1, tany, k0, k1, sid, q;
     int32_t ising;
+    int32_t nmerge;    // fused sweeps: merge groups of the lattice (0 if swept whole in LDS)
 };
 
 // How a batched launch finds the lattice of a tile.  Tile-indexed arrays
@@ -295,6 +296,12 @@ __global__ void k_zero_i32(int32_t *p, int n)
     if (i < n) p[i] = 0;
 }
 
+__global__ void k_iota_i32(int32_t *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = i;
+}
+
 // Advance a device-side sweep counter (the last launch of a batched sweep).
 __global__ void k_bump_u32(uint32_t *p)
 {
@@ -359,6 +366,12 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 __device__ __forceinline__ EO uniform_eo(EO m) { return EO{uniform64(m.e), uniform64(m.o)}; }
+// A pointer the caller knows to be wave-uniform, as a scalar value.
+template <typename T>
+__device__ __forceinline__ T *uniform_ptr(T *p)
+{
+    return reinterpret_cast<T *>(static_cast<uintptr_t>(uniform64(static_cast<uint64_t>(reinterpret_cast<uintptr_t>(p)))));
+}
 
 // Root of x (a byte offset, as the tile kernel's parents) once all unions are
 // done; a claimed root (negative entry) is a root.
@@ -426,48 +439,59 @@ __device__ __forceinline__ int wave_max_below(int v)
     return out;
 }
 
-// 8 waves per SIMD (four 128 x 64 workgroups per CU): the LDS use stays
-// under 40 KB per 64 rows and the registers are held to what 8 waves allow
-// (some scalar registers spill to vector lanes; the extra latency hiding is
-// worth more).
-template <int MODE, bool EVENW, bool BATCH, int TH_>
-__global__ __launch_bounds__(Tile<TH_>::NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_tile(TileArgs a)
+// LDS of the tile phase.  The image mode's extra occupancy masks are paid
+// for by slightly shorter lists, so every mode stays under 40 KB per 64 rows.
+template <int MODE, int TH_>
+struct TileSmem {
+    static constexpr int TH = TH_, TSITES = TW * TH, NWAVE = TH / RPW;
+    static constexpr int TL = MODE == M_SITES ? (TH < 64 ? TLIST - 16 : TLIST - 8) : TLIST;
+    int P[TSITES];                     // union-find parent per site slot, as 4 x slot
+    EO Rm[TH];                         // in-tile right bonds per row
+    EO Om[MODE == M_SITES ? TH : 1];   // occupied sites per row (images)
+    uint16_t wl[NWAVE][TL];            // per-wave work list (contacts, then run starts)
+    unsigned long long xr_w[NWAVE];    // right crossing bonds of each wave's rows (bit ly % 64)
+    EO xd_s;                           // bottom crossing bonds
+    int nb_s;
+    int act_w[NWAVE];
+};
+
+// A batched launch's tile: take the lattice's shape, buffers and keys from
+// its descriptor; lt is the tile's index inside its lattice.
+__device__ __forceinline__ void load_batch_tile(TileArgs &a, int tile, int &lt)
+{
+    const LatticeDesc &L = a.b.lat[a.b.lat_of_tile[tile]];
+    a.g = L.g;
+    a.in = L.spins;
+    a.bonds_out = L.bonds;
+    a.tm1 = L.tm1;
+    a.tany = L.tany;
+    a.k0 = L.k0;
+    a.k1 = L.k1;
+    a.sid = L.sid;
+    a.t = *a.b.t;
+    lt = tile - L.tile0;
+}
+
+// The tile phase of one tile: `tile` indexes the tile arrays, `lt` is the
+// tile inside its lattice (they differ in batches).  Uses every thread of a
+// Tile<TH>::NT-thread workgroup; ends with the workgroup's writes issued.
+template <int MODE, bool EVENW, int TH_>
+__device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int lt, TileSmem<MODE, TH_> &sm)
 {
     using S = Tile<TH_>;
     constexpr int TH = S::TH, TSITES = S::TSITES, CAP = S::CAP, EDGE = S::EDGE, XR = S::XR, XW = S::XW;
     constexpr int NT = S::NT, NWAVE = S::NWAVE;
     constexpr bool NEED_DOWN = MODE == M_SW || MODE == M_SITES;  // bonds from two rows
     constexpr bool NEED_HALO = MODE == M_SW || MODE == M_SITES;  // column right of the tile
-    __shared__ int P[TSITES];             // union-find parent per site slot, as 4 x slot
-    __shared__ EO Rm[TH];                 // in-tile right bonds per row
-    __shared__ EO Om[TH];                 // occupied sites per row
-    // the image mode's extra occupancy masks are paid for by slightly shorter
-    // lists, so every mode stays under 40 KB of LDS per 64 rows
-    constexpr int TL = MODE == M_SITES ? (TH < 64 ? TLIST - 16 : TLIST - 8) : TLIST;
-    __shared__ uint16_t wl[NWAVE][TL];    // per-wave work list (contacts, then run starts)
-    __shared__ unsigned long long xr_w[NWAVE];  // right crossing bonds of each wave's rows (bit ly % 64)
-    __shared__ EO xd_s;                   // bottom crossing bonds
-    __shared__ int nb_s;
-    __shared__ int act_w[NWAVE];
-
-    int tile, lt;  // tile in the arrays, tile inside its lattice
-    if constexpr (BATCH) {
-        tile = a.b.tile_base + xcd_remap(blockIdx.x, a.b.ntiles);
-        const LatticeDesc &L = a.b.lat[a.b.lat_of_tile[tile]];
-        a.g = L.g;
-        a.in = L.spins;
-        a.bonds_out = L.bonds;
-        a.tm1 = L.tm1;
-        a.tany = L.tany;
-        a.k0 = L.k0;
-        a.k1 = L.k1;
-        a.sid = L.sid;
-        a.t = *a.b.t;
-        lt = tile - L.tile0;
-    } else {
-        tile = lt = xcd_remap(blockIdx.x, a.g.ntiles);
-        if (a.g.rev) tile = lt = a.g.ntiles - 1 - tile;
-    }
+    constexpr int TL = TileSmem<MODE, TH_>::TL;
+    int *P = sm.P;
+    EO *Rm = sm.Rm;
+    EO *Om = sm.Om;
+    auto &wl = sm.wl;
+    unsigned long long *xr_w = sm.xr_w;
+    EO &xd_s = sm.xd_s;
+    int &nb_s = sm.nb_s;
+    int *act_w = sm.act_w;
     const int W = a.g.W, H = a.g.H;
     const int tx = lt % a.g.ntx, ty = lt / a.g.ntx;
     const int gx0 = tx * TW, gy0 = ty * TH;
@@ -571,7 +595,7 @@ __global__ __launch_bounds__(Tile<TH_>::NT) __attribute__((amdgpu_waves_per_eu(8
             uint32_t r0R, r0D, r1R, r1D;
             // the key schedule is recomputed per row (scalar adds) rather than
             // held in 20 scalar registers across the unrolled row loop
-            uint32_t k0 = a.k0, k1 = a.k1;
+            uint32_t k0 = __builtin_amdgcn_readfirstlane(a.k0), k1 = __builtin_amdgcn_readfirstlane(a.k1);
             asm volatile("" : "+s"(k0), "+s"(k1));
             const U4 blk = philox4x32_10(static_cast<uint32_t>(i0 >> 1), a.t, TAG_BOND, a.sid, k0, k1);
             if (EVENW || (i0 & 1) == 0) {  // the pair (i0, i0+1) shares one block
@@ -589,8 +613,8 @@ __global__ __launch_bounds__(Tile<TH_>::NT) __attribute__((amdgpu_waves_per_eu(8
             }
             // uniform flags are re-read per row as well (held across rows
             // as lane masks, they too would spill)
-            uint32_t tany = a.tany;
-            uint8_t *bonds_out = a.bonds_out;
+            uint32_t tany = __builtin_amdgcn_readfirstlane(a.tany);
+            uint8_t *bonds_out = uniform_ptr(a.bonds_out);
             asm volatile("" : "+s"(tany), "+s"(bonds_out));
             const uint64_t on0 = tany ? V0 : 0ull, on1 = tany ? V1 : 0ull;
             mR0 = lanes_eq(s0, sr0) & lanes_le(r0R, a.tm1) & on0;
@@ -645,7 +669,7 @@ __global__ __launch_bounds__(Tile<TH_>::NT) __attribute__((amdgpu_waves_per_eu(8
         if (lane_r == 0) {
             if (last) xd_s = EO{mD0, mD1};
             Rm[ly] = R;
-            if (MODE == M_SITES) Om[ly] = EO{O0, O1};
+            if constexpr (MODE == M_SITES) Om[ly] = EO{O0, O1};
         }
         const int base = ly * TW;
         // Run starts: site 2L starts a run unless bond 2L-1 -> 2L is present,
@@ -748,7 +772,8 @@ __global__ __launch_bounds__(Tile<TH_>::NT) __attribute__((amdgpu_waves_per_eu(8
             nrs = 0;
         }
         const EO R = uniform_eo(Rm[ly]);
-        const EO O = MODE == M_SITES ? uniform_eo(Om[ly]) : valid;
+        EO O = valid;
+        if constexpr (MODE == M_SITES) O = uniform_eo(Om[ly]);
         const int2 pp = ppr[r];
         const EO linked = EO{lanes_ne(static_cast<uint32_t>(pp.x), static_cast<uint32_t>(4 * (base + lx0))),
                              lanes_ne(static_cast<uint32_t>(pp.y), static_cast<uint32_t>(4 * (base + lx0 + 1)))};
@@ -789,7 +814,8 @@ __global__ __launch_bounds__(Tile<TH_>::NT) __attribute__((amdgpu_waves_per_eu(8
     for (int r = 0; r < RPW; ++r) {
         if (r >= nr) break;
         const int ly = ly0 + r;
-        const EO O = MODE == M_SITES ? Om[ly] : valid;
+        EO O = valid;
+        if constexpr (MODE == M_SITES) O = Om[ly];
         const int base = ly * TW;
         const int2 pp = *reinterpret_cast<const int2 *>(&P[base + lx0]);
         const uint32_t code0 = lane_bit(O.e, lane) ? code_of(base + lx0, pp.x) : CODE_BG;
@@ -820,6 +846,25 @@ __global__ __launch_bounds__(Tile<TH_>::NT) __attribute__((amdgpu_waves_per_eu(8
     }
 }
 
+// 8 waves per SIMD (four 128 x 64 workgroups per CU): the LDS use stays
+// under 40 KB per 64 rows and the registers are held to what 8 waves allow
+// (some scalar registers spill to vector lanes; the extra latency hiding is
+// worth more).
+template <int MODE, bool EVENW, bool BATCH, int TH_>
+__global__ __launch_bounds__(Tile<TH_>::NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_tile(TileArgs a)
+{
+    __shared__ TileSmem<MODE, TH_> sm;
+    int tile, lt;  // tile in the arrays, tile inside its lattice
+    if constexpr (BATCH) {
+        tile = a.b.tile_base + xcd_remap(blockIdx.x, a.b.ntiles);
+        load_batch_tile(a, tile, lt);
+    } else {
+        tile = lt = xcd_remap(blockIdx.x, a.g.ntiles);
+        if (a.g.rev) tile = lt = a.g.ntiles - 1 - tile;
+    }
+    tile_body<MODE, EVENW, TH_>(a, tile, lt, sm);
+}
+
 // ---------------------------------------------------------------- merge ----
 
 struct MergeArgs {
@@ -836,23 +881,18 @@ struct MergeArgs {
 // Consecutive crossing bonds that join the same pair of boundary ids are
 // skipped.  The workgroup size (tiles per workgroup, one wave each) is the
 // merge schedule's free parameter; it is read from blockDim.
+// The merge of one tile by the calling wave (`tile` indexes the tile arrays).
 template <bool BATCH, int TH_>
-__global__ __launch_bounds__(1024) void k_merge(MergeArgs a)
+__device__ __forceinline__ void merge_tile(MergeArgs a, const int tile)
 {
     using S = Tile<TH_>;
     constexpr int TH = S::TH, CAP = S::CAP, EDGE = S::EDGE, XR = S::XR, XW = S::XW;
-    const int lane = threadIdx.x & 63, wave = wave_id();
-    int tile = blockIdx.x * static_cast<int>(blockDim.x >> 6) + wave;
+    const int lane = threadIdx.x & 63;
     int tile0 = 0;  // first tile of the lattice in the arrays
     if constexpr (BATCH) {
-        if (tile >= a.b.ntiles) return;
-        tile += a.b.tile_base;
         const LatticeDesc &L = a.b.lat[a.b.lat_of_tile[tile]];
         a.g = L.g;
         tile0 = L.tile0;
-    } else {
-        if (tile >= a.g.ntiles) return;
-        if (a.g.rev) tile = a.g.ntiles - 1 - tile;
     }
     const int lt = tile - tile0;
     const int tx = lt % a.g.ntx, ty = lt / a.g.ntx;
@@ -906,6 +946,20 @@ __global__ __launch_bounds__(1024) void k_merge(MergeArgs a)
         gunite(a.gparent, a.gkey, tile * CAP + b2_a, ntD * CAP + b2_b);
 }
 
+template <bool BATCH, int TH_>
+__global__ __launch_bounds__(1024) void k_merge(MergeArgs a)
+{
+    int tile = blockIdx.x * static_cast<int>(blockDim.x >> 6) + wave_id();
+    if constexpr (BATCH) {
+        if (tile >= a.b.ntiles) return;
+        tile += a.b.tile_base;
+    } else {
+        if (tile >= a.g.ntiles) return;
+        if (a.g.rev) tile = a.g.ntiles - 1 - tile;
+    }
+    merge_tile<BATCH, TH_>(a, tile);
+}
+
 // -------------------------------------------------------------- flatten ----
 
 struct FlatArgs {
@@ -935,40 +989,49 @@ __device__ __forceinline__ uint8_t flip_state(uint32_t R, const FlatArgs &a)
     return static_cast<uint8_t>(draw_state(pick(b, R & 3u), a.q));
 }
 
-template <int MODE, bool SIZES, bool BATCH, int TH_>
-__global__ __launch_bounds__(Tile<TH_>::NT) void k_flatten(FlatArgs a)
+// LDS of the flatten phase.
+template <int MODE, bool SIZES, int TH_>
+struct FlatSmem {
+    static constexpr int TH = TH_, TSITES = TW * TH, CAP = 2 * (TW + TH), NWAVE = TH / RPW;
+    uint8_t ST[MODE == M_SW ? CAP + TSITES : 1];  // new state per code (boundary id or CAP + slot)
+    int32_t Rb[CAP];                              // canonical root (site index) per boundary id
+    int32_t Gid[CAP];                             // root id per boundary id
+    uint16_t rl[NWAVE][WLIST];                    // interior roots of each wave's rows
+    int ncl_w[NWAVE];
+    int32_t Ci[SIZES ? TSITES : 1];               // sizes of interior clusters
+    int32_t Cb[SIZES ? CAP : 1];                  // per-tile part of boundary clusters
+    int32_t rowc[TH + 1];
+};
+
+__device__ __forceinline__ void load_batch_flat(FlatArgs &a, int tile, int &lt)
+{
+    const LatticeDesc &L = a.b.lat[a.b.lat_of_tile[tile]];
+    a.g = L.g;
+    a.spins = L.spins;
+    a.labels = L.labels;
+    a.q = L.q;
+    a.k0 = L.k0;
+    a.k1 = L.k1;
+    a.sid = L.sid;
+    a.ising = L.ising;
+    a.t = *a.b.t;
+    lt = tile - L.tile0;
+}
+
+// The flatten + flip of one tile (`tile` in the arrays, `lt` inside its
+// lattice), by a Tile<TH>::NT-thread workgroup.
+template <int MODE, bool SIZES, int TH_>
+__device__ __forceinline__ void flatten_body(FlatArgs a, const int tile, const int lt, FlatSmem<MODE, SIZES, TH_> &sm)
 {
     using S = Tile<TH_>;
     constexpr int TH = S::TH, TSITES = S::TSITES, CAP = S::CAP, NT = S::NT, NWAVE = S::NWAVE;
     constexpr int BPT = (CAP + NT - 1) / NT;  // boundary ids per thread
     constexpr int NCODE = CAP + TSITES;
-    __shared__ uint8_t ST[MODE == M_SW ? NCODE : 1];  // new state per code (boundary id or CAP + slot)
-    __shared__ int32_t Rb[CAP];                        // canonical root (site index) per boundary id
-    __shared__ int32_t Gid[CAP];                       // root id per boundary id
-    __shared__ uint16_t rl[NWAVE][WLIST];              // interior roots of each wave's rows
-    __shared__ int ncl_w[NWAVE];
-    __shared__ int32_t Ci[SIZES ? TSITES : 1];         // sizes of interior clusters
-    __shared__ int32_t Cb[SIZES ? CAP : 1];            // per-tile part of boundary clusters
-    __shared__ int32_t rowc[TH + 1];
-
-    int tile, lt;  // tile in the arrays, tile inside its lattice
-    if constexpr (BATCH) {
-        tile = a.b.tile_base + xcd_remap(blockIdx.x, a.b.ntiles);
-        const LatticeDesc &L = a.b.lat[a.b.lat_of_tile[tile]];
-        a.g = L.g;
-        a.spins = L.spins;
-        a.labels = L.labels;
-        a.q = L.q;
-        a.k0 = L.k0;
-        a.k1 = L.k1;
-        a.sid = L.sid;
-        a.ising = L.ising;
-        a.t = *a.b.t;
-        lt = tile - L.tile0;
-    } else {
-        tile = lt = xcd_remap(blockIdx.x, a.g.ntiles);
-        if (a.g.rev) tile = lt = a.g.ntiles - 1 - tile;
-    }
+    uint8_t *ST = sm.ST;
+    int32_t *Rb = sm.Rb, *Gid = sm.Gid;
+    auto &rl = sm.rl;
+    int *ncl_w = sm.ncl_w;
+    int32_t *Ci = sm.Ci, *Cb = sm.Cb, *rowc = sm.rowc;
     const int W = a.g.W;
     const int tx = lt % a.g.ntx, ty = lt / a.g.ntx;
     const int gx0 = tx * TW, gy0 = ty * TH;
@@ -995,7 +1058,7 @@ __global__ __launch_bounds__(Tile<TH_>::NT) void k_flatten(FlatArgs a)
     if constexpr (SIZES) {
         // the scan's closing slot and the largest-size slot after the
         // per-(row, tile column) counts start at zero (no other block writes them)
-        if (blockIdx.x == 0 && threadIdx.x < 2) a.row_count[static_cast<int64_t>(a.g.H) * a.g.ntx + threadIdx.x] = 0;
+        if (lt == 0 && threadIdx.x < 2) a.row_count[static_cast<int64_t>(a.g.H) * a.g.ntx + threadIdx.x] = 0;
         for (int k = threadIdx.x; k < TSITES; k += NT) Ci[k] = 0;
         for (int k = threadIdx.x; k < CAP; k += NT) Cb[k] = 0;
     }
@@ -1161,6 +1224,21 @@ __global__ __launch_bounds__(Tile<TH_>::NT) void k_flatten(FlatArgs a)
     }
 }
 
+template <int MODE, bool SIZES, bool BATCH, int TH_>
+__global__ __launch_bounds__(Tile<TH_>::NT) void k_flatten(FlatArgs a)
+{
+    __shared__ FlatSmem<MODE, SIZES, TH_> sm;
+    int tile, lt;  // tile in the arrays, tile inside its lattice
+    if constexpr (BATCH) {
+        tile = a.b.tile_base + xcd_remap(blockIdx.x, a.b.ntiles);
+        load_batch_flat(a, tile, lt);
+    } else {
+        tile = lt = xcd_remap(blockIdx.x, a.g.ntiles);
+        if (a.g.rev) tile = lt = a.g.ntiles - 1 - tile;
+    }
+    flatten_body<MODE, SIZES, TH_>(a, tile, lt, sm);
+}
+
 // Sum of n per-tile int32 counters into *out64 and/or *out32 (one atomic per
 // workgroup; both outputs are cleared by the caller).
 __global__ __launch_bounds__(NT) void k_reduce_tiles(const int32_t *v, int n, unsigned long long *out64,
@@ -1306,13 +1384,25 @@ __device__ __forceinline__ int small_row(int i, float inv_w) { return static_cas
 
 constexpr int SMALL_NT = 1024;  // 16 waves: more LDS round trips in flight on the one CU
 
-__global__ __launch_bounds__(SMALL_NT) void k_small(SmallArgs a)
+// LDS of a lattice swept whole by an NT_-thread workgroup (at most SITES sites).
+template <int NT_, int SITES>
+struct SmallSmem {
+    int P[SITES];
+    uint8_t S[SITES];  // states 0..q-1
+    unsigned long long red[NT_ / 64][3];
+};
+
+// All a.n sweeps of a lattice of at most SITES sites (W <= SMALL_W, H <=
+// SMALL_H) in one NT_-thread workgroup.
+template <int NT_, int SITES>
+__device__ __forceinline__ void small_body(const SmallArgs &a, SmallSmem<NT_, SITES> &sm)
 {
-    constexpr int NT = SMALL_NT, NWAVE = SMALL_NT / 64, TSITES = SMALL_SITES;
-    constexpr int PAIRS_PER_THREAD = TSITES / 2 / NT;  // site pairs 2p, 2p+1 with p = tid + NT m
-    __shared__ int P[TSITES];
-    __shared__ uint8_t S[TSITES];   // states 0..q-1
-    __shared__ unsigned long long red[NWAVE][3];
+    constexpr int NT = NT_, NWAVE = NT_ / 64, TSITES = SITES;
+    constexpr int PAIRS_PER_THREAD = (TSITES / 2 + NT - 1) / NT;  // site pairs 2p, 2p+1 with p = tid + NT m
+    static_assert(PAIRS_PER_THREAD <= 8, "a thread's bonds fit one 32-bit mask");
+    int *P = sm.P;
+    uint8_t *S = sm.S;
+    auto &red = sm.red;
     static_assert(2 * TSITES < (1 << 16), "per-workgroup counters fit 16-bit fields");
     const int W = a.W, H = a.H, N = W * H;
     const float inv_w = 1.0f / static_cast<float>(W);
@@ -1460,6 +1550,12 @@ __global__ __launch_bounds__(SMALL_NT) void k_small(SmallArgs a)
     }
 }
 
+__global__ __launch_bounds__(SMALL_NT) void k_small(SmallArgs a)
+{
+    __shared__ SmallSmem<SMALL_NT, SMALL_SITES> sm;
+    small_body<SMALL_NT, SMALL_SITES>(a, sm);
+}
+
 // One per-sweep record from the observable slots (after k_observe and the
 // per-tile reductions of the sweep).
 __global__ void k_hist_row(const unsigned long long *st, const int32_t *max_size, int64_t *row)
@@ -1579,6 +1675,181 @@ __global__ __launch_bounds__(NT) void k_observe(const uint8_t *s, int W, int H, 
         add_stat(&out[slot], t);
     }
     (void)q;
+}
+
+// ------------------------------------------------------ fused batch sweep ---
+//
+// One launch per sweep of a whole batch of independent lattices.  Workgroups
+// take work items from a queue (a ticket counter) in a fixed order:
+//   1. lattices small enough to be swept whole in one workgroup's LDS,
+//   2. tiles of the other lattices (bond activation + tile labeling),
+//   3. merge groups (up to NWAVE tiles of one lattice, a wave each),
+//   4. tiles again (flatten + flip),
+// with the tiled lattices in the same order in 2-4.  A merge group waits
+// until every tile of its lattice is done, a flatten until every merge group
+// of its lattice is done.  Items are handed out in queue order, so every item
+// a workgroup waits for was taken earlier by a workgroup that is running and
+// itself waits only on items taken before that: the launch needs neither a
+// co-resident grid nor a grid-wide barrier, and lattices pipeline (one
+// lattice's flatten runs while another's tiles are still labeled).
+//
+// The counters only grow: every launch takes exactly n_items + gridDim.x
+// tickets (each workgroup ends on its first ticket past the items), adds
+// ntiles / nmerge to a lattice's counters and gridDim.x to the exit count, so
+// a launch finds its place from its first ticket and needs no reset (graph
+// replays hold no memset nodes).  The last workgroup to leave advances the
+// sweep counter t that the next launch reads.
+
+constexpr unsigned long long FUSED_SPIN_LIMIT = 1ull << 24;  // dependency polls before giving up
+
+struct FusedArgs {
+    TileArgs ta;                     // tile arrays and the batch tables (ta.b)
+    MergeArgs ma;
+    FlatArgs fa;
+    const int32_t *small_lat;        // [n_small] lattice of each whole-in-LDS item
+    const int32_t *ftile;            // [n_tiles] batch tile of each tile / flatten item
+    const int2 *mgroup;              // [n_mgroups] (first batch tile, number of tiles)
+    unsigned long long *ticket;      // queue position
+    unsigned long long *tiles_done;  // [nlat] tile items finished
+    unsigned long long *merge_done;  // [nlat] merge groups finished
+    unsigned long long *exit_ctr;    // workgroups finished
+    uint32_t *t;                     // sweep counter (the same word as ta.b.t)
+    int32_t *fault;                  // set when a dependency wait gave up (results invalid)
+    int32_t n_small, n_tiles, n_mgroups;
+};
+
+// Thread 0 waits until *p >= target with an acquire at agent scope; the
+// workgroup barrier then passes what it acquired on to the other waves.  On a
+// chip of several XCDs an agent-scope acquire invalidates the CU's L1 and the
+// XCD's L2, so it is taken once per item, by one thread.
+__device__ __forceinline__ void fused_wait(const unsigned long long *p, unsigned long long target, int32_t *fault)
+{
+    if (threadIdx.x == 0) {
+        for (unsigned long long k = 0;; ++k) {
+            if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            if (k == FUSED_SPIN_LIMIT) {
+                // a bounded wait: a broken invariant ends the launch instead of hanging it
+                __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+}
+
+// The workgroup barrier orders every wave's writes before thread 0's
+// agent-scope release, which publishes them with the count (a release writes
+// the XCD's L2 back, so it too is issued once per item).
+__device__ __forceinline__ void fused_signal(unsigned long long *p)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(p, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Lattices swept whole in LDS by a fused launch: at most this many sites (and
+// W <= SMALL_W, H <= SMALL_H), so their LDS (5 bytes a site) fits the tile
+// phase's budget per workgroup.
+template <int NT_>
+struct FusedSmall {
+    static constexpr int SITES = NT_ * 15 < 7680 ? NT_ * 15 : 7680;
+};
+
+template <int TH_>
+__global__ __launch_bounds__(Tile<TH_>::NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_batch_fused(FusedArgs a)
+{
+    using S = Tile<TH_>;
+    constexpr int NT = S::NT, NWAVE = S::NWAVE, SMALL = FusedSmall<NT>::SITES;
+    __shared__ union {
+        TileSmem<M_SW, TH_> tile;
+        FlatSmem<M_SW, false, TH_> flat;
+        SmallSmem<NT, SMALL> small;
+    } sm;
+    __shared__ unsigned long long ticket_s;
+    const uint32_t t = *a.t;  // every workgroup reads it before the last one leaves and advances it
+    const long long n_items = static_cast<long long>(a.n_small) + 2ll * a.n_tiles + a.n_mgroups;
+    const unsigned long long per_launch = static_cast<unsigned long long>(n_items) + gridDim.x;
+    unsigned long long base = 0, launch = 0;
+    for (bool first = true;; first = false) {
+        if (threadIdx.x == 0) ticket_s = __hip_atomic_fetch_add(a.ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const unsigned long long tk = uniform64(ticket_s);  // wave-uniform: the item's loads are scalar
+        __syncthreads();
+        if (first) {
+            launch = tk / per_launch;
+            base = launch * per_launch;
+        }
+        long long item = static_cast<long long>(tk - base);
+        if (item >= n_items) break;
+        if (item < a.n_small) {
+            const int j = __builtin_amdgcn_readfirstlane(a.small_lat[item]);
+            const LatticeDesc &L = a.ta.b.lat[j];
+            SmallArgs s{};
+            s.W = L.g.W;
+            s.H = L.g.H;
+            s.spins = L.spins;
+            s.bonds_out = L.bonds;
+            s.labels = L.labels;
+            s.hist = nullptr;
+            s.tile_act = a.ta.tile_act + L.tile0;
+            s.tile_ncl = a.fa.tile_ncl + L.tile0;
+            s.tm1 = L.tm1;
+            s.tany = L.tany;
+            s.k0 = L.k0;
+            s.k1 = L.k1;
+            s.sid = L.sid;
+            s.q = L.q;
+            s.t0 = t;
+            s.ising = L.ising;
+            s.n = 1;
+            small_body<NT, SMALL>(s, sm.small);
+            __syncthreads();  // the LDS is reused by the next item
+            continue;
+        }
+        item -= a.n_small;
+        if (item < a.n_tiles) {
+            const int tile = __builtin_amdgcn_readfirstlane(a.ftile[item]);
+            TileArgs ta = a.ta;
+            int lt;
+            load_batch_tile(ta, tile, lt);
+            if (ta.g.W % 2 == 0)
+                tile_body<M_SW, true, TH_>(ta, tile, lt, sm.tile);
+            else
+                tile_body<M_SW, false, TH_>(ta, tile, lt, sm.tile);
+            fused_signal(&a.tiles_done[a.ta.b.lat_of_tile[tile]]);
+            continue;
+        }
+        item -= a.n_tiles;
+        if (item < a.n_mgroups) {
+            const int2 g2 = a.mgroup[item];
+            const int2 grp = make_int2(__builtin_amdgcn_readfirstlane(g2.x), __builtin_amdgcn_readfirstlane(g2.y));
+            const int j = a.ta.b.lat_of_tile[grp.x];
+            const LatticeDesc &L = a.ta.b.lat[j];
+            fused_wait(&a.tiles_done[j], (launch + 1) * static_cast<unsigned long long>(L.g.ntiles), a.fault);
+            const int w = wave_id();
+            if (w < grp.y) merge_tile<true, TH_>(a.ma, grp.x + w);
+            fused_signal(&a.merge_done[j]);
+            continue;
+        }
+        item -= a.n_mgroups;
+        {
+            const int tile = __builtin_amdgcn_readfirstlane(a.ftile[item]);
+            const int j = a.ta.b.lat_of_tile[tile];
+            fused_wait(&a.merge_done[j], (launch + 1) * static_cast<unsigned long long>(a.ta.b.lat[j].nmerge),
+                       a.fault);
+            FlatArgs fa = a.fa;
+            int lt;
+            load_batch_flat(fa, tile, lt);
+            flatten_body<M_SW, false, TH_>(fa, tile, lt, sm.flat);
+            __syncthreads();  // the LDS is reused by the next item
+        }
+    }
+    (void)NWAVE;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long left = __hip_atomic_fetch_add(a.exit_ctr, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        if (left % gridDim.x == 0) __hip_atomic_store(a.t, t + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 }  // namespace swccl

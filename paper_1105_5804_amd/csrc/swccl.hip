@@ -59,6 +59,7 @@ struct Layout {
     size_t codes, gkey, gparent, gsize, edges, xbits, nb, tile_act, tile_ncl, stats;
     size_t row_count, row_off, scan_tmp, rl_slot, rl_size;
     size_t lat_desc, lat_of_tile, t_dev;  // batches only
+    size_t small_lat, ftile, mgroup, counters, fault;  // fused batch sweeps
     size_t total;
 };
 
@@ -154,6 +155,18 @@ Layout make_batch_layout(int64_t ntiles, int32_t nlat, int th, int mw)
     off += align_up(static_cast<size_t>(ntiles) * sizeof(int32_t));
     L.t_dev = off;
     off += align_up(sizeof(uint32_t));
+    // fused sweeps: the work-queue tables, then the counters (ticket, exit
+    // count, per-lattice tiles and merge groups done) and the fault flag
+    L.small_lat = off;
+    off += align_up(static_cast<size_t>(nlat) * sizeof(int32_t));
+    L.ftile = off;
+    off += align_up(static_cast<size_t>(ntiles) * sizeof(int32_t));
+    L.mgroup = off;
+    off += align_up(static_cast<size_t>(ntiles) * sizeof(int2));
+    L.counters = off;
+    off += align_up((2 + 2 * static_cast<size_t>(nlat)) * sizeof(unsigned long long));
+    L.fault = off;
+    off += align_up(sizeof(int32_t));
     L.total = off;
     return L;
 }
@@ -342,7 +355,7 @@ uint64_t sw_threshold(double K) { return threshold_of(K); }
 static int tile_h_of(const sw_params *p) { return p->tile_h ? p->tile_h : TH_DEFAULT; }
 static int merge_waves_of(const sw_params *p) { return p->merge_waves ? p->merge_waves : MERGE_WAVES_DEFAULT; }
 
-static sw_status check_params(const sw_params *p)
+static sw_status check_params(const sw_params *p, uint32_t extra_flags = 0)
 {
     if (!p) return SW_ERR_ARG;
     if (p->W < 2 || p->H < 2 || static_cast<int64_t>(p->W) * p->H >= (static_cast<int64_t>(1) << 31))
@@ -351,7 +364,8 @@ static sw_status check_params(const sw_params *p)
     if (p->spin_kind != SW_SPIN_ISING_I8 && p->spin_kind != SW_SPIN_POTTS_U8) return SW_ERR_ARG;
     if (p->spin_kind == SW_SPIN_ISING_I8 && p->q != 2) return SW_ERR_ARG;
     if (std::isnan(p->K)) return SW_ERR_ARG;
-    if (p->flags & ~static_cast<uint32_t>(SW_F_KEEP_SPINS | SW_F_SIZES | SW_F_REVERSE_TILES)) return SW_ERR_ARG;
+    if (p->flags & ~(static_cast<uint32_t>(SW_F_KEEP_SPINS | SW_F_SIZES | SW_F_REVERSE_TILES) | extra_flags))
+        return SW_ERR_ARG;
     if (p->tile_h != 0 && !valid_tile_h(p->tile_h)) return SW_ERR_ARG;
     if (p->merge_waves != 0 && !valid_merge_waves(p->merge_waves)) return SW_ERR_ARG;
     if (!valid_shape(p->W, p->H, 2, tile_h_of(p))) return SW_ERR_SIZE;
@@ -804,9 +818,15 @@ struct swb_batch {
     std::vector<uint64_t> T;
     std::vector<LatticeDesc> desc;     // host copies of what the device tables hold
     std::vector<int32_t> lat_of_tile;
+    std::vector<uint8_t> small;        // swept whole in LDS by the fused launch
+    std::vector<int32_t> small_lat, ftile;  // host copies of the fused work-queue tables
+    std::vector<int2> mgroup;
     Layout L;
     void *ws;
     int32_t tiles_even;  // tiles of even-width lattices come first
+    bool fused;          // one persistent launch per sweep (else one per phase)
+    int32_t grid;        // workgroups of the fused launch
+    int32_t n_small, n_ftiles, n_mgroups;
     uint64_t t;          // host mirror of the device sweep counter
     bool swept;
     // one sweep captured as a graph (swb_sweep_graph), made on first use
@@ -815,13 +835,72 @@ struct swb_batch {
     hipGraphExec_t exec = nullptr;
 };
 
+// The fused launch's work queue: lattices swept whole in LDS, then the tiles
+// of the others (largest lattice first), their merge groups (up to one tile
+// per wave of a workgroup) and, by the same table, their flattens; and the
+// grid: as many workgroups as the device holds at once (more would only wait).
+static sw_status build_fused_queue(swb_batch *h)
+{
+    const Layout &L = h->L;
+    const int n = h->n;
+    const int wg_threads = L.d.nt, nwave = L.d.th / RPW;
+    const int small_sites = std::min(15 * wg_threads, 7680);  // FusedSmall<NT>::SITES
+    try {
+        h->small.assign(static_cast<size_t>(n), 0);
+        std::vector<int32_t> order(static_cast<size_t>(n));
+        for (int j = 0; j < n; ++j) order[static_cast<size_t>(j)] = j;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return static_cast<int64_t>(h->p[a].W) * h->p[a].H > static_cast<int64_t>(h->p[b].W) * h->p[b].H;
+        });
+        for (const int j : order) {
+            const sw_params &q = h->p[static_cast<size_t>(j)];
+            LatticeDesc &d = h->desc[static_cast<size_t>(j)];
+            if (q.W <= SMALL_W && q.H <= SMALL_H && q.W * q.H <= small_sites) {
+                h->small[static_cast<size_t>(j)] = 1;
+                h->small_lat.push_back(j);
+                d.nmerge = 0;
+            }
+        }
+        for (const int j : order) {
+            if (h->small[static_cast<size_t>(j)]) continue;
+            LatticeDesc &d = h->desc[static_cast<size_t>(j)];
+            for (int k = 0; k < d.g.ntiles; ++k) h->ftile.push_back(d.tile0 + k);
+            int nm = 0;
+            for (int k = 0; k < d.g.ntiles; k += nwave, ++nm)
+                h->mgroup.push_back(make_int2(d.tile0 + k, std::min(nwave, d.g.ntiles - k)));
+            d.nmerge = nm;
+        }
+    } catch (const std::bad_alloc &) {
+        return SW_ERR_HOST_MEMORY;
+    }
+    h->n_small = static_cast<int32_t>(h->small_lat.size());
+    h->n_ftiles = static_cast<int32_t>(h->ftile.size());
+    h->n_mgroups = static_cast<int32_t>(h->mgroup.size());
+    int dev = 0, cus = 0, per_cu = 0;
+    sw_status st = device_status(hipGetDevice(&dev), "hipGetDevice");
+    if (st == SW_OK)
+        st = device_status(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+    if (st == SW_OK) {
+        hipError_t e = hipSuccess;
+        with_tile_h(L.d.th, [&](auto c) {
+            constexpr int TH = decltype(c)::value;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_fused<TH>, Tile<TH>::NT, 0);
+        });
+        st = device_status(e, "fused-sweep occupancy");
+    }
+    if (st != SW_OK) return st;
+    const int64_t items = static_cast<int64_t>(h->n_small) + 2 * static_cast<int64_t>(h->n_ftiles) + h->n_mgroups;
+    h->grid = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(items, static_cast<int64_t>(std::max(per_cu, 1)) * cus)));
+    return SW_OK;
+}
+
 static sw_status check_batch(const sw_params *p, const sw_buffers *b, int32_t n, int64_t *ntiles)
 {
     if (!p || !b || n < 1) return SW_ERR_ARG;
     int64_t nt = 0;
     const int th = tile_h_of(&p[0]);
     for (int32_t j = 0; j < n; ++j) {
-        const sw_status st = check_params(&p[j]);
+        const sw_status st = check_params(&p[j], SW_F_BATCH_FUSED);
         if (st != SW_OK) return st;
         if (p[j].flags & (SW_F_SIZES | SW_F_REVERSE_TILES)) return SW_ERR_UNSUPPORTED;
         // one tile shape and merge schedule per batch
@@ -905,7 +984,16 @@ sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int
     }
     for (int32_t j = 0; j < n; ++j) h->T[static_cast<size_t>(j)] = threshold_of(p[j].K);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    sw_status st = device_status(hipMemcpyAsync(at<LatticeDesc>(workspace, L.lat_desc), h->desc.data(),
+    h->fused = (p[0].flags & SW_F_BATCH_FUSED) != 0;
+    sw_status st = SW_OK;
+    if (h->fused) {
+        st = build_fused_queue(h);
+        if (st != SW_OK) {
+            delete h;
+            return st;
+        }
+    }
+    st = device_status(hipMemcpyAsync(at<LatticeDesc>(workspace, L.lat_desc), h->desc.data(),
                                                 h->desc.size() * sizeof(LatticeDesc), hipMemcpyHostToDevice, s),
                                  "copy lattice table");
     if (st == SW_OK)
@@ -915,6 +1003,35 @@ sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int
     if (st == SW_OK) {
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, at<int32_t>(workspace, L.t_dev), 1);
         st = launch_status("k_zero_i32");
+    }
+    if (st == SW_OK && h->fused) {
+        if (!h->small_lat.empty())
+            st = device_status(hipMemcpyAsync(at<int32_t>(workspace, L.small_lat), h->small_lat.data(),
+                                              h->small_lat.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+                               "copy small-lattice table");
+        if (st == SW_OK && !h->ftile.empty())
+            st = device_status(hipMemcpyAsync(at<int32_t>(workspace, L.ftile), h->ftile.data(),
+                                              h->ftile.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+                               "copy tile-item table");
+        if (st == SW_OK && !h->mgroup.empty())
+            st = device_status(hipMemcpyAsync(at<int2>(workspace, L.mgroup), h->mgroup.data(),
+                                              h->mgroup.size() * sizeof(int2), hipMemcpyHostToDevice, s),
+                               "copy merge-group table");
+        if (st == SW_OK) {
+            const int nc = 2 + 2 * n;
+            hipLaunchKernelGGL(k_zero_u64, dim3(static_cast<unsigned>(cdiv(nc, 256))), dim3(256), 0, s,
+                               at<unsigned long long>(workspace, L.counters), nc);
+            hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, at<int32_t>(workspace, L.fault), 1);
+            // every boundary-id parent a valid id and every tile's id count 0
+            // before the first sweep, so no read in a fused launch can leave
+            // the id tables, whatever it sees
+            const int nid = static_cast<int>(nt) * L.d.cap;
+            hipLaunchKernelGGL(k_iota_i32, dim3(static_cast<unsigned>(cdiv(nid, 256))), dim3(256), 0, s,
+                               at<int32_t>(workspace, L.gparent), nid);
+            hipLaunchKernelGGL(k_zero_i32, dim3(static_cast<unsigned>(cdiv(nt, 256))), dim3(256), 0, s,
+                               at<int32_t>(workspace, L.nb), static_cast<int>(nt));
+            st = launch_status("zero fused counters");
+        }
     }
     for (int32_t j = 0; j < n && st == SW_OK; ++j) {
         if (p[j].flags & SW_F_KEEP_SPINS) continue;
@@ -949,6 +1066,34 @@ void enqueue_batch_sweep(const swb_batch *h, hipStream_t s)
     bt.lat = at<LatticeDesc>(ws, L.lat_desc);
     bt.lat_of_tile = at<int32_t>(ws, L.lat_of_tile);
     bt.t = at<uint32_t>(ws, L.t_dev);
+    if (h->fused) {
+        FusedArgs fa{};
+        fa.ta = tile_args(L, ws, nullptr);
+        fa.ta.b = bt;
+        fa.ma = merge_args(L, ws);
+        fa.ma.b = bt;
+        fa.fa = flat_args(L, ws);
+        fa.fa.b = bt;
+        fa.small_lat = at<int32_t>(ws, L.small_lat);
+        fa.ftile = at<int32_t>(ws, L.ftile);
+        fa.mgroup = at<int2>(ws, L.mgroup);
+        unsigned long long *c = at<unsigned long long>(ws, L.counters);
+        fa.ticket = c;
+        fa.exit_ctr = c + 1;
+        fa.tiles_done = c + 2;
+        fa.merge_done = c + 2 + h->n;
+        fa.t = at<uint32_t>(ws, L.t_dev);
+        fa.fault = at<int32_t>(ws, L.fault);
+        fa.n_small = h->n_small;
+        fa.n_tiles = h->n_ftiles;
+        fa.n_mgroups = h->n_mgroups;
+        with_tile_h(L.d.th, [&](auto c2) {
+            constexpr int TH = decltype(c2)::value;
+            hipLaunchKernelGGL(k_batch_fused<TH>, dim3(static_cast<unsigned>(h->grid)), dim3(Tile<TH>::NT), 0, s,
+                               fa);
+        });
+        return;
+    }
     const int32_t total = L.g.ntiles, even = h->tiles_even;
     TileArgs ta = tile_args(L, ws, nullptr);
     ta.b = bt;
@@ -1048,10 +1193,23 @@ sw_status swb_observables(swb_batch *h, int32_t j, sw_obs *out, void *stream)
     if (!h || !out || j < 0 || j >= h->n) return SW_ERR_ARG;
     const Layout &L = h->L;
     const LatticeDesc &d = h->desc[static_cast<size_t>(j)];
-    return measure(h->p[static_cast<size_t>(j)], h->b[static_cast<size_t>(j)], h->swept,
-                   at<int32_t>(h->ws, L.tile_act) + d.tile0, at<int32_t>(h->ws, L.tile_ncl) + d.tile0, d.g.ntiles,
-                   at<unsigned long long>(h->ws, L.stats), nullptr, h->T[static_cast<size_t>(j)], h->t, out,
-                   static_cast<hipStream_t>(stream));
+    const bool in_lds = h->fused && h->small[static_cast<size_t>(j)];  // its counters are in its first tile
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const sw_status st = measure(h->p[static_cast<size_t>(j)], h->b[static_cast<size_t>(j)], h->swept,
+                                 at<int32_t>(h->ws, L.tile_act) + d.tile0, at<int32_t>(h->ws, L.tile_ncl) + d.tile0,
+                                 in_lds ? 1 : d.g.ntiles, at<unsigned long long>(h->ws, L.stats), nullptr,
+                                 h->T[static_cast<size_t>(j)], h->t, out, s);
+    if (st != SW_OK || !h->fused) return st;
+    int32_t fault = 0;
+    sw_status fs = device_status(hipMemcpyAsync(&fault, at<int32_t>(h->ws, L.fault), sizeof(fault),
+                                                hipMemcpyDeviceToHost, s), "copy fault flag");
+    if (fs == SW_OK) fs = device_status(hipStreamSynchronize(s), "sync");
+    if (fs != SW_OK) return fs;
+    if (fault) {
+        g_last_error = "fused batch sweep: a dependency wait gave up; the batch's results are invalid";
+        return SW_ERR_DEVICE;
+    }
+    return SW_OK;
 }
 
 sw_status swb_get_t(const swb_batch *h, uint64_t *t)

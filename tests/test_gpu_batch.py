@@ -33,8 +33,9 @@ MIX = [
 ]
 
 
-@pytest.mark.parametrize("tile", [{}, dict(tile_h=16, merge_waves=4), dict(tile_h=128, merge_waves=16)],
-                         ids=["default", "h16m4", "h128m16"])
+@pytest.mark.parametrize("tile", [{}, dict(tile_h=16, merge_waves=4), dict(tile_h=32), dict(tile_h=128, merge_waves=16),
+                                  dict(fused=True), dict(fused=True, tile_h=32, merge_waves=4)],
+                         ids=["phases", "phases-h16m4", "phases-h32", "phases-h128m16", "fused", "fused-h32m4"])
 def test_batch_mixed_parity(tile):
     specs = [dict(sp, stream_id=j) for j, sp in enumerate(MIX)]
     b = sw.SWBatch(specs, keep_labels=True, keep_bonds=True, **tile)
@@ -66,10 +67,11 @@ def test_batch_mixed_parity(tile):
     assert b.t == 3
 
 
-def test_batch256():
+@pytest.mark.parametrize("fused", [False, True], ids=["phases", "fused"])
+def test_batch256(fused):
     """The batched workload (256 Ising lattices, L = 32..1024): two sweeps, every lattice."""
     specs = wl.batch_specs()
-    b = sw.SWBatch(specs)
+    b = sw.SWBatch(specs, fused=fused)
     b.sweep(2)
     torch.cuda.synchronize()
     for j, sp in enumerate(b.specs):
@@ -83,12 +85,13 @@ def test_batch256():
             assert o["n_sat"] == rec[1, oracle.REC_NSAT], j
 
 
-def test_batch_graph_replays():
+@pytest.mark.parametrize("fused", [False, True], ids=["phases", "fused"])
+def test_batch_graph_replays(fused):
     """Sweeps replayed from a captured HIP graph, mixed with eager sweeps and
     with eager work and synchronisations between the replays: every sweep of
     every lattice matches the oracle."""
     specs = [dict(sp, stream_id=j) for j, sp in enumerate(MIX)]
-    b = sw.SWBatch(specs, keep_labels=True, keep_bonds=True)
+    b = sw.SWBatch(specs, keep_labels=True, keep_bonds=True, fused=fused)
     st = [oracle.init_states(sp["W"], sp["H"], sp["q"], sp["seed"], sp["stream_id"]) for sp in b.specs]
     for t, graph in enumerate([True, True, False, True, True]):
         print(f"batch graph replay t={t} graph={graph}", flush=True)

@@ -104,7 +104,8 @@ def test_potts16384_every_sweep(tile):
     _run_single("potts16384", tile)
 
 
-def test_batch256_checkpoints():
+@pytest.mark.parametrize("fused", [False, True], ids=["phases", "fused"])
+def test_batch256_checkpoints(fused):
     path = os.path.join(GOLDEN, "batch256.txt")
     if not os.path.exists(path):
         pytest.skip(f"{path} not written (tests/golden/make_sweep_records.py batch256)")
@@ -121,7 +122,7 @@ def test_batch256_checkpoints():
                 sp["W"], sp["H"], sp["K"], sp["seed"], sp["stream_id"]), j
             continue
         stored.setdefault(int(f[1]) + 1, {})[int(f[0])] = f[1:]  # by sweeps done
-    b = sw.SWBatch(specs, keep_labels=True, keep_bonds=True)
+    b = sw.SWBatch(specs, keep_labels=True, keep_bonds=True, fused=fused)
     done = 0
     for cp in sorted(stored):
         print(f"golden batch256: to sweep {cp}", flush=True)
