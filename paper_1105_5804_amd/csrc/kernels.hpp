@@ -137,15 +137,18 @@ __device__ __forceinline__ void lds_st(int *p, int v)
 
 // One step of a union of the trees holding a and b, with a straight-line body
 // (nested find/link loops cost more in exec-mask bookkeeping than in LDS
-// traffic).  A step climbs both nodes one level; when both are roots the
-// larger is linked below the smaller with an atomic min, so every root is the
-// minimum (local, hence global) index of its tree.  If the larger root had
-// meanwhile been linked elsewhere, the min leaves it below its old parent or
-// below the smaller root, and the union goes on with that old parent, so no
-// link is lost and every parent stays below its child.  done is set when the
-// two trees are one.  Entries only ever decrease, so a lane with nothing to
-// link applies min(P[a], P[a]-as-read), which changes nothing: every lane
-// issues the atomic and the step needs no branch.
+// traffic).  A step climbs both nodes two levels (parent, then grandparent);
+// when both are roots the larger is linked below the smaller with an atomic
+// min, so every root is the minimum (local, hence global) index of its tree.
+// If the larger root had meanwhile been linked elsewhere, the min leaves it
+// below its old parent or below the smaller root, and the union goes on with
+// that old parent, so no link is lost and every parent stays below its child.
+// done is set when the two trees are one.  A lane with nothing to link spends
+// its atomic on path halving: min(P[a], grandparent of a) points a at an
+// ancestor (entries only ever decrease), which is a no-op when a or its
+// parent is a root, so every lane issues the atomic and the step needs no
+// branch; the halving keeps the trees shallow for later steps and for the
+// compression that follows the unions.
 // With BYTES the node values are byte offsets of the entries (4 x index), so
 // a value is directly an LDS address.
 template <bool BYTES = false>
@@ -158,10 +161,11 @@ template <bool BYTES = false, bool SAME_PARENT = false>
 __device__ __forceinline__ void unite_step(int *P, int &a, int &b, int &done)
 {
     const int pa = lds_ld(lds_entry<BYTES>(P, a)), pb = lds_ld(lds_entry<BYTES>(P, b));
+    const int ga = lds_ld(lds_entry<BYTES>(P, pa)), gb = lds_ld(lds_entry<BYTES>(P, pb));
     const bool roots = pa == a && pb == b;
     const bool link = roots && a != b;
     const int hi = max(a, b), lo = min(a, b);
-    const int old = __hip_atomic_fetch_min(lds_entry<BYTES>(P, link ? hi : a), link ? lo : pa, __ATOMIC_RELAXED,
+    const int old = __hip_atomic_fetch_min(lds_entry<BYTES>(P, link ? hi : a), link ? lo : ga, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
     // with SAME_PARENT a common parent already makes one tree: the union ends
     // a step before both nodes reach the root (whose entry every finished
@@ -169,8 +173,8 @@ __device__ __forceinline__ void unite_step(int *P, int &a, int &b, int &done)
     // the site unions of the small-lattice kernel do not)
     // bitwise, not short-circuit: the flags stay lane masks (no selects)
     done = static_cast<int>((SAME_PARENT && pa == pb) | (roots & (!link | (old == hi))));
-    a = link ? old : pa;
-    b = link ? lo : pb;
+    a = link ? old : ga;
+    b = link ? lo : gb;
 }
 
 // ---- global union-find over boundary ids ----
@@ -532,9 +536,7 @@ __device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int 
         wave_lds_fence();
     };
     // wave-uniform lane masks
-    const uint64_t V0 = lanes_lt(lx0, tw), V1 = lanes_lt(lx1, tw);
-    const uint64_t L0 = lanes_eq(lx0, tw - 1), L1 = lanes_eq(lx1, tw - 1);  // last column
-    const EO valid = EO{V0, V1};
+    const EO valid = EO{lanes_lt(lx0, tw), lanes_lt(lx1, tw)};
 
     if (threadIdx.x == 0) nb_s = 0;  // first used after the barrier closing phase A
 
@@ -1279,7 +1281,7 @@ __global__ __launch_bounds__(NT) void k_scan_block(const int32_t *in, int32_t *o
     part[threadIdx.x] = sum;
     __syncthreads();
     for (int off = 1; off < NT; off <<= 1) {
-        const int32_t add = (threadIdx.x >= off) ? part[threadIdx.x - off] : 0;
+        const int32_t add = (static_cast<int>(threadIdx.x) >= off) ? part[threadIdx.x - off] : 0;
         __syncthreads();
         part[threadIdx.x] += add;
         __syncthreads();
