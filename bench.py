@@ -34,6 +34,7 @@ SWEEP_BYTES_PER_SITE = 10
 TILE_BYTES_PER_SITE = 5   # spin in (1) + label out (4)
 FLIP_BYTES_PER_SITE = 5   # label in (4) + spin out (1)
 CCL_BYTES_PER_SITE = 13   # input (1) + label write, read and canonical write (3 x 4)
+SERVE_BATCH_PX = 1 << 20  # the batched leg: requests of at most 1024^2 pixels share launches
 
 
 def _args():
@@ -78,7 +79,7 @@ def _profile(kernel: str):
     return None
 
 
-def _served(args, torch, sw, wl) -> dict:
+def _served(args, torch, sw, wl, batch_px: int = 0, closed_loop_only: bool = False) -> dict:
     """Open-loop image-segmentation requests through the labeling server.
 
     Pool buffers (one per occupancy level, i.i.d. pixels) sit in pinned host
@@ -104,7 +105,7 @@ def _served(args, torch, sw, wl) -> dict:
     flat = [p.view(-1) for p in pool]
     views = [flat[r["level"]][r["offset"]:r["offset"] + r["N"] * r["N"]].view(r["N"], r["N"]) for r in reqs]
     px = [r["N"] * r["N"] for r in reqs]
-    srv = sw.CCLServer(32 << 30, mode="sites_open", sizes=True, max_inflight=256, n_streams=8)
+    srv = sw.CCLServer(32 << 30, mode="sites_open", sizes=True, max_inflight=256, n_streams=8, batch_px=batch_px)
 
     def run(order, arrivals):
         lat = {}
@@ -126,6 +127,10 @@ def _served(args, torch, sw, wl) -> dict:
     nc = min(2000, len(reqs))
     _, tc = run(list(range(nc)), [0.0] * nc)
     cap = nc / tc
+    if closed_loop_only:
+        srv.close()
+        return {"batch_px": batch_px, "closed_loop_req_per_s": round(cap, 1),
+                "closed_loop_px_per_s": round(sum(px[:nc]) / tc, 1)}
     lam = 0.8 * cap
     arr, t = [], 0.0
     for r in reqs:
@@ -148,6 +153,7 @@ def _served(args, torch, sw, wl) -> dict:
     del dst
     return {"workload": f"{len(reqs)} site-percolation images, side 64..8192 log-uniform, p 0.40..0.70, "
                         f"Poisson arrivals at 0.8 x closed-loop capacity; H2D from pinned host memory included",
+            "batch_px": batch_px,
             "closed_loop_req_per_s": round(cap, 1),
             "closed_loop_px_per_s": round(sum(px[:nc]) / tc, 1),
             "offered_req_per_s": round(lam, 1),
@@ -596,6 +602,8 @@ def main() -> int:
     # ---- served labeling ----
     if not args.no_serve:
         out["served"] = _served(args, torch, sw, wl)
+        # continuous batching of the small requests: more throughput closed-loop
+        out["served"]["batched"] = _served(args, torch, sw, wl, batch_px=SERVE_BATCH_PX, closed_loop_only=True)
         torch.cuda.empty_cache()
 
     # ---- CPU oracle on the host cores: bounded samples of the same workloads ----

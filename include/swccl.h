@@ -357,7 +357,21 @@ sw_status ccl_label_noalloc(const uint8_t *in, int32_t W, int32_t H, int32_t mod
  * memory, not by a fixed slot size; a request that does not fit is refused
  * with SW_ERR_STATE and waits in the caller's queue until blocks are
  * released.  Requests go round-robin to the caller's streams, so copies and
- * labeling of different requests overlap.  The server allocates no device
+ * labeling of different requests overlap.
+ * Continuous batching: a request of at most batch_px pixels (and at most 128
+ * tiles of 128 x 64) joins an open batch instead of being labeled at once;
+ * ccl_server_flush, or the next ccl_server_poll or release of one of its
+ * requests, labels the batch with one launch per phase for all its requests
+ * (up to 256 requests and 8192 tiles; a fuller batch is flushed when the next
+ * request arrives), so small images share the fixed cost of a launch
+ * sequence.  Each request's results are those of ccl_label on it alone.
+ * New work goes to an idle stream when there is one (a single request never
+ * to the open batch's stream).  A batched image in pinned memory is pulled
+ * by a kernel rather than by the copy engines, so it does not queue behind
+ * the large copies of other requests.
+ * With batching, the front of the arena holds four batch tables per stream,
+ * and the server keeps their host copies in pinned host memory (its only
+ * allocation besides small host objects).  The server allocates no device
  * memory and is driven from one host thread. */
 typedef struct ccl_server ccl_server;
 typedef struct ccl_server_params {
@@ -365,6 +379,8 @@ typedef struct ccl_server_params {
     int32_t sizes;         /* 1: also roots and sizes per request, 0: labels  */
     int32_t max_inflight;  /* requests admitted at once, 1..4096              */
     int32_t n_streams;     /* streams passed to ccl_server_create, 1..64      */
+    int32_t batch_px;      /* batch requests of at most this many pixels; 0:
+                              label every request on its own at admission   */
 } ccl_server_params;
 
 /* Arena bytes one W x H request takes (0 if the shape or p is invalid). */
@@ -384,7 +400,11 @@ sw_status ccl_server_create(ccl_server **out, const ccl_server_params *p, void *
 sw_status ccl_server_submit(ccl_server *s, const uint8_t *image, int32_t W, int32_t H, size_t pitch, uint64_t tag,
                             int32_t *slot);
 
-/* Completed requests not reported before (non-blocking): up to max pairs
+/* Label the open batch now (asynchronous; no-op without one). */
+sw_status ccl_server_flush(ccl_server *s);
+
+/* Completed requests not reported before (non-blocking; flushes the open
+ * batch first): up to max pairs
  * (slot, tag) and their number *n.  On SW_ERR_DEVICE *n still counts the
  * pairs written before the request whose event query failed. */
 sw_status ccl_server_poll(ccl_server *s, int32_t *slots, uint64_t *tags, int32_t max, int32_t *n);

@@ -70,6 +70,7 @@ class CclServerParams(ctypes.Structure):
         ("sizes", ctypes.c_int32),
         ("max_inflight", ctypes.c_int32),
         ("n_streams", ctypes.c_int32),
+        ("batch_px", ctypes.c_int32),
     ]
 
 
@@ -120,6 +121,7 @@ SIGNATURES = {
                                            ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]),
     "ccl_server_submit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_size_t, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
+    "ccl_server_flush": (ctypes.c_int32, [ctypes.c_void_p]),
     "ccl_server_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32)]),

@@ -300,6 +300,18 @@ __global__ void k_zero_i32(int32_t *p, int n)
     if (i < n) p[i] = 0;
 }
 
+// Copy n bytes from host memory the device can read (pinned) into device
+// memory, in the compute queue: a small request's image and a batch's table
+// then never wait behind large copies queued on the copy engines.  4 bytes a
+// thread (byte loads: the source need not be aligned).
+__global__ __launch_bounds__(NT) void k_pull(uint8_t *dst, const uint8_t *src, int64_t n)
+{
+    const int64_t i = (static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x) * 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (i + j < n) dst[i + j] = src[i + j];
+}
+
 __global__ void k_iota_i32(int32_t *p, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1316,11 +1328,10 @@ struct EmitArgs {
 // Write each tile's roots (ascending site index within a row) at their global
 // positions; boundary clusters take their size from the global root id.
 template <int TH_>
-__global__ __launch_bounds__(NT) void k_emit(EmitArgs a)
+__device__ __forceinline__ void emit_body(const EmitArgs &a, const int tile)
 {
     constexpr int TH = Tile<TH_>::TH, TSITES = Tile<TH_>::TSITES;
     __shared__ int32_t rstart[TH + 1];
-    const int tile = xcd_remap(blockIdx.x, a.g.ntiles);
     const int tx = tile % a.g.ntx, ty = tile / a.g.ntx;
     const int gx0 = tx * TW, gy0 = ty * TH;
     const int th = min(TH, a.g.H - gy0);
@@ -1351,8 +1362,14 @@ __global__ __launch_bounds__(NT) void k_emit(EmitArgs a)
         mx = wave_max(mx);
         if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(a.max_size, mx);
     }
-    if (a.n_clusters && blockIdx.x == 0 && threadIdx.x == 0)
+    if (a.n_clusters && tile == 0 && threadIdx.x == 0)
         *a.n_clusters = a.row_off[static_cast<int64_t>(a.g.H) * a.g.ntx];
+}
+
+template <int TH_>
+__global__ __launch_bounds__(NT) void k_emit(EmitArgs a)
+{
+    emit_body<TH_>(a, xcd_remap(blockIdx.x, a.g.ntiles));
 }
 
 // ------------------------------------------------------- small lattices ---
@@ -1677,6 +1694,161 @@ __global__ __launch_bounds__(NT) void k_observe(const uint8_t *s, int W, int H, 
         add_stat(&out[slot], t);
     }
     (void)q;
+}
+
+// ------------------------------------------------ batched labeling requests --
+//
+// Many labeling requests (the served workload) in one launch per phase: each
+// request keeps its input, outputs and per-tile arrays in its own memory; the
+// launch's workgroups find their request through a tile -> request table, and
+// index the request's arrays with the tile's index inside the request.
+
+struct ReqDesc {
+    Grid g;
+    int32_t tile0;            // first tile of the request in the launch
+    const uint8_t *in;
+    int32_t *labels, *roots, *sizes, *n_clusters;  // roots / sizes nullptr without sizes
+    uint16_t *codes, *edges;
+    int32_t *gkey, *gparent, *gsize, *nb, *tile_ncl;
+    uint64_t *xbits;
+    int32_t *row_count, *row_off, *rl_slot, *rl_size;  // with sizes
+};
+
+struct ReqBatch {
+    const ReqDesc *req;
+    const int32_t *req_of_tile;  // launch tile -> request
+    int32_t ntiles;              // tiles of all requests
+};
+
+__device__ __forceinline__ const ReqDesc &req_of(const ReqBatch &rb, int t, int &lt)
+{
+    const ReqDesc &R = rb.req[rb.req_of_tile[t]];
+    lt = t - R.tile0;
+    return R;
+}
+
+template <int MODE, int TH_>
+__global__ __launch_bounds__(Tile<TH_>::NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_tile_reqs(ReqBatch rb)
+{
+    __shared__ TileSmem<MODE, TH_> sm;
+    int lt;
+    const ReqDesc &R = req_of(rb, xcd_remap(blockIdx.x, rb.ntiles), lt);
+    TileArgs a{};
+    a.g = R.g;
+    a.in = R.in;
+    a.codes = R.codes;
+    a.gkey = R.gkey;
+    a.gparent = R.gparent;
+    a.gsize = R.gsize;
+    a.edges = R.edges;
+    a.xbits = R.xbits;
+    a.nb = R.nb;
+    // any width: the odd-width form of the row loads serves even widths too
+    tile_body<MODE, false, TH_>(a, lt, lt, sm);
+}
+
+template <int TH_>
+__global__ __launch_bounds__(1024) void k_merge_reqs(ReqBatch rb)
+{
+    const int t = blockIdx.x * static_cast<int>(blockDim.x >> 6) + wave_id();
+    if (t >= rb.ntiles) return;
+    int lt;
+    const ReqDesc &R = req_of(rb, t, lt);
+    MergeArgs m{};
+    m.g = R.g;
+    m.edges = R.edges;
+    m.xbits = R.xbits;
+    m.gkey = R.gkey;
+    m.gparent = R.gparent;
+    merge_tile<false, TH_>(m, lt);
+}
+
+template <bool SIZES, int TH_>
+__global__ __launch_bounds__(Tile<TH_>::NT) void k_flatten_reqs(ReqBatch rb)
+{
+    __shared__ FlatSmem<M_BONDS_PERIODIC, SIZES, TH_> sm;
+    int lt;
+    const ReqDesc &R = req_of(rb, xcd_remap(blockIdx.x, rb.ntiles), lt);
+    FlatArgs f{};
+    f.g = R.g;
+    f.codes = R.codes;
+    f.gkey = R.gkey;
+    f.gparent = R.gparent;
+    f.nb = R.nb;
+    f.labels = R.labels;
+    f.tile_ncl = R.tile_ncl;
+    f.gsize = R.gsize;
+    f.row_count = R.row_count;
+    f.rl_slot = R.rl_slot;
+    f.rl_size = R.rl_size;
+    flatten_body<M_BONDS_PERIODIC, SIZES, TH_>(f, lt, lt, sm);
+}
+
+template <int TH_>
+__global__ __launch_bounds__(NT) void k_emit_reqs(ReqBatch rb)
+{
+    int lt;
+    const ReqDesc &R = req_of(rb, xcd_remap(blockIdx.x, rb.ntiles), lt);
+    EmitArgs e{};
+    e.g = R.g;
+    e.row_off = R.row_off;
+    e.rl_slot = R.rl_slot;
+    e.rl_size = R.rl_size;
+    e.gsize = R.gsize;
+    e.roots = R.roots;
+    e.sizes = R.sizes;
+    e.max_size = nullptr;
+    e.n_clusters = R.n_clusters;
+    emit_body<TH_>(e, lt);
+}
+
+// One workgroup per request: with sizes, the exclusive scan of the request's
+// per-(row, tile column) root counts (and their total, the cluster count,
+// which the emit writes); without, the cluster count as the sum of its tiles'.
+template <bool SIZES>
+__global__ __launch_bounds__(NT) void k_scan_reqs(const ReqDesc *req)
+{
+    const ReqDesc &R = req[blockIdx.x];
+    __shared__ int32_t part[NT];
+    if constexpr (SIZES) {
+        const int64_t n = static_cast<int64_t>(R.g.H) * R.g.ntx + 1;  // the closing slot is 0
+        int32_t carry = 0;
+        for (int64_t b0 = 0; b0 < n; b0 += SCAN_ITEMS) {
+            const int64_t base = b0 + static_cast<int64_t>(threadIdx.x) * 8;
+            int32_t v[8], sum = 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                v[j] = (base + j < n) ? R.row_count[base + j] : 0;
+                sum += v[j];
+            }
+            part[threadIdx.x] = sum;
+            __syncthreads();
+            for (int off = 1; off < NT; off <<= 1) {
+                const int32_t add = (static_cast<int>(threadIdx.x) >= off) ? part[threadIdx.x - off] : 0;
+                __syncthreads();
+                part[threadIdx.x] += add;
+                __syncthreads();
+            }
+            int32_t acc = carry + part[threadIdx.x] - sum;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (base + j < n) R.row_off[base + j] = acc;
+                acc += v[j];
+            }
+            carry += part[NT - 1];
+            __syncthreads();
+        }
+    } else {
+        int32_t acc = 0;
+        for (int k = threadIdx.x; k < R.g.ntiles; k += NT) acc += R.tile_ncl[k];
+        part[threadIdx.x] = acc;
+        __syncthreads();
+        for (int off = NT / 2; off > 0; off >>= 1) {
+            if (static_cast<int>(threadIdx.x) < off) part[threadIdx.x] += part[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && R.n_clusters) *R.n_clusters = part[0];
+    }
 }
 
 // ------------------------------------------------------ fused batch sweep ---

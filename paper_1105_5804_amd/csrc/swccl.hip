@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/swccl.h"
+#include "internal.hpp"
 #include "kernels.hpp"
 
 using namespace swccl;
@@ -1228,3 +1229,93 @@ sw_status swb_destroy(swb_batch *h)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------- batched labeling requests --
+
+namespace swccl_internal {
+
+int64_t request_tiles(int32_t W, int32_t H) { return cdiv(W, TW) * cdiv(H, TH_DEFAULT); }
+
+sw_status pull(void *dst, const void *src_dev, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return SW_OK;
+    hipLaunchKernelGGL(k_pull, dim3(static_cast<unsigned>(cdiv(n, static_cast<int64_t>(NT) * 4))), dim3(NT), 0, s,
+                       static_cast<uint8_t *>(dst), static_cast<const uint8_t *>(src_dev), n);
+    return launch_status("pull");
+}
+
+size_t batch_table_bytes(int32_t n, int64_t ntiles)
+{
+    return align_up(static_cast<size_t>(n) * sizeof(ReqDesc)) + align_up(static_cast<size_t>(ntiles) * sizeof(int32_t));
+}
+
+sw_status label_batch(const LabelRequest *r, int32_t n, int32_t mode, bool sizes, void *table, void *stage,
+                      size_t table_bytes, hipStream_t s)
+{
+    if (n < 1 || !r || !table || !stage) return SW_ERR_ARG;
+    int64_t nt = 0;
+    for (int32_t k = 0; k < n; ++k) nt += request_tiles(r[k].W, r[k].H);
+    const size_t desc_bytes = align_up(static_cast<size_t>(n) * sizeof(ReqDesc));
+    const size_t need = batch_table_bytes(n, nt);
+    if (need > table_bytes || nt >= (static_cast<int64_t>(1) << 31)) return SW_ERR_WORKSPACE;
+    std::memset(stage, 0, need);
+    ReqDesc *desc = static_cast<ReqDesc *>(stage);
+    int32_t *req_of_tile = reinterpret_cast<int32_t *>(static_cast<char *>(stage) + desc_bytes);
+    int32_t tile = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const Layout L = make_layout(r[k].W, r[k].H, sizes);
+        void *ws = r[k].ws;
+        ReqDesc &d = desc[k];
+        d.g = L.g;
+        d.tile0 = tile;
+        d.in = r[k].in;
+        d.labels = r[k].labels;
+        d.roots = sizes ? r[k].roots : nullptr;
+        d.sizes = sizes ? r[k].sizes : nullptr;
+        d.n_clusters = r[k].n_clusters;
+        d.codes = at<uint16_t>(ws, L.codes);
+        d.edges = at<uint16_t>(ws, L.edges);
+        d.gkey = at<int32_t>(ws, L.gkey);
+        d.gparent = at<int32_t>(ws, L.gparent);
+        d.gsize = sizes ? at<int32_t>(ws, L.gsize) : nullptr;
+        d.nb = at<int32_t>(ws, L.nb);
+        d.tile_ncl = at<int32_t>(ws, L.tile_ncl);
+        d.xbits = at<uint64_t>(ws, L.xbits);
+        d.row_count = sizes ? at<int32_t>(ws, L.row_count) : nullptr;
+        d.row_off = sizes ? at<int32_t>(ws, L.row_off) : nullptr;
+        d.rl_slot = sizes ? at<int32_t>(ws, L.rl_slot) : nullptr;
+        d.rl_size = sizes ? at<int32_t>(ws, L.rl_size) : nullptr;
+        for (int t = 0; t < L.g.ntiles; ++t) req_of_tile[tile + t] = k;
+        tile += L.g.ntiles;
+    }
+    // the table goes over by a kernel that reads the pinned stage: a copy-engine
+    // transfer would queue behind the large images other streams copy
+    void *dstage = nullptr;
+    if (const sw_status st = device_status(hipHostGetDevicePointer(&dstage, stage, 0), "stage device address"))
+        return st;
+    if (const sw_status st = pull(table, dstage, static_cast<int64_t>(need), s)) return st;
+    ReqBatch rb{};
+    rb.req = static_cast<const ReqDesc *>(table);
+    rb.req_of_tile = reinterpret_cast<const int32_t *>(static_cast<char *>(table) + desc_bytes);
+    rb.ntiles = tile;
+    constexpr int TH = TH_DEFAULT;
+    const dim3 tiles(static_cast<unsigned>(tile));
+    switch (mode) {
+    case CCL_BONDS_PERIODIC: hipLaunchKernelGGL((k_tile_reqs<M_BONDS_PERIODIC, TH>), tiles, dim3(Tile<TH>::NT), 0, s, rb); break;
+    case CCL_BONDS_OPEN: hipLaunchKernelGGL((k_tile_reqs<M_BONDS_OPEN, TH>), tiles, dim3(Tile<TH>::NT), 0, s, rb); break;
+    default: hipLaunchKernelGGL((k_tile_reqs<M_SITES, TH>), tiles, dim3(Tile<TH>::NT), 0, s, rb); break;
+    }
+    constexpr int MW = MERGE_WAVES_DEFAULT;
+    hipLaunchKernelGGL(k_merge_reqs<TH>, dim3(static_cast<unsigned>(cdiv(tile, MW))), dim3(64 * MW), 0, s, rb);
+    if (sizes) {
+        hipLaunchKernelGGL((k_flatten_reqs<true, TH>), tiles, dim3(Tile<TH>::NT), 0, s, rb);
+        hipLaunchKernelGGL(k_scan_reqs<true>, dim3(static_cast<unsigned>(n)), dim3(NT), 0, s, rb.req);
+        hipLaunchKernelGGL(k_emit_reqs<TH>, tiles, dim3(NT), 0, s, rb);
+    } else {
+        hipLaunchKernelGGL((k_flatten_reqs<false, TH>), tiles, dim3(Tile<TH>::NT), 0, s, rb);
+        hipLaunchKernelGGL(k_scan_reqs<false>, dim3(static_cast<unsigned>(n)), dim3(NT), 0, s, rb.req);
+    }
+    return launch_status("batched labeling");
+}
+
+}  // namespace swccl_internal

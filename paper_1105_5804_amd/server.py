@@ -27,16 +27,19 @@ class CCLServer:
     """Label host images (``(H, W)`` uint8 CPU tensors, ideally pinned) on the GPU.
 
     arena_bytes of device memory hold the requests in flight; ``sizes`` adds
-    the sorted roots and sizes of every request's clusters.
+    the sorted roots and sizes of every request's clusters.  Requests of at
+    most ``batch_px`` pixels are batched: those admitted between two pumps
+    (or polls) are labeled together, one launch per phase for all of them.
     """
 
     def __init__(self, arena_bytes: int, mode: str | int = "sites_open", sizes: bool = True,
-                 max_inflight: int = 256, n_streams: int = 4, device: str = "cuda"):
+                 max_inflight: int = 256, n_streams: int = 4, device: str = "cuda", batch_px: int = 0):
         torch = _torch()
         L = _lib.lib()
         self.mode = _MODES[mode] if isinstance(mode, str) else int(mode)
         self.sizes = bool(sizes)
-        self.params = _lib.CclServerParams(self.mode, 1 if sizes else 0, int(max_inflight), int(n_streams))
+        self.params = _lib.CclServerParams(self.mode, 1 if sizes else 0, int(max_inflight), int(n_streams),
+                                           int(batch_px))
         self.device = torch.device(device)
         # streams at the default priority
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
@@ -82,11 +85,15 @@ class CCLServer:
         if self._queue or not self._try_submit(tag, img):
             self._queue.append((tag, img, time.monotonic()))
 
+    def _flush(self) -> None:
+        _lib.check(_lib.lib().ccl_server_flush(self._h), "ccl_server_flush")
+
     def pump(self) -> list:
-        """Admit queued requests, in order, while they fit.  A queued request the
-        library refuses for any reason other than lack of room is dropped (so it
-        cannot block the requests behind it); returns the tags dropped by this
-        call, which are also appended, with their status, to ``rejected``."""
+        """Admit queued requests, in order, while they fit, then label the open
+        batch.  A queued request the library refuses for any reason other than
+        lack of room is dropped (so it cannot block the requests behind it);
+        returns the tags dropped by this call, which are also appended, with
+        their status, to ``rejected``."""
         dropped = []
         while self._queue:
             tag, img, _ = self._queue[0]
@@ -97,6 +104,7 @@ class CCLServer:
                 self.rejected.append((tag, e.status))
                 dropped.append(tag)
             self._queue.popleft()
+        self._flush()
         return dropped
 
     def cancel(self, tag: int) -> bool:

@@ -1,6 +1,7 @@
 """GPU parity of served labeling: every request's labels, roots and sizes equal
-the oracle's whether it runs alone or among others, and admission never puts
-more requests in flight than the arena holds."""
+the oracle's whether it runs alone or among others, on its own or in a batch
+of small requests labeled by shared launches (continuous batching), and
+admission never puts more requests in flight than the arena holds."""
 import numpy as np
 import pytest
 
@@ -36,8 +37,9 @@ SHAPES = [(1, 1), (1, 300), (300, 1), (2, 2), (127, 31), (128, 64), (129, 65), (
           (37, 1000), (700, 500), (1024, 1024)]
 
 
-def test_server_mix():
-    srv = sw.CCLServer(1 << 30, mode="sites_open", sizes=True, max_inflight=16, n_streams=3)
+@pytest.mark.parametrize("batch_px", [0, 1 << 20], ids=["unbatched", "batched"])
+def test_server_mix(batch_px):
+    srv = sw.CCLServer(1 << 30, mode="sites_open", sizes=True, max_inflight=16, n_streams=3, batch_px=batch_px)
     imgs = {}
     tag = 0
     for k, (W, H) in enumerate(SHAPES):
@@ -97,8 +99,9 @@ def test_identical_alone_and_in_mix():
     srv.close()
 
 
-def test_server_bonds_mode():
-    srv = sw.CCLServer(1 << 28, mode="bonds_periodic", sizes=False, max_inflight=4, n_streams=2)
+@pytest.mark.parametrize("batch_px", [0, 1 << 20], ids=["unbatched", "batched"])
+def test_server_bonds_mode(batch_px):
+    srv = sw.CCLServer(1 << 28, mode="bonds_periodic", sizes=False, max_inflight=4, n_streams=2, batch_px=batch_px)
     imgs = {t: wl.random_bonds(300 + t, 170, 0.5, seed=7000 + t) for t in range(5)}
     for t, img in imgs.items():
         srv.submit(t, _pinned(img))
@@ -114,4 +117,48 @@ def test_server_bonds_mode():
         H, W = img.shape
         want, n = oracle.label_bonds(W, H, img.reshape(-1), oracle.PERIODIC)
         assert got[t][1] == n and np.array_equal(got[t][0], want), t
+    srv.close()
+
+
+def test_identical_alone_and_in_batched_mix():
+    """Continuous batching with an 8192^2 image in the mix: the big image
+    (labeled on its own) and a small one (in a batch) give the same results
+    alone and among 30 others arriving around them, and every request of the
+    mix equals the oracle."""
+    srv = sw.CCLServer(6 << 30, sizes=True, max_inflight=64, n_streams=4, batch_px=1 << 20)
+    big = wl.site_image(8192, 8192, 0.5927, seed=6500)
+    small = wl.site_image(700, 500, 0.6, seed=6501)
+    print("served 8192^2 alone", flush=True)
+    srv.submit(0, _pinned(big))
+    srv.submit(1, _pinned(small))
+    alone = _drain(srv)
+    imgs = {2: big, 3: small}
+    for i in range(30):
+        W, H = SHAPES[i % len(SHAPES)]
+        imgs[100 + i] = wl.site_image(W, H, 0.4 + 0.01 * i, seed=6600 + i)
+    order = [100 + i for i in range(12)] + [2] + [100 + i for i in range(12, 20)] + [3] + \
+        [100 + i for i in range(20, 30)]
+    print("served mix with batching", flush=True)
+    for k, t in enumerate(order):
+        srv.submit(t, _pinned(imgs[t]))
+        if k % 7 == 6:
+            srv.pump()  # batches of those admitted so far
+    # a view into a pinned buffer at an odd offset (as the bench's pooled requests are)
+    buf = torch.zeros(3 + 300 * 200 + 5, dtype=torch.uint8).pin_memory()
+    img_v = wl.site_image(300, 200, 0.59, seed=6700)
+    buf[3:3 + 300 * 200] = torch.from_numpy(img_v.reshape(-1))
+    imgs[300] = img_v
+    srv.submit(300, buf[3:3 + 300 * 200].view(200, 300))
+    mixed = _drain(srv)
+    for a, m in ((0, 2), (1, 3)):
+        assert alone[a][3] == mixed[m][3]
+        for j in range(3):
+            assert np.array_equal(alone[a][j], mixed[m][j]), (a, j)
+    for t, img in imgs.items():
+        H, W = img.shape
+        want, n = oracle.label_sites(W, H, img.reshape(-1))
+        lab, roots, sizes, ng = mixed[t]
+        assert ng == n and np.array_equal(lab, want), t
+        r_ref, s_ref, _ = oracle.cluster_sizes(want)
+        assert np.array_equal(roots, r_ref) and np.array_equal(sizes, s_ref), t
     srv.close()

@@ -36,6 +36,12 @@ def _server(capacity):
         return True
 
     srv._try_submit = try_submit
+    srv.flushes = 0
+
+    def flush():
+        srv.flushes += 1
+
+    srv._flush = flush
     return srv
 
 
@@ -51,7 +57,7 @@ def test_fifo_admission():
     assert srv.pending == 5
     srv.room = 1
     srv.pump()
-    assert srv.admitted == [0, 1, 2]
+    assert srv.admitted == [0, 1, 2] and srv.flushes == 1  # the batch admitted so far is labeled
     srv.submit(5, _img())  # the queue is not empty: a new request waits behind it
     assert srv.admitted == [0, 1, 2] and [q[0] for q in srv._queue] == [3, 4, 5]
     srv.room = 10
