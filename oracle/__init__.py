@@ -23,7 +23,7 @@ _SRC = os.path.join(_HERE, "swccl_oracle.c")
 _HDR = os.path.join(_HERE, "swccl_oracle.h")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-TAG_INIT, TAG_BOND, TAG_FLIP = 0, 1, 2
+TAG_INIT, TAG_BOND, TAG_FLIP, TAG_SEED, TAG_FEW = 0, 1, 2, 3, 4
 PERIODIC, OPEN = 0, 1
 REC_ACTIVE, REC_NCLUST, REC_MAXCL, REC_NSAT, REC_COUNTS, REC_LEN = 0, 1, 2, 3, 4, 12
 
@@ -125,6 +125,13 @@ def _declare(lib):
     lib.orc_sw_run.argtypes = [c_i32, c_i32, c_i32, c_u64, c_u64, c_u32, c_u32, c_i32,
                                u8p, i64p]
     lib.orc_sw_run.restype = None
+    lib.orc_prob_threshold.argtypes = [ctypes.c_double]
+    lib.orc_prob_threshold.restype = c_u64
+    lib.orc_few_seeds.argtypes = [c_i32, c_i32, c_i32, c_u64, c_u32, c_u32, i32p]
+    lib.orc_few_seeds.restype = c_i64
+    lib.orc_few_sweep.argtypes = [c_i32, c_i32, c_u64, c_u64, c_i32, c_u64, c_u32, c_u32,
+                                  u8p, u8p, i32p, i64p, i64p]
+    lib.orc_few_sweep.restype = None
     lib.orc_digest_u8.argtypes = [c_i64, u8p]
     lib.orc_digest_u8.restype = c_u64
     lib.orc_digest_i32.argtypes = [c_i64, i32p]
@@ -252,3 +259,31 @@ def sw_run(W, H, q, T, seed, sid, t0, n, state):
     rec = np.zeros((max(n, 1), REC_LEN), dtype=np.int64)
     _load().orc_sw_run(W, H, q, T, seed, sid, t0, n, _u8(st), _i64(rec))
     return st, rec[:n]
+
+
+# ------------------------------------------------------------- few-cluster --
+def prob_threshold(p: float) -> int:
+    """floor(p 2^32) for p in [0, 1): an event of probability p happens iff a
+    uniform 32-bit word is below it."""
+    return int(_load().orc_prob_threshold(float(p)))
+
+
+def few_seeds(W, H, B, seed, t, sid=0) -> np.ndarray:
+    """Seed sites of sweep t, one per B x B seed tile (tiles in raster order)."""
+    n = ((W + B - 1) // B) * ((H + B - 1) // B)
+    sites = np.zeros(max(n, 1), dtype=np.int32)
+    _load().orc_few_seeds(W, H, B, seed, t, sid, _i32(sites))
+    return sites[:n].copy()
+
+
+def few_sweep(W, H, T, Tflip, B, seed, sid, t, state):
+    """One few-cluster sweep of a q = 2 lattice; returns (new_state, bonds,
+    labels, record, (seeded clusters, flipped clusters))."""
+    st = np.array(state, dtype=np.uint8).reshape(-1)
+    bonds = np.zeros(W * H, dtype=np.uint8)
+    labels = np.zeros(W * H, dtype=np.int32)
+    rec = np.zeros(REC_LEN, dtype=np.int64)
+    few = np.zeros(2, dtype=np.int64)
+    _load().orc_few_sweep(W, H, T, Tflip, B, seed, sid, t, _u8(st), _u8(bonds), _i32(labels), _i64(rec),
+                          _i64(few))
+    return st, bonds, labels, rec, (int(few[0]), int(few[1]))

@@ -12,7 +12,10 @@
  *     Sec. II, Eqs. fortuin1-fortuin3;
  *   - the three steps of the SW update (activate bonds, identify connected
  *     components, draw a new state per component), Sec. II, enumerated steps;
- *   - union-and-find with roots as set representatives, Sec. II.B.2.
+ *   - union-and-find with roots as set representatives, Sec. II.B.2;
+ *   - the few-cluster variant of the Wolff update (Sec. III): the same bond
+ *     decomposition, one seed per seed tile, every distinct seeded cluster
+ *     flipped with a probability p_flip < 1.
  * Philox4x32-10 follows its published definition (Salmon, Moraes, Dror, Shaw,
  * "Parallel random numbers: as easy as 1, 2, 3", SC'11).
  */
@@ -320,6 +323,102 @@ void orc_sw_sweep(int32_t W, int32_t H, int32_t q, uint64_t T, uint64_t seed,
     orc_flip(W, H, q, l, seed, t, sid, state);
     if (rec) rec[ORC_REC_NSAT] = orc_satisfied(W, H, q, state, rec + ORC_REC_COUNTS);
 
+    if (!bonds) free(b);
+    if (!labels) free(l);
+}
+
+/* ---------------------------------------------------------- few-cluster -- */
+
+/* floor(p 2^32) for a probability p in [0, 1): an event of probability p
+ * happens iff a uniform 32-bit word is below it. */
+uint64_t orc_prob_threshold(double p)
+{
+    if (!(p > 0.0)) return 0;
+    double v = floor(ldexp(p, 32));
+    if (v >= 4294967295.0) return 4294967295ull;
+    return (uint64_t)v;
+}
+
+/* The seeds of the few-cluster variant (Sec. III): the lattice is cut into
+ * seed tiles of B x B sites (the last column and row of tiles may be
+ * narrower), tile j = ty * ceil(W / B) + tx, and each tile draws one site
+ * uniformly from its own sites: x from word 0 and y from word 1 of the block
+ * (j, t, SEED, sid), each as floor(w * extent / 2^32).  Returns the number of
+ * seed tiles; sites[j] receives tile j's seed. */
+int64_t orc_few_seeds(int32_t W, int32_t H, int32_t B, uint64_t seed, uint32_t t,
+                      uint32_t sid, int32_t *sites)
+{
+    int32_t ntx = (W + B - 1) / B, nty = (H + B - 1) / B;
+    for (int32_t ty = 0; ty < nty; ++ty) {
+        for (int32_t tx = 0; tx < ntx; ++tx) {
+            int32_t j = ty * ntx + tx;
+            int32_t bw = W - tx * B < B ? W - tx * B : B;
+            int32_t bh = H - ty * B < B ? H - ty * B : B;
+            uint32_t b[4];
+            block_for(seed, (uint32_t)j, t, ORC_TAG_SEED, sid, b);
+            int32_t x = tx * B + (int32_t)(((uint64_t)b[0] * (uint64_t)bw) >> 32);
+            int32_t y = ty * B + (int32_t)(((uint64_t)b[1] * (uint64_t)bh) >> 32);
+            sites[j] = y * W + x;
+        }
+    }
+    return (int64_t)ntx * nty;
+}
+
+/* One few-cluster sweep t of a q = 2 lattice in place (Sec. III).  Steps 1
+ * and 2 are those of the SW update; then every cluster that holds at least
+ * one seed is flipped (state -> 1 - state) iff the word of the block
+ * (r >> 2, t, FEW, sid) picked by r & 3 is below Tflip, r its canonical root:
+ * one draw per distinct cluster, however many seeds it holds.  few (may be
+ * NULL) receives the number of distinct seeded clusters and of flipped
+ * clusters. */
+void orc_few_sweep(int32_t W, int32_t H, uint64_t T, uint64_t Tflip, int32_t B,
+                   uint64_t seed, uint32_t sid, uint32_t t, uint8_t *state, uint8_t *bonds,
+                   int32_t *labels, int64_t *rec, int64_t *few)
+{
+    int64_t N = (int64_t)W * H;
+    uint8_t *b = bonds ? bonds : (uint8_t *)malloc((size_t)N);
+    int32_t *l = labels ? labels : (int32_t *)malloc((size_t)N * sizeof(int32_t));
+
+    orc_activate_bonds(W, H, state, T, seed, t, sid, b);
+    int64_t ncl = orc_label_bonds(W, H, b, ORC_PERIODIC, l);
+    if (rec) {
+        int64_t active = 0;
+        for (int64_t i = 0; i < N; ++i) active += (b[i] & 1) + ((b[i] >> 1) & 1);
+        int64_t mx = 0;
+        orc_cluster_sizes(N, l, NULL, NULL, &mx);
+        rec[ORC_REC_ACTIVE] = active;
+        rec[ORC_REC_NCLUST] = ncl;
+        rec[ORC_REC_MAXCL] = mx;
+    }
+
+    int64_t nseed = (int64_t)((W + B - 1) / B) * ((H + B - 1) / B);
+    int32_t *sites = (int32_t *)malloc((size_t)nseed * sizeof(int32_t));
+    uint8_t *seeded = (uint8_t *)calloc((size_t)N, 1);   /* per canonical root */
+    uint8_t *flipped = (uint8_t *)calloc((size_t)N, 1);  /* per canonical root */
+    orc_few_seeds(W, H, B, seed, t, sid, sites);
+    for (int64_t j = 0; j < nseed; ++j) seeded[l[sites[j]]] = 1;
+    int64_t n_seeded = 0, n_flipped = 0;
+    for (int64_t r = 0; r < N; ++r) {
+        if (!seeded[r]) continue;
+        ++n_seeded;
+        uint32_t w[4];
+        block_for(seed, (uint32_t)(r >> 2), t, ORC_TAG_FEW, sid, w);
+        if ((uint64_t)w[r & 3] < Tflip) {
+            flipped[r] = 1;
+            ++n_flipped;
+        }
+    }
+    for (int64_t i = 0; i < N; ++i)
+        if (flipped[l[i]]) state[i] = (uint8_t)(1 - state[i]);
+    if (few) {
+        few[0] = n_seeded;
+        few[1] = n_flipped;
+    }
+    if (rec) rec[ORC_REC_NSAT] = orc_satisfied(W, H, 2, state, rec + ORC_REC_COUNTS);
+
+    free(sites);
+    free(seeded);
+    free(flipped);
     if (!bonds) free(b);
     if (!labels) free(l);
 }

@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-enum { ORC_TAG_INIT = 0, ORC_TAG_BOND = 1, ORC_TAG_FLIP = 2 };
+enum { ORC_TAG_INIT = 0, ORC_TAG_BOND = 1, ORC_TAG_FLIP = 2, ORC_TAG_SEED = 3, ORC_TAG_FEW = 4 };
 enum { ORC_PERIODIC = 0, ORC_OPEN = 1 };
 
 /* Per-sweep record written by orc_sw_run (one row of ORC_REC_LEN int64). */
@@ -97,6 +97,19 @@ enum { ORC_DIGEST_TAG = 0xD16E57 };
 uint64_t orc_digest_u8(int64_t N, const uint8_t *a);
 uint64_t orc_digest_i32(int64_t N, const int32_t *a);
 
+/* floor(p 2^32) for p in [0, 1), clamped to [0, 2^32 - 1]. */
+uint64_t orc_prob_threshold(double p);
+/* Few-cluster variant (Sec. III): one seed per B x B seed tile of sweep t
+ * (tag SEED, counter word = tile index).  Returns the tile count. */
+int64_t orc_few_seeds(int32_t W, int32_t H, int32_t B, uint64_t seed, uint32_t t,
+                      uint32_t sid, int32_t *sites);
+/* One few-cluster sweep of a q = 2 lattice: SW bonds and clusters, then every
+ * distinct seeded cluster flips iff its root's FEW word is below Tflip.
+ * few[0] = distinct seeded clusters, few[1] = flipped clusters (few may be
+ * NULL); bonds, labels and rec as for orc_sw_sweep. */
+void orc_few_sweep(int32_t W, int32_t H, uint64_t T, uint64_t Tflip, int32_t B,
+                   uint64_t seed, uint32_t sid, uint32_t t, uint8_t *state, uint8_t *bonds,
+                   int32_t *labels, int64_t *rec, int64_t *few);
 /* n sweeps t0..t0+n-1, one record per sweep into rec[n][ORC_REC_LEN]. */
 void orc_sw_run(int32_t W, int32_t H, int32_t q, uint64_t T, uint64_t seed,
                 uint32_t sid, uint32_t t0, int32_t n, uint8_t *state, int64_t *rec);

@@ -104,6 +104,23 @@ def test_percolation_16384():
     assert abs(n / L**2 - (3 * np.sqrt(3) - 5) / 2) < 1e-3
 
 
+def test_sites_16384():
+    """Full-size image labeling: site percolation near its threshold (occupancy
+    0.5927), L = 16384, with sizes."""
+    L = 16384
+    img = wl.site_image(L, L, 0.5927, seed=wl.SEED_BASE | 0x516)
+    g = torch.from_numpy(img).cuda()
+    print("sites_open 16384^2 with sizes", flush=True)
+    lab, roots, sizes, n = sw.ccl_label(g, "sites_open", sizes=True)
+    want, nref = oracle.label_sites(L, L, img.reshape(-1))
+    assert n == nref
+    assert np.array_equal(lab.cpu().numpy().reshape(-1), want)
+    del lab
+    r_ref, s_ref, _ = oracle.cluster_sizes(want)
+    assert np.array_equal(roots.cpu().numpy(), r_ref)
+    assert np.array_equal(sizes.cpu().numpy(), s_ref)
+
+
 def test_percolation_16384_repeated():
     """Eight labelings of the same full-size input all equal the oracle (race guard)."""
     L = 16384
