@@ -47,6 +47,7 @@ def _args():
     ap.add_argument("--no-ccl", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-few", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--study", action="store_true",
                     help="instead of the bench line: sweep time and phases over couplings and q at L=16384")
@@ -347,6 +348,17 @@ def _cpu_baseline(cfg, wl) -> dict:
                          "sample": "the first 400 requests of the served mix (same sides and occupancies), one "
                                    "process per request; each labeling timed in its process (image generation "
                                    "excluded), aggregate = per-core rate x cores"}
+    # the few-cluster update: one sweep of the Ising L = 4096 lattice at beta_c, seed tiles of 64 x 64
+    Lf = 4096
+    stf = oracle.init_states(Lf, Lf, 2, wl.SEED_BASE | 0xF7)
+    c = time.perf_counter()
+    oracle.few_sweep(Lf, Lf, oracle.threshold(wl.K_ISING_C), oracle.prob_threshold(0.5), 64, wl.SEED_BASE | 0xF7,
+                     0, 0, stf)
+    dt = time.perf_counter() - c
+    del stf
+    out["few_cluster"] = {"ns_per_spin_per_sweep": round(dt * 1e9 / (Lf * Lf), 3), "cores": 1,
+                          "sample": f"one few-cluster sweep (64 x 64 seed tiles, p_flip 0.5) of an Ising "
+                                    f"{Lf}x{Lf} lattice at beta_c from its seeded start, single thread"}
     out["paper_cpu_context"] = {"ns_per_spin_per_sweep": {"q2_L8192_Core2_Q6700": 77.39, "q2_L16384_Xeon_E5620": 152.1,
                                                           "q3_L8192_Core2_Q6700": 70.73},
                                 "note": "serial CPU timings the paper lists beside its GPU ones (Table of results)"}
@@ -366,6 +378,38 @@ def _phase_times(torch, lat, steps, stream):
             evs[k][ph + 1].record(stream)
     torch.cuda.synchronize()
     return [float(np.mean([evs[k][p].elapsed_time(evs[k][p + 1]) for k in range(steps)])) for p in range(3)]
+
+
+def _few_cluster(args, torch, sw, wl, stream) -> dict:
+    """Few-cluster sweeps (one seed per B x B seed tile, p_flip = 1/2) of the
+    Ising L = 16384 lattice at beta_c for several B, with the SW sweep of the
+    same lattice beside them; phases timed as in the main leg."""
+    import numpy as np
+
+    L, K = 16384, wl.K_ISING_C
+    rows = []
+    for B in (0, 16, 64, 256):
+        lat = sw.SWLattice(L, L, q=2, K=K, seed=wl.SEED_BASE | 0xF7, few_b=B, p_flip=0.5)
+        lat.sweep(args.warmup)
+        torch.cuda.synchronize()
+        steps = max(5, args.steps // 2)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps * 3 + 1)]
+        evs[0].record(stream)
+        for k in range(steps):
+            for ph in range(3):
+                lat.sweep_phase(ph)
+                evs[k * 3 + ph + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = evs[0].elapsed_time(evs[-1]) / steps
+        ph = [float(np.mean([evs[k * 3 + p].elapsed_time(evs[k * 3 + p + 1]) for k in range(steps)]))
+              for p in range(3)]
+        rows.append({"update": "sw" if B == 0 else "few", "seed_tile": B, "ms_per_sweep": round(ms, 4),
+                     "ns_per_spin": round(ms * 1e6 / (L * L), 6), "tile_ms": round(ph[0], 4),
+                     "merge_ms": round(ph[1], 4), "seed_flip_ms": round(ph[2], 4)})
+        del lat
+        torch.cuda.empty_cache()
+    return {"workload": f"Ising {L}x{L} at beta_c, seeds on B x B seed tiles, p_flip 0.5 (B = 0: the SW sweep)",
+            "rows": rows}
 
 
 def _tile_scan(args) -> int:
@@ -598,6 +642,10 @@ def main() -> int:
                             "mean_energy_per_site": round(float(e.mean()), 6)}
         del lat, hist
         torch.cuda.empty_cache()
+
+    # ---- few-cluster update (Sec. III) on Ising L=16384 at beta_c, against the SW sweep ----
+    if not args.no_few:
+        out["few_cluster"] = _few_cluster(args, torch, sw, wl, stream)
 
     # ---- served labeling ----
     if not args.no_serve:

@@ -32,6 +32,12 @@
  *       bonds (tag 1): block(i>>1, t): right uses word 2(i&1), down 2(i&1)+1
  *       flip  (tag 2): a cluster with canonical root r takes
  *                      (block(r>>2, t)[r&3] * q) >> 32
+ *       seed  (tag 3): few-cluster update, seed tile j of edge B (raster
+ *                      order, ceil(W/B) per row, narrower at the edges):
+ *                      x = tx*B + (w0 * bw) >> 32, y = ty*B + (w1 * bh) >> 32
+ *                      with (w0, w1) words 0 and 1 of block(j, t)
+ *       few   (tag 4): a seeded cluster with canonical root r flips iff
+ *                      block(r>>2, t)[r&3] < floor(p_flip * 2^32)
  *   - a bond between equal spins is active iff its word r < T, with
  *     T = floor((1 - exp(-K)) * 2^32) computed on the host in double.
  *   - the canonical label of a cluster is the minimum site index in it.
@@ -64,7 +70,7 @@
 extern "C" {
 #endif
 
-#define SWCCL_ABI_VERSION 4
+#define SWCCL_ABI_VERSION 5
 
 typedef int32_t sw_status;
 enum {
@@ -128,6 +134,18 @@ typedef struct sw_params {
     int32_t merge_waves; /* merge schedule: tiles per merge workgroup (one
                            wave each), 4, 8 or 16, or 0 for the default 8;
                            results do not depend on it                      */
+    double p_flip;      /* few-cluster update only: flip probability of a
+                           seeded cluster, 0 <= p_flip < 1                  */
+    int32_t few_b;      /* 0: the SW update (every cluster draws a new
+                           state).  B >= 1: the few-cluster variant of the
+                           Wolff update (Sec. III; q = 2 only, single
+                           lattices only): SW bonds and clusters, then one
+                           seed per B x B seed tile, and every distinct
+                           cluster holding a seed flips (state -> 1 - state)
+                           with probability p_flip, one draw per cluster at
+                           its canonical root; only flipped sites are
+                           written                                          */
+    int32_t reserved;   /* must be 0                                        */
 } sw_params;
 
 /* Device buffers of one lattice.  All are row-major (i = y*W + x). */
@@ -196,7 +214,9 @@ sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, voi
 /* Enqueue n_sweeps SW sweeps t, t+1, ... (Sec. II, steps 1-3).  After the call
  * the spins hold the configuration after the last sweep; labels / bonds (if
  * given) hold that sweep's canonical labels / bond bytes, taken before its
- * flip.  n_sweeps = 0 is a no-op. */
+ * flip.  n_sweeps = 0 is a no-op.  With p->few_b > 0 each sweep is a
+ * few-cluster update instead (Sec. III): the same bonds and clusters, then
+ * the seeded clusters flip as described at sw_params.few_b. */
 sw_status sw_sweep(sw_lattice *h, int32_t n_sweeps, void *stream);
 
 /* Per-sweep records of sw_sweep_history (int64 each). */
@@ -261,7 +281,8 @@ sw_status sw_destroy(sw_lattice *h);
 typedef struct swb_batch swb_batch;
 
 /* Workspace bytes of a batch of n >= 1 lattices (0 if a parameter set is
- * invalid, or asks for SW_F_SIZES, which batches do not support). */
+ * invalid, or asks for SW_F_SIZES or the few-cluster update, which batches do
+ * not support). */
 size_t swb_workspace_bytes(const sw_params *p, int32_t n);
 
 /* Create a batch over n caller-owned lattices: p[j] and b[j] as for sw_init
@@ -269,7 +290,7 @@ size_t swb_workspace_bytes(const sw_params *p, int32_t n);
  * 256-byte aligned workspace of swb_workspace_bytes() bytes serves the whole
  * batch.  Draws the initial spins of every lattice without SW_F_KEEP_SPINS.
  * The arrays p and b are copied.  Errors as for sw_init; SW_ERR_UNSUPPORTED
- * for SW_F_SIZES. */
+ * for SW_F_SIZES and for few_b != 0. */
 sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int32_t n, void *workspace,
                    size_t workspace_bytes, void *stream);
 

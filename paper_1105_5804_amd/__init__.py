@@ -107,15 +107,20 @@ class SWLattice:
     ``reverse_tiles`` runs the tiles in the reverse order (a schedule check:
     every output is the same).  ``tile_h`` (16, 32, 64, 128; 0 = 64) and
     ``merge_waves`` (4, 8, 16; 0 = 8) choose the tile shape and merge schedule
-    (outputs do not depend on them; ``paper_1105_5804_amd.tune`` picks them).  The constructor enqueues on the current
-    stream; methods given another ``stream`` are ordered only with that
-    stream's work (synchronise the two as with any torch side stream).
+    (outputs do not depend on them; ``paper_1105_5804_amd.tune`` picks them).
+    ``few_b`` > 0 makes every sweep the few-cluster variant of the Wolff
+    update (Sec. III, q = 2): the SW bonds and clusters, one seed per
+    ``few_b`` x ``few_b`` seed tile, and every distinct seeded cluster flipped
+    with probability ``p_flip`` (0 <= p_flip < 1).  The constructor enqueues on
+    the current stream; methods given another ``stream`` are ordered only with
+    that stream's work (synchronise the two as with any torch side stream).
     """
 
     def __init__(self, W: int, H: int, q: int = 2, K: float | None = None, seed: int = 0,
                  stream_id: int = 0, ising: bool | None = None, keep_labels: bool = False,
                  keep_bonds: bool = False, sizes: bool = False, spins=None, t: int = 0,
-                 device: str = "cuda", reverse_tiles: bool = False, tile_h: int = 0, merge_waves: int = 0):
+                 device: str = "cuda", reverse_tiles: bool = False, tile_h: int = 0, merge_waves: int = 0,
+                 few_b: int = 0, p_flip: float = 0.0):
         torch = _torch()
         L = _lib.lib()
         if ising is None:
@@ -129,6 +134,8 @@ class SWLattice:
                           self.K, self.seed & (2**64 - 1), self.stream_id,
                           (_lib.SW_F_SIZES if sizes else 0) | (_lib.SW_F_REVERSE_TILES if reverse_tiles else 0),
                           int(tile_h), int(merge_waves))
+        p.few_b, p.p_flip = int(few_b), float(p_flip)
+        self.few_b, self.p_flip = int(few_b), float(p_flip)
         self.tile_h, self.merge_waves = int(tile_h) or 64, int(merge_waves) or 8
         ws = L.sw_workspace_bytes(ctypes.byref(p))
         if ws == 0:

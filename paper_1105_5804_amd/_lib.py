@@ -7,7 +7,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libswccl.so")
 
-ABI_VERSION = 4  # the SWCCL_ABI_VERSION these declarations follow
+ABI_VERSION = 5  # the SWCCL_ABI_VERSION these declarations follow
 
 # status codes
 SW_OK, SW_ERR_ARG, SW_ERR_SIZE, SW_ERR_WORKSPACE, SW_ERR_DEVICE, SW_ERR_STATE, SW_ERR_UNSUPPORTED, SW_ERR_HOST_MEMORY = range(8)
@@ -33,6 +33,9 @@ class SwParams(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("tile_h", ctypes.c_int32),
         ("merge_waves", ctypes.c_int32),
+        ("p_flip", ctypes.c_double),
+        ("few_b", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

@@ -70,8 +70,10 @@ constexpr int NWAVE = NT / 64;
 // The one-tile lattices that k_small sweeps whole in LDS: W <= 128, H <= 64.
 constexpr int SMALL_W = 128, SMALL_H = 64, SMALL_SITES = SMALL_W * SMALL_H;
 
-enum : uint32_t { TAG_INIT = 0, TAG_BOND = 1, TAG_FLIP = 2 };
-enum Mode : int { M_SW = 0, M_BONDS_PERIODIC = 1, M_BONDS_OPEN = 2, M_SITES = 3 };
+enum : uint32_t { TAG_INIT = 0, TAG_BOND = 1, TAG_FLIP = 2, TAG_SEED = 3, TAG_FEW = 4 };
+// M_FEW is a flatten mode only: the few-cluster update labels with M_SW's
+// tile and merge kernels and flips in k_flatten<M_FEW>.
+enum Mode : int { M_SW = 0, M_BONDS_PERIODIC = 1, M_BONDS_OPEN = 2, M_SITES = 3, M_FEW = 4 };
 
 // Observable counters (unsigned 64-bit, two's complement for signed values).
 enum { ST_ACTIVE = 0, ST_NCLUST = 1, ST_NSAT = 2, ST_MAGNET = 3, ST_COUNTS = 4, ST_DIGEST = 12, ST_LEN = 16 };
@@ -993,7 +995,63 @@ struct FlatArgs {
     uint32_t q, k0, k1, t, sid;
     int ising;
     Batch b;                  // batched launches only
+    // few-cluster flips (M_FEW)
+    const uint32_t *sel;      // [ntiles][CAP]: == stamp at the root id of a seeded boundary cluster
+    uint32_t stamp;           // this sweep's mark (t + 1)
+    uint32_t tflip;           // a seeded cluster flips iff its FEW word is below this
+    int few_b, few_ntx;       // seed tile edge, seed tiles per lattice row
 };
+
+// The seed of seed tile j (Sec. III, few-cluster variant): the lattice is cut
+// into few_b x few_b seed tiles (narrower at the right and bottom edges), j in
+// raster order, and each draws one of its own sites from the block
+// (j, t, SEED, sid): x from word 0, y from word 1, each floor(w * extent / 2^32).
+__device__ __forceinline__ void seed_site(int j, int W, int H, int B, int ntx, uint32_t t, uint32_t sid, uint32_t k0,
+                                          uint32_t k1, int &x, int &y)
+{
+    const int tx = j % ntx, ty = j / ntx;
+    const uint32_t bw = static_cast<uint32_t>(min(B, W - tx * B)), bh = static_cast<uint32_t>(min(B, H - ty * B));
+    const U4 b = philox4x32_10(static_cast<uint32_t>(j), t, TAG_SEED, sid, k0, k1);
+    x = tx * B + static_cast<int>((static_cast<uint64_t>(b.v0) * bw) >> 32);
+    y = ty * B + static_cast<int>((static_cast<uint64_t>(b.v1) * bh) >> 32);
+}
+
+// Whether the seeded cluster with canonical root R flips (one draw per
+// distinct cluster, Sec. III).
+__device__ __forceinline__ bool few_flips(uint32_t R, const FlatArgs &a)
+{
+    const U4 b = philox4x32_10(R >> 2, a.t, TAG_FEW, a.sid, a.k0, a.k1);
+    return pick(b, R & 3u) < a.tflip;
+}
+
+// Spin byte <-> state 0..q-1 (Ising bytes are -1 / +1 for states 0 / 1).
+__device__ __forceinline__ uint32_t state_of_byte(uint32_t v, int ising) { return ising ? (v == 1u ? 1u : 0u) : v; }
+
+// Boundary clusters that hold a seed: one thread per seed tile finds the
+// boundary id of its seed's cluster (a seed in an interior cluster is left to
+// the flatten of its tile) and marks the id's root with this sweep's stamp.
+struct SeedArgs {
+    Grid g;
+    const uint16_t *codes;
+    const int32_t *gparent;
+    uint32_t *sel;
+    uint32_t stamp, t, sid, k0, k1;
+    int few_b, few_ntx, nseed;
+};
+
+template <int TH_>
+__global__ __launch_bounds__(NT) void k_seed(SeedArgs a)
+{
+    using S = Tile<TH_>;
+    const int j = static_cast<int>(blockIdx.x) * NT + static_cast<int>(threadIdx.x);
+    if (j >= a.nseed) return;
+    int x, y;
+    seed_site(j, a.g.W, a.g.H, a.few_b, a.few_ntx, a.t, a.sid, a.k0, a.k1, x, y);
+    const int lt = (y / S::TH) * a.g.ntx + x / TW;
+    const int slot = (y % S::TH) * TW + x % TW;
+    const uint32_t code = a.codes[static_cast<int64_t>(lt) * S::TSITES + slot];
+    if (code < static_cast<uint32_t>(S::CAP)) a.sel[gfind(a.gparent, lt * S::CAP + static_cast<int>(code))] = a.stamp;
+}
 
 // New state of the cluster whose canonical root is R (Sec. II.D: one uniform
 // draw per cluster, here taken at the minimum site index).
@@ -1007,7 +1065,9 @@ __device__ __forceinline__ uint8_t flip_state(uint32_t R, const FlatArgs &a)
 template <int MODE, bool SIZES, int TH_>
 struct FlatSmem {
     static constexpr int TH = TH_, TSITES = TW * TH, CAP = 2 * (TW + TH), NWAVE = TH / RPW;
-    uint8_t ST[MODE == M_SW ? CAP + TSITES : 1];  // new state per code (boundary id or CAP + slot)
+    uint8_t ST[MODE == M_SW || MODE == M_FEW ? CAP + TSITES : 1];  // new state per code (boundary id or
+                                                                    // CAP + slot); M_FEW: FEW_KEEP = no change
+    uint32_t seedbits[MODE == M_FEW ? TSITES / 32 : 1];  // M_FEW: interior roots that hold a seed
     int32_t Rb[CAP];                              // canonical root (site index) per boundary id
     int32_t Gid[CAP];                             // root id per boundary id
     uint16_t rl[NWAVE][WLIST];                    // interior roots of each wave's rows
@@ -1032,8 +1092,11 @@ __device__ __forceinline__ void load_batch_flat(FlatArgs &a, int tile, int &lt)
     lt = tile - L.tile0;
 }
 
+constexpr uint8_t FEW_KEEP = 0xFF;
+
 // The flatten + flip of one tile (`tile` in the arrays, `lt` inside its
-// lattice), by a Tile<TH>::NT-thread workgroup.
+// lattice), by a Tile<TH>::NT-thread workgroup.  M_FEW flips only the seeded
+// clusters whose draw says so and writes only their sites.
 template <int MODE, bool SIZES, int TH_>
 __device__ __forceinline__ void flatten_body(FlatArgs a, const int tile, const int lt, FlatSmem<MODE, SIZES, TH_> &sm)
 {
@@ -1076,6 +1139,29 @@ __device__ __forceinline__ void flatten_body(FlatArgs a, const int tile, const i
         for (int k = threadIdx.x; k < TSITES; k += NT) Ci[k] = 0;
         for (int k = threadIdx.x; k < CAP; k += NT) Cb[k] = 0;
     }
+    if constexpr (MODE == M_FEW) {
+        // seeds of the seed tiles that overlap this tile; a seed inside the
+        // tile whose cluster is interior marks that cluster's root
+        for (int k = threadIdx.x; k < TSITES / 32; k += NT) sm.seedbits[k] = 0;
+        __syncthreads();
+        const int B = a.few_b;
+        const int sx0 = gx0 / B, sy0 = gy0 / B;
+        const int nsx = (gx0 + tw - 1) / B - sx0 + 1, nsy = (gy0 + th - 1) / B - sy0 + 1;
+        for (int k = threadIdx.x; k < nsx * nsy; k += NT) {
+            int x, y;
+            seed_site((sy0 + k / nsx) * a.few_ntx + sx0 + k % nsx, W, a.g.H, B, a.few_ntx, a.t, a.sid, a.k0, a.k1,
+                      x, y);
+            x -= gx0;
+            y -= gy0;
+            if (x < 0 || x >= tw || y < 0 || y >= th) continue;
+            const uint32_t code = a.codes[static_cast<int64_t>(tile) * TSITES + y * TW + x];
+            if (code >= static_cast<uint32_t>(CAP) && code != CODE_BG) {
+                const uint32_t slot = code - CAP;
+                atomicOr(&sm.seedbits[slot >> 5], 1u << (slot & 31u));
+            }
+        }
+        __syncthreads();
+    }
     uint32_t cc[RPW];
     const uint32_t *codes32 = reinterpret_cast<const uint32_t *>(a.codes + static_cast<int64_t>(tile) * TSITES);
 #pragma unroll
@@ -1098,6 +1184,17 @@ __device__ __forceinline__ void flatten_body(FlatArgs a, const int tile, const i
             const int slot = mylist[i];
             ST[CAP + slot] = flip_state(static_cast<uint32_t>((gy0 + (slot >> 7)) * W + gx0 + (slot & (TW - 1))), a);
         }
+    } else if constexpr (MODE == M_FEW) {
+        // a seeded interior cluster that flips takes the other state of its
+        // root (every site of a cluster has the same spin)
+        for (int i = lane; i < nroot; i += 64) {
+            const int slot = mylist[i];
+            const uint32_t R = static_cast<uint32_t>((gy0 + (slot >> 7)) * W + gx0 + (slot & (TW - 1)));
+            uint8_t v = FEW_KEEP;
+            if (((sm.seedbits[slot >> 5] >> (slot & 31)) & 1u) && few_flips(R, a))
+                v = static_cast<uint8_t>(1u - state_of_byte(a.spins[R], a.ising));
+            ST[CAP + slot] = v;
+        }
     }
     // boundary ids: the root and its key (the cluster's minimum site index),
     // loaded at the start
@@ -1116,6 +1213,15 @@ __device__ __forceinline__ void flatten_body(FlatArgs a, const int tile, const i
             Gid[k] = r;
             nbr += r == id;
             if constexpr (MODE == M_SW) ST[k] = flip_state(static_cast<uint32_t>(key), a);
+            if constexpr (MODE == M_FEW) {
+                // seeded iff its root carries this sweep's mark; the old state
+                // is read at the id's own tile-local root (a site of this tile,
+                // not yet written)
+                uint8_t v = FEW_KEEP;
+                if (a.sel[r] == a.stamp && few_flips(static_cast<uint32_t>(key), a))
+                    v = static_cast<uint8_t>(1u - state_of_byte(a.spins[bR[j]], a.ising));
+                ST[k] = v;
+            }
         }
     }
     {
@@ -1147,6 +1253,19 @@ __device__ __forceinline__ void flatten_body(FlatArgs a, const int tile, const i
             } else {
                 if (v0) a.spins[i0] = static_cast<uint8_t>(b0);
                 if (v1) a.spins[i0 + 1] = static_cast<uint8_t>(b1);
+            }
+        } else if constexpr (MODE == M_FEW) {
+            // only the sites of flipping clusters are written
+            const uint32_t st0 = ST[min(c0, static_cast<uint32_t>(NCODE - 1))];
+            const uint32_t st1 = ST[min(c1, static_cast<uint32_t>(NCODE - 1))];
+            const bool f0 = v0 && st0 != FEW_KEEP, f1 = v1 && st1 != FEW_KEEP;
+            const uint32_t b0 = a.ising ? (2u * st0 - 1u) & 0xFFu : st0;
+            const uint32_t b1 = a.ising ? (2u * st1 - 1u) & 0xFFu : st1;
+            if (f0 && f1 && !(i0 & 1)) {
+                *reinterpret_cast<uint16_t *>(a.spins + i0) = static_cast<uint16_t>(b0 | (b1 << 8));
+            } else {
+                if (f0) a.spins[i0] = static_cast<uint8_t>(b0);
+                if (f1) a.spins[i0 + 1] = static_cast<uint8_t>(b1);
             }
         }
         if (a.labels) {

@@ -61,6 +61,8 @@ struct Layout {
     size_t row_count, row_off, scan_tmp, rl_slot, rl_size;
     size_t lat_desc, lat_of_tile, t_dev;  // batches only
     size_t small_lat, ftile, mgroup, counters, fault;  // fused batch sweeps
+    size_t sel;  // few-cluster sweeps: per-root-id seed marks
+    bool few;
     size_t total;
 };
 
@@ -109,7 +111,8 @@ size_t carve_tiles(Layout &L, size_t nt)
     return off;
 }
 
-Layout make_layout(int32_t W, int32_t H, bool sizes, int th = TH_DEFAULT, int mw = MERGE_WAVES_DEFAULT)
+Layout make_layout(int32_t W, int32_t H, bool sizes, int th = TH_DEFAULT, int mw = MERGE_WAVES_DEFAULT,
+                   bool few = false)
 {
     Layout L{};
     L.d = dims_of(th);
@@ -137,6 +140,8 @@ Layout make_layout(int32_t W, int32_t H, bool sizes, int th = TH_DEFAULT, int mw
         L.rl_slot = take(nt * static_cast<size_t>(L.d.tsites) * sizeof(int32_t));
         L.rl_size = take(nt * static_cast<size_t>(L.d.tsites) * sizeof(int32_t));
     }
+    L.few = few;
+    if (few) L.sel = take(nt * static_cast<size_t>(L.d.cap) * sizeof(uint32_t));
     L.total = off;
     return L;
 }
@@ -327,6 +332,8 @@ struct sw_lattice {
     uint64_t t;
     bool swept;       // at least one sweep since init / set_t
     bool small_last;  // the last sweep ran in k_small (its counters are in tile 0 alone)
+    bool sel_stale;   // few-cluster: the seed marks must be cleared before the next flip
+    uint32_t tflip;   // few-cluster: floor(p_flip 2^32)
     int32_t next_phase;  // SW_PHASE_* expected next
 };
 
@@ -369,14 +376,29 @@ static sw_status check_params(const sw_params *p, uint32_t extra_flags = 0)
         return SW_ERR_ARG;
     if (p->tile_h != 0 && !valid_tile_h(p->tile_h)) return SW_ERR_ARG;
     if (p->merge_waves != 0 && !valid_merge_waves(p->merge_waves)) return SW_ERR_ARG;
+    if (p->reserved != 0 || p->few_b < 0) return SW_ERR_ARG;
+    if (p->few_b > 0 && (p->q != 2 || !(p->p_flip >= 0.0 && p->p_flip < 1.0))) return SW_ERR_ARG;
     if (!valid_shape(p->W, p->H, 2, tile_h_of(p))) return SW_ERR_SIZE;
     return SW_OK;
+}
+
+// floor(p 2^32) for a probability 0 <= p < 1.
+static uint32_t prob_threshold(double p)
+{
+    if (!(p > 0.0)) return 0;
+    const double v = std::floor(std::ldexp(p, 32));
+    return v >= 4294967295.0 ? 0xFFFFFFFFu : static_cast<uint32_t>(v);
+}
+
+static Layout layout_of(const sw_params *p)
+{
+    return make_layout(p->W, p->H, (p->flags & SW_F_SIZES) != 0, tile_h_of(p), merge_waves_of(p), p->few_b > 0);
 }
 
 size_t sw_workspace_bytes(const sw_params *p)
 {
     if (check_params(p) != SW_OK) return 0;
-    return make_layout(p->W, p->H, (p->flags & SW_F_SIZES) != 0, tile_h_of(p), merge_waves_of(p)).total;
+    return layout_of(p).total;
 }
 
 sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, void *stream)
@@ -387,7 +409,7 @@ sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, voi
     if (!b->spins) return SW_ERR_ARG;
     const bool sizes = (p->flags & SW_F_SIZES) != 0;
     if (sizes && (!b->roots || !b->sizes)) return SW_ERR_ARG;
-    const Layout L = make_layout(p->W, p->H, sizes, tile_h_of(p), merge_waves_of(p));
+    const Layout L = layout_of(p);
     if (!b->workspace || b->workspace_bytes < L.total) return SW_ERR_WORKSPACE;
     if (reinterpret_cast<uintptr_t>(b->workspace) % ALIGN) return SW_ERR_WORKSPACE;
     sw_lattice *h = new (std::nothrow) sw_lattice();
@@ -399,6 +421,8 @@ sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, voi
     h->T = threshold_of(p->K);
     h->t = 0;
     h->swept = false;
+    h->sel_stale = L.few;  // the workspace holds anything: clear the marks before the first flip
+    h->tflip = prob_threshold(p->p_flip);
     h->next_phase = SW_PHASE_TILE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t N = static_cast<int64_t>(p->W) * p->H;
@@ -416,6 +440,42 @@ sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, voi
     }
     *out = h;
     return SW_OK;
+}
+
+// Few-cluster sweeps: one thread per seed tile marks the root id of a seeded
+// boundary cluster with t + 1.  The marks are cleared first after init and
+// after sw_set_t (a sweep number may then come round again).
+static sw_status launch_seeds(sw_lattice *h, hipStream_t s)
+{
+    const Layout &L = h->L;
+    void *ws = h->b.workspace;
+    const int64_t nsel = L.g.ntiles * static_cast<int64_t>(L.d.cap);
+    if (h->sel_stale) {
+        hipLaunchKernelGGL(k_zero_i32, dim3(static_cast<unsigned>(cdiv(nsel, NT))), dim3(NT), 0, s,
+                           at<int32_t>(ws, L.sel), static_cast<int>(nsel));
+        const sw_status st = launch_status("k_zero_i32");
+        if (st != SW_OK) return st;
+        h->sel_stale = false;
+    }
+    SeedArgs sa{};
+    sa.g = L.g;
+    sa.codes = at<uint16_t>(ws, L.codes);
+    sa.gparent = at<int32_t>(ws, L.gparent);
+    sa.sel = at<uint32_t>(ws, L.sel);
+    sa.t = static_cast<uint32_t>(h->t);
+    sa.stamp = sa.t + 1u;
+    sa.sid = h->p.stream_id;
+    sa.k0 = static_cast<uint32_t>(h->p.seed);
+    sa.k1 = static_cast<uint32_t>(h->p.seed >> 32);
+    sa.few_b = h->p.few_b;
+    sa.few_ntx = static_cast<int>(cdiv(h->p.W, h->p.few_b));
+    const int64_t nseed = sa.few_ntx * cdiv(h->p.H, h->p.few_b);
+    sa.nseed = static_cast<int>(nseed);
+    with_tile_h(L.d.th, [&](auto c) {
+        constexpr int TH = decltype(c)::value;
+        hipLaunchKernelGGL(k_seed<TH>, dim3(static_cast<unsigned>(cdiv(nseed, NT))), dim3(NT), 0, s, sa);
+    });
+    return launch_status("k_seed");
 }
 
 // Enqueue one phase of sweep h->t.
@@ -450,6 +510,24 @@ static sw_status launch_phase(sw_lattice *h, int32_t phase, hipStream_t s)
     fa.t = t;
     fa.sid = h->p.stream_id;
     fa.ising = h->p.spin_kind == SW_SPIN_ISING_I8 ? 1 : 0;
+    if (L.few) {
+        // few-cluster flip: mark the boundary clusters that hold a seed, then
+        // flatten with the seeded clusters' flips
+        const sw_status st = launch_seeds(h, s);
+        if (st != SW_OK) return st;
+        fa.sel = at<uint32_t>(ws, L.sel);
+        fa.stamp = t + 1u;
+        fa.tflip = h->tflip;
+        fa.few_b = h->p.few_b;
+        fa.few_ntx = static_cast<int>(cdiv(h->p.W, h->p.few_b));
+        if (!L.sizes) {
+            launch_flatten<M_FEW, false, false>(L, fa, L.g.ntiles, s);
+            return launch_status("k_flatten");
+        }
+        launch_flatten<M_FEW, true, false>(L, fa, L.g.ntiles, s);
+        emit_sizes(L, ws, fa, h->b.roots, h->b.sizes, fa.row_count + L.nrow + 1, nullptr, s);
+        return launch_status("k_flatten");
+    }
     if (!L.sizes) {
         launch_flatten<M_SW, false, false>(L, fa, L.g.ntiles, s);
         return launch_status("k_flatten");
@@ -481,7 +559,7 @@ sw_status sw_sweep_phase(sw_lattice *h, int32_t phase, void *stream)
 // per-phase entry point keeps the tiled path; both give the same results).
 static bool small_path(const sw_lattice *h)
 {
-    return h->p.W <= SMALL_W && h->p.H <= SMALL_H && !h->L.sizes;
+    return h->p.W <= SMALL_W && h->p.H <= SMALL_H && !h->L.sizes && !h->L.few;
 }
 
 static sw_status launch_small(sw_lattice *h, int32_t n, int64_t *hist, hipStream_t s)
@@ -659,6 +737,7 @@ sw_status sw_set_t(sw_lattice *h, uint64_t t)
     if (t > 0xFFFFFFFFull || h->next_phase != SW_PHASE_TILE) return SW_ERR_STATE;
     h->t = t;
     h->swept = false;
+    h->sel_stale = h->L.few;
     return SW_OK;
 }
 
@@ -903,7 +982,7 @@ static sw_status check_batch(const sw_params *p, const sw_buffers *b, int32_t n,
     for (int32_t j = 0; j < n; ++j) {
         const sw_status st = check_params(&p[j], SW_F_BATCH_FUSED);
         if (st != SW_OK) return st;
-        if (p[j].flags & (SW_F_SIZES | SW_F_REVERSE_TILES)) return SW_ERR_UNSUPPORTED;
+        if ((p[j].flags & (SW_F_SIZES | SW_F_REVERSE_TILES)) || p[j].few_b != 0) return SW_ERR_UNSUPPORTED;
         // one tile shape and merge schedule per batch
         if (tile_h_of(&p[j]) != th || merge_waves_of(&p[j]) != merge_waves_of(&p[0])) return SW_ERR_ARG;
         if (!b[j].spins || b[j].roots || b[j].sizes) return SW_ERR_ARG;

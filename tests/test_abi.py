@@ -78,6 +78,43 @@ def test_bad_params_rejected(kw):
     assert st in (_lib.SW_ERR_ARG, _lib.SW_ERR_SIZE)
 
 
+def _few(p, few_b, p_flip, reserved=0):
+    p.few_b, p.p_flip, p.reserved = few_b, p_flip, reserved
+    return p
+
+
+@pytest.mark.parametrize("kw,few_b,p_flip,reserved", [
+    (dict(q=3, kind=1), 8, 0.5, 0),  # q = 2 only
+    (dict(), 8, 1.0, 0),             # p_flip < 1 (else not ergodic)
+    (dict(), 8, -0.1, 0),
+    (dict(), 8, float("nan"), 0),
+    (dict(), -1, 0.5, 0),
+    (dict(), 0, 0.0, 1),             # reserved must be 0
+])
+def test_bad_few_params_rejected(kw, few_b, p_flip, reserved):
+    L = _lib.lib()
+    p = _few(_params(**kw), few_b, p_flip, reserved)
+    assert L.sw_workspace_bytes(ctypes.byref(p)) == 0
+    h = ctypes.c_void_p()
+    buf = _bufs(0x1000, 0x100000, 1 << 30)
+    assert L.sw_init(ctypes.byref(h), ctypes.byref(p), ctypes.byref(buf), None) == _lib.SW_ERR_ARG
+
+
+def test_few_params_sized_and_kept_out_of_batches():
+    """The few-cluster update takes its seed marks (4 B per boundary id) on
+    top of the SW workspace; batches refuse it."""
+    L = _lib.lib()
+    for kind in (0, 1):
+        base = L.sw_workspace_bytes(ctypes.byref(_params(W=1000, H=700, kind=kind)))
+        few = L.sw_workspace_bytes(ctypes.byref(_few(_params(W=1000, H=700, kind=kind), 16, 0.5)))
+        ntiles = -(-1000 // 128) * -(-700 // 64)
+        assert few >= base + ntiles * 384 * 4
+    assert L.sw_workspace_bytes(ctypes.byref(_few(_params(), 1, 0.0))) > 0
+    assert L.sw_workspace_bytes(ctypes.byref(_few(_params(), 10**6, 0.999))) > 0
+    P = (_lib.SwParams * 1)(_few(_params(), 8, 0.5))
+    assert L.swb_workspace_bytes(P, 1) == 0
+
+
 def test_good_params_sized():
     L = _lib.lib()
     for W, H in [(2, 2), (64, 64), (4096, 4096), (16384, 16384), (3, 1000)]:
