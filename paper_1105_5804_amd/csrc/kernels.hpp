@@ -997,9 +997,9 @@ struct FlatArgs {
     Batch b;                  // batched launches only
     // few-cluster flips (M_FEW)
     const uint32_t *sel;      // [ntiles][CAP]: == stamp at the root id of a seeded boundary cluster
+    uint32_t *seedmap;        // [ntiles][TSITES / 32]: interior roots that hold a seed (cleared here)
     uint32_t stamp;           // this sweep's mark (t + 1)
     uint32_t tflip;           // a seeded cluster flips iff its FEW word is below this
-    int few_b, few_ntx;       // seed tile edge, seed tiles per lattice row
 };
 
 // The seed of seed tile j (Sec. III, few-cluster variant): the lattice is cut
@@ -1027,14 +1027,16 @@ __device__ __forceinline__ bool few_flips(uint32_t R, const FlatArgs &a)
 // Spin byte <-> state 0..q-1 (Ising bytes are -1 / +1 for states 0 / 1).
 __device__ __forceinline__ uint32_t state_of_byte(uint32_t v, int ising) { return ising ? (v == 1u ? 1u : 0u) : v; }
 
-// Boundary clusters that hold a seed: one thread per seed tile finds the
-// boundary id of its seed's cluster (a seed in an interior cluster is left to
-// the flatten of its tile) and marks the id's root with this sweep's stamp.
+// Clusters that hold a seed: one thread per seed tile finds the code of its
+// seed's site.  A boundary cluster is marked at its root id with this sweep's
+// stamp; an interior cluster by the bit of its root slot in its tile's seed
+// map, which the flatten of that tile reads and clears.
 struct SeedArgs {
     Grid g;
     const uint16_t *codes;
     const int32_t *gparent;
     uint32_t *sel;
+    uint32_t *seedmap;
     uint32_t stamp, t, sid, k0, k1;
     int few_b, few_ntx, nseed;
 };
@@ -1050,7 +1052,12 @@ __global__ __launch_bounds__(NT) void k_seed(SeedArgs a)
     const int lt = (y / S::TH) * a.g.ntx + x / TW;
     const int slot = (y % S::TH) * TW + x % TW;
     const uint32_t code = a.codes[static_cast<int64_t>(lt) * S::TSITES + slot];
-    if (code < static_cast<uint32_t>(S::CAP)) a.sel[gfind(a.gparent, lt * S::CAP + static_cast<int>(code))] = a.stamp;
+    if (code < static_cast<uint32_t>(S::CAP)) {
+        a.sel[gfind(a.gparent, lt * S::CAP + static_cast<int>(code))] = a.stamp;
+    } else {
+        const uint32_t root = code - S::CAP;
+        atomicOr(&a.seedmap[static_cast<int64_t>(lt) * (S::TSITES / 32) + (root >> 5)], 1u << (root & 31u));
+    }
 }
 
 // New state of the cluster whose canonical root is R (Sec. II.D: one uniform
@@ -1067,7 +1074,6 @@ struct FlatSmem {
     static constexpr int TH = TH_, TSITES = TW * TH, CAP = 2 * (TW + TH), NWAVE = TH / RPW;
     uint8_t ST[MODE == M_SW || MODE == M_FEW ? CAP + TSITES : 1];  // new state per code (boundary id or
                                                                     // CAP + slot); M_FEW: FEW_KEEP = no change
-    uint32_t seedbits[MODE == M_FEW ? TSITES / 32 : 1];  // M_FEW: interior roots that hold a seed
     int32_t Rb[CAP];                              // canonical root (site index) per boundary id
     int32_t Gid[CAP];                             // root id per boundary id
     uint16_t rl[NWAVE][WLIST];                    // interior roots of each wave's rows
@@ -1075,6 +1081,7 @@ struct FlatSmem {
     int32_t Ci[SIZES ? TSITES : 1];               // sizes of interior clusters
     int32_t Cb[SIZES ? CAP : 1];                  // per-tile part of boundary clusters
     int32_t rowc[TH + 1];
+    uint32_t seedw_s[MODE == M_FEW ? NWAVE : 1][32];  // M_FEW: seed-map words of each wave's rows
 };
 
 __device__ __forceinline__ void load_batch_flat(FlatArgs &a, int tile, int &lt)
@@ -1139,28 +1146,16 @@ __device__ __forceinline__ void flatten_body(FlatArgs a, const int tile, const i
         for (int k = threadIdx.x; k < TSITES; k += NT) Ci[k] = 0;
         for (int k = threadIdx.x; k < CAP; k += NT) Cb[k] = 0;
     }
+    // M_FEW: the seed-map words of this wave's rows (RPW * TW / 32 = 32 of
+    // them, word l in lane l), cleared for the next sweep
+    uint32_t seedw = 0;
     if constexpr (MODE == M_FEW) {
-        // seeds of the seed tiles that overlap this tile; a seed inside the
-        // tile whose cluster is interior marks that cluster's root
-        for (int k = threadIdx.x; k < TSITES / 32; k += NT) sm.seedbits[k] = 0;
-        __syncthreads();
-        const int B = a.few_b;
-        const int sx0 = gx0 / B, sy0 = gy0 / B;
-        const int nsx = (gx0 + tw - 1) / B - sx0 + 1, nsy = (gy0 + th - 1) / B - sy0 + 1;
-        for (int k = threadIdx.x; k < nsx * nsy; k += NT) {
-            int x, y;
-            seed_site((sy0 + k / nsx) * a.few_ntx + sx0 + k % nsx, W, a.g.H, B, a.few_ntx, a.t, a.sid, a.k0, a.k1,
-                      x, y);
-            x -= gx0;
-            y -= gy0;
-            if (x < 0 || x >= tw || y < 0 || y >= th) continue;
-            const uint32_t code = a.codes[static_cast<int64_t>(tile) * TSITES + y * TW + x];
-            if (code >= static_cast<uint32_t>(CAP) && code != CODE_BG) {
-                const uint32_t slot = code - CAP;
-                atomicOr(&sm.seedbits[slot >> 5], 1u << (slot & 31u));
-            }
+        static_assert(RPW * TW / 32 == 32, "one seed-map word per lane of the lower half");
+        if (lane < 32) {
+            uint32_t *w = a.seedmap + static_cast<int64_t>(tile) * (TSITES / 32) + ly0 * (TW / 32) + lane;
+            seedw = *w;
+            if (seedw) *w = 0u;
         }
-        __syncthreads();
     }
     uint32_t cc[RPW];
     const uint32_t *codes32 = reinterpret_cast<const uint32_t *>(a.codes + static_cast<int64_t>(tile) * TSITES);
@@ -1186,13 +1181,22 @@ __device__ __forceinline__ void flatten_body(FlatArgs a, const int tile, const i
         }
     } else if constexpr (MODE == M_FEW) {
         // a seeded interior cluster that flips takes the other state of its
-        // root (every site of a cluster has the same spin)
+        // root (every site of a cluster has the same spin); the interior roots
+        // of the wave's list lie in its own rows, whose seed-map words the
+        // wave keeps in its own LDS words; a seeded root's spin is loaded
+        // ahead of the draw
+        uint32_t *myseed = sm.seedw_s[wave];
+        if (lane < 32) myseed[lane] = seedw;
+        wave_lds_fence();
         for (int i = lane; i < nroot; i += 64) {
             const int slot = mylist[i];
             const uint32_t R = static_cast<uint32_t>((gy0 + (slot >> 7)) * W + gx0 + (slot & (TW - 1)));
+            const uint32_t word = myseed[(slot >> 5) - ly0 * (TW / 32)];
+            const bool seeded = (word >> (slot & 31)) & 1u;
+            uint32_t old = 0;
+            if (seeded) old = a.spins[R];
             uint8_t v = FEW_KEEP;
-            if (((sm.seedbits[slot >> 5] >> (slot & 31)) & 1u) && few_flips(R, a))
-                v = static_cast<uint8_t>(1u - state_of_byte(a.spins[R], a.ising));
+            if (seeded && few_flips(R, a)) v = static_cast<uint8_t>(1u - state_of_byte(old, a.ising));
             ST[CAP + slot] = v;
         }
     }
@@ -1205,6 +1209,8 @@ __device__ __forceinline__ void flatten_body(FlatArgs a, const int tile, const i
         if (k < nbt) {
             const int id = tile * CAP + k;
             int r = broot[j], key = bR[j];
+            uint32_t old = 0;
+            if constexpr (MODE == M_FEW) old = a.spins[bR[j]];  // the id's own tile-local root, in this tile
             if (r != id) {  // below a root (the merge keeps trees shallow): walk up, take the root's key
                 r = gfind(a.gparent, r);
                 key = a.gkey[r];
@@ -1215,11 +1221,11 @@ __device__ __forceinline__ void flatten_body(FlatArgs a, const int tile, const i
             if constexpr (MODE == M_SW) ST[k] = flip_state(static_cast<uint32_t>(key), a);
             if constexpr (MODE == M_FEW) {
                 // seeded iff its root carries this sweep's mark; the old state
-                // is read at the id's own tile-local root (a site of this tile,
-                // not yet written)
+                // was read at the id's own tile-local root (a site of this
+                // tile, not yet written)
                 uint8_t v = FEW_KEEP;
                 if (a.sel[r] == a.stamp && few_flips(static_cast<uint32_t>(key), a))
-                    v = static_cast<uint8_t>(1u - state_of_byte(a.spins[bR[j]], a.ising));
+                    v = static_cast<uint8_t>(1u - state_of_byte(old, a.ising));
                 ST[k] = v;
             }
         }

@@ -61,7 +61,7 @@ struct Layout {
     size_t row_count, row_off, scan_tmp, rl_slot, rl_size;
     size_t lat_desc, lat_of_tile, t_dev;  // batches only
     size_t small_lat, ftile, mgroup, counters, fault;  // fused batch sweeps
-    size_t sel;  // few-cluster sweeps: per-root-id seed marks
+    size_t sel, seedmap;  // few-cluster sweeps: seed marks per root id, seed bits per interior root slot
     bool few;
     size_t total;
 };
@@ -141,7 +141,10 @@ Layout make_layout(int32_t W, int32_t H, bool sizes, int th = TH_DEFAULT, int mw
         L.rl_size = take(nt * static_cast<size_t>(L.d.tsites) * sizeof(int32_t));
     }
     L.few = few;
-    if (few) L.sel = take(nt * static_cast<size_t>(L.d.cap) * sizeof(uint32_t));
+    if (few) {
+        L.sel = take(nt * static_cast<size_t>(L.d.cap) * sizeof(uint32_t));
+        L.seedmap = take(nt * static_cast<size_t>(L.d.tsites / 32) * sizeof(uint32_t));
+    }
     L.total = off;
     return L;
 }
@@ -443,16 +446,21 @@ sw_status sw_init(sw_lattice **out, const sw_params *p, const sw_buffers *b, voi
 }
 
 // Few-cluster sweeps: one thread per seed tile marks the root id of a seeded
-// boundary cluster with t + 1.  The marks are cleared first after init and
-// after sw_set_t (a sweep number may then come round again).
+// boundary cluster with t + 1, or the root slot of a seeded interior cluster
+// in its tile's seed map (the flatten clears the map as it reads it).  The
+// marks are cleared first after init and after sw_set_t (a sweep number may
+// then come round again).
 static sw_status launch_seeds(sw_lattice *h, hipStream_t s)
 {
     const Layout &L = h->L;
     void *ws = h->b.workspace;
-    const int64_t nsel = L.g.ntiles * static_cast<int64_t>(L.d.cap);
     if (h->sel_stale) {
+        const int64_t nsel = L.g.ntiles * static_cast<int64_t>(L.d.cap);
+        const int64_t nmap = L.g.ntiles * static_cast<int64_t>(L.d.tsites / 32);
         hipLaunchKernelGGL(k_zero_i32, dim3(static_cast<unsigned>(cdiv(nsel, NT))), dim3(NT), 0, s,
                            at<int32_t>(ws, L.sel), static_cast<int>(nsel));
+        hipLaunchKernelGGL(k_zero_i32, dim3(static_cast<unsigned>(cdiv(nmap, NT))), dim3(NT), 0, s,
+                           at<int32_t>(ws, L.seedmap), static_cast<int>(nmap));
         const sw_status st = launch_status("k_zero_i32");
         if (st != SW_OK) return st;
         h->sel_stale = false;
@@ -462,6 +470,7 @@ static sw_status launch_seeds(sw_lattice *h, hipStream_t s)
     sa.codes = at<uint16_t>(ws, L.codes);
     sa.gparent = at<int32_t>(ws, L.gparent);
     sa.sel = at<uint32_t>(ws, L.sel);
+    sa.seedmap = at<uint32_t>(ws, L.seedmap);
     sa.t = static_cast<uint32_t>(h->t);
     sa.stamp = sa.t + 1u;
     sa.sid = h->p.stream_id;
@@ -516,10 +525,9 @@ static sw_status launch_phase(sw_lattice *h, int32_t phase, hipStream_t s)
         const sw_status st = launch_seeds(h, s);
         if (st != SW_OK) return st;
         fa.sel = at<uint32_t>(ws, L.sel);
+        fa.seedmap = at<uint32_t>(ws, L.seedmap);
         fa.stamp = t + 1u;
         fa.tflip = h->tflip;
-        fa.few_b = h->p.few_b;
-        fa.few_ntx = static_cast<int>(cdiv(h->p.W, h->p.few_b));
         if (!L.sizes) {
             launch_flatten<M_FEW, false, false>(L, fa, L.g.ntiles, s);
             return launch_status("k_flatten");
