@@ -209,14 +209,14 @@ def _batched(args, torch, sw, wl, stream) -> dict:
     sweeps each lattice with its own launch sequence."""
     specs = wl.batch_specs()
     nsite = sum(sp["W"] * sp["H"] for sp in specs)
-    reps = max(5, args.steps // 2)
+    reps = 16  # batched calls of 16 sweeps: two replays of the eight-sweep graph
     c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    def timed(fn):
+    def timed(fn, n=1):
         fn()
         torch.cuda.synchronize()
         c0.record(stream)
-        for _ in range(reps):
+        for _ in range(reps // n):
             fn()
         c1.record(stream)
         torch.cuda.synchronize()
@@ -226,8 +226,8 @@ def _batched(args, torch, sw, wl, stream) -> dict:
     for name, fused in (("fused", True), ("phases", False)):
         b = sw.SWBatch(specs, fused=fused)
         b.sweep(2)
-        res[name] = timed(lambda: b.sweep(1))
-        res[name + "_graph"] = timed(lambda: b.sweep(1, graph=True))
+        res[name] = timed(lambda: b.sweep(reps), reps)
+        res[name + "_graph"] = timed(lambda: b.sweep(reps, graph=True), reps)
         del b
     lats = [sw.SWLattice(sp["W"], sp["H"], q=2, K=sp["K"], seed=sp["seed"], stream_id=sp["stream_id"])
             for sp in specs]

@@ -48,7 +48,7 @@
  * caller; the library allocates no device memory.  Scratch space is the caller's
  * workspace of at least *_workspace_bytes() bytes.  A lattice handle is a small
  * host object created by sw_init and freed by sw_destroy (a batch that ran
- * swb_sweep_graph also holds a capture stream and an executable graph until
+ * swb_sweep_graph also holds a capture stream and executable graphs until
  * swb_destroy).
  *
  * Streams: every call enqueues on the given stream (a hipStream_t passed as
@@ -299,10 +299,11 @@ sw_status swb_init(swb_batch **out, const sw_params *p, const sw_buffers *b, int
  * advances on the device. */
 sw_status swb_sweep(swb_batch *h, int32_t n_sweeps, void *stream);
 
-/* As swb_sweep, but each sweep is one launch of a HIP graph holding the
- * sweep's kernels (Sec. II steps 1-3 for every lattice of the batch), captured
- * on the first call on a stream of the library's own and replayed afterwards;
- * the same trajectory as swb_sweep, and the two may be mixed.  The graph holds
+/* As swb_sweep, but the sweeps are replays of HIP graphs holding the sweeps'
+ * kernels (Sec. II steps 1-3 for every lattice of the batch): one graph of
+ * eight sweeps, launched once per eight, and one of a single sweep for the
+ * rest, each captured on first use on a stream of the library's own; the same
+ * trajectory as swb_sweep, and the two may be mixed.  The graph holds
  * no memset nodes.  Errors: SW_ERR_ARG, SW_ERR_STATE (t would pass 2^32 - 1),
  * SW_ERR_DEVICE if capture, instantiation or launch fails (sw_last_error()
  * says which).  Released by swb_destroy. */

@@ -917,10 +917,11 @@ struct swb_batch {
     int32_t n_small, n_ftiles, n_mgroups;
     uint64_t t;          // host mirror of the device sweep counter
     bool swept;
-    // one sweep captured as a graph (swb_sweep_graph), made on first use
+    // GRAPH_CHUNK[k] sweeps captured as one graph (swb_sweep_graph), each
+    // made on first use
     hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
 };
 
 // The fused launch's work queue: lattices swept whole in LDS, then the tiles
@@ -1215,12 +1216,39 @@ void enqueue_batch_sweep(const swb_batch *h, hipStream_t s)
 
 void drop_graph(swb_batch *h)
 {
-    if (h->exec) (void)hipGraphExecDestroy(h->exec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
+    for (int k = 0; k < 2; ++k) {
+        if (h->exec[k]) (void)hipGraphExecDestroy(h->exec[k]);
+        if (h->graph[k]) (void)hipGraphDestroy(h->graph[k]);
+        h->exec[k] = nullptr;
+        h->graph[k] = nullptr;
+    }
     if (h->cap) (void)hipStreamDestroy(h->cap);
-    h->exec = nullptr;
-    h->graph = nullptr;
     h->cap = nullptr;
+}
+
+// Sweeps per graph: one, and a chunk of eight that pays one graph launch for
+// eight sweeps.
+constexpr int32_t GRAPH_CHUNK[2] = {1, 8};
+
+// Capture GRAPH_CHUNK[k] sweeps as graph k, on a stream of the library's own:
+// capture runs nothing, and the caller's stream may be one that cannot be
+// captured.
+sw_status capture_graph(swb_batch *h, int k)
+{
+    sw_status st = SW_OK;
+    if (!h->cap) st = device_status(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking), "create capture stream");
+    if (st == SW_OK) st = device_status(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+    if (st == SW_OK) {
+        for (int32_t i = 0; i < GRAPH_CHUNK[k]; ++i) enqueue_batch_sweep(h, h->cap);
+        const hipError_t le = hipGetLastError();
+        const hipError_t ee = hipStreamEndCapture(h->cap, &h->graph[k]);
+        st = device_status(le != hipSuccess ? le : ee, "capture batched sweep");
+    }
+    if (st == SW_OK)
+        st = device_status(hipGraphInstantiate(&h->exec[k], h->graph[k], nullptr, nullptr, 0),
+                           "instantiate batched sweep");
+    if (st != SW_OK) drop_graph(h);
+    return st;
 }
 
 }  // namespace
@@ -1247,31 +1275,19 @@ sw_status swb_sweep_graph(swb_batch *h, int32_t n_sweeps, void *stream)
     if (!h || n_sweeps < 0) return SW_ERR_ARG;
     if (h->t + static_cast<uint64_t>(n_sweeps) > 0xFFFFFFFFull) return SW_ERR_STATE;
     if (n_sweeps == 0) return SW_OK;
-    if (!h->exec) {
-        // capture on a stream of the library's own: capture runs nothing, and
-        // the caller's stream may be one that cannot be captured
-        sw_status st = device_status(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking), "create capture stream");
-        if (st == SW_OK)
-            st = device_status(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal), "begin capture");
-        if (st == SW_OK) {
-            enqueue_batch_sweep(h, h->cap);
-            const hipError_t le = hipGetLastError();
-            const hipError_t ee = hipStreamEndCapture(h->cap, &h->graph);
-            st = device_status(le != hipSuccess ? le : ee, "capture batched sweep");
-        }
-        if (st == SW_OK) st = device_status(hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0),
-                                            "instantiate batched sweep");
-        if (st != SW_OK) {
-            drop_graph(h);
-            return st;
-        }
-    }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int32_t k = 0; k < n_sweeps; ++k) {
-        const sw_status st = device_status(hipGraphLaunch(h->exec, s), "launch batched sweep graph");
+    int32_t left = n_sweeps;
+    while (left > 0) {
+        const int k = left >= GRAPH_CHUNK[1] ? 1 : 0;
+        if (!h->exec[k]) {
+            const sw_status st = capture_graph(h, k);
+            if (st != SW_OK) return st;
+        }
+        const sw_status st = device_status(hipGraphLaunch(h->exec[k], s), "launch batched sweep graph");
         if (st != SW_OK) return st;
-        h->t += 1;
+        h->t += static_cast<uint64_t>(GRAPH_CHUNK[k]);
         h->swept = true;
+        left -= GRAPH_CHUNK[k];
     }
     return SW_OK;
 }

@@ -109,3 +109,26 @@ def test_batch_graph_replays(fused):
             assert o["n_clusters"] == rec[oracle.REC_NCLUST]
             st[j] = new
     assert b.t == 5
+
+
+@pytest.mark.parametrize("fused", [False, True], ids=["phases", "fused"])
+def test_batch_graph_chunks(fused):
+    """Calls of several sweeps replay the eight-sweep graph (then single-sweep
+    ones): after calls of 8, 11 and 8 sweeps, with eager work between them,
+    every lattice equals the oracle."""
+    specs = [dict(sp, stream_id=j) for j, sp in enumerate(MIX)]
+    b = sw.SWBatch(specs, fused=fused)
+    st = [oracle.init_states(sp["W"], sp["H"], sp["q"], sp["seed"], sp["stream_id"]) for sp in b.specs]
+    t = 0
+    for n in (8, 11, 8):
+        print(f"batch graph chunk t={t} n={n}", flush=True)
+        b.sweep(n, graph=True)
+        torch.cuda.synchronize()
+        for j, sp in enumerate(b.specs):
+            T = oracle.threshold(sp["K"])
+            st[j], rec = oracle.sw_run(sp["W"], sp["H"], sp["q"], T, sp["seed"], sp["stream_id"], t, n, st[j])
+            assert np.array_equal(_state(b.spins[j], sp["ising"]), st[j]), (j, t, n)
+            o = b.observables(j)  # eager work between the replays
+            assert o["t"] == t + n and o["n_clusters"] == rec[-1, oracle.REC_NCLUST], (j, t, n)
+        t += n
+    assert b.t == 27
