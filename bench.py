@@ -51,6 +51,8 @@ def _args():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--study", action="store_true",
                     help="instead of the bench line: sweep time and phases over couplings and q at L=16384")
+    ap.add_argument("--size-scan", action="store_true",
+                    help="per-phase sweep time per spin over L = 64 .. 16384 (q = 2 at beta_c), beside the oracle")
     ap.add_argument("--tile-scan", action="store_true",
                     help="instead of the bench line: sweep time and phases over tile shapes and merge schedules")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -199,6 +201,63 @@ def _study(args) -> int:
             print(json.dumps(rows[-1]), flush=True)
             del lat
             torch.cuda.empty_cache()
+    return 0
+
+
+def _size_scan(args) -> int:
+    """Sweep time per spin and its split into the three phases over the
+    lattice size (the q = 2 model at beta_c, Ising storage), beside the oracle
+    on one host core: the analogue of the paper's breakdown and speed-up over
+    L (Sec. II.E).  Whole sweeps go through sw_sweep (one-tile lattices take the
+    fused whole-in-LDS kernel); the phase split comes from per-phase launches."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1105_5804_amd as sw
+    from paper_1105_5804_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    oracle.use_flavor("native")
+    oracle.init_states(4, 4, 2, 1)  # builds the native oracle outside the timed calls
+    K = wl.K_ISING_C
+    for L in (64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384):
+        N = L * L
+        steps = max(args.steps, min(400, (1 << 26) // N))
+        lat = sw.SWLattice(L, L, q=2, K=K, seed=wl.SEED_BASE | 0x5C)
+        lat.sweep(max(args.warmup, 30))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lat.sweep(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        for k in range(steps):
+            evs[k][0].record(stream)
+            for ph in range(3):
+                lat.sweep_phase(ph)
+                evs[k][ph + 1].record(stream)
+        torch.cuda.synchronize()
+        ph_ms = [float(np.mean([evs[k][p].elapsed_time(evs[k][p + 1]) for k in range(steps)])) for p in range(3)]
+        st = ((lat.spins.cpu().numpy().reshape(-1).astype(np.int16) + 1) // 2).astype(np.uint8)
+        del lat
+        torch.cuda.empty_cache()
+        cpu_ns = None
+        if N <= 8192 * 8192:  # one sweep of the oracle from the equilibrated spins, bounded in time
+            c = time.perf_counter()
+            oracle.sw_run(L, L, 2, oracle.threshold(K), wl.SEED_BASE | 0x5C, 0, 10**6, 1, st)
+            cpu_ns = (time.perf_counter() - c) * 1e9 / N
+        row = {"L": L, "sweeps": steps, "ms_per_sweep": round(ms, 5), "ns_per_spin": round(ms * 1e6 / N, 5),
+               "tile_ns_per_spin": round(ph_ms[0] * 1e6 / N, 5), "merge_ns_per_spin": round(ph_ms[1] * 1e6 / N, 5),
+               "flip_ns_per_spin": round(ph_ms[2] * 1e6 / N, 5),
+               "phases_ns_per_spin": round(sum(ph_ms) * 1e6 / N, 5),
+               "cpu_oracle_ns_per_spin": None if cpu_ns is None else round(cpu_ns, 3),
+               "speedup_vs_oracle": None if cpu_ns is None else round(cpu_ns / (ms * 1e6 / N), 1)}
+        print(json.dumps(row), flush=True)
+    oracle.use_flavor("O2")
     return 0
 
 
@@ -478,6 +537,8 @@ def main() -> int:
         return _study(args)
     if args.tile_scan:
         return _tile_scan(args)
+    if args.size_scan:
+        return _size_scan(args)
 
     import numpy as np
     import torch
