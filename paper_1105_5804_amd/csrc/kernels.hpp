@@ -490,10 +490,24 @@ __device__ __forceinline__ void load_batch_tile(TileArgs &a, int tile, int &lt)
     lt = tile - L.tile0;
 }
 
+// The kernel's own TileArgs in the kernel-argument segment, behind an opaque
+// copy of the segment pointer: a field read through it is a scalar load at
+// that point, so output pointers used only at the end of the tile phase are
+// not held in scalar registers across it (which would spill some).
+typedef const __attribute__((address_space(4))) TileArgs KernTileArgs;
+__device__ __forceinline__ KernTileArgs *kernel_tile_args()
+{
+    KernTileArgs *k = (KernTileArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(k));
+    return k;
+}
+
 // The tile phase of one tile: `tile` indexes the tile arrays, `lt` is the
 // tile inside its lattice (they differ in batches).  Uses every thread of a
 // Tile<TH>::NT-thread workgroup; ends with the workgroup's writes issued.
-template <int MODE, bool EVENW, int TH_>
+// With KARG the launch's only argument is the TileArgs `a` came from, and the
+// output pointers are re-read from it where they are used.
+template <int MODE, bool EVENW, int TH_, bool KARG = false>
 __device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int lt, TileSmem<MODE, TH_> &sm)
 {
     using S = Tile<TH_>;
@@ -796,6 +810,13 @@ __device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int 
         eo_append<2>(mylist, nrs, eo_and(eo_andnot(O, eo_shift1(R)), linked), lane, base);
     }
     compress_list(nrs);
+    int32_t *gkey = a.gkey, *gparent = a.gparent, *gsize = a.gsize;
+    if constexpr (KARG) {
+        KernTileArgs *ka = kernel_tile_args();
+        gkey = ka->gkey;
+        gparent = ka->gparent;
+        gsize = ka->gsize;
+    }
     for (int t = threadIdx.x; t < EDGE; t += NT) {
         const int slot = border_slot<TH>(t, tw, th);
         if (slot < 0 || !occupied(slot)) continue;
@@ -806,9 +827,9 @@ __device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int 
             const int k = atomicAdd(&nb_s, 1);
             lds_st(lds_entry<true>(P, root4), -(k + 2));
             const int id = tile * CAP + k;
-            a.gkey[id] = (gy0 + (root >> 7)) * W + gx0 + (root & (TW - 1));
-            a.gparent[id] = id;
-            if (a.gsize) a.gsize[id] = 0;
+            gkey[id] = (gy0 + (root >> 7)) * W + gx0 + (root & (TW - 1));
+            gparent[id] = id;
+            if (gsize) gsize[id] = 0;
         }
     }
     __syncthreads();
@@ -824,7 +845,18 @@ __device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int 
         p = (y != x) ? *lds_entry<true>(P, y) : p;
         return p < 0 ? static_cast<uint32_t>(-p - 2) : static_cast<uint32_t>(CAP + (y >> 2));
     };
-    uint32_t *codes32 = reinterpret_cast<uint32_t *>(a.codes + static_cast<int64_t>(tile) * TSITES);
+    uint16_t *codes = a.codes, *edges = a.edges;
+    uint64_t *xbits = a.xbits;
+    int32_t *nbp = a.nb, *tile_act = a.tile_act;
+    if constexpr (KARG) {
+        KernTileArgs *ka = kernel_tile_args();
+        codes = ka->codes;
+        edges = ka->edges;
+        xbits = ka->xbits;
+        nbp = ka->nb;
+        tile_act = ka->tile_act;
+    }
+    uint32_t *codes32 = reinterpret_cast<uint32_t *>(codes + static_cast<int64_t>(tile) * TSITES);
     // unrolled: the rows' lookup chains are independent, so their LDS loads overlap
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
@@ -838,7 +870,7 @@ __device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int 
         const uint32_t code1 = lane_bit(O.o, lane) ? code_of(base + lx0 + 1, pp.y) : CODE_BG;
         codes32[(base + lx0) >> 1] = code0 | (code1 << 16);
     }
-    uint16_t *edg = a.edges + static_cast<int64_t>(tile) * EDGE;
+    uint16_t *edg = edges + static_cast<int64_t>(tile) * EDGE;
     for (int t = threadIdx.x; t < EDGE; t += NT) {
         const int slot = border_slot<TH>(t, tw, th);
         uint16_t eid = ID_NONE;
@@ -846,7 +878,7 @@ __device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int 
         edg[t] = eid;
     }
     if (threadIdx.x == 0) {
-        uint64_t *xb = a.xbits + static_cast<int64_t>(tile) * XW;
+        uint64_t *xb = xbits + static_cast<int64_t>(tile) * XW;
         int act = 0;
 #pragma unroll
         for (int j = 0; j < XR; ++j) {
@@ -857,8 +889,8 @@ __device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int 
         for (int w = 0; w < NWAVE; ++w) act += act_w[w];
         xb[XR] = xd_s.e;      // bottom crossing bonds of even columns
         xb[XR + 1] = xd_s.o;  // ... and of odd columns
-        a.nb[tile] = nb_s;
-        if (MODE == M_SW && a.tile_act) a.tile_act[tile] = act;
+        nbp[tile] = nb_s;
+        if (MODE == M_SW && tile_act) tile_act[tile] = act;
     }
 }
 
@@ -878,7 +910,7 @@ __global__ __launch_bounds__(Tile<TH_>::NT) __attribute__((amdgpu_waves_per_eu(8
         tile = lt = xcd_remap(blockIdx.x, a.g.ntiles);
         if (a.g.rev) tile = lt = a.g.ntiles - 1 - tile;
     }
-    tile_body<MODE, EVENW, TH_>(a, tile, lt, sm);
+    tile_body<MODE, EVENW, TH_, true>(a, tile, lt, sm);
 }
 
 // ---------------------------------------------------------------- merge ----
