@@ -13,11 +13,13 @@ satisfied bonds (-H/J, Eq. potts_hamiltonian) and state counts of the spins
 after the flip) and the order-independent array digests (spins after the flip;
 labels and bond bytes of the sweep, before the flip), in hexadecimal.
 
-    python tests/golden/make_sweep_records.py ising64 ising4096 potts16384 batch256
+    python tests/golden/make_sweep_records.py ising64 ising4096 potts16384 batch256 few1024
 
 ising64 / ising4096 / potts16384 record every sweep (1000, 200 + 1000 and 100
 sweeps); batch256 records every lattice of the batched workload after sweeps
-1, 10, 100 and 1000.  The oracle is built with -O3 -march=native for speed; a
+1, 10, 100 and 1000; few1024 records every sweep of the few-cluster update
+(Sec. III) on an Ising 1024 x 1024 lattice at beta_c with 32 x 32 seed tiles
+and p_flip = 1/2 (the FEW parameters below).  The oracle is built with -O3 -march=native for speed; a
 CPU test checks that this build agrees with the default one.
 """
 from __future__ import annotations
@@ -36,6 +38,8 @@ import oracle  # noqa: E402
 from paper_1105_5804_amd import workloads as wl  # noqa: E402
 
 BATCH_CHECKPOINTS = (1, 10, 100, 1000)
+# the few-cluster record: L, seed tile edge, p_flip, sweeps, seed
+FEW = dict(L=1024, B=32, p_flip=0.5, sweeps=300, seed=wl.SEED_BASE | 0xFE)
 
 
 def _line(t, rec, q, d_spins, d_labels, d_bonds) -> str:
@@ -117,14 +121,35 @@ def batch() -> None:
     print(f"batch256: wrote {out}", flush=True)
 
 
+def few() -> None:
+    """Every sweep of the few-cluster update on the FEW lattice."""
+    L, B, pf, n, seed = FEW["L"], FEW["B"], FEW["p_flip"], FEW["sweeps"], FEW["seed"]
+    K = wl.K_ISING_C
+    T, Tf = oracle.threshold(K), oracle.prob_threshold(pf)
+    st = oracle.init_states(L, L, 2, seed)
+    out = os.path.join(HERE, "sweeps_few1024.txt")
+    with open(out + ".tmp", "w") as f:
+        f.write(f"# few1024: W={L} H={L} q=2 K={K!r} seed={seed:#x} stream_id=0 few_b={B} p_flip={pf!r}, "
+                f"sweeps t=0..{n - 1}\n")
+        f.write("# written by tests/golden/make_sweep_records.py from the CPU oracle only\n")
+        f.write("# t active n_clusters max_cluster n_sat counts[0..1] digest_spins digest_labels digest_bonds\n")
+        for t in range(n):
+            st, bonds, labels, rec, _ = oracle.few_sweep(L, L, T, Tf, B, seed, 0, t, st)
+            f.write(_line(t, rec, 2, oracle.digest(st), oracle.digest(labels), oracle.digest(bonds)) + "\n")
+    os.replace(out + ".tmp", out)
+    print(f"few1024: wrote {out}", flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", nargs="+", choices=["ising64", "ising4096", "potts16384", "batch256"])
+    ap.add_argument("which", nargs="+", choices=["ising64", "ising4096", "potts16384", "batch256", "few1024"])
     args = ap.parse_args()
     oracle.use_flavor("native")
     for w in args.which:
         if w == "batch256":
             batch()
+        elif w == "few1024":
+            few()
         else:
             single(w)
     return 0

@@ -9,8 +9,8 @@ of the spins after the flip (step 3), and order-independent digests of the
 spins, labels and bond bytes.  The library must reproduce every record, sweep
 by sweep, over the whole run: 1000 sweeps of Ising L = 64, 200 + 1000 of
 Ising L = 4096, the 100 of q = 3 Potts L = 16384 (which covers the sweeps the
-benchmark times), and every lattice of the batched workload at its
-checkpoints.  A digest is a 64-bit sum of one Philox block per element, so any
+benchmark times), every lattice of the batched workload at its
+checkpoints, and 300 sweeps of the few-cluster update on Ising L = 1024.  A digest is a 64-bit sum of one Philox block per element, so any
 differing element shows in it.
 """
 import os
@@ -102,6 +102,24 @@ def test_ising4096_every_sweep():
                          ids=["default", "h32m16", "h128m4"])
 def test_potts16384_every_sweep(tile):
     _run_single("potts16384", tile)
+
+
+def test_few1024_every_sweep():
+    """The few-cluster update (Sec. III) on an Ising 1024 x 1024 lattice at
+    beta_c, 32 x 32 seed tiles, p_flip = 1/2: all 300 recorded sweeps."""
+    recs = _records("few1024")
+    head = open(os.path.join(GOLDEN, "sweeps_few1024.txt")).readline()
+    assert "few_b=32 p_flip=0.5" in head
+    L, seed = 1024, wl.SEED_BASE | 0xFE
+    lat = sw.SWLattice(L, L, q=2, K=wl.K_ISING_C, seed=seed, keep_labels=True, keep_bonds=True, sizes=True,
+                       few_b=32, p_flip=0.5)
+    print(f"golden few1024: {len(recs)} sweeps", flush=True)
+    for t in range(len(recs)):
+        lat.sweep(1)
+        _compare(lat.observables(), recs[t], 2, t, "few1024")
+        if t % 100 == 0:
+            print(f"golden few1024: sweep {t} ok", flush=True)
+    lat.close()
 
 
 @pytest.mark.parametrize("fused", [False, True], ids=["phases", "fused"])
