@@ -344,6 +344,8 @@ struct TileArgs {
     uint32_t tany;            // ... and tany (threshold T > 0); tm1 = T - 1
     uint32_t k0, k1, t, sid;
     Batch b;                  // batched launches only
+    uint32_t rk[20];          // single-lattice sweeps: the Philox key schedule of (k0, k1), round r in
+                              // rk[2r], rk[2r + 1]
 };
 
 // A tile row as two wave ballots: lane L owns sites 2L and 2L+1, bit L of `e`
@@ -506,8 +508,10 @@ __device__ __forceinline__ KernTileArgs *kernel_tile_args()
 // tile inside its lattice (they differ in batches).  Uses every thread of a
 // Tile<TH>::NT-thread workgroup; ends with the workgroup's writes issued.
 // With KARG the launch's only argument is the TileArgs `a` came from, and the
-// output pointers are re-read from it where they are used.
-template <int MODE, bool EVENW, int TH_, bool KARG = false>
+// output pointers are re-read from it where they are used; with RKEYS (a
+// single-lattice sweep) so is the bond generator's key schedule, row by row
+// (scalar loads in place of 18 scalar adds per row).
+template <int MODE, bool EVENW, int TH_, bool KARG = false, bool RKEYS = false>
 __device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int lt, TileSmem<MODE, TH_> &sm)
 {
     using S = Tile<TH_>;
@@ -627,7 +631,12 @@ __device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int 
             // held in 20 scalar registers across the unrolled row loop
             uint32_t k0 = __builtin_amdgcn_readfirstlane(a.k0), k1 = __builtin_amdgcn_readfirstlane(a.k1);
             asm volatile("" : "+s"(k0), "+s"(k1));
-            const U4 blk = philox4x32_10(static_cast<uint32_t>(i0 >> 1), a.t, TAG_BOND, a.sid, k0, k1);
+            U4 blk;
+            if constexpr (RKEYS) {
+                blk = philox4x32_10_rk(static_cast<uint32_t>(i0 >> 1), a.t, TAG_BOND, a.sid, kernel_tile_args()->rk);
+            } else {
+                blk = philox4x32_10(static_cast<uint32_t>(i0 >> 1), a.t, TAG_BOND, a.sid, k0, k1);
+            }
             if (EVENW || (i0 & 1) == 0) {  // the pair (i0, i0+1) shares one block
                 r0R = blk.v0;
                 r0D = blk.v1;
@@ -910,7 +919,7 @@ __global__ __launch_bounds__(Tile<TH_>::NT) __attribute__((amdgpu_waves_per_eu(8
         tile = lt = xcd_remap(blockIdx.x, a.g.ntiles);
         if (a.g.rev) tile = lt = a.g.ntiles - 1 - tile;
     }
-    tile_body<MODE, EVENW, TH_, true>(a, tile, lt, sm);
+    tile_body<MODE, EVENW, TH_, true, !BATCH && MODE == M_SW>(a, tile, lt, sm);
 }
 
 // ---------------------------------------------------------------- merge ----

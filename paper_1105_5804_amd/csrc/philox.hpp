@@ -50,6 +50,33 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     return U4{c0, c1, c2, c3};
 }
 
+// The same block with the key schedule given: rk[2r] and rk[2r + 1] are the
+// two key words of round r (the key bumped r times), read from scalar memory
+// where the caller keeps them rather than recomputed.
+template <typename RK>
+__device__ __forceinline__ U4 philox4x32_10_rk(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, RK *rk)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t b = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t k0 = rk[2 * r], k1 = rk[2 * r + 1];
+        uint32_t n0, n2;
+        if (r == 0) {
+            n0 = static_cast<uint32_t>(b >> 32) ^ c1 ^ k0;
+            n2 = static_cast<uint32_t>(a >> 32) ^ c3 ^ k1;
+        } else {
+            n0 = xor3_vvs(static_cast<uint32_t>(b >> 32), c1, k0);
+            n2 = xor3_vvs(static_cast<uint32_t>(a >> 32), c3, k1);
+        }
+        c1 = static_cast<uint32_t>(b);
+        c3 = static_cast<uint32_t>(a);
+        c0 = n0;
+        c2 = n2;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
 // Word j (0..3) of a block, by selects rather than branches.
 __device__ __forceinline__ uint32_t pick(const U4 &b, uint32_t j)
 {

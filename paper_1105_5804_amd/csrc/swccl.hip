@@ -501,6 +501,10 @@ static sw_status launch_phase(sw_lattice *h, int32_t phase, hipStream_t s)
         ta.tm1 = h->T > 0 ? static_cast<uint32_t>(h->T - 1) : 0u;
         ta.k0 = k0;
         ta.k1 = k1;
+        for (uint32_t r = 0; r < 10; ++r) {  // Philox's key schedule: the Weyl increments added r times
+            ta.rk[2 * r] = k0 + r * 0x9E3779B9u;
+            ta.rk[2 * r + 1] = k1 + r * 0xBB67AE85u;
+        }
         ta.t = t;
         ta.sid = h->p.stream_id;
         launch_tile<M_SW>(L, ta, s);
