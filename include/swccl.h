@@ -197,8 +197,8 @@ const char *sw_last_error(void);
  * bond's 32-bit uniform must stay below (Sec. II.A activation rule). */
 uint64_t sw_threshold(double K);
 
-/* Workspace bytes needed by a lattice with these parameters, SW_F_SIZES
- * included (0 if invalid). */
+/* Workspace bytes needed by a lattice with these parameters, SW_F_SIZES and
+ * the few-cluster update's seed marks included (0 if invalid). */
 size_t sw_workspace_bytes(const sw_params *p);
 
 /* Create a lattice handle over caller-owned buffers and, unless
