@@ -766,16 +766,16 @@ __device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int 
         }
     };
 
-    // ---- C: every occupied run start is pointed straight at its root, and
-    // the clusters that touch the tile border are claimed (one thread per
-    // border position).  A compressed entry only ever replaces a parent by an
-    // ancestor, and a root's own entry is left to the claims.
-    // Only run starts whose parent is not themselves need a walk.
-    // Lane L walks run starts L, L+64, ... of the list; a lane whose walk is
-    // done takes its next run start at once.  Claims of waves that are done
-    // compressing run concurrently, so a root already claimed (its entry
-    // negative, no longer its own offset) can be listed: its walk ends where
-    // it starts and its entry must not be written.
+    // ---- C: the clusters that touch the tile border are claimed (one
+    // thread per border position), then, after a barrier, every linked run
+    // start gets its cluster's final code, stored in its own entry as
+    // -(code + 2): the boundary id of a claimed root, else CAP + the root's
+    // slot (a claimed root's entry already reads -(id + 2)).  Lane L walks
+    // run starts L, L+64, ... of the wave's list up to the first entry that is
+    // negative (a claimed root, or a run start another lane has finished:
+    // either way the cluster's code) or its own (an unclaimed root); a lane
+    // whose walk is done takes its next run start at once.  Only linked run
+    // starts (entry neither their own nor negative) are listed.
     auto compress_list = [&](int n) {
         wave_lds_fence();
         int i = lane, s0 = 0, x = 0;
@@ -785,40 +785,13 @@ __device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int 
             if (p >= 0 && p != x) {
                 x = p;
             } else {
-                if (x != s0) lds_st(lds_entry<true>(P, s0), x);
+                lds_st(lds_entry<true>(P, s0), p < 0 ? p : -(CAP + (x >> 2)) - 2);
                 i += 64;
                 if (i < n) s0 = x = mylist[i];
             }
         }
         wave_lds_fence();
     };
-    int nrs = 0;
-    // The parents of the wave's sites are read up front (the loads overlap).
-    // A flush only rewrites entries that are not their own (linked stays
-    // linked); a root claimed meanwhile reads as unlinked here and is rightly
-    // left out.
-    int2 ppr[RPW];
-#pragma unroll
-    for (int r = 0; r < RPW; ++r)
-        ppr[r] = r < nr ? *reinterpret_cast<const int2 *>(&P[(ly0 + r) * TW + lx0]) : make_int2(0, 0);
-#pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-        if (r >= nr) break;
-        const int ly = ly0 + r;
-        const int base = ly * TW;
-        if (nrs > TL - TW) {
-            compress_list(nrs);
-            nrs = 0;
-        }
-        const EO R = uniform_eo(Rm[ly]);
-        EO O = valid;
-        if constexpr (MODE == M_SITES) O = uniform_eo(Om[ly]);
-        const int2 pp = ppr[r];
-        const EO linked = EO{lanes_ne(static_cast<uint32_t>(pp.x), static_cast<uint32_t>(4 * (base + lx0))),
-                             lanes_ne(static_cast<uint32_t>(pp.y), static_cast<uint32_t>(4 * (base + lx0 + 1)))};
-        eo_append<2>(mylist, nrs, eo_and(eo_andnot(O, eo_shift1(R)), linked), lane, base);
-    }
-    compress_list(nrs);
     int32_t *gkey = a.gkey, *gparent = a.gparent, *gsize = a.gsize;
     if constexpr (KARG) {
         KernTileArgs *ka = kernel_tile_args();
@@ -842,17 +815,43 @@ __device__ __forceinline__ void tile_body(TileArgs a, const int tile, const int 
         }
     }
     __syncthreads();
+    int nrs = 0;
+    // The entries of the wave's sites are read up front (the loads overlap);
+    // a flush of the list only rewrites linked run starts of this wave.
+    int2 ppr[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+        ppr[r] = r < nr ? *reinterpret_cast<const int2 *>(&P[(ly0 + r) * TW + lx0]) : make_int2(0, 0);
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        if (r >= nr) break;
+        const int ly = ly0 + r;
+        const int base = ly * TW;
+        if (nrs > TL - TW) {
+            compress_list(nrs);
+            nrs = 0;
+        }
+        const EO R = uniform_eo(Rm[ly]);
+        EO O = valid;
+        if constexpr (MODE == M_SITES) O = uniform_eo(Om[ly]);
+        const int2 pp = ppr[r];
+        const EO linked = EO{lanes_ne(static_cast<uint32_t>(pp.x), static_cast<uint32_t>(4 * (base + lx0))) &
+                                 lanes_lt(static_cast<uint32_t>(pp.x), 0x80000000u),
+                             lanes_ne(static_cast<uint32_t>(pp.y), static_cast<uint32_t>(4 * (base + lx0 + 1))) &
+                                 lanes_lt(static_cast<uint32_t>(pp.y), 0x80000000u)};
+        eo_append<2>(mylist, nrs, eo_and(eo_andnot(O, eo_shift1(R)), linked), lane, base);
+    }
+    compress_list(nrs);
+    __syncthreads();
 
     // ---- E: per-site codes (boundary id of a claimed root, else CAP + the
-    // root's slot), edge ids, crossing bits.  A site reaches its root in at
-    // most two steps: site -> run start -> root.
-    auto code_of = [&](int x, int p) {  // x a slot, p = P[x]; the walk runs on byte offsets
+    // root's slot), edge ids, crossing bits.  A site's code is one step past
+    // its entry: a run start holds its code (or, an unclaimed root, its own
+    // offset), any other site its run start's offset.
+    auto code_of = [&](int x, int p) {  // x a slot, p = P[x] (byte offsets)
         x *= 4;
-        x = (p >= 0 && p != x) ? p : x;
-        p = *lds_entry<true>(P, x);
-        const int y = (p >= 0 && p != x) ? p : x;
-        p = (y != x) ? *lds_entry<true>(P, y) : p;
-        return p < 0 ? static_cast<uint32_t>(-p - 2) : static_cast<uint32_t>(CAP + (y >> 2));
+        if (p >= 0 && p != x) p = *lds_entry<true>(P, p);
+        return p < 0 ? static_cast<uint32_t>(-p - 2) : static_cast<uint32_t>(CAP + (p >> 2));
     };
     uint16_t *codes = a.codes, *edges = a.edges;
     uint64_t *xbits = a.xbits;

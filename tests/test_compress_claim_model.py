@@ -1,26 +1,32 @@
-"""Interleaving model of the tile kernel's compression and border claims.
+"""Interleaving model of the tile kernel's border claims and compression.
 
 After the unions of a tile (Sec. II.B.2) every site's parent entry holds its
 run start, and the run starts form a forest with parents at smaller indices.
-Then, per wave and without a barrier between waves:
+Then:
 
-  1. the wave reads its sites' entries up front and lists the run starts whose
-     entry is not their own (linked, or a root some other wave has claimed);
-  2. its lanes walk the listed run starts to their roots (a walk stops at an
-     entry equal to its own index or negative) and point each start straight
-     at its root, never writing an entry where the walk ended at its start;
-  3. its threads claim the roots of their border sites: find the root, swing
-     the root's entry from its own index to CLAIMING (-1) by compare-and-swap,
-     take the next boundary id k and store -(k + 2).
+  1. (every thread of the workgroup) the threads of the border sites claim
+     their roots: walk to the root (an entry equal to its own index, or
+     negative), swing the root's entry from its own index to CLAIMING (-1) by
+     compare-and-swap, take the next boundary id k and store -(k + 2);
+  2. a barrier;
+  3. (per wave, without a barrier between waves) the wave reads its sites'
+     entries up front and lists the run starts whose entry is neither their
+     own nor negative (linked); its lanes walk the listed run starts up to the
+     first entry that is negative (a claimed root, or a start another lane
+     already finished) or their own (an unclaimed root) and write the final
+     code into the start's entry, encoded as -(code + 2): the boundary id of a
+     claimed root, else CAP + the root;
+  4. a barrier.
 
-After the barrier each site's code is the boundary id of its root if that
-root was claimed, else CAP + the root, read in at most two steps (site ->
-run start -> root).  A seeded random scheduler interleaves every load, store
-and compare-and-swap of all waves' lanes and threads; every schedule must give
-each site the code of its own root, one id per claimed root, every border
-root claimed.  Dropping the "walk ended at its start" guard must be caught:
-a walk that starts at a root claimed before its wave read the entry would
-overwrite the claim.
+Each site's code is then read in at most one step past its entry (site ->
+run start): the decoded negative entry, or CAP + the run start when that is an
+unclaimed root.  A seeded random scheduler interleaves every load, store and
+compare-and-swap of all threads and lanes; every schedule must give each site
+the code of its own root, one id per claimed root and every border root
+claimed.  Two mistakes must be caught: claims running beside the compression
+(no barrier between them: a walk can encode an interior code for a root that
+is claimed afterwards) and a compression that writes the root's index instead
+of its final code.
 """
 import random
 
@@ -52,111 +58,109 @@ def _root(P0, x):
     return x
 
 
-def _run(P0, border, n_waves, lanes, rng, mistake=None):
+def _run(P0, border, is_start, n_waves, lanes, rng, mistake=None):
     n = len(P0)
     P = list(P0)
     nb = [0]
     per = (n + n_waves - 1) // n_waves
-    # per wave: its sites, its border sites (claim threads), and a program
-    waves = []
-    for w in range(n_waves):
-        sites = list(range(w * per, min(n, (w + 1) * per)))
-        claims = [b for k, b in enumerate(border) if k % n_waves == w]
-        waves.append(dict(sites=sites, claims=claims, stage="read", read=[], list=None, walkers=None,
-                          claimers=None))
+    claimers = [dict(x=b, pc="walk") for b in border]
+    waves = [dict(sites=list(range(w * per, min(n, (w + 1) * per))), stage="read", read=[], list=None,
+                  walkers=None) for w in range(n_waves)]
+
+    def step_claim(c):
+        if c["pc"] == "walk":
+            p = P[c["x"]]
+            if p == c["x"] or p < 0:
+                c["pc"] = "cas"
+            else:
+                c["x"] = p
+        elif c["pc"] == "cas":
+            if P[c["x"]] == c["x"]:
+                P[c["x"]] = CLAIMING
+                c["pc"] = "store"
+            else:
+                c["pc"] = "done"  # another thread claims this root
+        else:
+            k = nb[0]
+            nb[0] += 1
+            P[c["x"]] = -(k + 2)
+            c["pc"] = "done"
 
     def step_wave(W):
-        """One event of wave W; returns False when the wave has finished."""
+        """One event of wave W's compression; returns False when it has finished."""
         if W["stage"] == "read":  # one up-front load per event
             k = len(W["read"])
             if k < len(W["sites"]):
                 x = W["sites"][k]
                 W["read"].append(P[x])
                 return True
-            # list linked run starts: entry not its own (claimed roots included);
-            # non-start sites never change and are not run starts
-            W["list"] = [x for x, p in zip(W["sites"], W["read"]) if p != x and _is_start[x]]
+            # linked run starts: entry neither their own nor negative
+            W["list"] = [x for x, p in zip(W["sites"], W["read"]) if p >= 0 and p != x and is_start[x]]
             W["walkers"] = [dict(i=L, s0=None, x=None) for L in range(lanes)]
             W["stage"] = "compress"
             return True
-        if W["stage"] == "compress":
-            live = [wk for wk in W["walkers"] if wk["i"] < len(W["list"])]
-            if not live:
-                W["claimers"] = [dict(b=b, x=b, pc="walk") for b in W["claims"]]
-                W["stage"] = "claim"
-                return True
-            wk = rng.choice(live)
-            if wk["s0"] is None:
-                wk["s0"] = wk["x"] = W["list"][wk["i"]]
-                return True
-            p = P[wk["x"]]
-            if p >= 0 and p != wk["x"]:
-                wk["x"] = p
-            else:
-                if wk["x"] != wk["s0"] or mistake == "no_start_guard":
-                    P[wk["s0"]] = wk["x"]
-                wk["i"] += lanes
-                wk["s0"] = None
+        live = [wk for wk in W["walkers"] if wk["i"] < len(W["list"])]
+        if not live:
+            return False
+        wk = rng.choice(live)
+        if wk["s0"] is None:
+            wk["s0"] = wk["x"] = W["list"][wk["i"]]
             return True
-        if W["stage"] == "claim":
-            live = [c for c in W["claimers"] if c["pc"] != "done"]
-            if not live:
-                W["stage"] = "done"
-                return False
-            c = rng.choice(live)
-            if c["pc"] == "walk":
-                p = P[c["x"]]
-                if p == c["x"] or p < 0:
-                    c["pc"] = "cas"
-                else:
-                    c["x"] = p
-            elif c["pc"] == "cas":
-                if P[c["x"]] == c["x"]:
-                    P[c["x"]] = CLAIMING
-                    c["pc"] = "store"
-                else:
-                    c["pc"] = "done"  # another thread claims this root
+        p = P[wk["x"]]
+        if p >= 0 and p != wk["x"]:
+            wk["x"] = p
+        else:
+            if mistake == "root_not_code":
+                P[wk["s0"]] = wk["x"]
             else:
-                k = nb[0]
-                nb[0] += 1
-                P[c["x"]] = -(k + 2)
-                c["pc"] = "done"
-            return True
-        return False
+                P[wk["s0"]] = p if p < 0 else -(CAP + wk["x"]) - 2
+            wk["i"] += lanes
+            wk["s0"] = None
+        return True
 
-    live = list(range(n_waves))
-    while live:
-        w = rng.choice(live)
-        if not step_wave(waves[w]):
-            live.remove(w)
+    # claims, then (after a barrier) the waves' compression; with the
+    # mistake the two run interleaved
+    live_c = list(claimers)
+    live_w = list(range(n_waves))
+    while live_c or live_w:
+        if mistake == "claims_concurrent":
+            pick_claim = bool(live_c) and (not live_w or rng.random() < 0.5)
+        else:
+            pick_claim = bool(live_c)
+        if pick_claim:
+            c = rng.choice(live_c)
+            step_claim(c)
+            if c["pc"] == "done":
+                live_c.remove(c)
+        else:
+            w = rng.choice(live_w)
+            if not step_wave(waves[w]):
+                live_w.remove(w)
 
     def code_of(x):
         p = P[x]
-        x = p if (p >= 0 and p != x) else x
-        p = P[x]
-        y = p if (p >= 0 and p != x) else x
-        p = P[y] if y != x else p
-        return ("id", -p - 2) if p < 0 else ("slot", y)
+        if p >= 0 and p != x:
+            p = P[p]
+        if p < 0:
+            c = -p - 2
+            return ("id", c) if c < CAP else ("slot", c - CAP)
+        return ("slot", p)
 
     return [code_of(x) for x in range(n)], nb[0]
 
 
-_is_start = None
-
-
-@pytest.mark.parametrize("mistake", [None, "no_start_guard"])
-def test_compress_with_concurrent_claims(mistake):
-    global _is_start
-    rng = random.Random(5 if mistake is None else 6)
+@pytest.mark.parametrize("mistake", [None, "claims_concurrent", "root_not_code"])
+def test_claims_then_encoding_compression(mistake):
+    rng = random.Random({None: 5, "claims_concurrent": 6, "root_not_code": 7}[mistake])
     caught = False
     for trial in range(1500):
         n = rng.choice((8, 16, 40))
         P0, starts, border = _tile(rng, n)
-        _is_start = [False] * n
+        is_start = [False] * n
         for s in starts:
-            _is_start[s] = True
-        codes, n_ids = _run(P0, border, n_waves=rng.choice((2, 3, 4)), lanes=rng.choice((1, 2, 4)), rng=rng,
-                            mistake=mistake)
+            is_start[s] = True
+        codes, n_ids = _run(P0, border, is_start, n_waves=rng.choice((2, 3, 4)), lanes=rng.choice((1, 2, 4)),
+                            rng=rng, mistake=mistake)
         roots = [_root(P0, x) for x in range(n)]
         claimed = sorted({roots[b] for b in border})
         try:
@@ -176,4 +180,4 @@ def test_compress_with_concurrent_claims(mistake):
             caught = True
             break
     if mistake is not None:
-        assert caught, "the dropped guard was not exposed by any schedule"
+        assert caught, f"the planted mistake {mistake!r} was not exposed by any schedule"
