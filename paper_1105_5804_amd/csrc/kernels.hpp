@@ -26,7 +26,9 @@
 //             and, optionally, labels.
 //
 // Labeling-only inputs (packed bond bytes or binary images) reuse the same
-// three kernels with a different bond source.
+// three kernels with a different bond source.  The few-cluster update
+// (Sec. III) labels with the same tile and merge launches, marks the clusters
+// that hold a seed in k_seed and flips only those in k_flatten<M_FEW>.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
