@@ -51,6 +51,8 @@ def _args():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--study", action="store_true",
                     help="instead of the bench line: sweep time and phases over couplings and q at L=16384")
+    ap.add_argument("--few-scan", action="store_true",
+                    help="few-cluster sweep time over L and the seed-tile edge B, beside the oracle")
     ap.add_argument("--size-scan", action="store_true",
                     help="per-phase sweep time per spin over L = 64 .. 16384 (q = 2 at beta_c), beside the oracle")
     ap.add_argument("--tile-scan", action="store_true",
@@ -257,6 +259,61 @@ def _size_scan(args) -> int:
                "cpu_oracle_ns_per_spin": None if cpu_ns is None else round(cpu_ns, 3),
                "speedup_vs_oracle": None if cpu_ns is None else round(cpu_ns / (ms * 1e6 / N), 1)}
         print(json.dumps(row), flush=True)
+    oracle.use_flavor("O2")
+    return 0
+
+
+def _few_scan(args) -> int:
+    """Few-cluster sweeps (Sec. III; q = 2 at beta_c, p_flip = 1/2) over the
+    lattice size and the seed-tile edge B, from SW-equilibrated spins, beside
+    the oracle's few-cluster sweep on one host core: the analogue of the
+    paper's speed-up of the few-cluster variant over L with the best B."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1105_5804_amd as sw
+    from paper_1105_5804_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    oracle.use_flavor("native")
+    oracle.init_states(4, 4, 2, 1)  # builds the native oracle outside the timed calls
+    K, seed = wl.K_ISING_C, wl.SEED_BASE | 0xF8
+    for L in (256, 1024, 4096, 16384):
+        N = L * L
+        steps = max(args.steps, min(200, (1 << 26) // N))
+        base = sw.SWLattice(L, L, q=2, K=K, seed=seed)
+        base.sweep(max(args.warmup, 30))
+        torch.cuda.synchronize()
+        start = base.spins.clone()
+        del base
+        for B in (8, 32, 128, 512):
+            if B > L:
+                continue
+            lat = sw.SWLattice(L, L, q=2, K=K, seed=seed, few_b=B, p_flip=0.5, spins=start.clone(), t=1000)
+            lat.sweep(2)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            lat.sweep(steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            del lat
+            cpu_ns = None
+            if N <= 4096 * 4096:
+                st = ((start.cpu().numpy().reshape(-1).astype(np.int16) + 1) // 2).astype(np.uint8)
+                c = time.perf_counter()
+                oracle.few_sweep(L, L, oracle.threshold(K), oracle.prob_threshold(0.5), B, seed, 0, 1000, st)
+                cpu_ns = (time.perf_counter() - c) * 1e9 / N
+            row = {"L": L, "B": B, "seeds": ((L + B - 1) // B) ** 2, "sweeps": steps, "ms_per_sweep": round(ms, 5),
+                   "ns_per_spin": round(ms * 1e6 / N, 5),
+                   "cpu_oracle_ns_per_spin": None if cpu_ns is None else round(cpu_ns, 3),
+                   "speedup_vs_oracle": None if cpu_ns is None else round(cpu_ns / (ms * 1e6 / N), 1)}
+            print(json.dumps(row), flush=True)
+        del start
+        torch.cuda.empty_cache()
     oracle.use_flavor("O2")
     return 0
 
@@ -539,6 +596,8 @@ def main() -> int:
         return _tile_scan(args)
     if args.size_scan:
         return _size_scan(args)
+    if args.few_scan:
+        return _few_scan(args)
 
     import numpy as np
     import torch
