@@ -23,9 +23,10 @@ _SRC = os.path.join(_HERE, "swccl_oracle.c")
 _HDR = os.path.join(_HERE, "swccl_oracle.h")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-TAG_INIT, TAG_BOND, TAG_FLIP, TAG_SEED, TAG_FEW = 0, 1, 2, 3, 4
+TAG_INIT, TAG_BOND, TAG_FLIP, TAG_SEED, TAG_FEW, TAG_BOND_Z = 0, 1, 2, 3, 4, 5
 PERIODIC, OPEN = 0, 1
 REC_ACTIVE, REC_NCLUST, REC_MAXCL, REC_NSAT, REC_COUNTS, REC_LEN = 0, 1, 2, 3, 4, 12
+REC3_ACTIVE, REC3_NCLUST, REC3_NSAT, REC3_COUNTS, REC3_LEN = 0, 1, 2, 3, 11
 
 
 def build(force: bool = False) -> str:
@@ -132,6 +133,16 @@ def _declare(lib):
     lib.orc_few_sweep.argtypes = [c_i32, c_i32, c_u64, c_u64, c_i32, c_u64, c_u32, c_u32,
                                   u8p, u8p, i32p, i64p, i64p]
     lib.orc_few_sweep.restype = None
+    lib.orc3_activate_bonds.argtypes = [c_i32, c_i32, c_i32, u8p, c_u64, c_u64, c_u32, c_u32, u8p]
+    lib.orc3_activate_bonds.restype = None
+    lib.orc3_label_bonds.argtypes = [c_i32, c_i32, c_i32, u8p, i32p]
+    lib.orc3_label_bonds.restype = c_i64
+    lib.orc3_satisfied.argtypes = [c_i32, c_i32, c_i32, c_i32, u8p, i64p]
+    lib.orc3_satisfied.restype = c_i64
+    lib.orc3_sw_sweep.argtypes = [c_i32, c_i32, c_i32, c_i32, c_u64, c_u64, c_u32, c_u32, u8p, u8p, i32p, i64p]
+    lib.orc3_sw_sweep.restype = None
+    lib.orc3_sw_run.argtypes = [c_i32, c_i32, c_i32, c_i32, c_u64, c_u64, c_u32, c_u32, c_i32, u8p, i64p]
+    lib.orc3_sw_run.restype = None
     lib.orc_digest_u8.argtypes = [c_i64, u8p]
     lib.orc_digest_u8.restype = c_u64
     lib.orc_digest_i32.argtypes = [c_i64, i32p]
@@ -287,3 +298,52 @@ def few_sweep(W, H, T, Tflip, B, seed, sid, t, state):
     _load().orc_few_sweep(W, H, T, Tflip, B, seed, sid, t, _u8(st), _u8(bonds), _i32(labels), _i64(rec),
                           _i64(few))
     return st, bonds, labels, rec, (int(few[0]), int(few[1]))
+
+
+# ---------------------------------------------------------- cubic lattices --
+# Lx x Ly x Lz, periodic, site i = (z Ly + y) Lx + x; bond bits +x, +y, +z.
+def init_states3(Lx, Ly, Lz, q, seed, sid=0) -> np.ndarray:
+    """Initial states: those of the square lattice at the same site index."""
+    return init_states(Lx, Ly * Lz, q, seed, sid)
+
+
+def activate_bonds3(Lx, Ly, Lz, state, T, seed, t, sid=0) -> np.ndarray:
+    st = np.ascontiguousarray(state, dtype=np.uint8).reshape(-1)
+    bonds = np.zeros(Lx * Ly * Lz, dtype=np.uint8)
+    _load().orc3_activate_bonds(Lx, Ly, Lz, _u8(st), T, seed, t, sid, _u8(bonds))
+    return bonds
+
+
+def label_bonds3(Lx, Ly, Lz, bonds):
+    """(labels, n_clusters) of packed 3D bond bytes (bit0 +x, bit1 +y, bit2 +z)."""
+    b = np.ascontiguousarray(bonds, dtype=np.uint8).reshape(-1)
+    labels = np.zeros(Lx * Ly * Lz, dtype=np.int32)
+    n = _load().orc3_label_bonds(Lx, Ly, Lz, _u8(b), _i32(labels))
+    return labels, int(n)
+
+
+def satisfied3(Lx, Ly, Lz, q, state):
+    """(n_sat over the 3N bonds, counts[8])."""
+    st = np.ascontiguousarray(state, dtype=np.uint8).reshape(-1)
+    counts = np.zeros(8, dtype=np.int64)
+    n = _load().orc3_satisfied(Lx, Ly, Lz, q, _u8(st), _i64(counts))
+    return int(n), counts
+
+
+def sw3_sweep(Lx, Ly, Lz, q, T, seed, sid, t, state):
+    """One sweep of the cubic lattice; returns (new_state, bonds, labels, record)."""
+    N = Lx * Ly * Lz
+    st = np.array(state, dtype=np.uint8).reshape(-1)
+    bonds = np.zeros(N, dtype=np.uint8)
+    labels = np.zeros(N, dtype=np.int32)
+    rec = np.zeros(REC3_LEN, dtype=np.int64)
+    _load().orc3_sw_sweep(Lx, Ly, Lz, q, T, seed, sid, t, _u8(st), _u8(bonds), _i32(labels), _i64(rec))
+    return st, bonds, labels, rec
+
+
+def sw3_run(Lx, Ly, Lz, q, T, seed, sid, t0, n, state):
+    """n sweeps of the cubic lattice in C; returns (final_state, records[n, REC3_LEN])."""
+    st = np.array(state, dtype=np.uint8).reshape(-1)
+    rec = np.zeros((max(n, 1), REC3_LEN), dtype=np.int64)
+    _load().orc3_sw_run(Lx, Ly, Lz, q, T, seed, sid, t0, n, _u8(st), _i64(rec))
+    return st, rec[:n]

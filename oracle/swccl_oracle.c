@@ -15,7 +15,9 @@
  *   - union-and-find with roots as set representatives, Sec. II.B.2;
  *   - the few-cluster variant of the Wolff update (Sec. III): the same bond
  *     decomposition, one seed per seed tile, every distinct seeded cluster
- *     flipped with a probability p_flip < 1.
+ *     flipped with a probability p_flip < 1;
+ *   - the same three steps on the simple cubic lattice (the generalisation to
+ *     three dimensions that Sec. II names): three bonds per site.
  * Philox4x32-10 follows its published definition (Salmon, Moraes, Dror, Shaw,
  * "Parallel random numbers: as easy as 1, 2, 3", SC'11).
  */
@@ -432,6 +434,113 @@ void orc_sw_run(int32_t W, int32_t H, int32_t q, uint64_t T, uint64_t seed,
     for (int32_t k = 0; k < n; ++k)
         orc_sw_sweep(W, H, q, T, seed, sid, t0 + (uint32_t)k, state, b, l,
                      rec ? rec + (int64_t)k * ORC_REC_LEN : NULL);
+    free(b);
+    free(l);
+}
+
+/* ------------------------------------------------------- cubic lattices -- */
+
+/* Step 1 on the simple cubic lattice: the bond-activation rule of Sec. II.A
+ * applied to the +x, +y and +z bond of every site. */
+void orc3_activate_bonds(int32_t Lx, int32_t Ly, int32_t Lz, const uint8_t *state, uint64_t T,
+                         uint64_t seed, uint32_t t, uint32_t sid, uint8_t *bonds)
+{
+    for (int32_t z = 0; z < Lz; ++z) {
+        for (int32_t y = 0; y < Ly; ++y) {
+            for (int32_t x = 0; x < Lx; ++x) {
+                int64_t i = ((int64_t)z * Ly + y) * Lx + x;
+                int64_t nx = ((int64_t)z * Ly + y) * Lx + (x + 1) % Lx;
+                int64_t ny = ((int64_t)z * Ly + (y + 1) % Ly) * Lx + x;
+                int64_t nz = ((int64_t)((z + 1) % Lz) * Ly + y) * Lx + x;
+                uint32_t b[4], bz[4];
+                block_for(seed, (uint32_t)(i >> 1), t, ORC_TAG_BOND, sid, b);
+                block_for(seed, (uint32_t)(i >> 2), t, ORC_TAG_BOND_Z, sid, bz);
+                int ax = state[i] == state[nx] && (uint64_t)b[2 * (i & 1)] < T;
+                int ay = state[i] == state[ny] && (uint64_t)b[2 * (i & 1) + 1] < T;
+                int az = state[i] == state[nz] && (uint64_t)bz[i & 3] < T;
+                bonds[i] = (uint8_t)(ax | (ay << 1) | (az << 2));
+            }
+        }
+    }
+}
+
+/* Step 2 on the cubic lattice: union-and-find over every active bond
+ * (Sec. II.B.2), canonical minimum-index labels. */
+int64_t orc3_label_bonds(int32_t Lx, int32_t Ly, int32_t Lz, const uint8_t *bonds, int32_t *labels)
+{
+    int64_t N = (int64_t)Lx * Ly * Lz;
+    int32_t *parent = (int32_t *)malloc((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
+    for (int64_t i = 0; i < N; ++i) parent[i] = (int32_t)i;
+    for (int32_t z = 0; z < Lz; ++z) {
+        for (int32_t y = 0; y < Ly; ++y) {
+            for (int32_t x = 0; x < Lx; ++x) {
+                int32_t i = (z * Ly + y) * Lx + x;
+                if (bonds[i] & 1) uf_union(parent, i, (z * Ly + y) * Lx + (x + 1) % Lx);
+                if (bonds[i] & 2) uf_union(parent, i, (z * Ly + (y + 1) % Ly) * Lx + x);
+                if (bonds[i] & 4) uf_union(parent, i, (((z + 1) % Lz) * Ly + y) * Lx + x);
+            }
+        }
+    }
+    int64_t n = uf_flatten(parent, N, labels);
+    free(parent);
+    return n;
+}
+
+/* -H/J of Eq. potts_hamiltonian on the cubic lattice: satisfied bonds among
+ * the 3N nearest-neighbour pairs (each site's +x, +y and +z pair). */
+int64_t orc3_satisfied(int32_t Lx, int32_t Ly, int32_t Lz, int32_t q, const uint8_t *state,
+                       int64_t counts[8])
+{
+    int64_t nsat = 0;
+    if (counts)
+        for (int k = 0; k < 8; ++k) counts[k] = 0;
+    for (int32_t z = 0; z < Lz; ++z) {
+        for (int32_t y = 0; y < Ly; ++y) {
+            for (int32_t x = 0; x < Lx; ++x) {
+                int64_t i = ((int64_t)z * Ly + y) * Lx + x;
+                nsat += state[i] == state[((int64_t)z * Ly + y) * Lx + (x + 1) % Lx];
+                nsat += state[i] == state[((int64_t)z * Ly + (y + 1) % Ly) * Lx + x];
+                nsat += state[i] == state[((int64_t)((z + 1) % Lz) * Ly + y) * Lx + x];
+                if (counts && state[i] < 8 && state[i] < q) counts[state[i]]++;
+            }
+        }
+    }
+    return nsat;
+}
+
+void orc3_sw_sweep(int32_t Lx, int32_t Ly, int32_t Lz, int32_t q, uint64_t T, uint64_t seed,
+                   uint32_t sid, uint32_t t, uint8_t *state, uint8_t *bonds, int32_t *labels,
+                   int64_t *rec)
+{
+    int64_t N = (int64_t)Lx * Ly * Lz;
+    uint8_t *b = bonds ? bonds : (uint8_t *)malloc((size_t)N);
+    int32_t *l = labels ? labels : (int32_t *)malloc((size_t)N * sizeof(int32_t));
+
+    orc3_activate_bonds(Lx, Ly, Lz, state, T, seed, t, sid, b);
+    int64_t ncl = orc3_label_bonds(Lx, Ly, Lz, b, l);
+    if (rec) {
+        int64_t active = 0;
+        for (int64_t i = 0; i < N; ++i) active += (b[i] & 1) + ((b[i] >> 1) & 1) + ((b[i] >> 2) & 1);
+        rec[ORC3_REC_ACTIVE] = active;
+        rec[ORC3_REC_NCLUST] = ncl;
+    }
+    /* step 3 is the square lattice's: one draw per canonical root */
+    orc_flip(Lx, Ly * Lz, q, l, seed, t, sid, state);
+    if (rec) rec[ORC3_REC_NSAT] = orc3_satisfied(Lx, Ly, Lz, q, state, rec + ORC3_REC_COUNTS);
+
+    if (!bonds) free(b);
+    if (!labels) free(l);
+}
+
+void orc3_sw_run(int32_t Lx, int32_t Ly, int32_t Lz, int32_t q, uint64_t T, uint64_t seed,
+                 uint32_t sid, uint32_t t0, int32_t n, uint8_t *state, int64_t *rec)
+{
+    int64_t N = (int64_t)Lx * Ly * Lz;
+    uint8_t *b = (uint8_t *)malloc((size_t)N);
+    int32_t *l = (int32_t *)malloc((size_t)N * sizeof(int32_t));
+    for (int32_t k = 0; k < n; ++k)
+        orc3_sw_sweep(Lx, Ly, Lz, q, T, seed, sid, t0 + (uint32_t)k, state, b, l,
+                      rec ? rec + (int64_t)k * ORC3_REC_LEN : NULL);
     free(b);
     free(l);
 }

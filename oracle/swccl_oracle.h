@@ -30,7 +30,8 @@
 extern "C" {
 #endif
 
-enum { ORC_TAG_INIT = 0, ORC_TAG_BOND = 1, ORC_TAG_FLIP = 2, ORC_TAG_SEED = 3, ORC_TAG_FEW = 4 };
+enum { ORC_TAG_INIT = 0, ORC_TAG_BOND = 1, ORC_TAG_FLIP = 2, ORC_TAG_SEED = 3, ORC_TAG_FEW = 4,
+       ORC_TAG_BOND_Z = 5 };
 enum { ORC_PERIODIC = 0, ORC_OPEN = 1 };
 
 /* Per-sweep record written by orc_sw_run (one row of ORC_REC_LEN int64). */
@@ -113,6 +114,40 @@ void orc_few_sweep(int32_t W, int32_t H, uint64_t T, uint64_t Tflip, int32_t B,
 /* n sweeps t0..t0+n-1, one record per sweep into rec[n][ORC_REC_LEN]. */
 void orc_sw_run(int32_t W, int32_t H, int32_t q, uint64_t T, uint64_t seed,
                 uint32_t sid, uint32_t t0, int32_t n, uint8_t *state, int64_t *rec);
+
+/* ---- Simple cubic lattices (the 3D generalisation of Sec. II) ----
+ * Lx x Ly x Lz sites, periodic along all three axes, site index
+ * i = (z*Ly + y)*Lx + x, N < 2^31.  Site i owns the +x bond to
+ * (x+1 mod Lx, y, z), the +y bond to (x, y+1 mod Ly, z) and the +z bond to
+ * (x, y, z+1 mod Lz); packed bond byte: bit0 = +x, bit1 = +y, bit2 = +z.
+ * The +x and +y words are those of the square lattice at the same index
+ * (block(i>>1, t, BOND), words 2(i&1) and 2(i&1)+1); the +z word is
+ * block(i>>2, t, BOND_Z)[i&3].  Initial states and cluster draws are those of
+ * the square lattice at the same index.  With Lz = 1 the +z bond joins a site
+ * to itself, and a sweep equals the square-lattice sweep of Lx x Ly. */
+enum {
+    ORC3_REC_ACTIVE = 0,  /* active bonds (all three directions)        */
+    ORC3_REC_NCLUST = 1,  /* clusters                                   */
+    ORC3_REC_NSAT = 2,    /* satisfied bonds of the spins after the flip */
+    ORC3_REC_COUNTS = 3,  /* counts[0..7] of states after the flip       */
+    ORC3_REC_LEN = 11
+};
+void orc3_activate_bonds(int32_t Lx, int32_t Ly, int32_t Lz, const uint8_t *state, uint64_t T,
+                         uint64_t seed, uint32_t t, uint32_t sid, uint8_t *bonds);
+/* Canonical labels of a packed 3D bond configuration (all bonds periodic);
+ * returns the cluster count. */
+int64_t orc3_label_bonds(int32_t Lx, int32_t Ly, int32_t Lz, const uint8_t *bonds, int32_t *labels);
+/* Satisfied bonds over all 3N bonds and, for k < min(q, 8), state counts. */
+int64_t orc3_satisfied(int32_t Lx, int32_t Ly, int32_t Lz, int32_t q, const uint8_t *state,
+                       int64_t counts[8]);
+/* One SW sweep t of the cubic lattice in place; bonds/labels/rec as for
+ * orc_sw_sweep (rec: one ORC3_REC_LEN record). */
+void orc3_sw_sweep(int32_t Lx, int32_t Ly, int32_t Lz, int32_t q, uint64_t T, uint64_t seed,
+                   uint32_t sid, uint32_t t, uint8_t *state, uint8_t *bonds, int32_t *labels,
+                   int64_t *rec);
+/* n sweeps t0..t0+n-1, one record per sweep into rec[n][ORC3_REC_LEN]. */
+void orc3_sw_run(int32_t Lx, int32_t Ly, int32_t Lz, int32_t q, uint64_t T, uint64_t seed,
+                 uint32_t sid, uint32_t t0, int32_t n, uint8_t *state, int64_t *rec);
 
 #ifdef __cplusplus
 }

@@ -9,7 +9,9 @@ algorithms for the same mathematical objects:
   configurations at once (used for exhaustive enumeration of tiny tori);
 * ``potts_exact`` -- exact Boltzmann averages by enumerating every spin state;
 * ``fk_exact`` -- exact random-cluster (Fortuin-Kasteleyn) expectations by
-  enumerating every bond set of a tiny torus, Eq. random_cluster.
+  enumerating every bond set of a tiny torus, Eq. random_cluster;
+* ``cubic_edges`` / ``bfs_labels_cubic`` -- the bonds of a periodic simple
+  cubic lattice and BFS labels of a packed 3D bond configuration.
 """
 from __future__ import annotations
 
@@ -230,3 +232,46 @@ __all__ = [
     "crossing_bits",
     "binned_error",
 ]
+
+
+def cubic_edges(Lx: int, Ly: int, Lz: int):
+    """List of (i, j, bit, owner) for every bond of the periodic Lx x Ly x Lz
+    simple cubic lattice, site i = (z Ly + y) Lx + x: bit 1 = +x, 2 = +y, 4 = +z."""
+    edges = []
+    for z in range(Lz):
+        for y in range(Ly):
+            for x in range(Lx):
+                i = (z * Ly + y) * Lx + x
+                edges.append((i, (z * Ly + y) * Lx + (x + 1) % Lx, 1, i))
+                edges.append((i, (z * Ly + (y + 1) % Ly) * Lx + x, 2, i))
+                edges.append((i, (((z + 1) % Lz) * Ly + y) * Lx + x, 4, i))
+    return edges
+
+
+def bfs_labels_cubic(Lx: int, Ly: int, Lz: int, bonds: np.ndarray) -> np.ndarray:
+    """Canonical labels (minimum site index per component) of packed cubic
+    bonds, by BFS over an explicit adjacency list."""
+    N = Lx * Ly * Lz
+    adj = [[] for _ in range(N)]
+    for i, j, bit, owner in cubic_edges(Lx, Ly, Lz):
+        if bonds[owner] & bit:
+            adj[i].append(j)
+            adj[j].append(i)
+    labels = np.full(N, -1, dtype=np.int64)
+    for s in range(N):
+        if labels[s] >= 0:
+            continue
+        comp = [s]
+        labels[s] = s
+        dq = deque([s])
+        while dq:
+            u = dq.popleft()
+            for v in adj[u]:
+                if labels[v] < 0:
+                    labels[v] = s
+                    comp.append(v)
+                    dq.append(v)
+        m = min(comp)
+        for v in comp:
+            labels[v] = m
+    return labels

@@ -88,7 +88,10 @@ def test_counter_layout_matches_rocrand():
 MUTANTS = {
     "right/down words swapped": [("uint32_t r_right = b[2 * (i & 1)];", "uint32_t r_right = b[2 * (i & 1) + 1];"),
                                  ("uint32_t r_down = b[2 * (i & 1) + 1];", "uint32_t r_down = b[2 * (i & 1)];")],
-    "bond block index i>>2": [("(uint32_t)(i >> 1), t, ORC_TAG_BOND", "(uint32_t)(i >> 2), t, ORC_TAG_BOND")],
+    "bond block index i>>2": [("block_for(seed, (uint32_t)(i >> 1), t, ORC_TAG_BOND, sid, b);\n"
+                               "            uint32_t r_right",
+                               "block_for(seed, (uint32_t)(i >> 2), t, ORC_TAG_BOND, sid, b);\n"
+                               "            uint32_t r_right")],
     "init word reversed": [("state[i] = state_from_word(b[i & 3], q);", "state[i] = state_from_word(b[3 - (i & 3)], q);")],
     "flip word shifted": [("root_state[r] = state_from_word(b[r & 3], q);",
                            "root_state[r] = state_from_word(b[(r + 1) & 3], q);")],
