@@ -70,7 +70,7 @@
 extern "C" {
 #endif
 
-#define SWCCL_ABI_VERSION 5
+#define SWCCL_ABI_VERSION 6
 
 typedef int32_t sw_status;
 enum {
@@ -442,6 +442,68 @@ sw_status ccl_server_release(ccl_server *s, int32_t slot);
 
 /* Wait for requests still running and free the host object. */
 sw_status ccl_server_destroy(ccl_server *s);
+
+/* ---- Simple cubic lattices: the SW sweep in three dimensions.
+ *
+ * The same three steps (Sec. II) on the periodic Lx x Ly x Lz simple cubic
+ * lattice, the generalisation to three dimensions that Sec. II names: six
+ * neighbours per site, -H/J = number of satisfied bonds among the 3N
+ * nearest-neighbour pairs (Eq. potts_hamiltonian).
+ *
+ * Conventions (bit-exact, shared by definition with the oracle):
+ *   - site index i = (z*Ly + y)*Lx + x (x fastest), N = Lx*Ly*Lz < 2^31.
+ *   - site i owns the +x bond to (x+1 mod Lx, y, z), the +y bond to
+ *     (x, y+1 mod Ly, z) and the +z bond to (x, y, z+1 mod Lz).  Packed bond
+ *     byte: bit0 = +x, bit1 = +y, bit2 = +z.
+ *   - the +x and +y words are the square lattice's right and down words at
+ *     the same index (block(i>>1, t, tag 1), words 2(i&1) and 2(i&1)+1); the
+ *     +z word is word i&3 of block(i>>2, t, tag 5).  Initial states (tag 0),
+ *     the activation rule r < T, the canonical (minimum-index) labels and the
+ *     per-cluster draw (tag 2) are the square lattice's.  With Lz = 1 the +z
+ *     bond joins a site to itself and the sweep follows the Lx x Ly
+ *     square-lattice trajectory exactly.
+ *
+ * The library labels on tiles of 128 x 8 x 8 sites (bonds fused with a
+ * union-find in LDS; the clusters touching a tile face get compact ids),
+ * merges the ids over the bonds that cross tile faces, then resolves every
+ * id, draws one state per cluster and writes the spins (Sec. II.B-II.D). */
+typedef struct sw3_params {
+    int32_t Lx, Ly, Lz;  /* extents, each >= 1, Lx*Ly*Lz < 2^31           */
+    int32_t q;           /* Potts states, 2..255 (2 for Ising)             */
+    int32_t spin_kind;   /* SW_SPIN_ISING_I8 (q = 2) or SW_SPIN_POTTS_U8   */
+    uint32_t flags;      /* 0 (no flags are defined)                       */
+    double K;            /* FK coupling: p = 1 - exp(-K), as sw_params.K   */
+    uint64_t seed;       /* Philox key                                     */
+    uint32_t stream_id;  /* fourth counter word                            */
+    int32_t reserved;    /* 0                                              */
+} sw3_params;
+
+/* One per-sweep record of sw3_sweep: int64 fields. */
+enum { SW3_REC_ACTIVE = 0, SW3_REC_NCLUST = 1, SW3_REC_NSAT = 2, SW3_REC_COUNTS = 3, SW3_REC_LEN = 11 };
+
+/* Workspace bytes sw3_sweep needs for these parameters (0 if they are
+ * invalid).  About 2 bytes per site of codes, 1 of bonds and 8 per tile
+ * boundary site of ids. */
+size_t sw3_workspace_bytes(const sw3_params *p);
+
+/* Initial states of the N sites (device, N bytes, stored as spin_kind says):
+ * the square lattice's init draws at the same site index (Sec. II step 3
+ * applied to a random start).  Errors: SW_ERR_ARG (null spins, bad
+ * parameters), SW_ERR_SIZE (extents). */
+sw_status sw3_init_spins(const sw3_params *p, uint8_t *spins, void *stream);
+
+/* n >= 0 SW sweeps t0 .. t0+n-1 of the cubic lattice, in place on `spins`
+ * (device, N bytes, stored as spin_kind says).  Optional device outputs
+ * (NULL to skip): `bonds` (N bytes) receives the packed bonds and `labels`
+ * (N int32) the canonical labels of the last sweep (both of its spins before
+ * the flip); `records` (n x SW3_REC_LEN int64) one record per sweep: active
+ * bonds, clusters, then satisfied bonds and state counts 0..7 of the spins
+ * after the flip.  `workspace` (device, 256-byte aligned, at least
+ * sw3_workspace_bytes) is scratch; its contents need not be kept between
+ * calls.  Errors: SW_ERR_ARG, SW_ERR_SIZE, SW_ERR_WORKSPACE, SW_ERR_STATE
+ * (t0 + n passes 2^32), SW_ERR_DEVICE. */
+sw_status sw3_sweep(const sw3_params *p, uint8_t *spins, uint32_t t0, int32_t n, uint8_t *bonds, int32_t *labels,
+                    int64_t *records, void *workspace, size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,7 @@ from ._lib import (  # noqa: F401
 
 __all__ = [
     "SWLattice",
+    "CubicLattice",
     "SWBatch",
     "ccl_label",
     "ccl_label_noalloc",
@@ -53,6 +54,9 @@ def potts_K(beta: float, J: float = 1.0) -> float:
 
 
 BETA_C_ISING = 0.5 * math.log1p(math.sqrt(2.0))
+# critical coupling of the 3D Ising model on the simple cubic lattice (from
+# the Monte Carlo literature; no closed form is known)
+BETA_C_ISING_3D = 0.22165455
 
 
 def _torch():
@@ -235,6 +239,74 @@ class SWLattice:
             self.close()
         except Exception:
             pass
+
+
+class CubicLattice:
+    """One periodic Lx x Ly x Lz simple cubic lattice advanced by SW sweeps.
+
+    ``spins`` is an (Lz, Ly, Lx) int8 (Ising, +-1) or uint8 (Potts, 0..q-1)
+    tensor.  With ``keep_labels`` / ``keep_bonds`` the canonical labels /
+    packed bonds (bit0 +x, bit1 +y, bit2 +z) of the last sweep of each call
+    are kept in ``labels`` / ``bonds``.  ``sweep(n, records=True)`` returns the
+    (n, 11) int64 device tensor of per-sweep records (active bonds, clusters,
+    satisfied bonds and counts[8] of the new spins).  The host keeps the sweep
+    counter ``t``; the calls enqueue on the current (or given) stream and do
+    not wait.
+    """
+
+    def __init__(self, Lx: int, Ly: int, Lz: int, q: int = 2, K: float | None = None, seed: int = 0,
+                 stream_id: int = 0, ising: bool | None = None, keep_labels: bool = False,
+                 keep_bonds: bool = False, spins=None, t: int = 0, device: str = "cuda"):
+        torch = _torch()
+        L = _lib.lib()
+        if ising is None:
+            ising = q == 2
+        if K is None:
+            K = ising_K(BETA_C_ISING_3D) if q == 2 else math.log1p(math.sqrt(q))
+        self.Lx, self.Ly, self.Lz, self.q, self.K = int(Lx), int(Ly), int(Lz), int(q), float(K)
+        self.seed, self.stream_id, self.ising = int(seed), int(stream_id), bool(ising)
+        self.device = torch.device(device)
+        self._params = _lib.Sw3Params(self.Lx, self.Ly, self.Lz, self.q,
+                                      _lib.SW_SPIN_ISING_I8 if ising else _lib.SW_SPIN_POTTS_U8, 0, self.K,
+                                      self.seed & (2**64 - 1), self.stream_id, 0)
+        ws = L.sw3_workspace_bytes(ctypes.byref(self._params))
+        if ws == 0:
+            bad_size = min(self.Lx, self.Ly, self.Lz) < 1 or self.Lx * self.Ly * self.Lz >= 2**31
+            _lib.check(_lib.SW_ERR_SIZE if bad_size else _lib.SW_ERR_ARG, "sw3_workspace_bytes")
+        shape = (self.Lz, self.Ly, self.Lx)
+        dt = torch.int8 if ising else torch.uint8
+        self._ws_buf, self._ws_ptr = _workspace(torch, ws, self.device)
+        self._ws = ws
+        self.labels = torch.empty(shape, dtype=torch.int32, device=self.device) if keep_labels else None
+        self.bonds = torch.empty(shape, dtype=torch.uint8, device=self.device) if keep_bonds else None
+        if spins is not None:
+            if tuple(spins.shape) != shape or spins.dtype != dt or spins.device.type != "cuda":
+                raise ValueError(f"spins must be a {shape} {dt} GPU tensor")
+            self.spins = spins.contiguous()
+        else:
+            self.spins = torch.empty(shape, dtype=dt, device=self.device)
+            _lib.check(L.sw3_init_spins(ctypes.byref(self._params), self.spins.data_ptr(), _stream(torch)),
+                       "sw3_init_spins")
+        self.t = int(t)
+
+    @property
+    def threshold(self) -> int:
+        return threshold(self.K)
+
+    def sweep(self, n: int = 1, records: bool = False, stream=None):
+        """Enqueue n sweeps t .. t+n-1 and advance t; with ``records`` return
+        their (n, 11) int64 device tensor of per-sweep records."""
+        torch = _torch()
+        rec = None
+        if records:
+            rec = torch.empty((max(int(n), 1), _lib.SW3_REC_LEN), dtype=torch.int64, device=self.device)
+        _lib.check(_lib.lib().sw3_sweep(ctypes.byref(self._params), self.spins.data_ptr(), int(self.t), int(n),
+                                        self.bonds.data_ptr() if self.bonds is not None else None,
+                                        self.labels.data_ptr() if self.labels is not None else None,
+                                        rec.data_ptr() if rec is not None else None, self._ws_ptr, self._ws,
+                                        _stream(torch, stream)), "sw3_sweep")
+        self.t += int(n)
+        return rec[: int(n)] if rec is not None else None
 
 
 class SWBatch:

@@ -7,7 +7,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libswccl.so")
 
-ABI_VERSION = 5  # the SWCCL_ABI_VERSION these declarations follow
+ABI_VERSION = 6  # the SWCCL_ABI_VERSION these declarations follow
 
 # status codes
 SW_OK, SW_ERR_ARG, SW_ERR_SIZE, SW_ERR_WORKSPACE, SW_ERR_DEVICE, SW_ERR_STATE, SW_ERR_UNSUPPORTED, SW_ERR_HOST_MEMORY = range(8)
@@ -19,6 +19,7 @@ TILE_HEIGHTS = (16, 32, 64, 128)  # sw_params.tile_h (0: 64)
 MERGE_WAVES = (4, 8, 16)          # sw_params.merge_waves (0: 8)
 SW_PHASE_TILE, SW_PHASE_MERGE, SW_PHASE_FLIP = 0, 1, 2
 SW_HIST_ACTIVE, SW_HIST_NCLUST, SW_HIST_MAXCL, SW_HIST_NSAT, SW_HIST_COUNTS, SW_HIST_LEN = 0, 1, 2, 3, 4, 12
+SW3_REC_ACTIVE, SW3_REC_NCLUST, SW3_REC_NSAT, SW3_REC_COUNTS, SW3_REC_LEN = 0, 1, 2, 3, 11
 
 
 class SwParams(ctypes.Structure):
@@ -64,6 +65,21 @@ class SwObs(ctypes.Structure):
         ("digest_spins", ctypes.c_uint64),
         ("digest_labels", ctypes.c_uint64),
         ("digest_bonds", ctypes.c_uint64),
+    ]
+
+
+class Sw3Params(ctypes.Structure):
+    _fields_ = [
+        ("Lx", ctypes.c_int32),
+        ("Ly", ctypes.c_int32),
+        ("Lz", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("spin_kind", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("K", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("stream_id", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -136,6 +152,11 @@ SIGNATURES = {
     "ccl_label": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "sw3_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Sw3Params)]),
+    "sw3_init_spins": (ctypes.c_int32, [ctypes.POINTER(Sw3Params), ctypes.c_void_p, ctypes.c_void_p]),
+    "sw3_sweep": (ctypes.c_int32, [ctypes.POINTER(Sw3Params), ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_size_t, ctypes.c_void_p]),
     "ccl_label_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p]),

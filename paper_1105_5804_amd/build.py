@@ -7,7 +7,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRCS = [os.path.join(HERE, "csrc", "swccl.hip"), os.path.join(HERE, "csrc", "server.hip")]
+SRCS = [os.path.join(HERE, "csrc", "swccl.hip"), os.path.join(HERE, "csrc", "server.hip"),
+        os.path.join(HERE, "csrc", "cubic.hip")]
 LIB = os.path.join(HERE, "libswccl.so")
 
 # -packed-fp32-ops keeps the compiler away from packed fp32 instructions.

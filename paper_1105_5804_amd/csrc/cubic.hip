@@ -1,0 +1,568 @@
+// cubic.hip -- the SW sweep on the periodic simple cubic lattice: the same
+// three steps as on the square lattice (Sec. II), generalised to three
+// dimensions, and the host side of the sw3_* calls of include/swccl.h.
+//
+// A sweep is three launches:
+//
+//   k3_tile     one 512-thread workgroup per 128 x 8 x 8 tile; each wave owns
+//               one z-plane of the tile (8 rows of 128 sites, two per lane).
+//               Bond activation of the +x, +y and +z bonds (Sec. II.A) fused
+//               with a lock-free union-find in LDS over the bonds that stay in
+//               the tile (Sec. II.B.2); the clusters touching any tile face
+//               are claimed and get compact ids; every site gets a 16-bit code
+//               (its cluster's id, or CAP + the slot of its interior root).
+//   k3_merge    every active bond that leaves a tile through its +x, +y or +z
+//               face (periodic wraps included) unites two ids in the global
+//               union-find, whose roots carry the minimum site index of their
+//               clusters (Sec. II.C).
+//   k3_flatten  every id resolved to its root and key, one draw per cluster
+//               at its minimum site index (Sec. II.D), spins and optionally
+//               labels written.
+//
+// With per-sweep records, k3_observe counts the satisfied bonds and states of
+// the new spins and k3_record moves the counters into the record.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/swccl.h"
+#include "internal.hpp"
+#include "philox.hpp"
+#include "uf.hpp"
+
+namespace swccl {
+namespace cubic {
+
+constexpr int CX = 128, CY = 8, CZ = 8;                       // tile extent: a wave owns a z-plane of CY rows
+constexpr int PLANE = CX * CY;                                 // sites of a tile z-plane
+constexpr int CSITES = PLANE * CZ;                             // 8192 sites per tile
+constexpr int CAP = CSITES - (CX - 2) * (CY - 2) * (CZ - 2);   // 3656: sites on a face of a full tile
+constexpr int NT3 = 64 * CZ;                                   // one wave per z-plane
+constexpr int MT = 256;                                        // merge workgroup
+constexpr int FX = CY * CZ, FY = CX * CZ, FZ = CX * CY;        // sites of the +x, +y, +z faces
+constexpr uint32_t TAG_BOND = 1, TAG_FLIP = 2, TAG_BOND_Z = 5;
+constexpr int CLAIMING = -1;
+constexpr uint16_t CODE_NONE = 0xFFFF;
+static_assert(CAP + CSITES < CODE_NONE, "codes are 16-bit");
+static_assert(CY * 6 <= 64, "a lane's bonds fit one 64-bit mask");
+
+// Counters of a sweep, in the order of the record fields.
+enum { S3_ACTIVE = 0, S3_NCLUST = 1, S3_NSAT = 2, S3_COUNTS = 3, S3_LEN = 11 };
+
+struct Geo3 {
+    int Lx, Ly, Lz;
+    int ntx, nty, ntz, ntiles;
+};
+
+// Tile of a workgroup and its extent (ragged at the +x, +y, +z ends).
+struct TileOf {
+    int tile, gx0, gy0, gz0, tw, th, td;
+};
+__device__ __forceinline__ TileOf tile_of(const Geo3 &g, int tile)
+{
+    const int tx = tile % g.ntx, ty = (tile / g.ntx) % g.nty, tz = tile / (g.ntx * g.nty);
+    TileOf t;
+    t.tile = tile;
+    t.gx0 = tx * CX;
+    t.gy0 = ty * CY;
+    t.gz0 = tz * CZ;
+    t.tw = min(CX, g.Lx - t.gx0);
+    t.th = min(CY, g.Ly - t.gy0);
+    t.td = min(CZ, g.Lz - t.gz0);
+    return t;
+}
+
+// Site index of tile slot s = (lz CY + ly) CX + lx.
+__device__ __forceinline__ int32_t site_of(const Geo3 &g, const TileOf &t, int s)
+{
+    const int lz = s / PLANE, ly = (s / CX) % CY, lx = s % CX;
+    return static_cast<int32_t>((static_cast<int64_t>(t.gz0 + lz) * g.Ly + t.gy0 + ly) * g.Lx + t.gx0 + lx);
+}
+
+struct Tile3Args {
+    Geo3 g;
+    const uint8_t *spins;
+    uint8_t *bonds;           // [N] packed bonds of the sweep (bit0 +x, bit1 +y, bit2 +z)
+    uint16_t *codes;          // [ntiles][CSITES]
+    int32_t *gkey, *gparent;  // [ntiles][CAP]
+    int32_t *nb;              // [ntiles]: ids of the tile
+    unsigned long long *stats;
+    uint32_t tm1, tany;       // a bond is active iff its word r <= tm1 and tany (T > 0; tm1 = T - 1)
+    uint32_t k0, k1, t, sid;
+};
+
+__global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
+{
+    __shared__ int P[CSITES];
+    __shared__ int nb_s;
+    const Geo3 g = a.g;
+    const TileOf T = tile_of(g, xcd_remap(blockIdx.x, g.ntiles));
+    const int lane = threadIdx.x & 63, lz = wave_id();
+    const int lx0 = 2 * lane;
+    const bool v0 = lx0 < T.tw, v1 = lx0 + 1 < T.tw;
+    if (threadIdx.x == 0) nb_s = 0;
+    for (int s = threadIdx.x; s < CSITES; s += NT3) P[s] = s;
+
+    // Bonds of the lane's two sites in each of the wave's rows; bit
+    // 6 ly + 3 j + d of `inside` is bond d (0 +x, 1 +y, 2 +z) of site
+    // lx0 + j when it stays in the tile (the others cross a face and are
+    // merged by k3_merge from the bond array).
+    uint64_t inside = 0;
+    unsigned act = 0;
+    if (lz < T.td) {
+        const int gz = T.gz0 + lz, zn = gz + 1 == g.Lz ? 0 : gz + 1;
+        // lanes past a ragged edge read a valid column and store nothing
+        const int xs0 = T.gx0 + min(lx0, T.tw - 1), xs1 = T.gx0 + min(lx0 + 1, T.tw - 1);
+        const int xn0 = xs0 + 1 == g.Lx ? 0 : xs0 + 1, xn1 = xs1 + 1 == g.Lx ? 0 : xs1 + 1;
+        const uint32_t in_x = (lx0 + 1 < T.tw ? 1u : 0u) | (lx0 + 2 < T.tw ? 8u : 0u);
+        const uint32_t in_z = lz + 1 < T.td ? 0x24u : 0u;
+        for (int ly = 0; ly < T.th; ++ly) {
+            const int gy = T.gy0 + ly, yn = gy + 1 == g.Ly ? 0 : gy + 1;
+            const int64_t row = (static_cast<int64_t>(gz) * g.Ly + gy) * g.Lx;
+            const int64_t rowy = (static_cast<int64_t>(gz) * g.Ly + yn) * g.Lx;
+            const int64_t rowz = (static_cast<int64_t>(zn) * g.Ly + gy) * g.Lx;
+            const uint32_t s0 = a.spins[row + xs0], s1 = a.spins[row + xs1];
+            const uint32_t x0 = a.spins[row + xn0], x1 = a.spins[row + xn1];
+            const uint32_t y0 = a.spins[rowy + xs0], y1 = a.spins[rowy + xs1];
+            const uint32_t z0 = a.spins[rowz + xs0], z1 = a.spins[rowz + xs1];
+            // words: +x and +y from block(i >> 1, BOND) as on the square
+            // lattice, +z word i & 3 of block(i >> 2, BOND_Z)
+            const int64_t i0 = row + T.gx0 + lx0;
+            const uint32_t c0 = static_cast<uint32_t>(i0 >> 1);
+            const U4 b = philox4x32_10(c0, a.t, TAG_BOND, a.sid, a.k0, a.k1);
+            uint32_t rx0, ry0, rx1, ry1;
+            if ((i0 & 1) == 0) {  // the row start's parity is the row's: uniform
+                rx0 = b.v0;
+                ry0 = b.v1;
+                rx1 = b.v2;
+                ry1 = b.v3;
+            } else {
+                rx0 = b.v2;
+                ry0 = b.v3;
+                const U4 b2 = philox4x32_10(c0 + 1u, a.t, TAG_BOND, a.sid, a.k0, a.k1);
+                rx1 = b2.v0;
+                ry1 = b2.v1;
+            }
+            const U4 bz = philox4x32_10(static_cast<uint32_t>(i0 >> 2), a.t, TAG_BOND_Z, a.sid, a.k0, a.k1);
+            const uint32_t rz0 = pick(bz, static_cast<uint32_t>(i0 & 3));
+            uint32_t rz1;
+            if (((i0 + 1) & 3) != 0) {
+                rz1 = pick(bz, static_cast<uint32_t>((i0 + 1) & 3));
+            } else {  // site i0 + 1 starts the next block
+                rz1 = philox4x32_10(static_cast<uint32_t>((i0 + 1) >> 2), a.t, TAG_BOND_Z, a.sid, a.k0, a.k1).v0;
+            }
+            uint32_t m0 = 0, m1 = 0;
+            if (v0 && a.tany)
+                m0 = (s0 == x0 && rx0 <= a.tm1 ? 1u : 0u) | (s0 == y0 && ry0 <= a.tm1 ? 2u : 0u) |
+                     (s0 == z0 && rz0 <= a.tm1 ? 4u : 0u);
+            if (v1 && a.tany)
+                m1 = (s1 == x1 && rx1 <= a.tm1 ? 1u : 0u) | (s1 == y1 && ry1 <= a.tm1 ? 2u : 0u) |
+                     (s1 == z1 && rz1 <= a.tm1 ? 4u : 0u);
+            act += __popc(m0) + __popc(m1);
+            if (v0) a.bonds[i0] = static_cast<uint8_t>(m0);
+            if (v1) a.bonds[i0 + 1] = static_cast<uint8_t>(m1);
+            const uint32_t in_y = ly + 1 < T.th ? 0x12u : 0u;
+            inside |= static_cast<uint64_t>((m0 | (m1 << 3)) & (in_x | in_y | in_z)) << (6 * ly);
+        }
+    }
+    __syncthreads();
+
+    // unions of the bonds inside the tile, one flat loop per lane: a finished
+    // union takes the lane's next bond at once
+    {
+        uint64_t todo = inside;
+        int u = 0, v = 0, busy = 0;
+        while (busy || todo) {
+            if (!busy) {
+                const int bit = __ffsll(static_cast<unsigned long long>(todo)) - 1;
+                todo &= todo - 1;
+                const int ly = bit / 6, j = (bit % 6) / 3, d = bit % 3;
+                u = (lz * CY + ly) * CX + lx0 + j;
+                v = u + (d == 0 ? 1 : d == 1 ? CX : PLANE);
+                busy = 1;
+            }
+            int done;
+            unite_step(P, u, v, done);
+            busy = !done;
+        }
+    }
+    __syncthreads();
+
+    // claims: the root of every cluster that touches a tile face gets an id
+    auto root_of = [&](int x) {
+        for (;;) {
+            const int p = lds_ld(&P[x]);
+            if (p == x || p < 0) return x;
+            x = p;
+        }
+    };
+    if (lz < T.td) {
+        for (int ly = 0; ly < T.th; ++ly) {
+            const bool plane_face = ly == 0 || ly == T.th - 1 || lz == 0 || lz == T.td - 1;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int lx = lx0 + j;
+                if (lx >= T.tw || !(plane_face || lx == 0 || lx == T.tw - 1)) continue;
+                const int r = root_of((lz * CY + ly) * CX + lx);
+                int expect = r;
+                if (__hip_atomic_compare_exchange_strong(&P[r], &expect, CLAIMING, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                    const int k = atomicAdd(&nb_s, 1);
+                    lds_st(&P[r], -(k + 2));
+                    const int id = T.tile * CAP + k;
+                    a.gkey[id] = site_of(g, T, r);
+                    a.gparent[id] = id;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // codes: the id of a claimed root, else CAP + the root's slot
+    if (lz < T.td) {
+        uint16_t *codes = a.codes + static_cast<int64_t>(T.tile) * CSITES;
+        for (int ly = 0; ly < T.th; ++ly) {
+            const int s = (lz * CY + ly) * CX + lx0;
+            uint32_t c[2] = {CODE_NONE, CODE_NONE};
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (lx0 + j >= T.tw) continue;
+                const int r = root_of(s + j);
+                const int pr = lds_ld(&P[r]);
+                c[j] = pr < 0 ? static_cast<uint32_t>(-pr - 2) : static_cast<uint32_t>(CAP + r);
+            }
+            *reinterpret_cast<uint32_t *>(codes + s) = c[0] | (c[1] << 16);
+        }
+    }
+    if (threadIdx.x == 0) a.nb[T.tile] = nb_s;
+    const unsigned long long tot = wave_sum(act);
+    if (lane == 0) add_stat(&a.stats[S3_ACTIVE], tot);
+}
+
+struct Merge3Args {
+    Geo3 g;
+    const uint8_t *bonds;
+    const uint16_t *codes;
+    const int32_t *gkey;
+    int32_t *gparent;
+};
+
+// Tile consolidation: each active bond leaving the tile through its +x, +y or
+// +z face joins the ids of its two ends (both are face sites, hence claimed).
+__global__ __launch_bounds__(MT) void k3_merge(Merge3Args a)
+{
+    const Geo3 g = a.g;
+    const TileOf T = tile_of(g, xcd_remap(blockIdx.x, g.ntiles));
+    for (int f = threadIdx.x; f < FX + FY + FZ; f += MT) {
+        int lx, ly, lz, d;
+        if (f < FX) {
+            d = 0;
+            lx = T.tw - 1;
+            ly = f % CY;
+            lz = f / CY;
+        } else if (f < FX + FY) {
+            d = 1;
+            lx = (f - FX) % CX;
+            ly = T.th - 1;
+            lz = (f - FX) / CX;
+        } else {
+            d = 2;
+            lx = (f - FX - FY) % CX;
+            ly = (f - FX - FY) / CX;
+            lz = T.td - 1;
+        }
+        if (lx >= T.tw || ly >= T.th || lz >= T.td) continue;
+        const int gx = T.gx0 + lx, gy = T.gy0 + ly, gz = T.gz0 + lz;
+        const int64_t i = (static_cast<int64_t>(gz) * g.Ly + gy) * g.Lx + gx;
+        if (!((a.bonds[i] >> d) & 1u)) continue;
+        int nx = gx, ny = gy, nz = gz;
+        if (d == 0) nx = gx + 1 == g.Lx ? 0 : gx + 1;
+        else if (d == 1) ny = gy + 1 == g.Ly ? 0 : gy + 1;
+        else nz = gz + 1 == g.Lz ? 0 : gz + 1;
+        const int t2 = ((nz / CZ) * g.nty + ny / CY) * g.ntx + nx / CX;
+        const int s1 = (lz * CY + ly) * CX + lx;
+        const int s2 = ((nz % CZ) * CY + ny % CY) * CX + nx % CX;
+        const int ca = a.codes[static_cast<int64_t>(T.tile) * CSITES + s1];
+        const int cb = a.codes[static_cast<int64_t>(t2) * CSITES + s2];
+        if (ca >= CAP || cb >= CAP) continue;  // face sites always hold ids; never index past the id tables
+        gunite(a.gparent, a.gkey, T.tile * CAP + ca, t2 * CAP + cb);
+    }
+}
+
+struct Flat3Args {
+    Geo3 g;
+    uint8_t *spins;
+    int32_t *labels;  // or nullptr
+    const uint16_t *codes;
+    const int32_t *gkey, *gparent, *nb;
+    unsigned long long *stats;
+    uint32_t q, ising, k0, k1, t, sid;
+};
+
+// New state of the cluster whose canonical root is R: word R & 3 of
+// block(R >> 2, t, FLIP), as on the square lattice.
+__device__ __forceinline__ uint32_t new_state(uint32_t R, const Flat3Args &a)
+{
+    const U4 b = philox4x32_10(R >> 2, a.t, TAG_FLIP, a.sid, a.k0, a.k1);
+    return draw_state(pick(b, R & 3u), a.q);
+}
+
+__global__ __launch_bounds__(NT3) void k3_flatten(Flat3Args a)
+{
+    __shared__ uint8_t ST[CAP + CSITES];  // new state per code
+    __shared__ int32_t Rb[CAP];           // canonical label per id
+    const Geo3 g = a.g;
+    const TileOf T = tile_of(g, xcd_remap(blockIdx.x, g.ntiles));
+    const int lane = threadIdx.x & 63, lz = wave_id();
+    const int lx0 = 2 * lane;
+    const bool v0 = lx0 < T.tw, v1 = lx0 + 1 < T.tw;
+    unsigned ncl = 0;
+    const int nbt = a.nb[T.tile];
+    for (int k = threadIdx.x; k < nbt; k += NT3) {
+        const int id = T.tile * CAP + k;
+        const int r = gfind(a.gparent, id);
+        const int32_t key = a.gkey[r];
+        ST[k] = static_cast<uint8_t>(new_state(static_cast<uint32_t>(key), a));
+        Rb[k] = key;
+        ncl += r == id ? 1u : 0u;
+    }
+    // the lane's codes (two per row); interior roots draw their state
+    const uint16_t *codes = a.codes + static_cast<int64_t>(T.tile) * CSITES;
+    uint32_t cc[CY];
+#pragma unroll
+    for (int ly = 0; ly < CY; ++ly) {
+        cc[ly] = 0xFFFFFFFFu;
+        if (lz >= T.td || ly >= T.th) continue;
+        const int s = (lz * CY + ly) * CX + lx0;
+        cc[ly] = *reinterpret_cast<const uint32_t *>(codes + s);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (!(j ? v1 : v0)) continue;
+            const uint32_t c = (cc[ly] >> (16 * j)) & 0xFFFFu;
+            if (c == static_cast<uint32_t>(CAP + s + j)) {
+                ST[CAP + s + j] = static_cast<uint8_t>(new_state(static_cast<uint32_t>(site_of(g, T, s + j)), a));
+                ++ncl;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ly = 0; ly < CY; ++ly) {
+        if (lz >= T.td || ly >= T.th) continue;
+        const int s = (lz * CY + ly) * CX + lx0;
+        const int64_t i0 = (static_cast<int64_t>(T.gz0 + lz) * g.Ly + T.gy0 + ly) * g.Lx + T.gx0 + lx0;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (!(j ? v1 : v0)) continue;
+            const uint32_t c = (cc[ly] >> (16 * j)) & 0xFFFFu;
+            const uint32_t st = ST[c];
+            a.spins[i0 + j] = static_cast<uint8_t>(a.ising ? 2u * st - 1u : st);
+            if (a.labels)
+                a.labels[i0 + j] = c < static_cast<uint32_t>(CAP) ? Rb[c] : site_of(g, T, static_cast<int>(c) - CAP);
+        }
+    }
+    const unsigned long long tot = wave_sum(ncl);
+    if (lane == 0) add_stat(&a.stats[S3_NCLUST], tot);
+}
+
+// Satisfied bonds among the 3N pairs and state counts 0..7 of the spins
+// (-H/J of Eq. potts_hamiltonian on the cubic lattice).
+__global__ __launch_bounds__(512) void k3_observe(const uint8_t *spins, Geo3 g, int ising, unsigned long long *stats)
+{
+    const int64_t N = static_cast<int64_t>(g.Lx) * g.Ly * g.Lz;
+    unsigned nsat = 0, cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 512 + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * 512) {
+        const int x = static_cast<int>(i % g.Lx);
+        const int64_t yz = i / g.Lx;
+        const int y = static_cast<int>(yz % g.Ly), z = static_cast<int>(yz / g.Ly);
+        const uint32_t s = spins[i];
+        const int64_t ix = i - x + (x + 1 == g.Lx ? 0 : x + 1);
+        const int64_t iy = i + (y + 1 == g.Ly ? -static_cast<int64_t>(y) * g.Lx : g.Lx);
+        const int64_t plane = static_cast<int64_t>(g.Lx) * g.Ly;
+        const int64_t iz = i + (z + 1 == g.Lz ? -static_cast<int64_t>(z) * plane : plane);
+        nsat += (s == spins[ix] ? 1u : 0u) + (s == spins[iy] ? 1u : 0u) + (s == spins[iz] ? 1u : 0u);
+        const uint32_t st = ising ? (s == 1u ? 1u : 0u) : s;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cnt[k] += st == static_cast<uint32_t>(k) ? 1u : 0u;
+    }
+    const int lane = threadIdx.x & 63;
+    const unsigned long long ns = wave_sum(nsat);
+    if (lane == 0) add_stat(&stats[S3_NSAT], ns);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const unsigned long long c = wave_sum(cnt[k]);
+        if (lane == 0) add_stat(&stats[S3_COUNTS + k], c);
+    }
+}
+
+// Move the sweep's counters into its record and clear them for the next one.
+__global__ void k3_record(unsigned long long *stats, int64_t *row)
+{
+    const int k = threadIdx.x;
+    if (k >= S3_LEN) return;
+    if (row) row[k] = static_cast<int64_t>(stats[k]);
+    stats[k] = 0ull;
+}
+
+}  // namespace cubic
+}  // namespace swccl
+
+using namespace swccl;
+using namespace swccl::cubic;
+
+namespace {
+
+constexpr size_t ALIGN3 = 256;
+size_t up3(size_t v) { return (v + ALIGN3 - 1) / ALIGN3 * ALIGN3; }
+int64_t cdiv3(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct Layout3 {
+    Geo3 g;
+    int64_t N;
+    size_t codes, gkey, gparent, nb, stats, bonds, total;
+};
+
+sw_status check3(const sw3_params *p)
+{
+    if (!p) return SW_ERR_ARG;
+    if (p->q < 2 || p->q > 255) return SW_ERR_ARG;
+    if (p->spin_kind != SW_SPIN_ISING_I8 && p->spin_kind != SW_SPIN_POTTS_U8) return SW_ERR_ARG;
+    if (p->spin_kind == SW_SPIN_ISING_I8 && p->q != 2) return SW_ERR_ARG;
+    if (std::isnan(p->K) || p->flags != 0 || p->reserved != 0) return SW_ERR_ARG;
+    if (p->Lx < 1 || p->Ly < 1 || p->Lz < 1) return SW_ERR_SIZE;
+    const int64_t N = static_cast<int64_t>(p->Lx) * p->Ly * p->Lz;
+    if (N >= (static_cast<int64_t>(1) << 31)) return SW_ERR_SIZE;
+    // the ids of all tiles (ntiles x CAP) index int32 arrays
+    const int64_t nt = cdiv3(p->Lx, CX) * cdiv3(p->Ly, CY) * cdiv3(p->Lz, CZ);
+    if (nt * CAP >= (static_cast<int64_t>(1) << 31)) return SW_ERR_SIZE;
+    return SW_OK;
+}
+
+Layout3 layout3(const sw3_params *p)
+{
+    Layout3 L{};
+    L.g.Lx = p->Lx;
+    L.g.Ly = p->Ly;
+    L.g.Lz = p->Lz;
+    L.g.ntx = static_cast<int>(cdiv3(p->Lx, CX));
+    L.g.nty = static_cast<int>(cdiv3(p->Ly, CY));
+    L.g.ntz = static_cast<int>(cdiv3(p->Lz, CZ));
+    L.g.ntiles = L.g.ntx * L.g.nty * L.g.ntz;
+    L.N = static_cast<int64_t>(p->Lx) * p->Ly * p->Lz;
+    const size_t nt = static_cast<size_t>(L.g.ntiles);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += up3(bytes);
+        return at;
+    };
+    L.codes = take(nt * CSITES * sizeof(uint16_t));
+    L.gkey = take(nt * CAP * sizeof(int32_t));
+    L.gparent = take(nt * CAP * sizeof(int32_t));
+    L.nb = take(nt * sizeof(int32_t));
+    L.stats = take(16 * sizeof(unsigned long long));
+    L.bonds = take(static_cast<size_t>(L.N));
+    L.total = off;
+    return L;
+}
+
+template <typename T>
+T *at3(void *ws, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sw3_workspace_bytes(const sw3_params *p)
+{
+    if (check3(p) != SW_OK) return 0;
+    return layout3(p).total;
+}
+
+sw_status sw3_init_spins(const sw3_params *p, uint8_t *spins, void *stream)
+{
+    const sw_status st = check3(p);
+    if (st != SW_OK) return st;
+    if (!spins) return SW_ERR_ARG;
+    const int64_t N = static_cast<int64_t>(p->Lx) * p->Ly * p->Lz;
+    return swccl_internal::init_spins(spins, N, p->q, p->spin_kind == SW_SPIN_ISING_I8, p->seed, p->stream_id,
+                                      static_cast<hipStream_t>(stream));
+}
+
+sw_status sw3_sweep(const sw3_params *p, uint8_t *spins, uint32_t t0, int32_t n, uint8_t *bonds, int32_t *labels,
+                    int64_t *records, void *workspace, size_t workspace_bytes, void *stream)
+{
+    const sw_status st = check3(p);
+    if (st != SW_OK) return st;
+    if (!spins || n < 0) return SW_ERR_ARG;
+    if (static_cast<uint64_t>(t0) + static_cast<uint64_t>(n) > (static_cast<uint64_t>(1) << 32)) return SW_ERR_STATE;
+    const Layout3 L = layout3(p);
+    if (!workspace || workspace_bytes < L.total || reinterpret_cast<uintptr_t>(workspace) % ALIGN3)
+        return SW_ERR_WORKSPACE;
+    if (n == 0) return SW_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint64_t T = swccl_internal::bond_threshold(p->K);
+    unsigned long long *stats = at3<unsigned long long>(workspace, L.stats);
+
+    Tile3Args ta{};
+    ta.g = L.g;
+    ta.spins = spins;
+    ta.bonds = bonds ? bonds : at3<uint8_t>(workspace, L.bonds);
+    ta.codes = at3<uint16_t>(workspace, L.codes);
+    ta.gkey = at3<int32_t>(workspace, L.gkey);
+    ta.gparent = at3<int32_t>(workspace, L.gparent);
+    ta.nb = at3<int32_t>(workspace, L.nb);
+    ta.stats = stats;
+    ta.tany = T > 0 ? 1u : 0u;
+    ta.tm1 = T > 0 ? static_cast<uint32_t>(T - 1) : 0u;
+    ta.k0 = static_cast<uint32_t>(p->seed);
+    ta.k1 = static_cast<uint32_t>(p->seed >> 32);
+    ta.sid = p->stream_id;
+
+    Merge3Args ma{};
+    ma.g = L.g;
+    ma.bonds = ta.bonds;
+    ma.codes = ta.codes;
+    ma.gkey = ta.gkey;
+    ma.gparent = ta.gparent;
+
+    Flat3Args fa{};
+    fa.g = L.g;
+    fa.spins = spins;
+    fa.codes = ta.codes;
+    fa.gkey = ta.gkey;
+    fa.gparent = ta.gparent;
+    fa.nb = ta.nb;
+    fa.stats = stats;
+    fa.q = static_cast<uint32_t>(p->q);
+    fa.ising = p->spin_kind == SW_SPIN_ISING_I8 ? 1u : 0u;
+    fa.k0 = ta.k0;
+    fa.k1 = ta.k1;
+    fa.sid = ta.sid;
+
+    const dim3 tiles(static_cast<unsigned>(L.g.ntiles));
+    const unsigned obs_blocks = static_cast<unsigned>(std::min<int64_t>(cdiv3(L.N, 512), 4096));
+    hipLaunchKernelGGL(k3_record, dim3(1), dim3(64), 0, s, stats, static_cast<int64_t *>(nullptr));  // clear
+    for (int32_t k = 0; k < n; ++k) {
+        const uint32_t t = t0 + static_cast<uint32_t>(k);
+        ta.t = t;
+        fa.t = t;
+        fa.labels = k + 1 == n ? labels : nullptr;
+        hipLaunchKernelGGL(k3_tile, tiles, dim3(NT3), 0, s, ta);
+        hipLaunchKernelGGL(k3_merge, tiles, dim3(MT), 0, s, ma);
+        hipLaunchKernelGGL(k3_flatten, tiles, dim3(NT3), 0, s, fa);
+        if (records) {
+            hipLaunchKernelGGL(k3_observe, dim3(obs_blocks), dim3(512), 0, s, spins, L.g, static_cast<int>(fa.ising),
+                               stats);
+            hipLaunchKernelGGL(k3_record, dim3(1), dim3(64), 0, s, stats, records + static_cast<int64_t>(k) * SW3_REC_LEN);
+        }
+    }
+    return swccl_internal::device_error(hipGetLastError(), "sw3_sweep");
+}
+
+}  // extern "C"

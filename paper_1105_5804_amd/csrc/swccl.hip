@@ -1343,6 +1343,19 @@ namespace swccl_internal {
 
 int64_t request_tiles(int32_t W, int32_t H) { return cdiv(W, TW) * cdiv(H, TH_DEFAULT); }
 
+sw_status device_error(hipError_t e, const char *where) { return device_status(e, where); }
+
+sw_status init_spins(uint8_t *spins, int64_t N, int32_t q, bool ising, uint64_t seed, uint32_t sid, hipStream_t s)
+{
+    if (N <= 0) return SW_OK;
+    hipLaunchKernelGGL(k_init, dim3(static_cast<unsigned>(cdiv(cdiv(N, 4), NT))), dim3(NT), 0, s, spins, N,
+                       static_cast<uint32_t>(q), ising ? 1 : 0, static_cast<uint32_t>(seed),
+                       static_cast<uint32_t>(seed >> 32), sid);
+    return launch_status("k_init");
+}
+
+uint64_t bond_threshold(double K) { return threshold_of(K); }
+
 sw_status pull(void *dst, const void *src_dev, int64_t n, hipStream_t s)
 {
     if (n <= 0) return SW_OK;

@@ -338,8 +338,8 @@ def test_ctypes_layout_matches_header(tmp_path):
     if cc is None:
         pytest.skip("gcc not found")
     structs = {"sw_params": _lib.SwParams, "sw_buffers": _lib.SwBuffers, "sw_obs": _lib.SwObs,
-               "ccl_server_params": _lib.CclServerParams}
-    consts = ["SWCCL_ABI_VERSION", "SW_OK", "SW_ERR_ARG", "SW_ERR_SIZE", "SW_ERR_WORKSPACE", "SW_ERR_DEVICE",
+               "ccl_server_params": _lib.CclServerParams, "sw3_params": _lib.Sw3Params}
+    consts = ["SW3_REC_ACTIVE", "SW3_REC_NCLUST", "SW3_REC_NSAT", "SW3_REC_COUNTS", "SW3_REC_LEN","SWCCL_ABI_VERSION", "SW_OK", "SW_ERR_ARG", "SW_ERR_SIZE", "SW_ERR_WORKSPACE", "SW_ERR_DEVICE",
               "SW_ERR_STATE", "SW_ERR_UNSUPPORTED", "SW_ERR_HOST_MEMORY", "SW_SPIN_ISING_I8", "SW_SPIN_POTTS_U8",
               "SW_F_KEEP_SPINS", "SW_F_SIZES", "SW_F_REVERSE_TILES", "CCL_BONDS_PERIODIC", "CCL_BONDS_OPEN",
               "CCL_SITES_OPEN", "SW_PHASE_TILE", "SW_PHASE_MERGE", "SW_PHASE_FLIP", "SW_HIST_ACTIVE",
@@ -386,7 +386,7 @@ def test_ctypes_signatures_match_prototypes():
     scalars = {"int32_t": ctypes.c_int32, "sw_status": ctypes.c_int32, "uint32_t": ctypes.c_uint32,
                "uint64_t": ctypes.c_uint64, "size_t": ctypes.c_size_t, "double": ctypes.c_double}
     structs = {"sw_params": _lib.SwParams, "sw_buffers": _lib.SwBuffers, "sw_obs": _lib.SwObs,
-               "ccl_server_params": _lib.CclServerParams}
+               "ccl_server_params": _lib.CclServerParams, "sw3_params": _lib.Sw3Params}
 
     def agrees(ctype: str, py) -> bool:
         ctype = " ".join(ctype.replace("const", " ").split())
@@ -416,3 +416,37 @@ def test_ctypes_signatures_match_prototypes():
             assert agrees(ctype, py), (name, p, py)
         checked += 1
     assert checked == len(_lib.SIGNATURES)
+
+
+def _p3(**kw):
+    d = dict(Lx=64, Ly=32, Lz=16, q=2, spin_kind=_lib.SW_SPIN_ISING_I8, flags=0, K=0.44, seed=1, stream_id=0,
+             reserved=0)
+    d.update(kw)
+    return _lib.Sw3Params(**d)
+
+
+def test_cubic_params():
+    """sw3_* size good parameters and refuse bad ones before any device work."""
+    L = _lib.lib()
+    ok = L.sw3_workspace_bytes(ctypes.byref(_p3()))
+    assert ok > 64 * 32 * 16 * 3
+    for kw in (dict(Lx=0), dict(Ly=-1), dict(Lz=0), dict(Lx=2048, Ly=2048, Lz=512), dict(Lx=1, Ly=1, Lz=2**30),
+               dict(q=1), dict(q=256), dict(q=3), dict(spin_kind=7), dict(flags=1), dict(reserved=1),
+               dict(K=float("nan"))):
+        assert L.sw3_workspace_bytes(ctypes.byref(_p3(**kw))) == 0, kw
+    assert L.sw3_workspace_bytes(ctypes.byref(_p3(Lx=1, Ly=1, Lz=1))) > 0
+    assert L.sw3_workspace_bytes(ctypes.byref(_p3(q=5, spin_kind=_lib.SW_SPIN_POTTS_U8))) == ok
+    # errors found before anything is enqueued (no device pointer is touched)
+    p = _p3()
+    assert L.sw3_sweep(ctypes.byref(p), None, 0, 1, None, None, None, 256, ok, None) == _lib.SW_ERR_ARG
+    assert L.sw3_sweep(ctypes.byref(p), 256, 0, -1, None, None, None, 256, ok, None) == _lib.SW_ERR_ARG
+    assert L.sw3_sweep(ctypes.byref(p), 256, 0, 1, None, None, None, None, ok, None) == _lib.SW_ERR_WORKSPACE
+    assert L.sw3_sweep(ctypes.byref(p), 256, 0, 1, None, None, None, 256, ok - 1, None) == _lib.SW_ERR_WORKSPACE
+    assert L.sw3_sweep(ctypes.byref(p), 256, 0, 1, None, None, None, 257, ok, None) == _lib.SW_ERR_WORKSPACE
+    assert L.sw3_sweep(ctypes.byref(p), 256, 2**32 - 2, 3, None, None, None, 256, ok, None) == _lib.SW_ERR_STATE
+    assert L.sw3_sweep(ctypes.byref(_p3(Lx=0)), 256, 0, 1, None, None, None, 256, ok, None) == _lib.SW_ERR_SIZE
+    assert L.sw3_sweep(ctypes.byref(_p3(q=1)), 256, 0, 1, None, None, None, 256, ok, None) == _lib.SW_ERR_ARG
+    assert L.sw3_sweep(None, 256, 0, 1, None, None, None, 256, ok, None) == _lib.SW_ERR_ARG
+    assert L.sw3_sweep(ctypes.byref(p), 256, 0, 0, None, None, None, 256, ok, None) == _lib.SW_OK  # nothing to do
+    assert L.sw3_init_spins(ctypes.byref(p), None, None) == _lib.SW_ERR_ARG
+    assert L.sw3_init_spins(ctypes.byref(_p3(Lz=0)), 256, None) == _lib.SW_ERR_SIZE

@@ -1,0 +1,119 @@
+"""GPU parity of the simple cubic lattice sweep against the CPU oracle
+(bit-exact): packed bonds, canonical labels, spins and the per-sweep records
+after every sweep.
+
+Shapes cover one tile with its periodic wraps inside the tile, ragged tiles
+along each axis, odd Lx (rows starting at odd site indices), extents 1 and 2
+(self-bonds and doubled bonds), a restart at a sweep number other than 0,
+Lz = 1 against the square-lattice sweep of the same library, and the 256^3
+and 512^3 Ising lattices at the 3D critical coupling.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1105_5804_amd as sw
+from paper_1105_5804_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+K3 = sw.ising_K(sw.BETA_C_ISING_3D)
+
+
+def _state(lat):
+    s = lat.spins.cpu().numpy().reshape(-1)
+    if lat.ising:
+        return ((s.astype(np.int16) + 1) // 2).astype(np.uint8)
+    return s.astype(np.uint8)
+
+
+CASES = [
+    # Lx, Ly, Lz, q, K, ising
+    (16, 8, 8, 2, K3, True),
+    (128, 8, 8, 3, 1.0051, False),
+    (130, 9, 17, 2, K3, True),
+    (257, 11, 9, 2, 0.6, True),
+    (5, 3, 7, 3, 1.2, False),
+    (1, 1, 6, 2, 1.0, True),
+    (2, 2, 2, 2, 0.5, True),
+    (1, 40, 3, 4, 1.1, False),
+    (300, 1, 2, 2, 0.9, True),
+    (64, 64, 64, 2, K3, True),
+    (33, 70, 20, 3, 0.8, False),
+]
+
+
+@pytest.mark.parametrize("Lx,Ly,Lz,q,K,ising", CASES)
+def test_cubic_parity(Lx, Ly, Lz, q, K, ising):
+    print(f"cubic Lx={Lx} Ly={Ly} Lz={Lz} q={q} K={K}", flush=True)
+    seed, sid = wl.SEED_BASE | 0x3D1, 7
+    lat = sw.CubicLattice(Lx, Ly, Lz, q=q, K=K, seed=seed, stream_id=sid, ising=ising, keep_labels=True,
+                          keep_bonds=True)
+    T = oracle.threshold(K)
+    assert lat.threshold == T
+    st = oracle.init_states3(Lx, Ly, Lz, q, seed, sid)
+    torch.cuda.synchronize()
+    assert np.array_equal(_state(lat), st)
+    for t in range(5):
+        rec = lat.sweep(1, records=True)
+        st, bonds, labels, want = oracle.sw3_sweep(Lx, Ly, Lz, q, T, seed, sid, t, st)
+        torch.cuda.synchronize()
+        assert np.array_equal(lat.bonds.cpu().numpy().reshape(-1), bonds), t
+        assert np.array_equal(lat.labels.cpu().numpy().reshape(-1), labels), t
+        assert np.array_equal(_state(lat), st), t
+        assert [int(v) for v in rec[0].cpu()] == [int(v) for v in want], t
+
+
+def test_cubic_many_sweeps_per_call_and_restart():
+    """Twelve sweeps in one call (records of each), then a lattice restarted
+    from the saved spins at t = 12; both follow the oracle."""
+    Lx, Ly, Lz, q, seed = 140, 20, 12, 2, wl.SEED_BASE | 0x3D2
+    lat = sw.CubicLattice(Lx, Ly, Lz, q=q, K=K3, seed=seed)
+    rec = lat.sweep(12, records=True)
+    T = oracle.threshold(K3)
+    st, want = oracle.sw3_run(Lx, Ly, Lz, q, T, seed, 0, 0, 12, oracle.init_states3(Lx, Ly, Lz, q, seed))
+    torch.cuda.synchronize()
+    assert np.array_equal(rec.cpu().numpy(), want)
+    assert np.array_equal(_state(lat), st)
+    lat2 = sw.CubicLattice(Lx, Ly, Lz, q=q, K=K3, seed=seed, spins=lat.spins.clone(), t=12, keep_labels=True)
+    lat2.sweep(3)
+    st2, _ = oracle.sw3_run(Lx, Ly, Lz, q, T, seed, 0, 12, 2, st)
+    st2, _b, labels, _r = oracle.sw3_sweep(Lx, Ly, Lz, q, T, seed, 0, 14, st2)
+    torch.cuda.synchronize()
+    assert np.array_equal(_state(lat2), st2)
+    assert np.array_equal(lat2.labels.cpu().numpy().reshape(-1), labels)
+
+
+@pytest.mark.parametrize("W,H,q", [(300, 200, 2), (129, 70, 3)])
+def test_lz1_equals_square_lattice_on_gpu(W, H, q):
+    """A cubic lattice with Lz = 1 follows the square-lattice sweep of the
+    same library (its +z bonds join each site to itself)."""
+    seed, K = wl.SEED_BASE | 0x3D3, (sw.ising_K(sw.BETA_C_ISING) if q == 2 else 1.0051)
+    a = sw.SWLattice(W, H, q=q, K=K, seed=seed, keep_labels=True)
+    b = sw.CubicLattice(W, H, 1, q=q, K=K, seed=seed, keep_labels=True)
+    for t in range(4):
+        a.sweep(1)
+        b.sweep(1)
+        torch.cuda.synchronize()
+        assert torch.equal(a.spins.reshape(-1), b.spins.reshape(-1)), t
+        assert torch.equal(a.labels.reshape(-1), b.labels.reshape(-1)), t
+
+
+@pytest.mark.parametrize("L,sweeps", [(256, 3), (512, 2)])
+def test_cubic_full_size(L, sweeps):
+    """The 3D Ising lattice at the critical coupling, against the oracle after
+    every sweep (spins and records; labels of the last sweep)."""
+    seed = wl.SEED_BASE | 0x3D4
+    print(f"cubic L={L}^3 Ising at beta_c", flush=True)
+    lat = sw.CubicLattice(L, L, L, q=2, K=K3, seed=seed, keep_labels=True)
+    T = oracle.threshold(K3)
+    st = oracle.init_states3(L, L, L, 2, seed)
+    for t in range(sweeps):
+        rec = lat.sweep(1, records=True)
+        st, _b, labels, want = oracle.sw3_sweep(L, L, L, 2, T, seed, 0, t, st)
+        torch.cuda.synchronize()
+        assert [int(v) for v in rec[0].cpu()] == [int(v) for v in want], t
+        assert np.array_equal(_state(lat), st), t
+    assert np.array_equal(lat.labels.cpu().numpy().reshape(-1), labels)
