@@ -48,6 +48,7 @@ def _args():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-few", action="store_true")
+    ap.add_argument("--no-cubic", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--study", action="store_true",
                     help="instead of the bench line: sweep time and phases over couplings and q at L=16384")
@@ -475,6 +476,19 @@ def _cpu_baseline(cfg, wl) -> dict:
     out["few_cluster"] = {"ns_per_spin_per_sweep": round(dt * 1e9 / (Lf * Lf), 3), "cores": 1,
                           "sample": f"one few-cluster sweep (64 x 64 seed tiles, p_flip 0.5) of an Ising "
                                     f"{Lf}x{Lf} lattice at beta_c from its seeded start, single thread"}
+    # the simple cubic lattice: one sweep of an Ising 256^3 lattice at its critical coupling
+    import paper_1105_5804_amd as sw3
+
+    Lc = 256
+    stc = oracle.init_states3(Lc, Lc, Lc, 2, wl.SEED_BASE | 0x3D5)
+    c = time.perf_counter()
+    oracle.sw3_sweep(Lc, Lc, Lc, 2, oracle.threshold(sw3.ising_K(sw3.BETA_C_ISING_3D)), wl.SEED_BASE | 0x3D5, 0, 0,
+                     stc)
+    dt = time.perf_counter() - c
+    del stc
+    out["cubic"] = {"ns_per_spin_per_sweep": round(dt * 1e9 / Lc**3, 3), "cores": 1,
+                    "sample": f"one sweep of an Ising {Lc}^3 simple cubic lattice at beta_c from its seeded start, "
+                              f"single thread"}
     out["paper_cpu_context"] = {"ns_per_spin_per_sweep": {"q2_L8192_Core2_Q6700": 77.39, "q2_L16384_Xeon_E5620": 152.1,
                                                           "q3_L8192_Core2_Q6700": 70.73},
                                 "note": "serial CPU timings the paper lists beside its GPU ones (Table of results)"}
@@ -536,6 +550,42 @@ def _few_cluster(args, torch, sw, wl, stream) -> dict:
         torch.cuda.empty_cache()
     return {"workload": f"Ising {L}x{L} at beta_c from SW-equilibrated spins; few-cluster rows: one seed per "
                         f"B x B seed tile, p_flip 0.5", "rows": rows}
+
+
+def _cubic(args, torch, sw, wl, stream) -> dict:
+    """SW sweeps of the simple cubic Ising lattice (L = 512, 134 M sites) at
+    its critical coupling, after equilibration sweeps: time per sweep, with
+    and without per-sweep records, and the mean energy per site over the
+    recorded sweeps.  The same 10 B/site model as the square lattice (spin in
+    and out, a label carried across the local/global split) gives the HBM
+    roofline fraction."""
+    L = 512
+    N = L**3
+    K = sw.ising_K(sw.BETA_C_ISING_3D)
+    lat = sw.CubicLattice(L, L, L, q=2, K=K, seed=wl.SEED_BASE | 0x3D5)
+    lat.sweep(max(20, args.warmup))
+    torch.cuda.synchronize()
+    steps = max(5, args.steps)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    lat.sweep(steps)
+    ev[1].record(stream)
+    rec = lat.sweep(steps, records=True)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    ms_rec = ev[1].elapsed_time(ev[2]) / steps
+    e = -(2.0 * rec[:, 2].double() - 3.0 * N) / N
+    out = {"workload": f"Ising {L}^3 simple cubic at beta_c = {sw.BETA_C_ISING_3D}, {max(20, args.warmup)} "
+                       f"equilibration sweeps, then {steps} timed",
+           "ms_per_sweep": round(ms, 4), "ns_per_spin": round(ms * 1e6 / N, 6),
+           "ms_per_sweep_with_records": round(ms_rec, 4),
+           "mean_energy_per_site": round(float(e.mean()), 5),
+           "hbm_frac_10B_per_site": round(SWEEP_BYTES_PER_SITE * N / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "mean_clusters_per_site": round(float(rec[:, 1].double().mean()) / N, 5)}
+    del lat, rec
+    torch.cuda.empty_cache()
+    return out
 
 
 def _tile_scan(args) -> int:
@@ -776,6 +826,10 @@ def main() -> int:
     # ---- few-cluster update (Sec. III) on Ising L=16384 at beta_c, against the SW sweep ----
     if not args.no_few:
         out["few_cluster"] = _few_cluster(args, torch, sw, wl, stream)
+
+    # ---- the same sweep on the simple cubic lattice ----
+    if not args.no_cubic:
+        out["cubic"] = _cubic(args, torch, sw, wl, stream)
 
     # ---- served labeling ----
     if not args.no_serve:

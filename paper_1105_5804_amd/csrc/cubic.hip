@@ -2,7 +2,7 @@
 // three steps as on the square lattice (Sec. II), generalised to three
 // dimensions, and the host side of the sw3_* calls of include/swccl.h.
 //
-// A sweep is three launches:
+// A sweep is four launches:
 //
 //   k3_tile     one 512-thread workgroup per 128 x 8 x 8 tile; each wave owns
 //               one z-plane of the tile (8 rows of 128 sites, two per lane).
@@ -13,11 +13,15 @@
 //               (its cluster's id, or CAP + the slot of its interior root).
 //   k3_merge    every active bond that leaves a tile through its +x, +y or +z
 //               face (periodic wraps included) unites two ids in the global
-//               union-find, whose roots carry the minimum site index of their
-//               clusters (Sec. II.C).
-//   k3_flatten  every id resolved to its root and key, one draw per cluster
-//               at its minimum site index (Sec. II.D), spins and optionally
-//               labels written.
+//               union-find (Sec. II.C).  Roots are linked by a fixed random
+//               priority of the ids rather than by key: on the cubic lattice
+//               at criticality key-ordered links build trees too deep to walk
+//               for the ~10^7 ids of a sweep.
+//   k3_resolve  every id pointed at its root, and the cluster's minimum site
+//               index (its canonical label) gathered at the root's key;
+//   k3_flatten  one draw per cluster at that index (Sec. II.D): the tile's ids
+//               and its interior roots, then every site's new state (and
+//               optionally label) from its code.
 //
 // With per-sweep records, k3_observe counts the satisfied bonds and states of
 // the new spins and k3_record moves the counters into the record.
@@ -40,6 +44,7 @@ constexpr int CSITES = PLANE * CZ;                             // 8192 sites per
 constexpr int CAP = CSITES - (CX - 2) * (CY - 2) * (CZ - 2);   // 3656: sites on a face of a full tile
 constexpr int NT3 = 64 * CZ;                                   // one wave per z-plane
 constexpr int MT = 256;                                        // merge workgroup
+constexpr int MSEEN = 1024;                                    // merge: pair-dedup slots per face
 constexpr int FX = CY * CZ, FY = CX * CZ, FZ = CX * CY;        // sites of the +x, +y, +z faces
 constexpr uint32_t TAG_BOND = 1, TAG_FLIP = 2, TAG_BOND_Z = 5;
 constexpr int CLAIMING = -1;
@@ -87,7 +92,7 @@ struct Tile3Args {
     uint16_t *codes;          // [ntiles][CSITES]
     int32_t *gkey, *gparent;  // [ntiles][CAP]
     int32_t *nb;              // [ntiles]: ids of the tile
-    unsigned long long *stats;
+    int32_t *tile_act;        // [ntiles]: active bonds owned by the tile
     uint32_t tm1, tany;       // a bond is active iff its word r <= tm1 and tany (T > 0; tm1 = T - 1)
     uint32_t k0, k1, t, sid;
 };
@@ -96,6 +101,7 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
 {
     __shared__ int P[CSITES];
     __shared__ int nb_s;
+    __shared__ unsigned act_w[CZ];
     const Geo3 g = a.g;
     const TileOf T = tile_of(g, xcd_remap(blockIdx.x, g.ntiles));
     const int lane = threadIdx.x & 63, lz = wave_id();
@@ -235,27 +241,77 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
             *reinterpret_cast<uint32_t *>(codes + s) = c[0] | (c[1] << 16);
         }
     }
-    if (threadIdx.x == 0) a.nb[T.tile] = nb_s;
     const unsigned long long tot = wave_sum(act);
-    if (lane == 0) add_stat(&a.stats[S3_ACTIVE], tot);
+    if (lane == 0) act_w[lz] = static_cast<unsigned>(tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned sum = 0;
+        for (int w = 0; w < CZ; ++w) sum += act_w[w];
+        a.nb[T.tile] = nb_s;
+        a.tile_act[T.tile] = static_cast<int32_t>(sum);
+    }
 }
 
 struct Merge3Args {
     Geo3 g;
     const uint8_t *bonds;
     const uint16_t *codes;
-    const int32_t *gkey;
     int32_t *gparent;
 };
 
+// Fixed random priority of an id: a bijection of the 32-bit integers
+// (multiplications by odd constants and xor-shifts), so no two ids tie.
+__device__ __forceinline__ uint32_t id_prio(int x)
+{
+    uint32_t h = static_cast<uint32_t>(x) * 0x9E3779B1u;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    return h;
+}
+
+// Union of the trees holding ids a and b: the root of lower priority is
+// linked below the other by a device-scope compare-and-swap (randomised
+// linking keeps the expected depth logarithmic); a failed swap returns the
+// root's new parent, from which the union goes on.  The walks halve their
+// paths as in the square-lattice merge.
+__device__ __forceinline__ void gunite_prio(int *G, int a, int b)
+{
+    gfind2(G, a, b);
+    for (;;) {
+        if (a == b) return;
+        if (id_prio(a) > id_prio(b)) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        int expect = a;
+        if (__hip_atomic_compare_exchange_strong(&G[a], &expect, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return;
+        a = expect;
+        gfind2(G, a, b);
+    }
+}
+
 // Tile consolidation: each active bond leaving the tile through its +x, +y or
 // +z face joins the ids of its two ends (both are face sites, hence claimed).
+// Face positions run along x (y for the +x face), so neighbouring lanes often
+// join the same pair of ids; a lane skips a pair its lower neighbour holds.
 __global__ __launch_bounds__(MT) void k3_merge(Merge3Args a)
 {
+    // seen[d][h]: the last pair (ca << 16 | cb) registered across face d in
+    // hash slot h = ca mod MSEEN.  A lane that gets its own pair back from
+    // the exchange skips the union: the lane that registered the pair
+    // performs it (pairs that share a slot only cost a repeated union).
+    __shared__ unsigned int seen[3][MSEEN];
     const Geo3 g = a.g;
     const TileOf T = tile_of(g, xcd_remap(blockIdx.x, g.ntiles));
-    for (int f = threadIdx.x; f < FX + FY + FZ; f += MT) {
-        int lx, ly, lz, d;
+    for (int k = threadIdx.x; k < 3 * MSEEN; k += MT) (&seen[0][0])[k] = 0xFFFFFFFFu;
+    __syncthreads();
+    for (int f0 = 0; f0 < FX + FY + FZ; f0 += MT) {  // uniform trip count: the lane exchange needs every lane
+        const int f = f0 + static_cast<int>(threadIdx.x);
+        int lx = 0, ly = 0, lz = 0, d = 0;
         if (f < FX) {
             d = 0;
             lx = T.tw - 1;
@@ -266,27 +322,38 @@ __global__ __launch_bounds__(MT) void k3_merge(Merge3Args a)
             lx = (f - FX) % CX;
             ly = T.th - 1;
             lz = (f - FX) / CX;
-        } else {
+        } else if (f < FX + FY + FZ) {
             d = 2;
             lx = (f - FX - FY) % CX;
             ly = (f - FX - FY) / CX;
             lz = T.td - 1;
         }
-        if (lx >= T.tw || ly >= T.th || lz >= T.td) continue;
-        const int gx = T.gx0 + lx, gy = T.gy0 + ly, gz = T.gz0 + lz;
-        const int64_t i = (static_cast<int64_t>(gz) * g.Ly + gy) * g.Lx + gx;
-        if (!((a.bonds[i] >> d) & 1u)) continue;
-        int nx = gx, ny = gy, nz = gz;
-        if (d == 0) nx = gx + 1 == g.Lx ? 0 : gx + 1;
-        else if (d == 1) ny = gy + 1 == g.Ly ? 0 : gy + 1;
-        else nz = gz + 1 == g.Lz ? 0 : gz + 1;
-        const int t2 = ((nz / CZ) * g.nty + ny / CY) * g.ntx + nx / CX;
-        const int s1 = (lz * CY + ly) * CX + lx;
-        const int s2 = ((nz % CZ) * CY + ny % CY) * CX + nx % CX;
-        const int ca = a.codes[static_cast<int64_t>(T.tile) * CSITES + s1];
-        const int cb = a.codes[static_cast<int64_t>(t2) * CSITES + s2];
-        if (ca >= CAP || cb >= CAP) continue;  // face sites always hold ids; never index past the id tables
-        gunite(a.gparent, a.gkey, T.tile * CAP + ca, t2 * CAP + cb);
+        int ca = -1, cb = -1;  // the pair of ids this lane's bond joins, or -1
+        int t2 = 0;
+        if (f < FX + FY + FZ && lx < T.tw && ly < T.th && lz < T.td) {
+            const int gx = T.gx0 + lx, gy = T.gy0 + ly, gz = T.gz0 + lz;
+            const int64_t i = (static_cast<int64_t>(gz) * g.Ly + gy) * g.Lx + gx;
+            if ((a.bonds[i] >> d) & 1u) {
+                int nx = gx, ny = gy, nz = gz;
+                if (d == 0) nx = gx + 1 == g.Lx ? 0 : gx + 1;
+                else if (d == 1) ny = gy + 1 == g.Ly ? 0 : gy + 1;
+                else nz = gz + 1 == g.Lz ? 0 : gz + 1;
+                t2 = ((nz / CZ) * g.nty + ny / CY) * g.ntx + nx / CX;
+                const int s1 = (lz * CY + ly) * CX + lx;
+                const int s2 = ((nz % CZ) * CY + ny % CY) * CX + nx % CX;
+                ca = a.codes[static_cast<int64_t>(T.tile) * CSITES + s1];
+                cb = a.codes[static_cast<int64_t>(t2) * CSITES + s2];
+                // face sites always hold ids; never index past the id tables
+                if (ca >= CAP || cb >= CAP) ca = cb = -1;
+            }
+        }
+        const int pa = __shfl_up(ca, 1), pb = __shfl_up(cb, 1), pt = __shfl_up(t2, 1);
+        bool dup = (threadIdx.x & 63) != 0 && pa == ca && pb == cb && pt == t2;
+        if (ca >= 0 && !dup) {  // one face has one neighbouring tile: (d, ca, cb) names the pair
+            const unsigned int key = (static_cast<unsigned int>(ca) << 16) | static_cast<unsigned int>(cb);
+            dup = atomicExch(&seen[d][ca % MSEEN], key) == key;
+        }
+        if (ca >= 0 && !dup) gunite_prio(a.gparent, T.tile * CAP + ca, t2 * CAP + cb);
     }
 }
 
@@ -295,8 +362,10 @@ struct Flat3Args {
     uint8_t *spins;
     int32_t *labels;  // or nullptr
     const uint16_t *codes;
-    const int32_t *gkey, *gparent, *nb;
-    unsigned long long *stats;
+    const int32_t *gkey;     // a root's key: its cluster's minimum site index
+    const int32_t *gparent;  // resolved: every id's entry is its root
+    const int32_t *nb;
+    int32_t *tile_ncl;       // [ntiles]: clusters whose root lies in the tile
     uint32_t q, ising, k0, k1, t, sid;
 };
 
@@ -308,43 +377,83 @@ __device__ __forceinline__ uint32_t new_state(uint32_t R, const Flat3Args &a)
     return draw_state(pick(b, R & 3u), a.q);
 }
 
+// Every id of every tile resolved after the merge, one thread per id slot:
+// the id's entry is pointed at its root (the trees are final, so concurrent
+// walks stay valid) and the id's key (the minimum site index of its part of
+// the cluster) is taken into the root's key by an atomic minimum, issued only
+// when the root's key, read first, is larger (a stale read is larger still),
+// so the ids of a large cluster do not all contend for its root.  The root's
+// key then holds the cluster's minimum site index: its canonical label.
+struct Resolve3Args {
+    Geo3 g;
+    int32_t *gkey;
+    int32_t *gparent;
+    const int32_t *nb;
+};
+
+__global__ __launch_bounds__(512) void k3_resolve(Resolve3Args a)
+{
+    const int64_t slot = static_cast<int64_t>(blockIdx.x) * 512 + threadIdx.x;
+    const int tile = static_cast<int>(slot / CAP), k = static_cast<int>(slot % CAP);
+    if (tile >= a.g.ntiles || k >= a.nb[tile]) return;
+    const int id = static_cast<int>(slot);
+    int x = id, p = a.gparent[x];
+    while (p != x) {
+        x = p;
+        p = a.gparent[x];
+    }
+    if (x == id) return;
+    a.gparent[id] = x;
+    const int32_t key = a.gkey[id];  // not a root: its key never changes
+    if (key < a.gkey[x]) atomicMin(&a.gkey[x], key);
+}
+
 __global__ __launch_bounds__(NT3) void k3_flatten(Flat3Args a)
 {
-    __shared__ uint8_t ST[CAP + CSITES];  // new state per code
-    __shared__ int32_t Rb[CAP];           // canonical label per id
+    __shared__ uint8_t ST[CAP + CSITES];   // new state per code
+    __shared__ int32_t Rb[CAP];            // canonical label per id (labels only)
+    __shared__ uint16_t roots[CZ][PLANE];  // interior root slots of each wave's plane
+    __shared__ unsigned ncl_w[CZ];
     const Geo3 g = a.g;
     const TileOf T = tile_of(g, xcd_remap(blockIdx.x, g.ntiles));
     const int lane = threadIdx.x & 63, lz = wave_id();
     const int lx0 = 2 * lane;
     const bool v0 = lx0 < T.tw, v1 = lx0 + 1 < T.tw;
-    unsigned ncl = 0;
     const int nbt = a.nb[T.tile];
+    unsigned nbroot = 0;
     for (int k = threadIdx.x; k < nbt; k += NT3) {
         const int id = T.tile * CAP + k;
-        const int r = gfind(a.gparent, id);
+        const int r = a.gparent[id];  // resolved: the entry is the root
         const int32_t key = a.gkey[r];
         ST[k] = static_cast<uint8_t>(new_state(static_cast<uint32_t>(key), a));
         Rb[k] = key;
-        ncl += r == id ? 1u : 0u;
+        nbroot += r == id ? 1u : 0u;
     }
-    // the lane's codes (two per row); interior roots draw their state
+    // the lane's codes (two per row); the interior roots (code CAP + own
+    // slot) of the wave's plane are listed, then draw their states 64 at a time
     const uint16_t *codes = a.codes + static_cast<int64_t>(T.tile) * CSITES;
     uint32_t cc[CY];
+    int nroot = 0;
+    uint16_t *mylist = roots[lz];
+    const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll
     for (int ly = 0; ly < CY; ++ly) {
         cc[ly] = 0xFFFFFFFFu;
         if (lz >= T.td || ly >= T.th) continue;
         const int s = (lz * CY + ly) * CX + lx0;
         cc[ly] = *reinterpret_cast<const uint32_t *>(codes + s);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            if (!(j ? v1 : v0)) continue;
-            const uint32_t c = (cc[ly] >> (16 * j)) & 0xFFFFu;
-            if (c == static_cast<uint32_t>(CAP + s + j)) {
-                ST[CAP + s + j] = static_cast<uint8_t>(new_state(static_cast<uint32_t>(site_of(g, T, s + j)), a));
-                ++ncl;
-            }
-        }
+        const bool r0 = v0 && (cc[ly] & 0xFFFFu) == static_cast<uint32_t>(CAP + s);
+        const bool r1 = v1 && (cc[ly] >> 16) == static_cast<uint32_t>(CAP + s + 1);
+        const uint64_t m0 = __ballot(r0), m1 = __ballot(r1);
+        const int at = nroot + __popcll(m0 & below) + __popcll(m1 & below);
+        if (r0) mylist[at] = static_cast<uint16_t>(s);
+        if (r1) mylist[at + (r0 ? 1 : 0)] = static_cast<uint16_t>(s + 1);
+        nroot += __popcll(m0) + __popcll(m1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    for (int k = lane; k < nroot; k += 64) {
+        const int s = mylist[k];
+        ST[CAP + s] = static_cast<uint8_t>(new_state(static_cast<uint32_t>(site_of(g, T, s)), a));
     }
     __syncthreads();
 #pragma unroll
@@ -362,38 +471,82 @@ __global__ __launch_bounds__(NT3) void k3_flatten(Flat3Args a)
                 a.labels[i0 + j] = c < static_cast<uint32_t>(CAP) ? Rb[c] : site_of(g, T, static_cast<int>(c) - CAP);
         }
     }
-    const unsigned long long tot = wave_sum(ncl);
-    if (lane == 0) add_stat(&a.stats[S3_NCLUST], tot);
+    const unsigned long long tot = wave_sum(nbroot);
+    if (lane == 0) ncl_w[lz] = static_cast<unsigned>(tot) + static_cast<unsigned>(nroot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned sum = 0;
+        for (int w = 0; w < CZ; ++w) sum += ncl_w[w];
+        a.tile_ncl[T.tile] = static_cast<int32_t>(sum);
+    }
+}
+
+// The sweep's active bonds and clusters from the per-tile counts.
+__global__ __launch_bounds__(1024) void k3_reduce_tiles(const int32_t *tile_act, const int32_t *tile_ncl, int ntiles,
+                                                        unsigned long long *stats)
+{
+    __shared__ unsigned long long red[2][16];
+    unsigned long long act = 0, ncl = 0;
+    for (int t = threadIdx.x; t < ntiles; t += 1024) {
+        act += static_cast<unsigned>(tile_act[t]);
+        ncl += static_cast<unsigned>(tile_ncl[t]);
+    }
+    act = wave_sum(act);
+    ncl = wave_sum(ncl);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][w] = act;
+        red[1][w] = ncl;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        unsigned long long v = 0;
+        for (int k = 0; k < 16; ++k) v += red[threadIdx.x][k];
+        stats[threadIdx.x == 0 ? S3_ACTIVE : S3_NCLUST] = v;
+    }
 }
 
 // Satisfied bonds among the 3N pairs and state counts 0..7 of the spins
 // (-H/J of Eq. potts_hamiltonian on the cubic lattice).
 __global__ __launch_bounds__(512) void k3_observe(const uint8_t *spins, Geo3 g, int ising, unsigned long long *stats)
 {
-    const int64_t N = static_cast<int64_t>(g.Lx) * g.Ly * g.Lz;
+    // a wave per row segment of 64 sites, a lane per site: no division per site
+    const uint32_t Lx = static_cast<uint32_t>(g.Lx), Ly = static_cast<uint32_t>(g.Ly);
+    const uint32_t Lz = static_cast<uint32_t>(g.Lz);
+    const uint32_t segs = (Lx + 63u) / 64u;
+    const uint32_t nseg = Ly * Lz * segs;
+    const uint32_t plane = Lx * Ly;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t nwaves = gridDim.x * 8u;
     unsigned nsat = 0, cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 512 + threadIdx.x; i < N;
-         i += static_cast<int64_t>(gridDim.x) * 512) {
-        const int x = static_cast<int>(i % g.Lx);
-        const int64_t yz = i / g.Lx;
-        const int y = static_cast<int>(yz % g.Ly), z = static_cast<int>(yz / g.Ly);
-        const uint32_t s = spins[i];
-        const int64_t ix = i - x + (x + 1 == g.Lx ? 0 : x + 1);
-        const int64_t iy = i + (y + 1 == g.Ly ? -static_cast<int64_t>(y) * g.Lx : g.Lx);
-        const int64_t plane = static_cast<int64_t>(g.Lx) * g.Ly;
-        const int64_t iz = i + (z + 1 == g.Lz ? -static_cast<int64_t>(z) * plane : plane);
-        nsat += (s == spins[ix] ? 1u : 0u) + (s == spins[iy] ? 1u : 0u) + (s == spins[iz] ? 1u : 0u);
+    for (uint32_t w = blockIdx.x * 8u + (threadIdx.x >> 6); w < nseg; w += nwaves) {
+        const uint32_t row = w / segs, x = (w - row * segs) * 64u + lane;
+        if (x >= Lx) continue;
+        const uint32_t y = row % Ly, z = row / Ly;
+        const uint32_t base = row * Lx;
+        const uint32_t ry = y + 1u == Ly ? base - y * Lx : base + Lx;  // the row at y + 1
+        const uint32_t rz = z + 1u == Lz ? y * Lx : base + plane;      // the row at z + 1
+        const uint32_t s = spins[base + x];
+        const uint32_t xn = x + 1u == Lx ? 0u : x + 1u;
+        nsat += (s == spins[base + xn] ? 1u : 0u) + (s == spins[ry + x] ? 1u : 0u) + (s == spins[rz + x] ? 1u : 0u);
         const uint32_t st = ising ? (s == 1u ? 1u : 0u) : s;
 #pragma unroll
         for (int k = 0; k < 8; ++k) cnt[k] += st == static_cast<uint32_t>(k) ? 1u : 0u;
     }
-    const int lane = threadIdx.x & 63;
+    // one atomic per counter and workgroup
+    __shared__ unsigned long long red[9][8];
     const unsigned long long ns = wave_sum(nsat);
-    if (lane == 0) add_stat(&stats[S3_NSAT], ns);
+    if (lane == 0) red[0][threadIdx.x >> 6] = ns;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const unsigned long long c = wave_sum(cnt[k]);
-        if (lane == 0) add_stat(&stats[S3_COUNTS + k], c);
+        if (lane == 0) red[1 + k][threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        unsigned long long v = 0;
+        for (int w = 0; w < 8; ++w) v += red[threadIdx.x][w];
+        add_stat(&stats[threadIdx.x == 0 ? S3_NSAT : S3_COUNTS + threadIdx.x - 1], v);
     }
 }
 
@@ -421,7 +574,7 @@ int64_t cdiv3(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Layout3 {
     Geo3 g;
     int64_t N;
-    size_t codes, gkey, gparent, nb, stats, bonds, total;
+    size_t codes, gkey, gparent, nb, tile_act, tile_ncl, stats, bonds, total;
 };
 
 sw_status check3(const sw3_params *p)
@@ -462,6 +615,8 @@ Layout3 layout3(const sw3_params *p)
     L.gkey = take(nt * CAP * sizeof(int32_t));
     L.gparent = take(nt * CAP * sizeof(int32_t));
     L.nb = take(nt * sizeof(int32_t));
+    L.tile_act = take(nt * sizeof(int32_t));
+    L.tile_ncl = take(nt * sizeof(int32_t));
     L.stats = take(16 * sizeof(unsigned long long));
     L.bonds = take(static_cast<size_t>(L.N));
     L.total = off;
@@ -517,7 +672,7 @@ sw_status sw3_sweep(const sw3_params *p, uint8_t *spins, uint32_t t0, int32_t n,
     ta.gkey = at3<int32_t>(workspace, L.gkey);
     ta.gparent = at3<int32_t>(workspace, L.gparent);
     ta.nb = at3<int32_t>(workspace, L.nb);
-    ta.stats = stats;
+    ta.tile_act = at3<int32_t>(workspace, L.tile_act);
     ta.tany = T > 0 ? 1u : 0u;
     ta.tm1 = T > 0 ? static_cast<uint32_t>(T - 1) : 0u;
     ta.k0 = static_cast<uint32_t>(p->seed);
@@ -528,7 +683,6 @@ sw_status sw3_sweep(const sw3_params *p, uint8_t *spins, uint32_t t0, int32_t n,
     ma.g = L.g;
     ma.bonds = ta.bonds;
     ma.codes = ta.codes;
-    ma.gkey = ta.gkey;
     ma.gparent = ta.gparent;
 
     Flat3Args fa{};
@@ -538,15 +692,23 @@ sw_status sw3_sweep(const sw3_params *p, uint8_t *spins, uint32_t t0, int32_t n,
     fa.gkey = ta.gkey;
     fa.gparent = ta.gparent;
     fa.nb = ta.nb;
-    fa.stats = stats;
+    fa.tile_ncl = at3<int32_t>(workspace, L.tile_ncl);
     fa.q = static_cast<uint32_t>(p->q);
     fa.ising = p->spin_kind == SW_SPIN_ISING_I8 ? 1u : 0u;
     fa.k0 = ta.k0;
     fa.k1 = ta.k1;
     fa.sid = ta.sid;
 
+    Resolve3Args ra{};
+    ra.g = L.g;
+    ra.gkey = ta.gkey;
+    ra.gparent = ta.gparent;
+    ra.nb = ta.nb;
+
     const dim3 tiles(static_cast<unsigned>(L.g.ntiles));
-    const unsigned obs_blocks = static_cast<unsigned>(std::min<int64_t>(cdiv3(L.N, 512), 4096));
+    const dim3 id_blocks(static_cast<unsigned>(cdiv3(static_cast<int64_t>(L.g.ntiles) * CAP, 512)));
+    const int64_t segs = static_cast<int64_t>(L.g.Ly) * L.g.Lz * cdiv3(L.g.Lx, 64);
+    const unsigned obs_blocks = static_cast<unsigned>(std::min<int64_t>(cdiv3(segs, 8), 1024));
     hipLaunchKernelGGL(k3_record, dim3(1), dim3(64), 0, s, stats, static_cast<int64_t *>(nullptr));  // clear
     for (int32_t k = 0; k < n; ++k) {
         const uint32_t t = t0 + static_cast<uint32_t>(k);
@@ -555,8 +717,10 @@ sw_status sw3_sweep(const sw3_params *p, uint8_t *spins, uint32_t t0, int32_t n,
         fa.labels = k + 1 == n ? labels : nullptr;
         hipLaunchKernelGGL(k3_tile, tiles, dim3(NT3), 0, s, ta);
         hipLaunchKernelGGL(k3_merge, tiles, dim3(MT), 0, s, ma);
+        hipLaunchKernelGGL(k3_resolve, id_blocks, dim3(512), 0, s, ra);
         hipLaunchKernelGGL(k3_flatten, tiles, dim3(NT3), 0, s, fa);
         if (records) {
+            hipLaunchKernelGGL(k3_reduce_tiles, dim3(1), dim3(1024), 0, s, ta.tile_act, fa.tile_ncl, L.g.ntiles, stats);
             hipLaunchKernelGGL(k3_observe, dim3(obs_blocks), dim3(512), 0, s, spins, L.g, static_cast<int>(fa.ising),
                                stats);
             hipLaunchKernelGGL(k3_record, dim3(1), dim3(64), 0, s, stats, records + static_cast<int64_t>(k) * SW3_REC_LEN);
