@@ -50,6 +50,7 @@ constexpr uint32_t TAG_BOND = 1, TAG_FLIP = 2, TAG_BOND_Z = 5;
 constexpr int CLAIMING = -1;
 constexpr uint16_t CODE_NONE = 0xFFFF;
 static_assert(CAP + CSITES < CODE_NONE, "codes are 16-bit");
+static_assert(CAP < (1 << 15), "merge list entries hold two ids in 15 bits each");
 static_assert(CY * 6 <= 64, "a lane's bonds fit one 64-bit mask");
 
 // Counters of a sweep, in the order of the record fields.
@@ -296,22 +297,35 @@ __device__ __forceinline__ void gunite_prio(int *G, int a, int b)
 
 // Tile consolidation: each active bond leaving the tile through its +x, +y or
 // +z face joins the ids of its two ends (both are face sites, hence claimed).
-// Face positions run along x (y for the +x face), so neighbouring lanes often
-// join the same pair of ids; a lane skips a pair its lower neighbour holds.
+// Every face has one neighbouring tile, so (face, id, id across) names a
+// union.  The workgroup first gathers its distinct unions into a list (the
+// bond bits of all its face positions loaded at once, then the codes of the
+// active ones, duplicates dropped), then works the list off with every lane
+// busy: a lane no longer waits for its wave's deepest union at each of its
+// face positions.
+constexpr int MPOS = (FX + FY + FZ + MT - 1) / MT;  // face positions per merge thread
+
 __global__ __launch_bounds__(MT) void k3_merge(Merge3Args a)
 {
     // seen[d][h]: the last pair (ca << 16 | cb) registered across face d in
-    // hash slot h = ca mod MSEEN.  A lane that gets its own pair back from
-    // the exchange skips the union: the lane that registered the pair
-    // performs it (pairs that share a slot only cost a repeated union).
+    // hash slot h = ca mod MSEEN; a lane that gets its own pair back skips it
+    // (the lane that registered it lists it; pairs sharing a slot are at
+    // worst listed twice)
     __shared__ unsigned int seen[3][MSEEN];
+    __shared__ unsigned int list[FX + FY + FZ];  // d << 30 | ca << 15 | cb
+    __shared__ int nlist;
     const Geo3 g = a.g;
     const TileOf T = tile_of(g, xcd_remap(blockIdx.x, g.ntiles));
     for (int k = threadIdx.x; k < 3 * MSEEN; k += MT) (&seen[0][0])[k] = 0xFFFFFFFFu;
-    __syncthreads();
-    for (int f0 = 0; f0 < FX + FY + FZ; f0 += MT) {  // uniform trip count: the lane exchange needs every lane
-        const int f = f0 + static_cast<int>(threadIdx.x);
-        int lx = 0, ly = 0, lz = 0, d = 0;
+    if (threadIdx.x == 0) nlist = 0;
+    // the neighbouring tile across each face
+    const int tx = T.gx0 / CX, ty = T.gy0 / CY, tz = T.gz0 / CZ;
+    const int nbr[3] = {(tz * g.nty + ty) * g.ntx + (tx + 1 == g.ntx ? 0 : tx + 1),
+                        (tz * g.nty + (ty + 1 == g.nty ? 0 : ty + 1)) * g.ntx + tx,
+                        ((tz + 1 == g.ntz ? 0 : tz + 1) * g.nty + ty) * g.ntx + tx};
+    // site index and the neighbour's slot of face position f, or -1
+    auto face = [&](int f, int &d, int &s1, int &s2) -> int64_t {
+        int lx, ly, lz;
         if (f < FX) {
             d = 0;
             lx = T.tw - 1;
@@ -322,38 +336,55 @@ __global__ __launch_bounds__(MT) void k3_merge(Merge3Args a)
             lx = (f - FX) % CX;
             ly = T.th - 1;
             lz = (f - FX) / CX;
-        } else if (f < FX + FY + FZ) {
+        } else {
             d = 2;
             lx = (f - FX - FY) % CX;
             ly = (f - FX - FY) / CX;
             lz = T.td - 1;
         }
-        int ca = -1, cb = -1;  // the pair of ids this lane's bond joins, or -1
-        int t2 = 0;
-        if (f < FX + FY + FZ && lx < T.tw && ly < T.th && lz < T.td) {
-            const int gx = T.gx0 + lx, gy = T.gy0 + ly, gz = T.gz0 + lz;
-            const int64_t i = (static_cast<int64_t>(gz) * g.Ly + gy) * g.Lx + gx;
-            if ((a.bonds[i] >> d) & 1u) {
-                int nx = gx, ny = gy, nz = gz;
-                if (d == 0) nx = gx + 1 == g.Lx ? 0 : gx + 1;
-                else if (d == 1) ny = gy + 1 == g.Ly ? 0 : gy + 1;
-                else nz = gz + 1 == g.Lz ? 0 : gz + 1;
-                t2 = ((nz / CZ) * g.nty + ny / CY) * g.ntx + nx / CX;
-                const int s1 = (lz * CY + ly) * CX + lx;
-                const int s2 = ((nz % CZ) * CY + ny % CY) * CX + nx % CX;
-                ca = a.codes[static_cast<int64_t>(T.tile) * CSITES + s1];
-                cb = a.codes[static_cast<int64_t>(t2) * CSITES + s2];
-                // face sites always hold ids; never index past the id tables
-                if (ca >= CAP || cb >= CAP) ca = cb = -1;
-            }
+        if (f >= FX + FY + FZ || lx >= T.tw || ly >= T.th || lz >= T.td) return -1;
+        s1 = (lz * CY + ly) * CX + lx;
+        // across the face the neighbour sits at coordinate 0 of that axis
+        s2 = d == 0 ? (lz * CY + ly) * CX : d == 1 ? lz * PLANE + lx : ly * CX + lx;
+        return (static_cast<int64_t>(T.gz0 + lz) * g.Ly + T.gy0 + ly) * g.Lx + T.gx0 + lx;
+    };
+    int ca[MPOS], cb[MPOS], dd[MPOS];
+    bool act[MPOS];
+#pragma unroll
+    for (int j = 0; j < MPOS; ++j) {  // every bond bit first (independent loads)
+        int s1, s2;
+        const int64_t i = face(j * MT + static_cast<int>(threadIdx.x), dd[j], s1, s2);
+        act[j] = i >= 0 && ((a.bonds[i] >> dd[j]) & 1u);
+        ca[j] = s1;
+        cb[j] = s2;
+    }
+#pragma unroll
+    for (int j = 0; j < MPOS; ++j) {  // then the codes of the active ones
+        if (!act[j]) continue;
+        ca[j] = a.codes[static_cast<int64_t>(T.tile) * CSITES + ca[j]];
+        cb[j] = a.codes[static_cast<int64_t>(nbr[dd[j]]) * CSITES + cb[j]];
+        if (ca[j] >= CAP || cb[j] >= CAP) act[j] = false;  // face sites always hold ids
+    }
+    __syncthreads();  // seen and nlist are set
+#pragma unroll
+    for (int j = 0; j < MPOS; ++j) {
+        const int pa = __shfl_up(act[j] ? ca[j] : -1, 1), pb = __shfl_up(cb[j], 1), pd = __shfl_up(dd[j], 1);
+        bool keep = act[j] && !((threadIdx.x & 63) != 0 && pa == ca[j] && pb == cb[j] && pd == dd[j]);
+        if (keep) {
+            const unsigned int key = (static_cast<unsigned int>(ca[j]) << 16) | static_cast<unsigned int>(cb[j]);
+            keep = atomicExch(&seen[dd[j]][ca[j] % MSEEN], key) != key;
         }
-        const int pa = __shfl_up(ca, 1), pb = __shfl_up(cb, 1), pt = __shfl_up(t2, 1);
-        bool dup = (threadIdx.x & 63) != 0 && pa == ca && pb == cb && pt == t2;
-        if (ca >= 0 && !dup) {  // one face has one neighbouring tile: (d, ca, cb) names the pair
-            const unsigned int key = (static_cast<unsigned int>(ca) << 16) | static_cast<unsigned int>(cb);
-            dup = atomicExch(&seen[d][ca % MSEEN], key) == key;
-        }
-        if (ca >= 0 && !dup) gunite_prio(a.gparent, T.tile * CAP + ca, t2 * CAP + cb);
+        if (keep)
+            list[atomicAdd(&nlist, 1)] = (static_cast<unsigned int>(dd[j]) << 30) |
+                                         (static_cast<unsigned int>(ca[j]) << 15) | static_cast<unsigned int>(cb[j]);
+    }
+    __syncthreads();
+    const int n = nlist;
+    for (int k = threadIdx.x; k < n; k += MT) {
+        const unsigned int e = list[k];
+        const int d = static_cast<int>(e >> 30), ia = static_cast<int>((e >> 15) & 0x7FFFu),
+                  ib = static_cast<int>(e & 0x7FFFu);
+        gunite_prio(a.gparent, T.tile * CAP + ia, nbr[d] * CAP + ib);
     }
 }
 
