@@ -51,7 +51,7 @@ constexpr int CLAIMING = -1;
 constexpr uint16_t CODE_NONE = 0xFFFF;
 static_assert(CAP + CSITES < CODE_NONE, "codes are 16-bit");
 static_assert(CAP < (1 << 15), "merge list entries hold two ids in 15 bits each");
-static_assert(CY * 6 <= 64, "a lane's bonds fit one 64-bit mask");
+static_assert(CY * 8 <= 64, "a lane's bonds fit one 64-bit mask");
 
 // Counters of a sweep, in the order of the record fields.
 enum { S3_ACTIVE = 0, S3_NCLUST = 1, S3_NSAT = 2, S3_COUNTS = 3, S3_LEN = 11 };
@@ -112,34 +112,54 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
     for (int s = threadIdx.x; s < CSITES; s += NT3) P[s] = s;
 
     // Bonds of the lane's two sites in each of the wave's rows; bit
-    // 6 ly + 3 j + d of `inside` is bond d (0 +x, 1 +y, 2 +z) of site
+    // 8 ly + 4 j + d of `inside` is bond d (0 +x, 1 +y, 2 +z) of site
     // lx0 + j when it stays in the tile (the others cross a face and are
-    // merged by k3_merge from the bond array).
+    // merged by k3_merge from the bond array).  Site indices fit 32 bits.
     uint64_t inside = 0;
     unsigned act = 0;
     if (lz < T.td) {
-        const int gz = T.gz0 + lz, zn = gz + 1 == g.Lz ? 0 : gz + 1;
+        const uint32_t Lx = static_cast<uint32_t>(g.Lx), Ly = static_cast<uint32_t>(g.Ly);
+        const uint32_t gz = static_cast<uint32_t>(T.gz0 + lz), zn = gz + 1u == static_cast<uint32_t>(g.Lz) ? 0u : gz + 1u;
         // lanes past a ragged edge read a valid column and store nothing
-        const int xs0 = T.gx0 + min(lx0, T.tw - 1), xs1 = T.gx0 + min(lx0 + 1, T.tw - 1);
-        const int xn0 = xs0 + 1 == g.Lx ? 0 : xs0 + 1, xn1 = xs1 + 1 == g.Lx ? 0 : xs1 + 1;
-        const uint32_t in_x = (lx0 + 1 < T.tw ? 1u : 0u) | (lx0 + 2 < T.tw ? 8u : 0u);
-        const uint32_t in_z = lz + 1 < T.td ? 0x24u : 0u;
+        const uint32_t xs0 = static_cast<uint32_t>(T.gx0 + min(lx0, T.tw - 1));
+        const uint32_t xs1 = static_cast<uint32_t>(T.gx0 + min(lx0 + 1, T.tw - 1));
+        const uint32_t xn0 = xs0 + 1u == Lx ? 0u : xs0 + 1u, xn1 = xs1 + 1u == Lx ? 0u : xs1 + 1u;
+        const bool even_lx = (Lx & 1u) == 0u;
+        const bool next_in = lx0 + 2 < T.tw;  // the +x neighbour of site lx0 + 1 is the next lane's first site
+        const uint32_t in_x = (lx0 + 1 < T.tw ? 0x01u : 0u) | (next_in ? 0x10u : 0u);
+        const uint32_t in_z = lz + 1 < T.td ? 0x44u : 0u;
         for (int ly = 0; ly < T.th; ++ly) {
-            const int gy = T.gy0 + ly, yn = gy + 1 == g.Ly ? 0 : gy + 1;
-            const int64_t row = (static_cast<int64_t>(gz) * g.Ly + gy) * g.Lx;
-            const int64_t rowy = (static_cast<int64_t>(gz) * g.Ly + yn) * g.Lx;
-            const int64_t rowz = (static_cast<int64_t>(zn) * g.Ly + gy) * g.Lx;
-            const uint32_t s0 = a.spins[row + xs0], s1 = a.spins[row + xs1];
-            const uint32_t x0 = a.spins[row + xn0], x1 = a.spins[row + xn1];
-            const uint32_t y0 = a.spins[rowy + xs0], y1 = a.spins[rowy + xs1];
-            const uint32_t z0 = a.spins[rowz + xs0], z1 = a.spins[rowz + xs1];
+            const uint32_t gy = static_cast<uint32_t>(T.gy0 + ly), yn = gy + 1u == Ly ? 0u : gy + 1u;
+            const uint32_t row = (gz * Ly + gy) * Lx, rowy = (gz * Ly + yn) * Lx, rowz = (zn * Ly + gy) * Lx;
+            const uint32_t i0 = row + static_cast<uint32_t>(T.gx0 + lx0);
+            uint32_t s0, s1, y0, y1, z0, z1;
+            if (even_lx && v1) {  // the pair in one aligned 16-bit load per row (every row starts even)
+                const uint32_t c = *reinterpret_cast<const uint16_t *>(a.spins + row + xs0);
+                const uint32_t yy = *reinterpret_cast<const uint16_t *>(a.spins + rowy + xs0);
+                const uint32_t zz = *reinterpret_cast<const uint16_t *>(a.spins + rowz + xs0);
+                s0 = c & 0xFFu;
+                s1 = c >> 8;
+                y0 = yy & 0xFFu;
+                y1 = yy >> 8;
+                z0 = zz & 0xFFu;
+                z1 = zz >> 8;
+            } else {
+                s0 = a.spins[row + xs0];
+                s1 = a.spins[row + xs1];
+                y0 = a.spins[rowy + xs0];
+                y1 = a.spins[rowy + xs1];
+                z0 = a.spins[rowz + xs0];
+                z1 = a.spins[rowz + xs1];
+            }
+            const uint32_t nxt = from_next_lane(s0);
+            const uint32_t x0 = v1 ? s1 : a.spins[row + xn0];
+            const uint32_t x1 = next_in ? nxt : a.spins[row + xn1];
             // words: +x and +y from block(i >> 1, BOND) as on the square
             // lattice, +z word i & 3 of block(i >> 2, BOND_Z)
-            const int64_t i0 = row + T.gx0 + lx0;
-            const uint32_t c0 = static_cast<uint32_t>(i0 >> 1);
+            const uint32_t c0 = i0 >> 1;
             const U4 b = philox4x32_10(c0, a.t, TAG_BOND, a.sid, a.k0, a.k1);
             uint32_t rx0, ry0, rx1, ry1;
-            if ((i0 & 1) == 0) {  // the row start's parity is the row's: uniform
+            if ((i0 & 1u) == 0u) {  // the row start's parity is the row's: uniform
                 rx0 = b.v0;
                 ry0 = b.v1;
                 rx1 = b.v2;
@@ -151,13 +171,13 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
                 rx1 = b2.v0;
                 ry1 = b2.v1;
             }
-            const U4 bz = philox4x32_10(static_cast<uint32_t>(i0 >> 2), a.t, TAG_BOND_Z, a.sid, a.k0, a.k1);
-            const uint32_t rz0 = pick(bz, static_cast<uint32_t>(i0 & 3));
+            const U4 bz = philox4x32_10(i0 >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1);
+            const uint32_t rz0 = pick(bz, i0 & 3u);
             uint32_t rz1;
-            if (((i0 + 1) & 3) != 0) {
-                rz1 = pick(bz, static_cast<uint32_t>((i0 + 1) & 3));
+            if (((i0 + 1u) & 3u) != 0u) {
+                rz1 = pick(bz, (i0 + 1u) & 3u);
             } else {  // site i0 + 1 starts the next block
-                rz1 = philox4x32_10(static_cast<uint32_t>((i0 + 1) >> 2), a.t, TAG_BOND_Z, a.sid, a.k0, a.k1).v0;
+                rz1 = philox4x32_10((i0 + 1u) >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1).v0;
             }
             uint32_t m0 = 0, m1 = 0;
             if (v0 && a.tany)
@@ -167,10 +187,14 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
                 m1 = (s1 == x1 && rx1 <= a.tm1 ? 1u : 0u) | (s1 == y1 && ry1 <= a.tm1 ? 2u : 0u) |
                      (s1 == z1 && rz1 <= a.tm1 ? 4u : 0u);
             act += __popc(m0) + __popc(m1);
-            if (v0) a.bonds[i0] = static_cast<uint8_t>(m0);
-            if (v1) a.bonds[i0 + 1] = static_cast<uint8_t>(m1);
-            const uint32_t in_y = ly + 1 < T.th ? 0x12u : 0u;
-            inside |= static_cast<uint64_t>((m0 | (m1 << 3)) & (in_x | in_y | in_z)) << (6 * ly);
+            if ((i0 & 1u) == 0u && v1) {
+                *reinterpret_cast<uint16_t *>(a.bonds + i0) = static_cast<uint16_t>(m0 | (m1 << 8));
+            } else {
+                if (v0) a.bonds[i0] = static_cast<uint8_t>(m0);
+                if (v1) a.bonds[i0 + 1] = static_cast<uint8_t>(m1);
+            }
+            const uint32_t in_y = ly + 1 < T.th ? 0x22u : 0u;
+            inside |= static_cast<uint64_t>((m0 | (m1 << 4)) & (in_x | in_y | in_z)) << (8 * ly);
         }
     }
     __syncthreads();
@@ -184,7 +208,7 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
             if (!busy) {
                 const int bit = __ffsll(static_cast<unsigned long long>(todo)) - 1;
                 todo &= todo - 1;
-                const int ly = bit / 6, j = (bit % 6) / 3, d = bit % 3;
+                const int ly = bit >> 3, j = (bit >> 2) & 1, d = bit & 3;
                 u = (lz * CY + ly) * CX + lx0 + j;
                 v = u + (d == 0 ? 1 : d == 1 ? CX : PLANE);
                 busy = 1;

@@ -270,12 +270,6 @@ __device__ __forceinline__ uint64_t lanes_ne(uint32_t x, uint32_t y) { return __
 __device__ __forceinline__ uint64_t lanes_lt(uint32_t x, uint32_t y) { return __builtin_amdgcn_uicmp(x, y, CMP_ULT); }
 __device__ __forceinline__ uint64_t lanes_le(uint32_t x, uint32_t y) { return __builtin_amdgcn_uicmp(x, y, CMP_ULE); }
 
-// Value of x held by the next lane (DPP wave shift; the last lane gets 0).
-__device__ __forceinline__ uint32_t from_next_lane(uint32_t x)
-{
-    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x130, 0xF, 0xF, false));
-}
-
 // Maximum of v over the lanes below the calling one (0 for lane 0), v >= 0:
 // an inclusive max-scan by row shifts and row broadcasts, then a shift by one
 // lane.  Out-of-row sources read 0, the identity; rows outside a broadcast's

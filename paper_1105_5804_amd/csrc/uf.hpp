@@ -26,6 +26,12 @@ __device__ __forceinline__ bool lane_bit(uint64_t m, int lane)
 }
 
 
+// Value of x held by the next lane (DPP wave shift; the last lane gets 0).
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t x)
+{
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x130, 0xF, 0xF, false));
+}
+
 // ---- LDS union-find (workgroup scope) ----
 __device__ __forceinline__ int lds_ld(int *p)
 {

@@ -13,14 +13,17 @@ satisfied bonds (-H/J, Eq. potts_hamiltonian) and state counts of the spins
 after the flip) and the order-independent array digests (spins after the flip;
 labels and bond bytes of the sweep, before the flip), in hexadecimal.
 
-    python tests/golden/make_sweep_records.py ising64 ising4096 potts16384 batch256 few1024
+    python tests/golden/make_sweep_records.py ising64 ising4096 potts16384 batch256 few1024 cubic128
 
 ising64 / ising4096 / potts16384 record every sweep (1000, 200 + 1000 and 100
 sweeps); batch256 records every lattice of the batched workload after sweeps
 1, 10, 100 and 1000; few1024 records every sweep of the few-cluster update
 (Sec. III) on an Ising 1024 x 1024 lattice at beta_c with 32 x 32 seed tiles
-and p_flip = 1/2 (the FEW parameters below).  The oracle is built with -O3 -march=native for speed; a
-CPU test checks that this build agrees with the default one.
+and p_flip = 1/2 (the FEW parameters below); cubic128 records every sweep of
+the SW update on the simple cubic Ising lattice 128^3 at its critical
+coupling (the CUBIC parameters below; lines "t active n_clusters n_sat
+counts[0..1] digest_spins").  The oracle is built with -O3 -march=native for
+speed; a CPU test checks that this build agrees with the default one.
 """
 from __future__ import annotations
 
@@ -40,6 +43,8 @@ from paper_1105_5804_amd import workloads as wl  # noqa: E402
 BATCH_CHECKPOINTS = (1, 10, 100, 1000)
 # the few-cluster record: L, seed tile edge, p_flip, sweeps, seed
 FEW = dict(L=1024, B=32, p_flip=0.5, sweeps=300, seed=wl.SEED_BASE | 0xFE)
+# the cubic-lattice record: L, sweeps, seed; K = 2 beta_c of the 3D Ising model
+CUBIC = dict(L=128, sweeps=400, seed=wl.SEED_BASE | 0x3DC, K=2 * 0.22165455)
 
 
 def _line(t, rec, q, d_spins, d_labels, d_bonds) -> str:
@@ -140,9 +145,31 @@ def few() -> None:
     print(f"few1024: wrote {out}", flush=True)
 
 
+def cubic() -> None:
+    """Every sweep of the SW update on the CUBIC lattice."""
+    L, n, seed, K = CUBIC["L"], CUBIC["sweeps"], CUBIC["seed"], CUBIC["K"]
+    T = oracle.threshold(K)
+    st = oracle.init_states3(L, L, L, 2, seed)
+    out = os.path.join(HERE, "sweeps_cubic128.txt")
+    t0 = time.time()
+    with open(out + ".tmp", "w") as f:
+        f.write(f"# cubic128: Lx=Ly=Lz={L} q=2 K={K!r} seed={seed:#x} stream_id=0, sweeps t=0..{n - 1}\n")
+        f.write("# written by tests/golden/make_sweep_records.py from the CPU oracle only\n")
+        f.write("# t active n_clusters n_sat counts[0..1] digest_spins\n")
+        for t in range(n):
+            st, _b, _l, rec = oracle.sw3_sweep(L, L, L, 2, T, seed, 0, t, st)
+            f.write(f"{t} {int(rec[oracle.REC3_ACTIVE])} {int(rec[oracle.REC3_NCLUST])} {int(rec[oracle.REC3_NSAT])} "
+                    f"{int(rec[oracle.REC3_COUNTS])} {int(rec[oracle.REC3_COUNTS + 1])} {oracle.digest(st):016x}\n")
+            if t % 20 == 0:
+                print(f"cubic128: sweep {t} of {n} ({time.time() - t0:.0f} s)", flush=True)
+    os.replace(out + ".tmp", out)
+    print(f"cubic128: wrote {out}", flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", nargs="+", choices=["ising64", "ising4096", "potts16384", "batch256", "few1024"])
+    ap.add_argument("which", nargs="+", choices=["ising64", "ising4096", "potts16384", "batch256", "few1024",
+                                                 "cubic128"])
     args = ap.parse_args()
     oracle.use_flavor("native")
     for w in args.which:
@@ -150,6 +177,8 @@ def main() -> int:
             batch()
         elif w == "few1024":
             few()
+        elif w == "cubic128":
+            cubic()
         else:
             single(w)
     return 0

@@ -10,13 +10,16 @@ spins, labels and bond bytes.  The library must reproduce every record, sweep
 by sweep, over the whole run: 1000 sweeps of Ising L = 64, 200 + 1000 of
 Ising L = 4096, the 100 of q = 3 Potts L = 16384 (which covers the sweeps the
 benchmark times), every lattice of the batched workload at its
-checkpoints, and 300 sweeps of the few-cluster update on Ising L = 1024.  A digest is a 64-bit sum of one Philox block per element, so any
-differing element shows in it.
+checkpoints, 300 sweeps of the few-cluster update on Ising L = 1024, and 400
+sweeps of the simple cubic Ising lattice 128^3.  A digest is a 64-bit sum of
+one Philox block per element, so any differing element shows in it.
 """
 import os
 
+import numpy as np
 import pytest
 
+import oracle
 import paper_1105_5804_amd as sw
 from paper_1105_5804_amd import workloads as wl
 
@@ -150,3 +153,29 @@ def test_batch256_checkpoints(fused):
             o = b.observables(j)
             f = stored[cp][j]
             _compare(dict(o, max_cluster=int(f[3])), f, 2, cp - 1, f"batch lattice {j}")
+
+
+def test_cubic128_every_sweep():
+    """The simple cubic Ising lattice 128^3 at its critical coupling: the
+    record of every one of 400 sweeps (active bonds, clusters, satisfied
+    bonds, state counts; sweeps run 40 to a call) and the spins' digest after
+    every 40th sweep, against the oracle's file."""
+    path = os.path.join(GOLDEN, "sweeps_cubic128.txt")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written (tests/golden/make_sweep_records.py cubic128)")
+    head = open(path).readline()
+    L = int(head.split("Lx=Ly=Lz=")[1].split()[0])
+    K = float(head.split("K=")[1].split()[0])
+    seed = int(head.split("seed=")[1].split()[0], 16)
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    lat = sw.CubicLattice(L, L, L, q=2, K=K, seed=seed)
+    print(f"golden cubic128: {len(rows)} sweeps", flush=True)
+    for c0 in range(0, len(rows), 40):
+        rec = lat.sweep(min(40, len(rows) - c0), records=True).cpu().numpy()
+        for k, r in enumerate(rows[c0:c0 + 40]):
+            assert int(r[0]) == c0 + k
+            assert [int(v) for v in rec[k][:5]] == [int(v) for v in r[1:6]], (c0 + k, rec[k][:5], r)
+        s = lat.spins.cpu().numpy().reshape(-1)
+        st = ((s.astype(np.int16) + 1) // 2).astype(np.uint8)
+        assert oracle.digest(st) == int(rows[c0 + len(rec) - 1][6], 16), c0 + len(rec) - 1
+        print(f"golden cubic128: sweep {c0 + len(rec) - 1} ok", flush=True)
