@@ -44,6 +44,7 @@ constexpr int CSITES = PLANE * CZ;                             // 8192 sites per
 constexpr int CAP = CSITES - (CX - 2) * (CY - 2) * (CZ - 2);   // 3656: sites on a face of a full tile
 constexpr int NT3 = 64 * CZ;                                   // one wave per z-plane
 constexpr int MT = 256;                                        // merge workgroup
+constexpr int RT = 256;                                        // resolve workgroup
 constexpr int MSEEN = 1024;                                    // merge: pair-dedup slots per face
 constexpr int FX = CY * CZ, FY = CX * CZ, FZ = CX * CY;        // sites of the +x, +y, +z faces
 constexpr uint32_t TAG_BOND = 1, TAG_FLIP = 2, TAG_BOND_Z = 5;
@@ -432,7 +433,7 @@ __device__ __forceinline__ uint32_t new_state(uint32_t R, const Flat3Args &a)
     return draw_state(pick(b, R & 3u), a.q);
 }
 
-// Every id of every tile resolved after the merge, one thread per id slot:
+// Every id of every tile resolved after the merge:
 // the id's entry is pointed at its root (the trees are final, so concurrent
 // walks stay valid) and the id's key (the minimum site index of its part of
 // the cluster) is taken into the root's key by an atomic minimum, issued only
@@ -446,21 +447,23 @@ struct Resolve3Args {
     const int32_t *nb;
 };
 
-__global__ __launch_bounds__(512) void k3_resolve(Resolve3Args a)
+__global__ __launch_bounds__(RT) void k3_resolve(Resolve3Args a)
 {
-    const int64_t slot = static_cast<int64_t>(blockIdx.x) * 512 + threadIdx.x;
-    const int tile = static_cast<int>(slot / CAP), k = static_cast<int>(slot % CAP);
-    if (tile >= a.g.ntiles || k >= a.nb[tile]) return;
-    const int id = static_cast<int>(slot);
-    int x = id, p = a.gparent[x];
-    while (p != x) {
-        x = p;
-        p = a.gparent[x];
+    // a workgroup per tile, its threads over the tile's ids
+    const int tile = static_cast<int>(blockIdx.x);
+    const int nbt = a.nb[tile];
+    for (int k = threadIdx.x; k < nbt; k += RT) {
+        const int id = tile * CAP + k;
+        int x = id, p = a.gparent[x];
+        while (p != x) {
+            x = p;
+            p = a.gparent[x];
+        }
+        if (x == id) continue;
+        a.gparent[id] = x;
+        const int32_t key = a.gkey[id];  // not a root: its key never changes
+        if (key < a.gkey[x]) atomicMin(&a.gkey[x], key);
     }
-    if (x == id) return;
-    a.gparent[id] = x;
-    const int32_t key = a.gkey[id];  // not a root: its key never changes
-    if (key < a.gkey[x]) atomicMin(&a.gkey[x], key);
 }
 
 __global__ __launch_bounds__(NT3) void k3_flatten(Flat3Args a)
@@ -761,7 +764,6 @@ sw_status sw3_sweep(const sw3_params *p, uint8_t *spins, uint32_t t0, int32_t n,
     ra.nb = ta.nb;
 
     const dim3 tiles(static_cast<unsigned>(L.g.ntiles));
-    const dim3 id_blocks(static_cast<unsigned>(cdiv3(static_cast<int64_t>(L.g.ntiles) * CAP, 512)));
     const int64_t segs = static_cast<int64_t>(L.g.Ly) * L.g.Lz * cdiv3(L.g.Lx, 64);
     const unsigned obs_blocks = static_cast<unsigned>(std::min<int64_t>(cdiv3(segs, 8), 1024));
     hipLaunchKernelGGL(k3_record, dim3(1), dim3(64), 0, s, stats, static_cast<int64_t *>(nullptr));  // clear
@@ -772,7 +774,7 @@ sw_status sw3_sweep(const sw3_params *p, uint8_t *spins, uint32_t t0, int32_t n,
         fa.labels = k + 1 == n ? labels : nullptr;
         hipLaunchKernelGGL(k3_tile, tiles, dim3(NT3), 0, s, ta);
         hipLaunchKernelGGL(k3_merge, tiles, dim3(MT), 0, s, ma);
-        hipLaunchKernelGGL(k3_resolve, id_blocks, dim3(512), 0, s, ra);
+        hipLaunchKernelGGL(k3_resolve, tiles, dim3(RT), 0, s, ra);
         hipLaunchKernelGGL(k3_flatten, tiles, dim3(NT3), 0, s, fa);
         if (records) {
             hipLaunchKernelGGL(k3_reduce_tiles, dim3(1), dim3(1024), 0, s, ta.tile_act, fa.tile_ncl, L.g.ntiles, stats);
