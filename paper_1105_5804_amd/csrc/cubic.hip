@@ -221,7 +221,10 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
     }
     __syncthreads();
 
-    // claims: the root of every cluster that touches a tile face gets an id
+    // Every site's root, walked once (the trees are final after the unions)
+    // and kept in registers for the claims and the codes.  Other waves may
+    // already be claiming: a claimed root's entry is negative, and the walk
+    // ends there too.
     auto root_of = [&](int x) {
         for (;;) {
             const int p = lds_ld(&P[x]);
@@ -229,38 +232,51 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
             x = p;
         }
     };
-    if (lz < T.td) {
-        for (int ly = 0; ly < T.th; ++ly) {
-            const bool plane_face = ly == 0 || ly == T.th - 1 || lz == 0 || lz == T.td - 1;
+    int rt[CY][2];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int lx = lx0 + j;
-                if (lx >= T.tw || !(plane_face || lx == 0 || lx == T.tw - 1)) continue;
-                const int r = root_of((lz * CY + ly) * CX + lx);
-                int expect = r;
-                if (__hip_atomic_compare_exchange_strong(&P[r], &expect, CLAIMING, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_WORKGROUP)) {
-                    const int k = atomicAdd(&nb_s, 1);
-                    lds_st(&P[r], -(k + 2));
-                    const int id = T.tile * CAP + k;
-                    a.gkey[id] = site_of(g, T, r);
-                    a.gparent[id] = id;
-                }
+    for (int ly = 0; ly < CY; ++ly) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            rt[ly][j] = 0;
+            if (lz < T.td && ly < T.th && lx0 + j < T.tw) rt[ly][j] = root_of((lz * CY + ly) * CX + lx0 + j);
+        }
+    }
+    // claims: the root of every cluster that touches a tile face gets an id
+#pragma unroll
+    for (int ly = 0; ly < CY; ++ly) {
+        if (lz >= T.td || ly >= T.th) continue;
+        const bool plane_face = ly == 0 || ly == T.th - 1 || lz == 0 || lz == T.td - 1;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int lx = lx0 + j;
+            if (lx >= T.tw || !(plane_face || lx == 0 || lx == T.tw - 1)) continue;
+            const int r = rt[ly][j];
+            int expect = r;
+            if (__hip_atomic_compare_exchange_strong(&P[r], &expect, CLAIMING, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                const int k = atomicAdd(&nb_s, 1);
+                lds_st(&P[r], -(k + 2));
+                const int id = T.tile * CAP + k;
+                a.gkey[id] = site_of(g, T, r);
+                a.gparent[id] = id;
             }
         }
     }
     __syncthreads();
 
-    // codes: the id of a claimed root, else CAP + the root's slot
+    // codes: the id of a claimed root (its entry reads -(id + 2)), else CAP +
+    // the root's slot
     if (lz < T.td) {
         uint16_t *codes = a.codes + static_cast<int64_t>(T.tile) * CSITES;
-        for (int ly = 0; ly < T.th; ++ly) {
+#pragma unroll
+        for (int ly = 0; ly < CY; ++ly) {
+            if (ly >= T.th) continue;
             const int s = (lz * CY + ly) * CX + lx0;
             uint32_t c[2] = {CODE_NONE, CODE_NONE};
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 if (lx0 + j >= T.tw) continue;
-                const int r = root_of(s + j);
+                const int r = rt[ly][j];
                 const int pr = lds_ld(&P[r]);
                 c[j] = pr < 0 ? static_cast<uint32_t>(-pr - 2) : static_cast<uint32_t>(CAP + r);
             }
