@@ -87,6 +87,13 @@ __device__ __forceinline__ int32_t site_of(const Geo3 &g, const TileOf &t, int s
     return static_cast<int32_t>((static_cast<int64_t>(t.gz0 + lz) * g.Ly + t.gy0 + ly) * g.Lx + t.gx0 + lx);
 }
 
+// Value of x held by the other lane of the calling lane's pair (2m <-> 2m + 1;
+// DPP quad permutation 1, 0, 3, 2).
+__device__ __forceinline__ uint32_t swap_pair_lanes(uint32_t x)
+{
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0xB1, 0xF, 0xF, false));
+}
+
 struct Tile3Args {
     Geo3 g;
     const uint8_t *spins;
@@ -126,6 +133,12 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
         const uint32_t xs1 = static_cast<uint32_t>(T.gx0 + min(lx0 + 1, T.tw - 1));
         const uint32_t xn0 = xs0 + 1u == Lx ? 0u : xs0 + 1u, xn1 = xs1 + 1u == Lx ? 0u : xs1 + 1u;
         const bool even_lx = (Lx & 1u) == 0u;
+        // with Lx a multiple of 4 every row starts at a multiple of 4, so the
+        // two lanes of a pair share one +z block per row: each draws one of
+        // two rows' blocks and the halves are swapped between the pair
+        const bool quad_lx = (Lx & 3u) == 0u;
+        const bool odd_lane = (lane & 1) != 0;
+        uint32_t zpend0 = 0, zpend1 = 0;  // +z words of the next row, drawn with this one
         const bool next_in = lx0 + 2 < T.tw;  // the +x neighbour of site lx0 + 1 is the next lane's first site
         const uint32_t in_x = (lx0 + 1 < T.tw ? 0x01u : 0u) | (next_in ? 0x10u : 0u);
         const uint32_t in_z = lz + 1 < T.td ? 0x44u : 0u;
@@ -172,13 +185,30 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
                 rx1 = b2.v0;
                 ry1 = b2.v1;
             }
-            const U4 bz = philox4x32_10(i0 >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1);
-            const uint32_t rz0 = pick(bz, i0 & 3u);
-            uint32_t rz1;
-            if (((i0 + 1u) & 3u) != 0u) {
-                rz1 = pick(bz, (i0 + 1u) & 3u);
-            } else {  // site i0 + 1 starts the next block
-                rz1 = philox4x32_10((i0 + 1u) >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1).v0;
+            uint32_t rz0, rz1;
+            if (quad_lx && (ly & 1) == 0 && ly + 1 < T.th) {
+                // the even lane draws its pair's block of this row, the odd
+                // lane that of the next row (ly + 1 < th: no wrap in y)
+                const uint32_t pair = static_cast<uint32_t>(T.gx0 + 2 * (lane & ~1));
+                const U4 bz = philox4x32_10((odd_lane ? row + Lx + pair : row + pair) >> 2, a.t, TAG_BOND_Z, a.sid,
+                                            a.k0, a.k1);
+                const uint32_t ra = swap_pair_lanes(odd_lane ? bz.v0 : bz.v2);
+                const uint32_t rb = swap_pair_lanes(odd_lane ? bz.v1 : bz.v3);
+                rz0 = odd_lane ? ra : bz.v0;  // this row: words 0, 1 (even lane) or 2, 3 (odd lane)
+                rz1 = odd_lane ? rb : bz.v1;
+                zpend0 = odd_lane ? bz.v2 : ra;  // the next row's
+                zpend1 = odd_lane ? bz.v3 : rb;
+            } else if (quad_lx && (ly & 1) == 1) {
+                rz0 = zpend0;
+                rz1 = zpend1;
+            } else {
+                const U4 bz = philox4x32_10(i0 >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1);
+                rz0 = pick(bz, i0 & 3u);
+                if (((i0 + 1u) & 3u) != 0u) {
+                    rz1 = pick(bz, (i0 + 1u) & 3u);
+                } else {  // site i0 + 1 starts the next block
+                    rz1 = philox4x32_10((i0 + 1u) >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1).v0;
+                }
             }
             uint32_t m0 = 0, m1 = 0;
             if (v0 && a.tany)

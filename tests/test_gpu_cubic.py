@@ -3,7 +3,9 @@
 after every sweep.
 
 Shapes cover one tile with its periodic wraps inside the tile, ragged tiles
-along each axis, odd Lx (rows starting at odd site indices), extents 1 and 2
+along each axis, odd Lx (rows starting at odd site indices), Lx a multiple of
+4 with an odd number of rows in a tile (the +z draws shared by lane pairs
+over row pairs, and a last single row), extents 1 and 2
 (self-bonds and doubled bonds), a restart at a sweep number other than 0,
 Lz = 1 against the square-lattice sweep of the same library, and the 256^3
 and 512^3 Ising lattices at the 3D critical coupling.
@@ -42,6 +44,7 @@ CASES = [
     (300, 1, 2, 2, 0.9, True),
     (64, 64, 64, 2, K3, True),
     (33, 70, 20, 3, 0.8, False),
+    (132, 13, 9, 2, K3, True),               # Lx a multiple of 4 (lane pairs share +z blocks), odd tile heights
 ]
 
 
