@@ -7,8 +7,10 @@ along each axis, odd Lx (rows starting at odd site indices), Lx a multiple of
 4 with an odd number of rows in a tile (the +z draws shared by lane pairs
 over row pairs, and a last single row), extents 1 and 2
 (self-bonds and doubled bonds), a restart at a sweep number other than 0,
-Lz = 1 against the square-lattice sweep of the same library, and the 256^3
-and 512^3 Ising lattices at the 3D critical coupling.
+Lz = 1 against the square-lattice sweep of the same library, the 256^3 and
+512^3 Ising lattices at the 3D critical coupling, and the largest accepted
+shape class (1024 x 1024 x 2047) by sampled definitions and whole-lattice
+counts.
 """
 import numpy as np
 import pytest
@@ -120,3 +122,61 @@ def test_cubic_full_size(L, sweeps):
         assert [int(v) for v in rec[0].cpu()] == [int(v) for v in want], t
         assert np.array_equal(_state(lat), st), t
     assert np.array_equal(lat.labels.cpu().numpy().reshape(-1), labels)
+
+
+def test_cubic_largest():
+    """The largest cubic shape class the library accepts (N just below 2^31,
+    ragged along z): one sweep, checked where the oracle cannot run whole.
+    At 6000 sampled sites (and the corners): the initial state, the three
+    bond bits from the Philox words of the definition, labels that are
+    canonical (a root labels itself and is the smallest index seen) and equal
+    across every active sampled bond, and the new state drawn at the label;
+    over the whole lattice, the recorded state counts, active bonds and
+    clusters."""
+    Lx, Ly, Lz = 1024, 1024, 2047
+    N = Lx * Ly * Lz
+    assert N < 2**31
+    seed = wl.SEED_BASE | 0x3D7
+    print(f"cubic {Lx}x{Ly}x{Lz} (N={N})", flush=True)
+    lat = sw.CubicLattice(Lx, Ly, Lz, q=2, K=K3, seed=seed, keep_labels=True, keep_bonds=True)
+    before = _state(lat)
+    rec = lat.sweep(1, records=True)[0].cpu().numpy()
+    torch.cuda.synchronize()
+    after = _state(lat)
+    bonds = lat.bonds.cpu().numpy().reshape(-1)
+    labels = lat.labels.cpu().numpy().reshape(-1)
+    del lat
+    torch.cuda.empty_cache()
+    T = oracle.threshold(K3)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    rng = np.random.default_rng(11)
+    sample = [0, Lx - 1, Lx * Ly - 1, N - Lx * Ly, N - 1] + [int(v) for v in rng.integers(0, N, 6000)]
+    plane = Lx * Ly
+    for i in sample:
+        x, y, z = i % Lx, (i // Lx) % Ly, i // plane
+        w = oracle.philox([i >> 2, 0, oracle.TAG_INIT, 0], key)[i & 3]
+        nbr = [z * plane + y * Lx + (x + 1) % Lx, z * plane + ((y + 1) % Ly) * Lx + x,
+               ((z + 1) % Lz) * plane + y * Lx + x]
+        b = oracle.philox([i >> 1, 0, oracle.TAG_BOND, 0], key)
+        bz = oracle.philox([i >> 2, 0, oracle.TAG_BOND_Z, 0], key)
+        words = [int(b[2 * (i & 1)]), int(b[2 * (i & 1) + 1]), int(bz[i & 3])]
+        want = sum(1 << k for k in range(3) if before[i] == before[nbr[k]] and words[k] < T)
+        assert before[i] == (int(w) * 2) >> 32, i
+        assert bonds[i] == want, i
+        r = int(labels[i])
+        assert 0 <= r <= i and labels[r] == r, i
+        for k in range(3):
+            if (want >> k) & 1:
+                assert labels[nbr[k]] == r, (i, k)
+                assert r <= nbr[k]
+        f = oracle.philox([r >> 2, 0, oracle.TAG_FLIP, 0], key)[r & 3]
+        assert after[i] == (int(f) * 2) >> 32, i
+    n1 = int(np.count_nonzero(after))
+    assert [int(v) for v in rec[oracle.REC3_COUNTS:oracle.REC3_COUNTS + 2]] == [N - n1, n1]
+    active = sum(int(np.count_nonzero(bonds & (1 << k))) for k in range(3))
+    assert int(rec[oracle.REC3_ACTIVE]) == active
+    roots, step = 0, 1 << 27
+    for c0 in range(0, N, step):
+        c1 = min(N, c0 + step)
+        roots += int(np.count_nonzero(labels[c0:c1] == np.arange(c0, c1, dtype=np.int32)))
+    assert int(rec[oracle.REC3_NCLUST]) == roots
