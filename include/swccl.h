@@ -463,7 +463,7 @@ sw_status ccl_server_destroy(ccl_server *s);
  *     bond joins a site to itself and the sweep follows the Lx x Ly
  *     square-lattice trajectory exactly.
  *
- * The library labels on tiles of 128 x 8 x 8 sites (bonds fused with a
+ * The library labels on tiles of 32 x 16 x 16 sites (bonds fused with a
  * union-find in LDS; the clusters touching a tile face get compact ids),
  * merges the ids over the bonds that cross tile faces, then resolves every
  * id, draws one state per cluster and writes the spins (Sec. II.B-II.D). */

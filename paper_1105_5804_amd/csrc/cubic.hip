@@ -4,8 +4,10 @@
 //
 // A sweep is four launches:
 //
-//   k3_tile     one 512-thread workgroup per 128 x 8 x 8 tile; each wave owns
-//               one z-plane of the tile (8 rows of 128 sites, two per lane).
+//   k3_tile     one 512-thread workgroup per 32 x 16 x 16 tile (the shape of
+//               8192 sites with the fewest face sites and crossing bonds);
+//               two sites per lane, a wave-wide step covering four tile rows,
+//               each wave eight steps.
 //               Bond activation of the +x, +y and +z bonds (Sec. II.A) fused
 //               with a lock-free union-find in LDS over the bonds that stay in
 //               the tile (Sec. II.B.2); the clusters touching any tile face
@@ -38,11 +40,21 @@
 namespace swccl {
 namespace cubic {
 
-constexpr int CX = 128, CY = 8, CZ = 8;                       // tile extent: a wave owns a z-plane of CY rows
+constexpr int CX = 32, CY = 16, CZ = 16;                      // tile extent (x fastest)
 constexpr int PLANE = CX * CY;                                 // sites of a tile z-plane
-constexpr int CSITES = PLANE * CZ;                             // 8192 sites per tile
-constexpr int CAP = CSITES - (CX - 2) * (CY - 2) * (CZ - 2);   // 3656: sites on a face of a full tile
-constexpr int NT3 = 64 * CZ;                                   // one wave per z-plane
+constexpr int CSITES = PLANE * CZ;                             // sites per tile
+constexpr int CAP = CSITES - (CX - 2) * (CY - 2) * (CZ - 2);   // sites on a face of a full tile
+// Lanes: two sites each, so a wave-wide step covers 128 sites, RPI tile rows
+// of CX sites; the tile's CY * CZ rows are dealt to NW3 waves, RW rows (ITER
+// steps) each.  Row R of a tile is (ly, lz) = (R mod CY, R / CY).
+constexpr int NW3 = 8;                                         // waves per tile workgroup
+constexpr int NT3 = 64 * NW3;
+constexpr int LPR = CX / 2;                                    // lanes per tile row
+constexpr int RPI = 64 / LPR;                                  // tile rows per step
+constexpr int RW = CY * CZ / NW3;                              // tile rows per wave
+constexpr int ITER = RW / RPI;                                 // steps per wave
+static_assert(CSITES == 128 * NW3 * ITER && ITER == 8, "eight steps of 128 sites per wave");
+static_assert(CY % (2 * RPI) == 0 && RW % (2 * RPI) == 0, "steps pair up inside a z-plane");
 constexpr int MT = 256;                                        // merge workgroup
 constexpr int RT = 256;                                        // resolve workgroup
 constexpr int MSEEN = 1024;                                    // merge: pair-dedup slots per face
@@ -52,7 +64,7 @@ constexpr int CLAIMING = -1;
 constexpr uint16_t CODE_NONE = 0xFFFF;
 static_assert(CAP + CSITES < CODE_NONE, "codes are 16-bit");
 static_assert(CAP < (1 << 15), "merge list entries hold two ids in 15 bits each");
-static_assert(CY * 8 <= 64, "a lane's bonds fit one 64-bit mask");
+static_assert(ITER * 8 <= 64, "a lane's bonds fit one 64-bit mask");
 
 // Counters of a sweep, in the order of the record fields.
 enum { S3_ACTIVE = 0, S3_NCLUST = 1, S3_NSAT = 2, S3_COUNTS = 3, S3_LEN = 11 };
@@ -110,123 +122,129 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
 {
     __shared__ int P[CSITES];
     __shared__ int nb_s;
-    __shared__ unsigned act_w[CZ];
+    __shared__ unsigned act_w[NW3];
     const Geo3 g = a.g;
     const TileOf T = tile_of(g, xcd_remap(blockIdx.x, g.ntiles));
-    const int lane = threadIdx.x & 63, lz = wave_id();
-    const int lx0 = 2 * lane;
-    const bool v0 = lx0 < T.tw, v1 = lx0 + 1 < T.tw;
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const int sub = lane / LPR, lx0 = 2 * (lane % LPR);  // the lane's row in a step, its first site
+    // the lane's tile row at step it, and whether that row lies in the tile
+    auto row_of = [&](int it) { return w * RW + it * RPI + sub; };
+    auto row_in = [&](int R) { return R % CY < T.th && R / CY < T.td; };
     if (threadIdx.x == 0) nb_s = 0;
-    for (int s = threadIdx.x; s < CSITES; s += NT3) P[s] = s;
+    for (int k = threadIdx.x; k < CSITES; k += NT3) P[k] = k;
 
-    // Bonds of the lane's two sites in each of the wave's rows; bit
-    // 8 ly + 4 j + d of `inside` is bond d (0 +x, 1 +y, 2 +z) of site
-    // lx0 + j when it stays in the tile (the others cross a face and are
-    // merged by k3_merge from the bond array).  Site indices fit 32 bits.
+    // Bonds of the lane's two sites at each step; bit 8 it + 4 j + d of
+    // `inside` is bond d (0 +x, 1 +y, 2 +z) of site lx0 + j of the step's row
+    // when it stays in the tile (the others cross a face and are merged by
+    // k3_merge from the bond array).  Site indices fit 32 bits.
     uint64_t inside = 0;
     unsigned act = 0;
-    if (lz < T.td) {
-        const uint32_t Lx = static_cast<uint32_t>(g.Lx), Ly = static_cast<uint32_t>(g.Ly);
-        const uint32_t gz = static_cast<uint32_t>(T.gz0 + lz), zn = gz + 1u == static_cast<uint32_t>(g.Lz) ? 0u : gz + 1u;
-        // lanes past a ragged edge read a valid column and store nothing
-        const uint32_t xs0 = static_cast<uint32_t>(T.gx0 + min(lx0, T.tw - 1));
-        const uint32_t xs1 = static_cast<uint32_t>(T.gx0 + min(lx0 + 1, T.tw - 1));
-        const uint32_t xn0 = xs0 + 1u == Lx ? 0u : xs0 + 1u, xn1 = xs1 + 1u == Lx ? 0u : xs1 + 1u;
-        const bool even_lx = (Lx & 1u) == 0u;
-        // with Lx a multiple of 4 every row starts at a multiple of 4, so the
-        // two lanes of a pair share one +z block per row: each draws one of
-        // two rows' blocks and the halves are swapped between the pair
-        const bool quad_lx = (Lx & 3u) == 0u;
-        const bool odd_lane = (lane & 1) != 0;
-        uint32_t zpend0 = 0, zpend1 = 0;  // +z words of the next row, drawn with this one
-        const bool next_in = lx0 + 2 < T.tw;  // the +x neighbour of site lx0 + 1 is the next lane's first site
-        const uint32_t in_x = (lx0 + 1 < T.tw ? 0x01u : 0u) | (next_in ? 0x10u : 0u);
-        const uint32_t in_z = lz + 1 < T.td ? 0x44u : 0u;
-        for (int ly = 0; ly < T.th; ++ly) {
-            const uint32_t gy = static_cast<uint32_t>(T.gy0 + ly), yn = gy + 1u == Ly ? 0u : gy + 1u;
-            const uint32_t row = (gz * Ly + gy) * Lx, rowy = (gz * Ly + yn) * Lx, rowz = (zn * Ly + gy) * Lx;
-            const uint32_t i0 = row + static_cast<uint32_t>(T.gx0 + lx0);
-            uint32_t s0, s1, y0, y1, z0, z1;
-            if (even_lx && v1) {  // the pair in one aligned 16-bit load per row (every row starts even)
-                const uint32_t c = *reinterpret_cast<const uint16_t *>(a.spins + row + xs0);
-                const uint32_t yy = *reinterpret_cast<const uint16_t *>(a.spins + rowy + xs0);
-                const uint32_t zz = *reinterpret_cast<const uint16_t *>(a.spins + rowz + xs0);
-                s0 = c & 0xFFu;
-                s1 = c >> 8;
-                y0 = yy & 0xFFu;
-                y1 = yy >> 8;
-                z0 = zz & 0xFFu;
-                z1 = zz >> 8;
-            } else {
-                s0 = a.spins[row + xs0];
-                s1 = a.spins[row + xs1];
-                y0 = a.spins[rowy + xs0];
-                y1 = a.spins[rowy + xs1];
-                z0 = a.spins[rowz + xs0];
-                z1 = a.spins[rowz + xs1];
-            }
-            const uint32_t nxt = from_next_lane(s0);
-            const uint32_t x0 = v1 ? s1 : a.spins[row + xn0];
-            const uint32_t x1 = next_in ? nxt : a.spins[row + xn1];
-            // words: +x and +y from block(i >> 1, BOND) as on the square
-            // lattice, +z word i & 3 of block(i >> 2, BOND_Z)
-            const uint32_t c0 = i0 >> 1;
-            const U4 b = philox4x32_10(c0, a.t, TAG_BOND, a.sid, a.k0, a.k1);
-            uint32_t rx0, ry0, rx1, ry1;
-            if ((i0 & 1u) == 0u) {  // the row start's parity is the row's: uniform
-                rx0 = b.v0;
-                ry0 = b.v1;
-                rx1 = b.v2;
-                ry1 = b.v3;
-            } else {
-                rx0 = b.v2;
-                ry0 = b.v3;
-                const U4 b2 = philox4x32_10(c0 + 1u, a.t, TAG_BOND, a.sid, a.k0, a.k1);
-                rx1 = b2.v0;
-                ry1 = b2.v1;
-            }
-            uint32_t rz0, rz1;
-            if (quad_lx && (ly & 1) == 0 && ly + 1 < T.th) {
-                // the even lane draws its pair's block of this row, the odd
-                // lane that of the next row (ly + 1 < th: no wrap in y)
-                const uint32_t pair = static_cast<uint32_t>(T.gx0 + 2 * (lane & ~1));
-                const U4 bz = philox4x32_10((odd_lane ? row + Lx + pair : row + pair) >> 2, a.t, TAG_BOND_Z, a.sid,
-                                            a.k0, a.k1);
-                const uint32_t ra = swap_pair_lanes(odd_lane ? bz.v0 : bz.v2);
-                const uint32_t rb = swap_pair_lanes(odd_lane ? bz.v1 : bz.v3);
-                rz0 = odd_lane ? ra : bz.v0;  // this row: words 0, 1 (even lane) or 2, 3 (odd lane)
-                rz1 = odd_lane ? rb : bz.v1;
-                zpend0 = odd_lane ? bz.v2 : ra;  // the next row's
-                zpend1 = odd_lane ? bz.v3 : rb;
-            } else if (quad_lx && (ly & 1) == 1) {
-                rz0 = zpend0;
-                rz1 = zpend1;
-            } else {
-                const U4 bz = philox4x32_10(i0 >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1);
-                rz0 = pick(bz, i0 & 3u);
-                if (((i0 + 1u) & 3u) != 0u) {
-                    rz1 = pick(bz, (i0 + 1u) & 3u);
-                } else {  // site i0 + 1 starts the next block
-                    rz1 = philox4x32_10((i0 + 1u) >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1).v0;
-                }
-            }
-            uint32_t m0 = 0, m1 = 0;
-            if (v0 && a.tany)
-                m0 = (s0 == x0 && rx0 <= a.tm1 ? 1u : 0u) | (s0 == y0 && ry0 <= a.tm1 ? 2u : 0u) |
-                     (s0 == z0 && rz0 <= a.tm1 ? 4u : 0u);
-            if (v1 && a.tany)
-                m1 = (s1 == x1 && rx1 <= a.tm1 ? 1u : 0u) | (s1 == y1 && ry1 <= a.tm1 ? 2u : 0u) |
-                     (s1 == z1 && rz1 <= a.tm1 ? 4u : 0u);
-            act += __popc(m0) + __popc(m1);
-            if ((i0 & 1u) == 0u && v1) {
-                *reinterpret_cast<uint16_t *>(a.bonds + i0) = static_cast<uint16_t>(m0 | (m1 << 8));
-            } else {
-                if (v0) a.bonds[i0] = static_cast<uint8_t>(m0);
-                if (v1) a.bonds[i0 + 1] = static_cast<uint8_t>(m1);
-            }
-            const uint32_t in_y = ly + 1 < T.th ? 0x22u : 0u;
-            inside |= static_cast<uint64_t>((m0 | (m1 << 4)) & (in_x | in_y | in_z)) << (8 * ly);
+    const uint32_t Lx = static_cast<uint32_t>(g.Lx), Ly = static_cast<uint32_t>(g.Ly);
+    // lanes past a ragged edge read a valid column and store nothing
+    const uint32_t xs0 = static_cast<uint32_t>(T.gx0 + min(lx0, T.tw - 1));
+    const uint32_t xs1 = static_cast<uint32_t>(T.gx0 + min(lx0 + 1, T.tw - 1));
+    const uint32_t xn0 = xs0 + 1u == Lx ? 0u : xs0 + 1u, xn1 = xs1 + 1u == Lx ? 0u : xs1 + 1u;
+    const bool even_lx = (Lx & 1u) == 0u;
+    // with Lx a multiple of 4 every row starts at a multiple of 4, so the two
+    // lanes of a pair share one +z block per row: in a tile full along y and
+    // z each draws the block of one of two consecutive steps' rows and the
+    // halves are swapped between the pair
+    const bool zpairs = (Lx & 3u) == 0u && T.th == CY && T.td == CZ;
+    const bool odd_lane = (lane & 1) != 0;
+    uint32_t zpend0 = 0, zpend1 = 0;  // +z words of the next step's row, drawn with this one
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+        const int R = row_of(it), ly = R % CY, lz = R / CY;
+        const bool rin = row_in(R);
+        const bool v0 = rin && lx0 < T.tw, v1 = rin && lx0 + 1 < T.tw;
+        const bool next_in = rin && lx0 + 2 < T.tw;  // the +x neighbour of site lx0 + 1 is the next lane's first
+        // rows outside the tile read a valid row and store nothing
+        const uint32_t gy = static_cast<uint32_t>(T.gy0 + min(ly, T.th - 1));
+        const uint32_t gz = static_cast<uint32_t>(T.gz0 + min(lz, T.td - 1));
+        const uint32_t yn = gy + 1u == Ly ? 0u : gy + 1u, zn = gz + 1u == static_cast<uint32_t>(g.Lz) ? 0u : gz + 1u;
+        const uint32_t row = (gz * Ly + gy) * Lx, rowy = (gz * Ly + yn) * Lx, rowz = (zn * Ly + gy) * Lx;
+        const uint32_t i0 = row + static_cast<uint32_t>(T.gx0 + lx0);
+        uint32_t s0, s1, y0, y1, z0, z1;
+        if (even_lx && v1) {  // the pair in one aligned 16-bit load per row (every row starts even)
+            const uint32_t c = *reinterpret_cast<const uint16_t *>(a.spins + row + xs0);
+            const uint32_t yy = *reinterpret_cast<const uint16_t *>(a.spins + rowy + xs0);
+            const uint32_t zz = *reinterpret_cast<const uint16_t *>(a.spins + rowz + xs0);
+            s0 = c & 0xFFu;
+            s1 = c >> 8;
+            y0 = yy & 0xFFu;
+            y1 = yy >> 8;
+            z0 = zz & 0xFFu;
+            z1 = zz >> 8;
+        } else {
+            s0 = a.spins[row + xs0];
+            s1 = a.spins[row + xs1];
+            y0 = a.spins[rowy + xs0];
+            y1 = a.spins[rowy + xs1];
+            z0 = a.spins[rowz + xs0];
+            z1 = a.spins[rowz + xs1];
         }
+        const uint32_t nxt = from_next_lane(s0);
+        const uint32_t x0 = v1 ? s1 : a.spins[row + xn0];
+        const uint32_t x1 = next_in ? nxt : a.spins[row + xn1];
+        // words: +x and +y from block(i >> 1, BOND) as on the square
+        // lattice, +z word i & 3 of block(i >> 2, BOND_Z)
+        const uint32_t c0 = i0 >> 1;
+        const U4 bk = philox4x32_10(c0, a.t, TAG_BOND, a.sid, a.k0, a.k1);
+        uint32_t rx0, ry0, rx1, ry1;
+        if ((i0 & 1u) == 0u) {
+            rx0 = bk.v0;
+            ry0 = bk.v1;
+            rx1 = bk.v2;
+            ry1 = bk.v3;
+        } else {  // odd row start (odd Lx): i0 is the second site of its block
+            rx0 = bk.v2;
+            ry0 = bk.v3;
+            const U4 b2 = philox4x32_10(c0 + 1u, a.t, TAG_BOND, a.sid, a.k0, a.k1);
+            rx1 = b2.v0;
+            ry1 = b2.v1;
+        }
+        uint32_t rz0, rz1;
+        if (zpairs && (it & 1) == 0) {
+            // the even lane draws its pair's block of this row, the odd lane
+            // that of the next step's row (RPI rows on, same plane, no wrap)
+            const uint32_t pair = static_cast<uint32_t>(T.gx0 + 2 * ((lane % LPR) & ~1));
+            const U4 bz = philox4x32_10((odd_lane ? row + RPI * Lx + pair : row + pair) >> 2, a.t, TAG_BOND_Z,
+                                        a.sid, a.k0, a.k1);
+            const uint32_t ra = swap_pair_lanes(odd_lane ? bz.v0 : bz.v2);
+            const uint32_t rb = swap_pair_lanes(odd_lane ? bz.v1 : bz.v3);
+            rz0 = odd_lane ? ra : bz.v0;  // this row: words 0, 1 (even lane) or 2, 3 (odd lane)
+            rz1 = odd_lane ? rb : bz.v1;
+            zpend0 = odd_lane ? bz.v2 : ra;  // the next step's row
+            zpend1 = odd_lane ? bz.v3 : rb;
+        } else if (zpairs) {
+            rz0 = zpend0;
+            rz1 = zpend1;
+        } else {
+            const U4 bz = philox4x32_10(i0 >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1);
+            rz0 = pick(bz, i0 & 3u);
+            if (((i0 + 1u) & 3u) != 0u) {
+                rz1 = pick(bz, (i0 + 1u) & 3u);
+            } else {  // site i0 + 1 starts the next block
+                rz1 = philox4x32_10((i0 + 1u) >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1).v0;
+            }
+        }
+        uint32_t m0 = 0, m1 = 0;
+        if (v0 && a.tany)
+            m0 = (s0 == x0 && rx0 <= a.tm1 ? 1u : 0u) | (s0 == y0 && ry0 <= a.tm1 ? 2u : 0u) |
+                 (s0 == z0 && rz0 <= a.tm1 ? 4u : 0u);
+        if (v1 && a.tany)
+            m1 = (s1 == x1 && rx1 <= a.tm1 ? 1u : 0u) | (s1 == y1 && ry1 <= a.tm1 ? 2u : 0u) |
+                 (s1 == z1 && rz1 <= a.tm1 ? 4u : 0u);
+        act += __popc(m0) + __popc(m1);
+        if ((i0 & 1u) == 0u && v1) {
+            *reinterpret_cast<uint16_t *>(a.bonds + i0) = static_cast<uint16_t>(m0 | (m1 << 8));
+        } else {
+            if (v0) a.bonds[i0] = static_cast<uint8_t>(m0);
+            if (v1) a.bonds[i0 + 1] = static_cast<uint8_t>(m1);
+        }
+        const uint32_t in_x = (lx0 + 1 < T.tw ? 0x01u : 0u) | (lx0 + 2 < T.tw ? 0x10u : 0u);
+        const uint32_t in_y = ly + 1 < T.th ? 0x22u : 0u, in_z = lz + 1 < T.td ? 0x44u : 0u;
+        inside |= static_cast<uint64_t>((m0 | (m1 << 4)) & (in_x | in_y | in_z)) << (8 * it);
     }
     __syncthreads();
 
@@ -239,8 +257,8 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
             if (!busy) {
                 const int bit = __ffsll(static_cast<unsigned long long>(todo)) - 1;
                 todo &= todo - 1;
-                const int ly = bit >> 3, j = (bit >> 2) & 1, d = bit & 3;
-                u = (lz * CY + ly) * CX + lx0 + j;
+                const int it = bit >> 3, j = (bit >> 2) & 1, d = bit & 3;
+                u = row_of(it) * CX + lx0 + j;
                 v = u + (d == 0 ? 1 : d == 1 ? CX : PLANE);
                 busy = 1;
             }
@@ -262,25 +280,27 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
             x = p;
         }
     };
-    int rt[CY][2];
+    int rt[ITER][2];
 #pragma unroll
-    for (int ly = 0; ly < CY; ++ly) {
+    for (int it = 0; it < ITER; ++it) {
+        const int R = row_of(it);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            rt[ly][j] = 0;
-            if (lz < T.td && ly < T.th && lx0 + j < T.tw) rt[ly][j] = root_of((lz * CY + ly) * CX + lx0 + j);
+            rt[it][j] = 0;
+            if (row_in(R) && lx0 + j < T.tw) rt[it][j] = root_of(R * CX + lx0 + j);
         }
     }
     // claims: the root of every cluster that touches a tile face gets an id
 #pragma unroll
-    for (int ly = 0; ly < CY; ++ly) {
-        if (lz >= T.td || ly >= T.th) continue;
+    for (int it = 0; it < ITER; ++it) {
+        const int R = row_of(it), ly = R % CY, lz = R / CY;
+        if (!row_in(R)) continue;
         const bool plane_face = ly == 0 || ly == T.th - 1 || lz == 0 || lz == T.td - 1;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int lx = lx0 + j;
             if (lx >= T.tw || !(plane_face || lx == 0 || lx == T.tw - 1)) continue;
-            const int r = rt[ly][j];
+            const int r = rt[it][j];
             int expect = r;
             if (__hip_atomic_compare_exchange_strong(&P[r], &expect, CLAIMING, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_WORKGROUP)) {
@@ -296,17 +316,18 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
 
     // codes: the id of a claimed root (its entry reads -(id + 2)), else CAP +
     // the root's slot
-    if (lz < T.td) {
+    {
         uint16_t *codes = a.codes + static_cast<int64_t>(T.tile) * CSITES;
 #pragma unroll
-        for (int ly = 0; ly < CY; ++ly) {
-            if (ly >= T.th) continue;
-            const int s = (lz * CY + ly) * CX + lx0;
+        for (int it = 0; it < ITER; ++it) {
+            const int R = row_of(it);
+            if (!row_in(R)) continue;
+            const int s = R * CX + lx0;
             uint32_t c[2] = {CODE_NONE, CODE_NONE};
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 if (lx0 + j >= T.tw) continue;
-                const int r = rt[ly][j];
+                const int r = rt[it][j];
                 const int pr = lds_ld(&P[r]);
                 c[j] = pr < 0 ? static_cast<uint32_t>(-pr - 2) : static_cast<uint32_t>(CAP + r);
             }
@@ -314,11 +335,11 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
         }
     }
     const unsigned long long tot = wave_sum(act);
-    if (lane == 0) act_w[lz] = static_cast<unsigned>(tot);
+    if (lane == 0) act_w[w] = static_cast<unsigned>(tot);
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned sum = 0;
-        for (int w = 0; w < CZ; ++w) sum += act_w[w];
+        for (int k = 0; k < NW3; ++k) sum += act_w[k];
         a.nb[T.tile] = nb_s;
         a.tile_act[T.tile] = static_cast<int32_t>(sum);
     }
@@ -514,15 +535,16 @@ __global__ __launch_bounds__(RT) void k3_resolve(Resolve3Args a)
 
 __global__ __launch_bounds__(NT3) void k3_flatten(Flat3Args a)
 {
-    __shared__ uint8_t ST[CAP + CSITES];   // new state per code
-    __shared__ int32_t Rb[CAP];            // canonical label per id (labels only)
-    __shared__ uint16_t roots[CZ][PLANE];  // interior root slots of each wave's plane
-    __shared__ unsigned ncl_w[CZ];
+    __shared__ uint8_t ST[CAP + CSITES];          // new state per code
+    __shared__ int32_t Rb[CAP];                   // canonical label per id (labels only)
+    __shared__ uint16_t roots[NW3][128 * ITER];   // interior root slots of each wave's rows
+    __shared__ unsigned ncl_w[NW3];
     const Geo3 g = a.g;
     const TileOf T = tile_of(g, xcd_remap(blockIdx.x, g.ntiles));
-    const int lane = threadIdx.x & 63, lz = wave_id();
-    const int lx0 = 2 * lane;
-    const bool v0 = lx0 < T.tw, v1 = lx0 + 1 < T.tw;
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const int sub = lane / LPR, lx0 = 2 * (lane % LPR);
+    auto row_of = [&](int it) { return w * RW + it * RPI + sub; };
+    auto row_in = [&](int R) { return R % CY < T.th && R / CY < T.td; };
     const int nbt = a.nb[T.tile];
     unsigned nbroot = 0;
     for (int k = threadIdx.x; k < nbt; k += NT3) {
@@ -533,21 +555,22 @@ __global__ __launch_bounds__(NT3) void k3_flatten(Flat3Args a)
         Rb[k] = key;
         nbroot += r == id ? 1u : 0u;
     }
-    // the lane's codes (two per row); the interior roots (code CAP + own
-    // slot) of the wave's plane are listed, then draw their states 64 at a time
+    // the lane's codes (two per step); the interior roots (code CAP + own
+    // slot) of the wave's rows are listed, then draw their states 64 at a time
     const uint16_t *codes = a.codes + static_cast<int64_t>(T.tile) * CSITES;
-    uint32_t cc[CY];
+    uint32_t cc[ITER];
     int nroot = 0;
-    uint16_t *mylist = roots[lz];
+    uint16_t *mylist = roots[w];
     const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll
-    for (int ly = 0; ly < CY; ++ly) {
-        cc[ly] = 0xFFFFFFFFu;
-        if (lz >= T.td || ly >= T.th) continue;
-        const int s = (lz * CY + ly) * CX + lx0;
-        cc[ly] = *reinterpret_cast<const uint32_t *>(codes + s);
-        const bool r0 = v0 && (cc[ly] & 0xFFFFu) == static_cast<uint32_t>(CAP + s);
-        const bool r1 = v1 && (cc[ly] >> 16) == static_cast<uint32_t>(CAP + s + 1);
+    for (int it = 0; it < ITER; ++it) {
+        const int R = row_of(it);
+        const bool rin = row_in(R);
+        const bool v0 = rin && lx0 < T.tw, v1 = rin && lx0 + 1 < T.tw;
+        const int s = R * CX + lx0;
+        cc[it] = rin ? *reinterpret_cast<const uint32_t *>(codes + s) : 0xFFFFFFFFu;
+        const bool r0 = v0 && (cc[it] & 0xFFFFu) == static_cast<uint32_t>(CAP + s);
+        const bool r1 = v1 && (cc[it] >> 16) == static_cast<uint32_t>(CAP + s + 1);
         const uint64_t m0 = __ballot(r0), m1 = __ballot(r1);
         const int at = nroot + __popcll(m0 & below) + __popcll(m1 & below);
         if (r0) mylist[at] = static_cast<uint16_t>(s);
@@ -561,14 +584,14 @@ __global__ __launch_bounds__(NT3) void k3_flatten(Flat3Args a)
     }
     __syncthreads();
 #pragma unroll
-    for (int ly = 0; ly < CY; ++ly) {
-        if (lz >= T.td || ly >= T.th) continue;
-        const int s = (lz * CY + ly) * CX + lx0;
+    for (int it = 0; it < ITER; ++it) {
+        const int R = row_of(it), ly = R % CY, lz = R / CY;
+        if (!row_in(R)) continue;
         const int64_t i0 = (static_cast<int64_t>(T.gz0 + lz) * g.Ly + T.gy0 + ly) * g.Lx + T.gx0 + lx0;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            if (!(j ? v1 : v0)) continue;
-            const uint32_t c = (cc[ly] >> (16 * j)) & 0xFFFFu;
+            if (lx0 + j >= T.tw) continue;
+            const uint32_t c = (cc[it] >> (16 * j)) & 0xFFFFu;
             const uint32_t st = ST[c];
             a.spins[i0 + j] = static_cast<uint8_t>(a.ising ? 2u * st - 1u : st);
             if (a.labels)
@@ -576,11 +599,11 @@ __global__ __launch_bounds__(NT3) void k3_flatten(Flat3Args a)
         }
     }
     const unsigned long long tot = wave_sum(nbroot);
-    if (lane == 0) ncl_w[lz] = static_cast<unsigned>(tot) + static_cast<unsigned>(nroot);
+    if (lane == 0) ncl_w[w] = static_cast<unsigned>(tot) + static_cast<unsigned>(nroot);
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned sum = 0;
-        for (int w = 0; w < CZ; ++w) sum += ncl_w[w];
+        for (int k = 0; k < NW3; ++k) sum += ncl_w[k];
         a.tile_ncl[T.tile] = static_cast<int32_t>(sum);
     }
 }
