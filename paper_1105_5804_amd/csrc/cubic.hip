@@ -139,7 +139,14 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
     // k3_merge from the bond array).  Site indices fit 32 bits.
     uint64_t inside = 0;
     unsigned act = 0;
-    const uint32_t Lx = static_cast<uint32_t>(g.Lx), Ly = static_cast<uint32_t>(g.Ly);
+    const uint32_t Lx = static_cast<uint32_t>(g.Lx), Ly = static_cast<uint32_t>(g.Ly), Lz = static_cast<uint32_t>(g.Lz);
+    // a tile full along y and z: every row of every step lies in it, the
+    // lane's rows are its first one plus uniform offsets (a wave owns whole
+    // z-planes, RW a multiple of CY)
+    static_assert(RW % CY == 0, "a wave owns whole z-planes");
+    const bool full = T.th == CY && T.td == CZ;
+    const uint32_t row_first = ((static_cast<uint32_t>(T.gz0 + w * (RW / CY))) * Ly + static_cast<uint32_t>(T.gy0 + sub)) * Lx;
+    const bool ywrap_at_last = static_cast<uint32_t>(T.gy0 + CY) == Ly, zwrap_at_last = static_cast<uint32_t>(T.gz0 + CZ) == Lz;
     // lanes past a ragged edge read a valid column and store nothing
     const uint32_t xs0 = static_cast<uint32_t>(T.gx0 + min(lx0, T.tw - 1));
     const uint32_t xs1 = static_cast<uint32_t>(T.gx0 + min(lx0 + 1, T.tw - 1));
@@ -159,10 +166,22 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
         const bool v0 = rin && lx0 < T.tw, v1 = rin && lx0 + 1 < T.tw;
         const bool next_in = rin && lx0 + 2 < T.tw;  // the +x neighbour of site lx0 + 1 is the next lane's first
         // rows outside the tile read a valid row and store nothing
-        const uint32_t gy = static_cast<uint32_t>(T.gy0 + min(ly, T.th - 1));
-        const uint32_t gz = static_cast<uint32_t>(T.gz0 + min(lz, T.td - 1));
-        const uint32_t yn = gy + 1u == Ly ? 0u : gy + 1u, zn = gz + 1u == static_cast<uint32_t>(g.Lz) ? 0u : gz + 1u;
-        const uint32_t row = (gz * Ly + gy) * Lx, rowy = (gz * Ly + yn) * Lx, rowz = (zn * Ly + gy) * Lx;
+        uint32_t row, rowy, rowz;
+        if (full) {
+            // the lane's first row plus a wave-uniform offset: RPI rows a
+            // step, a plane every CY / RPI steps; the +y and +z rows follow
+            // by Lx and Lx Ly except across the lattice's own boundary
+            row = row_first + static_cast<uint32_t>(((it * RPI) / CY) * Ly + (it * RPI) % CY) * Lx;
+            rowy = ywrap_at_last && ly == CY - 1 ? row - (Ly - 1u) * Lx : row + Lx;
+            rowz = zwrap_at_last && lz == CZ - 1 ? row - (Lz - 1u) * Ly * Lx : row + Ly * Lx;
+        } else {
+            const uint32_t gy = static_cast<uint32_t>(T.gy0 + min(ly, T.th - 1));
+            const uint32_t gz = static_cast<uint32_t>(T.gz0 + min(lz, T.td - 1));
+            const uint32_t yn = gy + 1u == Ly ? 0u : gy + 1u, zn = gz + 1u == Lz ? 0u : gz + 1u;
+            row = (gz * Ly + gy) * Lx;
+            rowy = (gz * Ly + yn) * Lx;
+            rowz = (zn * Ly + gy) * Lx;
+        }
         const uint32_t i0 = row + static_cast<uint32_t>(T.gx0 + lx0);
         uint32_t s0, s1, y0, y1, z0, z1;
         if (even_lx && v1) {  // the pair in one aligned 16-bit load per row (every row starts even)
