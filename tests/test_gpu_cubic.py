@@ -5,7 +5,8 @@ after every sweep.
 Shapes cover one tile with its periodic wraps inside the tile, ragged tiles
 along each axis, odd Lx (rows starting at odd site indices), Lx a multiple of
 4 with an odd number of rows in a tile (the +z draws shared by lane pairs
-over row pairs, and a last single row), extents 1 and 2
+over row pairs, and a last single row), the couplings K = 0 and K = inf,
+sweeps on a side stream, extents 1 and 2
 (self-bonds and doubled bonds), a restart at a sweep number other than 0,
 Lz = 1 against the square-lattice sweep of the same library, the 256^3 and
 512^3 Ising lattices at the 3D critical coupling, and the largest accepted
@@ -47,6 +48,8 @@ CASES = [
     (64, 64, 64, 2, K3, True),
     (33, 70, 20, 3, 0.8, False),
     (132, 13, 9, 2, K3, True),               # Lx a multiple of 4 (lane pairs share +z blocks), odd tile heights
+    (40, 20, 18, 3, 0.0, False),             # K = 0: no bond is active, every site its own cluster
+    (40, 20, 18, 2, float("inf"), True),     # K = inf: every bond between equal spins is active
 ]
 
 
@@ -180,3 +183,21 @@ def test_cubic_largest():
         c1 = min(N, c0 + step)
         roots += int(np.count_nonzero(labels[c0:c1] == np.arange(c0, c1, dtype=np.int32)))
     assert int(rec[oracle.REC3_NCLUST]) == roots
+
+
+def test_cubic_side_stream():
+    """Sweeps enqueued on a stream other than the current one follow the
+    oracle once that stream is synchronised."""
+    Lx, Ly, Lz, seed = 96, 40, 33, wl.SEED_BASE | 0x3D8
+    lat = sw.CubicLattice(Lx, Ly, Lz, q=3, K=1.0, seed=seed, ising=False, keep_labels=True)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    rec = lat.sweep(4, records=True, stream=side)
+    side.synchronize()
+    T = oracle.threshold(1.0)
+    st, want = oracle.sw3_run(Lx, Ly, Lz, 3, T, seed, 0, 0, 3, oracle.init_states3(Lx, Ly, Lz, 3, seed))
+    st, _b, labels, last = oracle.sw3_sweep(Lx, Ly, Lz, 3, T, seed, 0, 3, st)
+    assert np.array_equal(rec.cpu().numpy()[:3], want)
+    assert [int(v) for v in rec[3].cpu()] == [int(v) for v in last]
+    assert np.array_equal(lat.spins.cpu().numpy().reshape(-1), st)
+    assert np.array_equal(lat.labels.cpu().numpy().reshape(-1), labels)
