@@ -5,7 +5,8 @@ after every sweep.
 Shapes cover one tile with its periodic wraps inside the tile, ragged tiles
 along each axis, odd Lx (rows starting at odd site indices), Lx a multiple of
 4 with an odd number of rows in a tile (the +z draws shared by lane pairs
-over row pairs, and a last single row), the couplings K = 0 and K = inf,
+over row pairs, and a last single row), the couplings K = 0, K = inf and
+1.4 and 0.6 times the critical one,
 sweeps on a side stream, extents 1 and 2
 (self-bonds and doubled bonds), a restart at a sweep number other than 0,
 Lz = 1 against the square-lattice sweep of the same library, the 256^3 and
@@ -50,6 +51,8 @@ CASES = [
     (132, 13, 9, 2, K3, True),               # Lx a multiple of 4 (lane pairs share +z blocks), odd tile heights
     (40, 20, 18, 3, 0.0, False),             # K = 0: no bond is active, every site its own cluster
     (40, 20, 18, 2, float("inf"), True),     # K = inf: every bond between equal spins is active
+    (160, 64, 48, 2, 1.4 * K3, True),        # ordered phase: one cluster spans the lattice
+    (160, 64, 48, 2, 0.6 * K3, True),        # disordered phase: many small clusters
 ]
 
 
