@@ -576,8 +576,24 @@ def _cubic(args, torch, sw, wl, stream) -> dict:
     ms = ev[0].elapsed_time(ev[1]) / steps
     ms_rec = ev[1].elapsed_time(ev[2]) / steps
     e = -(2.0 * rec[:, 2].double() - 3.0 * N) / N
+    # labeling alone: bond percolation near the simple cubic threshold (p = 0.2488)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(wl.SEED_BASE & 0xFFFFFFFF)
+    on = torch.rand((3, L, L, L), device="cuda", generator=gen) < 0.2488
+    bonds = (on[0].to(torch.uint8) | (on[1].to(torch.uint8) << 1) | (on[2].to(torch.uint8) << 2)).contiguous()
+    del on
+    sw.ccl3_label(bonds)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    _labels, _n = sw.ccl3_label(bonds)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    ccl_ms = c0.elapsed_time(c1)
+    del bonds, _labels
     out = {"workload": f"Ising {L}^3 simple cubic at beta_c = {sw.BETA_C_ISING_3D}, {max(20, args.warmup)} "
                        f"equilibration sweeps, then {steps} timed",
+           "ccl3_labeled_sites_per_s": round(N / (ccl_ms * 1e-3), 1),
+           "ccl3_workload": "bond percolation on the same lattice at p = 0.2488 (labels and count, one call)",
            "ms_per_sweep": round(ms, 4), "ns_per_spin": round(ms * 1e6 / N, 6),
            "ms_per_sweep_with_records": round(ms_rec, 4),
            "mean_energy_per_site": round(float(e.mean()), 5),

@@ -70,7 +70,7 @@
 extern "C" {
 #endif
 
-#define SWCCL_ABI_VERSION 6
+#define SWCCL_ABI_VERSION 7
 
 typedef int32_t sw_status;
 enum {
@@ -504,6 +504,23 @@ sw_status sw3_init_spins(const sw3_params *p, uint8_t *spins, void *stream);
  * (t0 + n passes 2^32), SW_ERR_DEVICE. */
 sw_status sw3_sweep(const sw3_params *p, uint8_t *spins, uint32_t t0, int32_t n, uint8_t *bonds, int32_t *labels,
                     int64_t *records, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes ccl3_label needs for an Lx x Ly x Lz lattice (0 if the
+ * shape is invalid). */
+size_t ccl3_workspace_bytes(int32_t Lx, int32_t Ly, int32_t Lz);
+
+/* Connected-component labeling of given bonds on the periodic simple cubic
+ * lattice: the cluster identification of the SW update (Sec. II.B-II.C,
+ * three dimensions), e.g. for bond percolation.  `bonds` (device, N bytes):
+ * bit0 +x, bit1 +y, bit2 +z of each site as for sw3_sweep, wrapping along all
+ * three axes; higher bits are ignored.  `labels` (device, N int32) receives
+ * the canonical labels (each site's cluster's minimum site index);
+ * `n_clusters` (device, one int32, or NULL) the number of clusters.
+ * `workspace` (device, 256-byte aligned, at least ccl3_workspace_bytes) is
+ * scratch.  Errors: SW_ERR_ARG (null bonds or labels), SW_ERR_SIZE,
+ * SW_ERR_WORKSPACE, SW_ERR_DEVICE. */
+sw_status ccl3_label(const uint8_t *bonds, int32_t Lx, int32_t Ly, int32_t Lz, int32_t *labels, int32_t *n_clusters,
+                     void *workspace, size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -23,6 +23,7 @@ from ._lib import (  # noqa: F401
 __all__ = [
     "SWLattice",
     "CubicLattice",
+    "ccl3_label",
     "SWBatch",
     "ccl_label",
     "ccl_label_noalloc",
@@ -307,6 +308,36 @@ class CubicLattice:
                                         _stream(torch, stream)), "sw3_sweep")
         self.t += int(n)
         return rec[: int(n)] if rec is not None else None
+
+
+def ccl3_label(bonds, workspace=None, stream=None):
+    """Canonical labels of packed cubic bonds: ``bonds`` is an (Lz, Ly, Lx)
+    uint8 GPU tensor (bit0 +x, bit1 +y, bit2 +z, periodic).  Returns
+    (labels as an (Lz, Ly, Lx) int32 tensor, n_clusters); enqueues on the
+    current (or given) stream and waits for it to read the count."""
+    torch = _torch()
+    if bonds.dim() != 3 or bonds.dtype != torch.uint8 or bonds.device.type != "cuda":
+        raise ValueError("bonds must be an (Lz, Ly, Lx) uint8 GPU tensor")
+    bonds = bonds.contiguous()
+    Lz, Ly, Lx = (int(v) for v in bonds.shape)
+    L = _lib.lib()
+    ws = L.ccl3_workspace_bytes(Lx, Ly, Lz)
+    if ws == 0:
+        _lib.check(_lib.SW_ERR_SIZE, "ccl3_workspace_bytes")
+    if workspace is None:
+        buf, wptr = _workspace(torch, ws, bonds.device)
+    else:
+        buf, wptr = workspace, workspace.data_ptr()
+        if workspace.device.type != "cuda" or workspace.numel() < ws or wptr % 256:
+            raise ValueError(f"workspace must be a 256-byte aligned GPU buffer of at least {ws} bytes")
+    labels = torch.empty((Lz, Ly, Lx), dtype=torch.int32, device=bonds.device)
+    ncl = torch.zeros(1, dtype=torch.int32, device=bonds.device)
+    s = stream if stream is not None else torch.cuda.current_stream(bonds.device)
+    _lib.check(L.ccl3_label(bonds.data_ptr(), Lx, Ly, Lz, labels.data_ptr(), ncl.data_ptr(), wptr, ws,
+                            _stream(torch, s)), "ccl3_label")
+    s.synchronize()
+    del buf
+    return labels, int(ncl.item())
 
 
 class SWBatch:

@@ -7,7 +7,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libswccl.so")
 
-ABI_VERSION = 6  # the SWCCL_ABI_VERSION these declarations follow
+ABI_VERSION = 7  # the SWCCL_ABI_VERSION these declarations follow
 
 # status codes
 SW_OK, SW_ERR_ARG, SW_ERR_SIZE, SW_ERR_WORKSPACE, SW_ERR_DEVICE, SW_ERR_STATE, SW_ERR_UNSUPPORTED, SW_ERR_HOST_MEMORY = range(8)
@@ -157,6 +157,9 @@ SIGNATURES = {
     "sw3_sweep": (ctypes.c_int32, [ctypes.POINTER(Sw3Params), ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_size_t, ctypes.c_void_p]),
+    "ccl3_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "ccl3_label": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "ccl_label_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p]),

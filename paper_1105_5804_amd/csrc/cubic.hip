@@ -27,6 +27,9 @@
 //
 // With per-sweep records, k3_observe counts the satisfied bonds and states of
 // the new spins and k3_record moves the counters into the record.
+//
+// ccl3_label runs the same tile, merge, resolve and flatten kernels on given
+// bond bytes (LABEL = true): no spins, no draws, labels out.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -118,6 +121,9 @@ struct Tile3Args {
     uint32_t k0, k1, t, sid;
 };
 
+// LABEL: the bonds are given (a.bonds is read, never written); otherwise they
+// are drawn from the spins and written.
+template <bool LABEL>
 __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
 {
     __shared__ int P[CSITES];
@@ -183,83 +189,96 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
             rowz = (zn * Ly + gy) * Lx;
         }
         const uint32_t i0 = row + static_cast<uint32_t>(T.gx0 + lx0);
-        uint32_t s0, s1, y0, y1, z0, z1;
-        if (even_lx && v1) {  // the pair in one aligned 16-bit load per row (every row starts even)
-            const uint32_t c = *reinterpret_cast<const uint16_t *>(a.spins + row + xs0);
-            const uint32_t yy = *reinterpret_cast<const uint16_t *>(a.spins + rowy + xs0);
-            const uint32_t zz = *reinterpret_cast<const uint16_t *>(a.spins + rowz + xs0);
-            s0 = c & 0xFFu;
-            s1 = c >> 8;
-            y0 = yy & 0xFFu;
-            y1 = yy >> 8;
-            z0 = zz & 0xFFu;
-            z1 = zz >> 8;
-        } else {
-            s0 = a.spins[row + xs0];
-            s1 = a.spins[row + xs1];
-            y0 = a.spins[rowy + xs0];
-            y1 = a.spins[rowy + xs1];
-            z0 = a.spins[rowz + xs0];
-            z1 = a.spins[rowz + xs1];
-        }
-        const uint32_t nxt = from_next_lane(s0);
-        const uint32_t x0 = v1 ? s1 : a.spins[row + xn0];
-        const uint32_t x1 = next_in ? nxt : a.spins[row + xn1];
-        // words: +x and +y from block(i >> 1, BOND) as on the square
-        // lattice, +z word i & 3 of block(i >> 2, BOND_Z)
-        const uint32_t c0 = i0 >> 1;
-        const U4 bk = philox4x32_10(c0, a.t, TAG_BOND, a.sid, a.k0, a.k1);
-        uint32_t rx0, ry0, rx1, ry1;
-        if ((i0 & 1u) == 0u) {
-            rx0 = bk.v0;
-            ry0 = bk.v1;
-            rx1 = bk.v2;
-            ry1 = bk.v3;
-        } else {  // odd row start (odd Lx): i0 is the second site of its block
-            rx0 = bk.v2;
-            ry0 = bk.v3;
-            const U4 b2 = philox4x32_10(c0 + 1u, a.t, TAG_BOND, a.sid, a.k0, a.k1);
-            rx1 = b2.v0;
-            ry1 = b2.v1;
-        }
-        uint32_t rz0, rz1;
-        if (zpairs && (it & 1) == 0) {
-            // the even lane draws its pair's block of this row, the odd lane
-            // that of the next step's row (RPI rows on, same plane, no wrap)
-            const uint32_t pair = static_cast<uint32_t>(T.gx0 + 2 * ((lane % LPR) & ~1));
-            const U4 bz = philox4x32_10((odd_lane ? row + RPI * Lx + pair : row + pair) >> 2, a.t, TAG_BOND_Z,
-                                        a.sid, a.k0, a.k1);
-            const uint32_t ra = swap_pair_lanes(odd_lane ? bz.v0 : bz.v2);
-            const uint32_t rb = swap_pair_lanes(odd_lane ? bz.v1 : bz.v3);
-            rz0 = odd_lane ? ra : bz.v0;  // this row: words 0, 1 (even lane) or 2, 3 (odd lane)
-            rz1 = odd_lane ? rb : bz.v1;
-            zpend0 = odd_lane ? bz.v2 : ra;  // the next step's row
-            zpend1 = odd_lane ? bz.v3 : rb;
-        } else if (zpairs) {
-            rz0 = zpend0;
-            rz1 = zpend1;
-        } else {
-            const U4 bz = philox4x32_10(i0 >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1);
-            rz0 = pick(bz, i0 & 3u);
-            if (((i0 + 1u) & 3u) != 0u) {
-                rz1 = pick(bz, (i0 + 1u) & 3u);
-            } else {  // site i0 + 1 starts the next block
-                rz1 = philox4x32_10((i0 + 1u) >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1).v0;
-            }
-        }
         uint32_t m0 = 0, m1 = 0;
-        if (v0 && a.tany)
-            m0 = (s0 == x0 && rx0 <= a.tm1 ? 1u : 0u) | (s0 == y0 && ry0 <= a.tm1 ? 2u : 0u) |
-                 (s0 == z0 && rz0 <= a.tm1 ? 4u : 0u);
-        if (v1 && a.tany)
-            m1 = (s1 == x1 && rx1 <= a.tm1 ? 1u : 0u) | (s1 == y1 && ry1 <= a.tm1 ? 2u : 0u) |
-                 (s1 == z1 && rz1 <= a.tm1 ? 4u : 0u);
-        act += __popc(m0) + __popc(m1);
-        if ((i0 & 1u) == 0u && v1) {
-            *reinterpret_cast<uint16_t *>(a.bonds + i0) = static_cast<uint16_t>(m0 | (m1 << 8));
+        if constexpr (LABEL) {
+            (void)rowy;
+            (void)rowz;
+            if (even_lx && v1) {  // the pair in one aligned 16-bit load
+                const uint32_t c = *reinterpret_cast<const uint16_t *>(a.bonds + i0);
+                m0 = c & 7u;
+                m1 = (c >> 8) & 7u;
+            } else {
+                if (v0) m0 = a.bonds[i0] & 7u;
+                if (v1) m1 = a.bonds[i0 + 1] & 7u;
+            }
         } else {
-            if (v0) a.bonds[i0] = static_cast<uint8_t>(m0);
-            if (v1) a.bonds[i0 + 1] = static_cast<uint8_t>(m1);
+            uint32_t s0, s1, y0, y1, z0, z1;
+            if (even_lx && v1) {  // the pair in one aligned 16-bit load per row (every row starts even)
+                const uint32_t c = *reinterpret_cast<const uint16_t *>(a.spins + row + xs0);
+                const uint32_t yy = *reinterpret_cast<const uint16_t *>(a.spins + rowy + xs0);
+                const uint32_t zz = *reinterpret_cast<const uint16_t *>(a.spins + rowz + xs0);
+                s0 = c & 0xFFu;
+                s1 = c >> 8;
+                y0 = yy & 0xFFu;
+                y1 = yy >> 8;
+                z0 = zz & 0xFFu;
+                z1 = zz >> 8;
+            } else {
+                s0 = a.spins[row + xs0];
+                s1 = a.spins[row + xs1];
+                y0 = a.spins[rowy + xs0];
+                y1 = a.spins[rowy + xs1];
+                z0 = a.spins[rowz + xs0];
+                z1 = a.spins[rowz + xs1];
+            }
+            const uint32_t nxt = from_next_lane(s0);
+            const uint32_t x0 = v1 ? s1 : a.spins[row + xn0];
+            const uint32_t x1 = next_in ? nxt : a.spins[row + xn1];
+            // words: +x and +y from block(i >> 1, BOND) as on the square
+            // lattice, +z word i & 3 of block(i >> 2, BOND_Z)
+            const uint32_t c0 = i0 >> 1;
+            const U4 bk = philox4x32_10(c0, a.t, TAG_BOND, a.sid, a.k0, a.k1);
+            uint32_t rx0, ry0, rx1, ry1;
+            if ((i0 & 1u) == 0u) {
+                rx0 = bk.v0;
+                ry0 = bk.v1;
+                rx1 = bk.v2;
+                ry1 = bk.v3;
+            } else {  // odd row start (odd Lx): i0 is the second site of its block
+                rx0 = bk.v2;
+                ry0 = bk.v3;
+                const U4 b2 = philox4x32_10(c0 + 1u, a.t, TAG_BOND, a.sid, a.k0, a.k1);
+                rx1 = b2.v0;
+                ry1 = b2.v1;
+            }
+            uint32_t rz0, rz1;
+            if (zpairs && (it & 1) == 0) {
+                // the even lane draws its pair's block of this row, the odd lane
+                // that of the next step's row (RPI rows on, same plane, no wrap)
+                const uint32_t pair = static_cast<uint32_t>(T.gx0 + 2 * ((lane % LPR) & ~1));
+                const U4 bz = philox4x32_10((odd_lane ? row + RPI * Lx + pair : row + pair) >> 2, a.t, TAG_BOND_Z,
+                                            a.sid, a.k0, a.k1);
+                const uint32_t ra = swap_pair_lanes(odd_lane ? bz.v0 : bz.v2);
+                const uint32_t rb = swap_pair_lanes(odd_lane ? bz.v1 : bz.v3);
+                rz0 = odd_lane ? ra : bz.v0;  // this row: words 0, 1 (even lane) or 2, 3 (odd lane)
+                rz1 = odd_lane ? rb : bz.v1;
+                zpend0 = odd_lane ? bz.v2 : ra;  // the next step's row
+                zpend1 = odd_lane ? bz.v3 : rb;
+            } else if (zpairs) {
+                rz0 = zpend0;
+                rz1 = zpend1;
+            } else {
+                const U4 bz = philox4x32_10(i0 >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1);
+                rz0 = pick(bz, i0 & 3u);
+                if (((i0 + 1u) & 3u) != 0u) {
+                    rz1 = pick(bz, (i0 + 1u) & 3u);
+                } else {  // site i0 + 1 starts the next block
+                    rz1 = philox4x32_10((i0 + 1u) >> 2, a.t, TAG_BOND_Z, a.sid, a.k0, a.k1).v0;
+                }
+            }
+            if (v0 && a.tany)
+                m0 = (s0 == x0 && rx0 <= a.tm1 ? 1u : 0u) | (s0 == y0 && ry0 <= a.tm1 ? 2u : 0u) |
+                     (s0 == z0 && rz0 <= a.tm1 ? 4u : 0u);
+            if (v1 && a.tany)
+                m1 = (s1 == x1 && rx1 <= a.tm1 ? 1u : 0u) | (s1 == y1 && ry1 <= a.tm1 ? 2u : 0u) |
+                     (s1 == z1 && rz1 <= a.tm1 ? 4u : 0u);
+            act += __popc(m0) + __popc(m1);
+            if ((i0 & 1u) == 0u && v1) {
+                *reinterpret_cast<uint16_t *>(a.bonds + i0) = static_cast<uint16_t>(m0 | (m1 << 8));
+            } else {
+                if (v0) a.bonds[i0] = static_cast<uint8_t>(m0);
+                if (v1) a.bonds[i0 + 1] = static_cast<uint8_t>(m1);
+            }
         }
         const uint32_t in_x = (lx0 + 1 < T.tw ? 0x01u : 0u) | (lx0 + 2 < T.tw ? 0x10u : 0u);
         const uint32_t in_y = ly + 1 < T.th ? 0x22u : 0u, in_z = lz + 1 < T.td ? 0x44u : 0u;
@@ -552,6 +571,8 @@ __global__ __launch_bounds__(RT) void k3_resolve(Resolve3Args a)
     }
 }
 
+// LABEL: labels only (no draws, spins untouched).
+template <bool LABEL>
 __global__ __launch_bounds__(NT3) void k3_flatten(Flat3Args a)
 {
     __shared__ uint8_t ST[CAP + CSITES];          // new state per code
@@ -570,7 +591,7 @@ __global__ __launch_bounds__(NT3) void k3_flatten(Flat3Args a)
         const int id = T.tile * CAP + k;
         const int r = a.gparent[id];  // resolved: the entry is the root
         const int32_t key = a.gkey[r];
-        ST[k] = static_cast<uint8_t>(new_state(static_cast<uint32_t>(key), a));
+        if constexpr (!LABEL) ST[k] = static_cast<uint8_t>(new_state(static_cast<uint32_t>(key), a));
         Rb[k] = key;
         nbroot += r == id ? 1u : 0u;
     }
@@ -597,9 +618,11 @@ __global__ __launch_bounds__(NT3) void k3_flatten(Flat3Args a)
         nroot += __popcll(m0) + __popcll(m1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    for (int k = lane; k < nroot; k += 64) {
-        const int s = mylist[k];
-        ST[CAP + s] = static_cast<uint8_t>(new_state(static_cast<uint32_t>(site_of(g, T, s)), a));
+    if constexpr (!LABEL) {
+        for (int k = lane; k < nroot; k += 64) {
+            const int s = mylist[k];
+            ST[CAP + s] = static_cast<uint8_t>(new_state(static_cast<uint32_t>(site_of(g, T, s)), a));
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -611,8 +634,10 @@ __global__ __launch_bounds__(NT3) void k3_flatten(Flat3Args a)
         for (int j = 0; j < 2; ++j) {
             if (lx0 + j >= T.tw) continue;
             const uint32_t c = (cc[it] >> (16 * j)) & 0xFFFFu;
-            const uint32_t st = ST[c];
-            a.spins[i0 + j] = static_cast<uint8_t>(a.ising ? 2u * st - 1u : st);
+            if constexpr (!LABEL) {
+                const uint32_t st = ST[c];
+                a.spins[i0 + j] = static_cast<uint8_t>(a.ising ? 2u * st - 1u : st);
+            }
             if (a.labels)
                 a.labels[i0 + j] = c < static_cast<uint32_t>(CAP) ? Rb[c] : site_of(g, T, static_cast<int>(c) - CAP);
         }
@@ -696,6 +721,12 @@ __global__ __launch_bounds__(512) void k3_observe(const uint8_t *spins, Geo3 g, 
     }
 }
 
+// The cluster count of a labeling into the caller's int32.
+__global__ void k3_count_out(const unsigned long long *stats, int32_t *n_clusters)
+{
+    if (threadIdx.x == 0) *n_clusters = static_cast<int32_t>(stats[S3_NCLUST]);
+}
+
 // Move the sweep's counters into its record and clear them for the next one.
 __global__ void k3_record(unsigned long long *stats, int64_t *row)
 {
@@ -723,6 +754,18 @@ struct Layout3 {
     size_t codes, gkey, gparent, nb, tile_act, tile_ncl, stats, bonds, total;
 };
 
+// Extents >= 1, N < 2^31, and the ids of all tiles (ntiles x CAP) index
+// int32 arrays.
+sw_status check_shape3(int32_t Lx, int32_t Ly, int32_t Lz)
+{
+    if (Lx < 1 || Ly < 1 || Lz < 1) return SW_ERR_SIZE;
+    const int64_t N = static_cast<int64_t>(Lx) * Ly * Lz;
+    if (N >= (static_cast<int64_t>(1) << 31)) return SW_ERR_SIZE;
+    const int64_t nt = cdiv3(Lx, CX) * cdiv3(Ly, CY) * cdiv3(Lz, CZ);
+    if (nt * CAP >= (static_cast<int64_t>(1) << 31)) return SW_ERR_SIZE;
+    return SW_OK;
+}
+
 sw_status check3(const sw3_params *p)
 {
     if (!p) return SW_ERR_ARG;
@@ -730,26 +773,20 @@ sw_status check3(const sw3_params *p)
     if (p->spin_kind != SW_SPIN_ISING_I8 && p->spin_kind != SW_SPIN_POTTS_U8) return SW_ERR_ARG;
     if (p->spin_kind == SW_SPIN_ISING_I8 && p->q != 2) return SW_ERR_ARG;
     if (std::isnan(p->K) || p->flags != 0 || p->reserved != 0) return SW_ERR_ARG;
-    if (p->Lx < 1 || p->Ly < 1 || p->Lz < 1) return SW_ERR_SIZE;
-    const int64_t N = static_cast<int64_t>(p->Lx) * p->Ly * p->Lz;
-    if (N >= (static_cast<int64_t>(1) << 31)) return SW_ERR_SIZE;
-    // the ids of all tiles (ntiles x CAP) index int32 arrays
-    const int64_t nt = cdiv3(p->Lx, CX) * cdiv3(p->Ly, CY) * cdiv3(p->Lz, CZ);
-    if (nt * CAP >= (static_cast<int64_t>(1) << 31)) return SW_ERR_SIZE;
-    return SW_OK;
+    return check_shape3(p->Lx, p->Ly, p->Lz);
 }
 
-Layout3 layout3(const sw3_params *p)
+Layout3 layout3(int32_t Lx, int32_t Ly, int32_t Lz, bool own_bonds = true)
 {
     Layout3 L{};
-    L.g.Lx = p->Lx;
-    L.g.Ly = p->Ly;
-    L.g.Lz = p->Lz;
-    L.g.ntx = static_cast<int>(cdiv3(p->Lx, CX));
-    L.g.nty = static_cast<int>(cdiv3(p->Ly, CY));
-    L.g.ntz = static_cast<int>(cdiv3(p->Lz, CZ));
+    L.g.Lx = Lx;
+    L.g.Ly = Ly;
+    L.g.Lz = Lz;
+    L.g.ntx = static_cast<int>(cdiv3(Lx, CX));
+    L.g.nty = static_cast<int>(cdiv3(Ly, CY));
+    L.g.ntz = static_cast<int>(cdiv3(Lz, CZ));
     L.g.ntiles = L.g.ntx * L.g.nty * L.g.ntz;
-    L.N = static_cast<int64_t>(p->Lx) * p->Ly * p->Lz;
+    L.N = static_cast<int64_t>(Lx) * Ly * Lz;
     const size_t nt = static_cast<size_t>(L.g.ntiles);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -764,10 +801,12 @@ Layout3 layout3(const sw3_params *p)
     L.tile_act = take(nt * sizeof(int32_t));
     L.tile_ncl = take(nt * sizeof(int32_t));
     L.stats = take(16 * sizeof(unsigned long long));
-    L.bonds = take(static_cast<size_t>(L.N));
+    L.bonds = own_bonds ? take(static_cast<size_t>(L.N)) : 0;
     L.total = off;
     return L;
 }
+
+Layout3 layout3(const sw3_params *p) { return layout3(p->Lx, p->Ly, p->Lz); }
 
 template <typename T>
 T *at3(void *ws, size_t off)
@@ -793,6 +832,62 @@ sw_status sw3_init_spins(const sw3_params *p, uint8_t *spins, void *stream)
     const int64_t N = static_cast<int64_t>(p->Lx) * p->Ly * p->Lz;
     return swccl_internal::init_spins(spins, N, p->q, p->spin_kind == SW_SPIN_ISING_I8, p->seed, p->stream_id,
                                       static_cast<hipStream_t>(stream));
+}
+
+size_t ccl3_workspace_bytes(int32_t Lx, int32_t Ly, int32_t Lz)
+{
+    if (check_shape3(Lx, Ly, Lz) != SW_OK) return 0;
+    return layout3(Lx, Ly, Lz, false).total;
+}
+
+sw_status ccl3_label(const uint8_t *bonds, int32_t Lx, int32_t Ly, int32_t Lz, int32_t *labels, int32_t *n_clusters,
+                     void *workspace, size_t workspace_bytes, void *stream)
+{
+    const sw_status st = check_shape3(Lx, Ly, Lz);
+    if (st != SW_OK) return st;
+    if (!bonds || !labels) return SW_ERR_ARG;
+    const Layout3 L = layout3(Lx, Ly, Lz, false);
+    if (!workspace || workspace_bytes < L.total || reinterpret_cast<uintptr_t>(workspace) % ALIGN3)
+        return SW_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned long long *stats = at3<unsigned long long>(workspace, L.stats);
+    Tile3Args ta{};
+    ta.g = L.g;
+    ta.bonds = const_cast<uint8_t *>(bonds);  // LABEL mode only reads them
+    ta.codes = at3<uint16_t>(workspace, L.codes);
+    ta.gkey = at3<int32_t>(workspace, L.gkey);
+    ta.gparent = at3<int32_t>(workspace, L.gparent);
+    ta.nb = at3<int32_t>(workspace, L.nb);
+    ta.tile_act = at3<int32_t>(workspace, L.tile_act);
+    ta.tany = 1u;
+    Merge3Args ma{};
+    ma.g = L.g;
+    ma.bonds = bonds;
+    ma.codes = ta.codes;
+    ma.gparent = ta.gparent;
+    Resolve3Args ra{};
+    ra.g = L.g;
+    ra.gkey = ta.gkey;
+    ra.gparent = ta.gparent;
+    ra.nb = ta.nb;
+    Flat3Args fa{};
+    fa.g = L.g;
+    fa.labels = labels;
+    fa.codes = ta.codes;
+    fa.gkey = ta.gkey;
+    fa.gparent = ta.gparent;
+    fa.nb = ta.nb;
+    fa.tile_ncl = at3<int32_t>(workspace, L.tile_ncl);
+    const dim3 tiles(static_cast<unsigned>(L.g.ntiles));
+    hipLaunchKernelGGL(k3_tile<true>, tiles, dim3(NT3), 0, s, ta);
+    hipLaunchKernelGGL(k3_merge, tiles, dim3(MT), 0, s, ma);
+    hipLaunchKernelGGL(k3_resolve, tiles, dim3(RT), 0, s, ra);
+    hipLaunchKernelGGL(k3_flatten<true>, tiles, dim3(NT3), 0, s, fa);
+    if (n_clusters) {
+        hipLaunchKernelGGL(k3_reduce_tiles, dim3(1), dim3(1024), 0, s, ta.tile_act, fa.tile_ncl, L.g.ntiles, stats);
+        hipLaunchKernelGGL(k3_count_out, dim3(1), dim3(64), 0, s, stats, n_clusters);
+    }
+    return swccl_internal::device_error(hipGetLastError(), "ccl3_label");
 }
 
 sw_status sw3_sweep(const sw3_params *p, uint8_t *spins, uint32_t t0, int32_t n, uint8_t *bonds, int32_t *labels,
@@ -860,10 +955,10 @@ sw_status sw3_sweep(const sw3_params *p, uint8_t *spins, uint32_t t0, int32_t n,
         ta.t = t;
         fa.t = t;
         fa.labels = k + 1 == n ? labels : nullptr;
-        hipLaunchKernelGGL(k3_tile, tiles, dim3(NT3), 0, s, ta);
+        hipLaunchKernelGGL(k3_tile<false>, tiles, dim3(NT3), 0, s, ta);
         hipLaunchKernelGGL(k3_merge, tiles, dim3(MT), 0, s, ma);
         hipLaunchKernelGGL(k3_resolve, tiles, dim3(RT), 0, s, ra);
-        hipLaunchKernelGGL(k3_flatten, tiles, dim3(NT3), 0, s, fa);
+        hipLaunchKernelGGL(k3_flatten<false>, tiles, dim3(NT3), 0, s, fa);
         if (records) {
             hipLaunchKernelGGL(k3_reduce_tiles, dim3(1), dim3(1024), 0, s, ta.tile_act, fa.tile_ncl, L.g.ntiles, stats);
             hipLaunchKernelGGL(k3_observe, dim3(obs_blocks), dim3(512), 0, s, spins, L.g, static_cast<int>(fa.ising),

@@ -450,3 +450,25 @@ def test_cubic_params():
     assert L.sw3_sweep(ctypes.byref(p), 256, 0, 0, None, None, None, 256, ok, None) == _lib.SW_OK  # nothing to do
     assert L.sw3_init_spins(ctypes.byref(p), None, None) == _lib.SW_ERR_ARG
     assert L.sw3_init_spins(ctypes.byref(_p3(Lz=0)), 256, None) == _lib.SW_ERR_SIZE
+
+
+def test_ccl3_argument_errors():
+    """ccl3_* size good shapes, refuse bad ones and bad arguments before any
+    device work."""
+    L = _lib.lib()
+    ok = L.ccl3_workspace_bytes(64, 32, 16)
+    assert ok > 0 and L.ccl3_workspace_bytes(1, 1, 1) > 0
+    for shape in ((0, 4, 4), (4, -1, 4), (4, 4, 0), (2048, 2048, 512), (1, 1, 2**30)):
+        assert L.ccl3_workspace_bytes(*shape) == 0, shape
+    args = dict(bonds=256, labels=256, ws=256, nbytes=ok)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return L.ccl3_label(a["bonds"], 64, 32, a.get("Lz", 16), a["labels"], None, a["ws"], a["nbytes"], None)
+
+    assert call(bonds=None) == _lib.SW_ERR_ARG
+    assert call(labels=None) == _lib.SW_ERR_ARG
+    assert call(ws=None) == _lib.SW_ERR_WORKSPACE
+    assert call(nbytes=ok - 1) == _lib.SW_ERR_WORKSPACE
+    assert call(ws=260) == _lib.SW_ERR_WORKSPACE
+    assert call(Lz=0) == _lib.SW_ERR_SIZE

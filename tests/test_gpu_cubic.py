@@ -204,3 +204,45 @@ def test_cubic_side_stream():
     assert [int(v) for v in rec[3].cpu()] == [int(v) for v in last]
     assert np.array_equal(lat.spins.cpu().numpy().reshape(-1), st)
     assert np.array_equal(lat.labels.cpu().numpy().reshape(-1), labels)
+
+
+def _bonds3(Lx, Ly, Lz, p, seed, junk=False):
+    """Random packed cubic bonds, each bond present with probability p; with
+    junk the unused high bits are set at random too."""
+    rng = np.random.default_rng(seed)
+    N = Lx * Ly * Lz
+    b = ((rng.random((N, 3)) < p) * np.array([1, 2, 4])).sum(axis=1).astype(np.uint8)
+    if junk:
+        b |= (rng.integers(0, 32, N).astype(np.uint8) << 3)
+    return b
+
+
+@pytest.mark.parametrize("Lx,Ly,Lz", [(1, 1, 1), (2, 2, 2), (1, 40, 3), (33, 70, 20), (132, 13, 9), (64, 64, 64),
+                                       (257, 11, 17)])
+def test_ccl3_parity(Lx, Ly, Lz):
+    """Labels and cluster counts of random cubic bonds (several densities,
+    junk in the unused bits) against the oracle."""
+    print(f"ccl3 Lx={Lx} Ly={Ly} Lz={Lz}", flush=True)
+    for k, p in enumerate((0.0, 0.2, 0.2488, 0.4, 1.0)):
+        b = _bonds3(Lx, Ly, Lz, p, seed=7000 + k + Lx * 131 + Ly * 7 + Lz, junk=k % 2 == 1)
+        labels, n = sw.ccl3_label(torch.from_numpy(b.reshape(Lz, Ly, Lx)).cuda())
+        want, nref = oracle.label_bonds3(Lx, Ly, Lz, b & 7)
+        assert n == nref, (p, n, nref)
+        assert np.array_equal(labels.cpu().numpy().reshape(-1), want), p
+
+
+def test_ccl3_percolation_512():
+    """Bond percolation on the simple cubic lattice 512^3 near its threshold
+    (p = 0.2488), against the oracle; a caller workspace reused twice."""
+    L = 512
+    b = _bonds3(L, L, L, 0.2488, seed=wl.SEED_BASE | 0xCC3)
+    g = torch.from_numpy(b.reshape(L, L, L)).cuda()
+    ws = torch.empty(sw._lib.lib().ccl3_workspace_bytes(L, L, L) + 256, dtype=torch.uint8, device="cuda")
+    ws = ws[(-ws.data_ptr()) % 256:]
+    print("ccl3 512^3 bond percolation", flush=True)
+    labels, n = sw.ccl3_label(g, workspace=ws)
+    want, nref = oracle.label_bonds3(L, L, L, b)
+    assert n == nref
+    assert np.array_equal(labels.cpu().numpy().reshape(-1), want)
+    labels2, n2 = sw.ccl3_label(g, workspace=ws)
+    assert n2 == n and torch.equal(labels, labels2)
