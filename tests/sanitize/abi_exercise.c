@@ -189,6 +189,48 @@ int main(void)
     EXPECT(ccl_server_result(NULL, 0, NULL, NULL, NULL, NULL) == SW_ERR_ARG);
     EXPECT(ccl_server_release(NULL, 0) == SW_ERR_ARG && ccl_server_destroy(NULL) == SW_ERR_ARG);
 
+    /* cubic lattices: sizes over many shapes (up to the largest accepted
+     * classes and past them) and every argument error */
+    sw3_params c3;
+    memset(&c3, 0, sizeof c3);
+    c3.Lx = 64;
+    c3.Ly = 32;
+    c3.Lz = 16;
+    c3.q = 2;
+    c3.spin_kind = SW_SPIN_ISING_I8;
+    c3.K = 0.44;
+    c3.seed = 1;
+    const int32_t ext[] = {1, 2, 3, 31, 32, 33, 127, 128, 129, 1024, 2047, 65536};
+    for (size_t a = 0; a < sizeof ext / sizeof ext[0]; ++a)
+        for (size_t b = 0; b < sizeof ext / sizeof ext[0]; ++b)
+            for (size_t c = 0; c < sizeof ext / sizeof ext[0]; ++c) {
+                sw3_params q3 = c3;
+                q3.Lx = ext[a];
+                q3.Ly = ext[b];
+                q3.Lz = ext[c];
+                const int64_t N = (int64_t)ext[a] * ext[b] * ext[c];
+                const size_t w3 = sw3_workspace_bytes(&q3), l3 = ccl3_workspace_bytes(ext[a], ext[b], ext[c]);
+                if (N >= ((int64_t)1 << 31)) EXPECT(w3 == 0 && l3 == 0);
+                EXPECT((w3 == 0) == (l3 == 0));
+                if (w3) EXPECT(w3 > l3 && w3 >= (size_t)N * 3);
+            }
+    const size_t w3 = sw3_workspace_bytes(&c3);
+    EXPECT(w3 > 0);
+    sw3_params bad3 = c3;
+    bad3.flags = 1;
+    EXPECT(sw3_workspace_bytes(&bad3) == 0 && sw3_workspace_bytes(NULL) == 0);
+    EXPECT(sw3_sweep(&c3, NULL, 0, 1, NULL, NULL, NULL, ws, w3, NULL) == SW_ERR_ARG);
+    EXPECT(sw3_sweep(&c3, (uint8_t *)ws, 0, 1, NULL, NULL, NULL, ws, w3 - 1, NULL) == SW_ERR_WORKSPACE);
+    EXPECT(sw3_sweep(&c3, (uint8_t *)ws, UINT32_MAX, 2, NULL, NULL, NULL, ws, w3, NULL) == SW_ERR_STATE);
+    EXPECT(sw3_sweep(&bad3, (uint8_t *)ws, 0, 1, NULL, NULL, NULL, ws, w3, NULL) == SW_ERR_ARG);
+    EXPECT(sw3_sweep(&c3, (uint8_t *)ws, 0, 0, NULL, NULL, NULL, ws, w3, NULL) == SW_OK);
+    EXPECT(sw3_init_spins(&c3, NULL, NULL) == SW_ERR_ARG && sw3_init_spins(NULL, (uint8_t *)ws, NULL) == SW_ERR_ARG);
+    const size_t l3 = ccl3_workspace_bytes(64, 32, 16);
+    EXPECT(ccl3_label(NULL, 64, 32, 16, (int32_t *)ws, NULL, ws, l3, NULL) == SW_ERR_ARG);
+    EXPECT(ccl3_label(in, 64, 32, 16, NULL, NULL, ws, l3, NULL) == SW_ERR_ARG);
+    EXPECT(ccl3_label(in, 64, 32, 16, (int32_t *)ws, NULL, ws, l3 - 1, NULL) == SW_ERR_WORKSPACE);
+    EXPECT(ccl3_label(in, 0, 32, 16, (int32_t *)ws, NULL, ws, l3, NULL) == SW_ERR_SIZE);
+
     if (fails) return 1;
     printf("ok\n");
     return 0;

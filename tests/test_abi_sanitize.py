@@ -2,7 +2,7 @@
 with the sanitizers on its host side only (the device part is compiled but never run),
 and a C program that calls every entry point answering before the device is
 touched (sizes, status strings, thresholds, every argument error of the
-lattice, batch, labeling and server calls)."""
+lattice, batch, labeling, server and cubic-lattice calls)."""
 import os
 import shutil
 import subprocess
@@ -25,7 +25,8 @@ def test_abi_host_code_clean_under_sanitizers(tmp_path):
                     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                     "-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-sanitize-recover=all",
                     "-Xarch_host", "-fno-omit-frame-pointer",
-                    "-I", inc, "-o", lib, os.path.join(csrc, "swccl.hip"), os.path.join(csrc, "server.hip")],
+                    "-I", inc, "-o", lib, os.path.join(csrc, "swccl.hip"), os.path.join(csrc, "server.hip"),
+                    os.path.join(csrc, "cubic.hip")],
                    check=True, capture_output=True, timeout=600)
     exe = str(tmp_path / "abi_exercise")
     subprocess.run([CLANG, "-std=c11", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
