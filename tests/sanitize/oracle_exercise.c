@@ -74,6 +74,28 @@ static void sweeps(int32_t W, int32_t H, int32_t q, double K)
     free(lab);
 }
 
+/* Every cubic-lattice function on one Lx x Ly x Lz lattice. */
+static void cubic(int32_t Lx, int32_t Ly, int32_t Lz, int32_t q, double K, uint32_t *rs)
+{
+    const int64_t N = (int64_t)Lx * Ly * Lz;
+    uint8_t *st = xmalloc((size_t)N), *bonds = xmalloc((size_t)N);
+    int32_t *lab = xmalloc((size_t)N * 4);
+    int64_t rec[ORC3_REC_LEN], recs[3 * ORC3_REC_LEN], counts[8];
+    const uint64_t T = orc_threshold(K);
+    orc_init_states(Lx, Ly * Lz, q, 13u, 2u, st);
+    orc3_activate_bonds(Lx, Ly, Lz, st, T, 13u, 0u, 2u, bonds);
+    for (int64_t i = 0; i < N; ++i) bonds[i] = (uint8_t)(lcg(rs) & 7u);
+    (void)orc3_label_bonds(Lx, Ly, Lz, bonds, lab);
+    (void)orc3_satisfied(Lx, Ly, Lz, q, st, counts);
+    (void)orc3_satisfied(Lx, Ly, Lz, q, st, NULL);
+    orc3_sw_sweep(Lx, Ly, Lz, q, T, 13u, 2u, 1u, st, bonds, lab, rec);
+    orc3_sw_sweep(Lx, Ly, Lz, q, T, 13u, 2u, 2u, st, NULL, NULL, NULL);
+    orc3_sw_run(Lx, Ly, Lz, q, T, 13u, 2u, 3u, 3, st, recs);
+    free(st);
+    free(bonds);
+    free(lab);
+}
+
 int main(void)
 {
     uint32_t ctr[4] = {0u, 0u, 0u, 0u}, key[2] = {0u, 0u}, out[4];
@@ -93,6 +115,11 @@ int main(void)
         for (size_t j = 0; j < sizeof qs / sizeof qs[0]; ++j)
             for (size_t k = 0; k < sizeof Ks / sizeof Ks[0]; k += 3)
                 sweeps(sw_shapes[s][0], sw_shapes[s][1], qs[j], Ks[k]);
+    const int32_t cubes[][3] = {{1, 1, 1}, {1, 1, 5}, {2, 2, 2}, {3, 1, 2}, {5, 4, 3}, {17, 9, 6}, {32, 16, 16}};
+    for (size_t s = 0; s < sizeof cubes / sizeof cubes[0]; ++s)
+        for (size_t j = 0; j < sizeof qs / sizeof qs[0]; j += 2)
+            for (size_t k = 0; k < sizeof Ks / sizeof Ks[0]; k += 2)
+                cubic(cubes[s][0], cubes[s][1], cubes[s][2], qs[j], Ks[k], &rs);
     printf("ok\n");
     return 0;
 }
