@@ -114,6 +114,7 @@ struct Tile3Args {
     const uint8_t *spins;
     uint8_t *bonds;           // [N] packed bonds of the sweep (bit0 +x, bit1 +y, bit2 +z)
     uint16_t *codes;          // [ntiles][CSITES]
+    uint16_t *xface;          // [ntiles][2][FX]: codes of the x = 0 sites, then of the x = tw - 1 sites | +x bond << 15
     int32_t *gkey, *gparent;  // [ntiles][CAP]
     int32_t *nb;              // [ntiles]: ids of the tile
     int32_t *tile_act;        // [ntiles]: active bonds owned by the tile
@@ -144,6 +145,7 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
     // when it stays in the tile (the others cross a face and are merged by
     // k3_merge from the bond array).  Site indices fit 32 bits.
     uint64_t inside = 0;
+    uint32_t xbit = 0;  // bit 2 it + j: the +x bond of site lx0 + j of the step's row
     unsigned act = 0;
     const uint32_t Lx = static_cast<uint32_t>(g.Lx), Ly = static_cast<uint32_t>(g.Ly), Lz = static_cast<uint32_t>(g.Lz);
     // a tile full along y and z: every row of every step lies in it, the
@@ -280,6 +282,7 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
                 if (v1) a.bonds[i0 + 1] = static_cast<uint8_t>(m1);
             }
         }
+        xbit |= ((m0 & 1u) | ((m1 & 1u) << 1)) << (2 * it);
         const uint32_t in_x = (lx0 + 1 < T.tw ? 0x01u : 0u) | (lx0 + 2 < T.tw ? 0x10u : 0u);
         const uint32_t in_y = ly + 1 < T.th ? 0x22u : 0u, in_z = lz + 1 < T.td ? 0x44u : 0u;
         inside |= static_cast<uint64_t>((m0 | (m1 << 4)) & (in_x | in_y | in_z)) << (8 * it);
@@ -370,6 +373,13 @@ __global__ __launch_bounds__(NT3) void k3_tile(Tile3Args a)
                 c[j] = pr < 0 ? static_cast<uint32_t>(-pr - 2) : static_cast<uint32_t>(CAP + r);
             }
             *reinterpret_cast<uint32_t *>(codes + s) = c[0] | (c[1] << 16);
+            // the x faces again, packed by row (the merge reads them whole);
+            // a row's x-face position is its tile row R
+            uint16_t *xf = a.xface + static_cast<int64_t>(T.tile) * (2 * FX);
+            if (lx0 == 0) xf[R] = static_cast<uint16_t>(c[0]);
+            const int jl = T.tw - 1 - lx0;
+            if (jl == 0 || jl == 1)
+                xf[FX + R] = static_cast<uint16_t>((jl == 0 ? c[0] : c[1]) | (((xbit >> (2 * it + jl)) & 1u) << 15));
         }
     }
     const unsigned long long tot = wave_sum(act);
@@ -387,6 +397,7 @@ struct Merge3Args {
     Geo3 g;
     const uint8_t *bonds;
     const uint16_t *codes;
+    const uint16_t *xface;  // as written by k3_tile
     int32_t *gparent;
 };
 
@@ -483,16 +494,28 @@ __global__ __launch_bounds__(MT) void k3_merge(Merge3Args a)
 #pragma unroll
     for (int j = 0; j < MPOS; ++j) {  // every bond bit first (independent loads)
         int s1, s2;
-        const int64_t i = face(j * MT + static_cast<int>(threadIdx.x), dd[j], s1, s2);
-        act[j] = i >= 0 && ((a.bonds[i] >> dd[j]) & 1u);
-        ca[j] = s1;
-        cb[j] = s2;
+        const int f = j * MT + static_cast<int>(threadIdx.x);
+        const int64_t i = face(f, dd[j], s1, s2);
+        if (dd[j] == 0) {  // the +x face from the packed x faces: bond bit and code at once
+            const uint32_t h = i >= 0 ? a.xface[static_cast<int64_t>(T.tile) * (2 * FX) + FX + f] : 0u;
+            act[j] = ((h >> 15) & 1u) != 0u;
+            ca[j] = static_cast<int>(h & 0x7FFFu);
+            cb[j] = f;
+        } else {
+            act[j] = i >= 0 && ((a.bonds[i] >> dd[j]) & 1u);
+            ca[j] = s1;
+            cb[j] = s2;
+        }
     }
 #pragma unroll
     for (int j = 0; j < MPOS; ++j) {  // then the codes of the active ones
         if (!act[j]) continue;
-        ca[j] = a.codes[static_cast<int64_t>(T.tile) * CSITES + ca[j]];
-        cb[j] = a.codes[static_cast<int64_t>(nbr[dd[j]]) * CSITES + cb[j]];
+        if (dd[j] == 0) {
+            cb[j] = a.xface[static_cast<int64_t>(nbr[0]) * (2 * FX) + cb[j]];
+        } else {
+            ca[j] = a.codes[static_cast<int64_t>(T.tile) * CSITES + ca[j]];
+            cb[j] = a.codes[static_cast<int64_t>(nbr[dd[j]]) * CSITES + cb[j]];
+        }
         if (ca[j] >= CAP || cb[j] >= CAP) act[j] = false;  // face sites always hold ids
     }
     __syncthreads();  // seen and nlist are set
@@ -751,7 +774,7 @@ int64_t cdiv3(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Layout3 {
     Geo3 g;
     int64_t N;
-    size_t codes, gkey, gparent, nb, tile_act, tile_ncl, stats, bonds, total;
+    size_t codes, xface, gkey, gparent, nb, tile_act, tile_ncl, stats, bonds, total;
 };
 
 // Extents >= 1, N < 2^31, and the ids of all tiles (ntiles x CAP) index
@@ -795,6 +818,7 @@ Layout3 layout3(int32_t Lx, int32_t Ly, int32_t Lz, bool own_bonds = true)
         return at;
     };
     L.codes = take(nt * CSITES * sizeof(uint16_t));
+    L.xface = take(nt * 2 * FX * sizeof(uint16_t));
     L.gkey = take(nt * CAP * sizeof(int32_t));
     L.gparent = take(nt * CAP * sizeof(int32_t));
     L.nb = take(nt * sizeof(int32_t));
@@ -855,6 +879,7 @@ sw_status ccl3_label(const uint8_t *bonds, int32_t Lx, int32_t Ly, int32_t Lz, i
     ta.g = L.g;
     ta.bonds = const_cast<uint8_t *>(bonds);  // LABEL mode only reads them
     ta.codes = at3<uint16_t>(workspace, L.codes);
+    ta.xface = at3<uint16_t>(workspace, L.xface);
     ta.gkey = at3<int32_t>(workspace, L.gkey);
     ta.gparent = at3<int32_t>(workspace, L.gparent);
     ta.nb = at3<int32_t>(workspace, L.nb);
@@ -864,6 +889,7 @@ sw_status ccl3_label(const uint8_t *bonds, int32_t Lx, int32_t Ly, int32_t Lz, i
     ma.g = L.g;
     ma.bonds = bonds;
     ma.codes = ta.codes;
+    ma.xface = ta.xface;
     ma.gparent = ta.gparent;
     Resolve3Args ra{};
     ra.g = L.g;
@@ -910,6 +936,7 @@ sw_status sw3_sweep(const sw3_params *p, uint8_t *spins, uint32_t t0, int32_t n,
     ta.spins = spins;
     ta.bonds = bonds ? bonds : at3<uint8_t>(workspace, L.bonds);
     ta.codes = at3<uint16_t>(workspace, L.codes);
+    ta.xface = at3<uint16_t>(workspace, L.xface);
     ta.gkey = at3<int32_t>(workspace, L.gkey);
     ta.gparent = at3<int32_t>(workspace, L.gparent);
     ta.nb = at3<int32_t>(workspace, L.nb);
@@ -924,6 +951,7 @@ sw_status sw3_sweep(const sw3_params *p, uint8_t *spins, uint32_t t0, int32_t n,
     ma.g = L.g;
     ma.bonds = ta.bonds;
     ma.codes = ta.codes;
+    ma.xface = ta.xface;
     ma.gparent = ta.gparent;
 
     Flat3Args fa{};
