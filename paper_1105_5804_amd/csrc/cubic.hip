@@ -59,7 +59,7 @@ constexpr int ITER = RW / RPI;                                 // steps per wave
 static_assert(CSITES == 128 * NW3 * ITER && ITER == 8, "eight steps of 128 sites per wave");
 static_assert(CY % (2 * RPI) == 0 && RW % (2 * RPI) == 0, "steps pair up inside a z-plane");
 constexpr int MT = 256;                                        // merge workgroup
-constexpr int RT = 256;                                        // resolve workgroup
+constexpr int RT = 64;                                         // resolve workgroup: one wave per tile
 constexpr int MSEEN = 1024;                                    // merge: pair-dedup slots per face
 constexpr int FX = CY * CZ, FY = CX * CZ, FZ = CX * CY;        // sites of the +x, +y, +z faces
 constexpr uint32_t TAG_BOND = 1, TAG_FLIP = 2, TAG_BOND_Z = 5;
@@ -577,7 +577,8 @@ struct Resolve3Args {
 
 __global__ __launch_bounds__(RT) void k3_resolve(Resolve3Args a)
 {
-    // a workgroup per tile, its threads over the tile's ids
+    // a one-wave workgroup per tile, its lanes over the tile's ids (few idle
+    // lanes in the last pass over a tile's few hundred ids)
     const int tile = static_cast<int>(blockIdx.x);
     const int nbt = a.nb[tile];
     for (int k = threadIdx.x; k < nbt; k += RT) {
